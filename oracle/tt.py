@@ -1,0 +1,268 @@
+"""Plain 2-core tensor-train algebra (Section 3 of the paper).
+
+Oracle (test infrastructure only).
+
+A 2-core TT of an n1 x n2 matrix is X(i1, i2) = G1(i1) G2(i2) (Section 3.1, the 2-D form
+of the TT definition).  It is stored here as two factors A = G1 (n1 x r) and B = G2^T
+(n2 x r), so X = A @ B.T.
+
+Operations
+  round        Section 3.2: orthogonalise the second core (RQ of G2, done as QR of B),
+               then truncated SVD of G1 R at relative Frobenius accuracy eps, rank <= rmax.
+  add / scale  sums of TTs concatenate the cores (ranks add); when two terms share the
+               second core object the first cores are added instead.
+  hadamard     elementwise product: row-wise Kronecker (face-splitting) product of cores,
+               ranks multiply (used throughout Section 4.2).
+  tt_sum, norm sum of all entries and Frobenius norm (used by Algorithm 1).
+  reciprocal   Algorithm 1 (Taylor series of 1/x about the mean of x).
+  maxvol       maximum-volume row selection (Goreinov et al., cited in Section 3.3).
+  cross        alternating skeleton (CUR) cross interpolation with maxvol pivots
+               (Section 3.3; a plain alternating-maxvol stand-in for AMEn cross).
+  splitmix64   counter-based generator (Steele, Lea and Flood 2014) for the index kicks.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class TT:
+    A: np.ndarray   # n1 x r  (first core G1)
+    B: np.ndarray   # n2 x r  (second core G2, transposed)
+
+    @property
+    def rank(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def shape(self):
+        return (self.A.shape[0], self.B.shape[0])
+
+    def full(self) -> np.ndarray:
+        return self.A @ self.B.T
+
+    def T(self) -> "TT":
+        return TT(self.B, self.A)
+
+
+def zero_tt(n1: int, n2: int) -> TT:
+    return TT(np.zeros((n1, 1)), np.zeros((n2, 1)))
+
+
+def ones_tt(n1: int, n2: int) -> TT:
+    return TT(np.ones((n1, 1)), np.ones((n2, 1)))
+
+
+def trunc_rank(s: np.ndarray, eps: float, rmax: int) -> int:
+    """Smallest k >= 1 with ||s[k:]|| <= eps ||s||, then capped at rmax."""
+    ss = s * s
+    total = float(ss.sum())
+    tail = np.cumsum(ss[::-1])[::-1]          # tail[k] = sum_{i >= k} s_i^2
+    thr = (eps * eps) * total
+    k = len(s)
+    for kk in range(1, len(s) + 1):
+        t = float(tail[kk]) if kk < len(s) else 0.0
+        if t <= thr:
+            k = kk
+            break
+    return max(1, min(k, rmax))
+
+
+def tt_round(X: TT, eps: float, rmax: int) -> TT:
+    """TT rounding (Section 3.2): QR of the second core, truncated SVD of G1 R."""
+    qb, rb = np.linalg.qr(X.B)              # B = qb rb  <=>  G2 = rb^T qb^T (RQ of G2)
+    W = X.A @ rb.T                          # G1 R, n1 x min(n2, r)
+    u, s, vt = np.linalg.svd(W, full_matrices=False)
+    if s.size == 0 or s[0] == 0.0:
+        return zero_tt(*X.shape)
+    k = trunc_rank(s, eps, rmax)
+    return TT(u[:, :k] * s[None, :k], qb @ vt[:k].T)
+
+
+def add(terms) -> TT:
+    """Sum of (coefficient, TT) pairs; terms sharing the same B array object add their A."""
+    groups = []
+    for c, X in terms:
+        for g in groups:
+            if g[1] is X.B:
+                g[0] = g[0] + c * X.A
+                break
+        else:
+            groups.append([c * X.A, X.B])
+    return TT(np.concatenate([g[0] for g in groups], axis=1),
+              np.concatenate([g[1] for g in groups], axis=1))
+
+
+def scale(X: TT, c: float) -> TT:
+    return TT(c * X.A, X.B)
+
+
+def hadamard(X: TT, Y: TT) -> TT:
+    """Elementwise product; column a*ry + b of each core is X_col(a) * Y_col(b)."""
+    n1, n2 = X.shape
+    A = (X.A[:, :, None] * Y.A[:, None, :]).reshape(n1, -1)
+    B = (X.B[:, :, None] * Y.B[:, None, :]).reshape(n2, -1)
+    return TT(A, B)
+
+
+def tt_sum(X: TT) -> float:
+    return float(X.A.sum(axis=0) @ X.B.sum(axis=0))
+
+
+def norm(X: TT) -> float:
+    v = float(np.sum((X.A.T @ X.A) * (X.B.T @ X.B)))
+    return math.sqrt(max(v, 0.0))
+
+
+def reciprocal(x: TT, eps: float, max_terms: int, rmax: int):
+    """Algorithm 1: Taylor series of 1/x about its mean value.
+
+    max_terms counts the constant term, so at most max_terms - 1 products are formed.
+    The loop stops as soon as Err = ||dy||_F / sqrt(N) <= eps.
+    Returns (y, err, terms).
+    """
+    n1, n2 = x.shape
+    N = n1 * n2
+    xavg = tt_sum(x) / N
+    one = ones_tt(n1, n2)
+    xt = tt_round(add([(1.0, one), (-1.0 / xavg, x)]), eps, rmax)
+    y = ones_tt(n1, n2)
+    dy = ones_tt(n1, n2)
+    err = 1.0
+    terms = 1
+    while err > eps and terms < max_terms:
+        dy = tt_round(hadamard(dy, xt), eps, rmax)
+        y = tt_round(add([(1.0, y), (1.0, dy)]), eps, rmax)
+        err = norm(dy) / math.sqrt(N)
+        terms += 1
+    return scale(y, 1.0 / xavg), err, terms
+
+
+# ---------------------------------------------------------------------------
+# maxvol and cross
+
+def greedy_rows(Q: np.ndarray) -> np.ndarray:
+    """Initial rows for maxvol: repeatedly take the row of largest residual norm and project
+    its direction out of all rows (pivoted QR of Q^T).  For an orthonormal basis Q the
+    choice does not depend on which orthonormal basis of the column space is used."""
+    n, r = Q.shape
+    R = Q.copy()
+    rows = []
+    for _ in range(r):
+        nrm = np.einsum("ij,ij->i", R, R)
+        i = int(np.argmax(nrm))          # ties -> smallest index
+        rows.append(i)
+        v = R[i] / math.sqrt(nrm[i])
+        R = R - np.outer(R @ v, v)
+    return np.array(rows, dtype=np.int64)
+
+
+def maxvol(Q: np.ndarray, tau: float = 1.05, maxit: int = 100):
+    """Rows I of Q (n x r, n >= r) with |Q Q[I]^{-1}| <= tau entrywise (dominant submatrix).
+
+    Swap loop of Goreinov et al.: B = Q Q[I]^{-1}; while max|B_ij| > tau, replace the j-th
+    chosen row by row i and update B by a rank-one correction.  Ties in argmax go to the
+    smallest row, then the smallest column.
+    """
+    n, r = Q.shape
+    I = greedy_rows(Q)
+    B = np.linalg.solve(Q[I].T, Q.T).T          # Q Q[I]^{-1}
+    for _ in range(maxit):
+        flat = int(np.argmax(np.abs(B)))
+        i, j = divmod(flat, r)
+        if abs(B[i, j]) <= tau:
+            break
+        bj = B[:, j].copy()
+        bi = B[i, :].copy()
+        bi[j] -= 1.0
+        B -= np.outer(bj, bi) / bj[i]
+        I[j] = i
+    return I
+
+
+def orth(C: np.ndarray, drop: float = 1e-13) -> np.ndarray:
+    """Orthonormal basis of range(C): QR, SVD of R, drop directions with s <= drop*s_max.
+
+    Each kept column is given a fixed sign (its entry of largest magnitude is positive) so
+    the basis is unique up to rounding.
+    """
+    q, r = np.linalg.qr(C)
+    u, s, _ = np.linalg.svd(r)
+    if s.size == 0 or s[0] == 0.0:
+        return np.zeros((C.shape[0], 0))
+    k = int(np.sum(s > drop * s[0]))
+    U = q @ u[:, :k]
+    idx = np.argmax(np.abs(U), axis=0)
+    sg = np.sign(U[idx, np.arange(k)])
+    sg[sg == 0] = 1.0
+    return U * sg[None, :]
+
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(state: int):
+    """One step of SplitMix64; returns (new_state, output)."""
+    state = (state + 0x9E3779B97F4A7C15) & MASK64
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return state, z ^ (z >> 31)
+
+
+def kick_indices(existing, n: int, count: int, key: int):
+    """`count` new indices in [0, n) not in `existing`, drawn with SplitMix64 from `key`."""
+    have = set(int(v) for v in existing)
+    out = []
+    state = key & MASK64
+    tries = 0
+    while len(out) < count and len(have) < n and tries < 64 * (count + 1):
+        state, z = splitmix64(state)
+        idx = int(z % n)
+        tries += 1
+        if idx not in have:
+            have.add(idx)
+            out.append(idx)
+    return out
+
+
+def cross(fun, n1: int, n2: int, J0, eps: float, rmax: int, sweeps: int = 3,
+          kick: int = 4, key: int = 0):
+    """Alternating maxvol skeleton cross of the n1 x n2 matrix defined by `fun`.
+
+    fun.cols(J) -> n1 x |J| array of entries, fun.rows(I) -> |I| x n2 array.
+    Each sweep: C = f(:, J); Qc = orth(C); I = maxvol(Qc); R = f(I, :); and, except in the
+    last sweep, J = maxvol(orth(R^T)) enlarged by `kick` fresh indices while |J| < rmax.
+    Result: round(Qc Qc[I]^{-1} R, eps, rmax).  Returns (TT, J used by the last sweep).
+    """
+    J = np.array(J0, dtype=np.int64)
+    Qc = I = Rw = None
+    for s in range(sweeps):
+        C = fun.cols(J)
+        Qc = orth(C)
+        if Qc.shape[1] == 0:
+            return zero_tt(n1, n2), J
+        I = maxvol(Qc)
+        Rw = fun.rows(I)
+        if s == sweeps - 1:
+            break
+        Qr = orth(Rw.T)
+        if Qr.shape[1] == 0:
+            return zero_tt(n1, n2), J
+        J = maxvol(Qr)
+        if len(J) < rmax and kick > 0:
+            extra = kick_indices(J, n2, min(kick, rmax - len(J)), key + 1000003 * (s + 1))
+            J = np.concatenate([J, np.array(extra, dtype=np.int64)])
+    G1 = np.linalg.solve(Qc[I].T, Qc.T).T         # Qc Qc[I]^{-1}
+    return tt_round(TT(G1, Rw.T), eps, rmax), J
+
+
+def initial_columns(Y: TT) -> np.ndarray:
+    """Starting column set for a cross: maxvol rows of an orthonormal basis of Y's second core."""
+    Q = orth(Y.B)
+    if Q.shape[1] == 0:
+        return np.array([0], dtype=np.int64)
+    return maxvol(Q)

@@ -1,0 +1,287 @@
+"""The tensor-train finite-volume step (Section 4), as a fixed sequence of TT operations.
+
+Oracle (test infrastructure only).
+
+State: three 2-core TTs (x index on the first core, y index on the second), the conserved
+variables (eta, u, v) of the linear SWE or (h, hu, hv) of the nonlinear SWE.
+
+One evaluation of L(Q) (Sections 4.1-4.3):
+
+  x direction (the y direction is the same sequence applied to the transposed TTs with the
+  two momenta swapped, so the normal momentum always comes second):
+    reconstruction  Upwind: the face stencils act on the first core (Step 1, faces),
+                    the Gauss-point stencils on the second core (Step 2); the minus and plus
+                    states share the second core (Section 4.3.1).
+                    WENO5: Algorithm 2 (two crosses over the 5 shifted copies in x) and
+                    Algorithm 3 (two crosses over 5 shifted copies in y, all Gauss points at
+                    once on the merged column index j*nq + m) (Section 4.3.2).
+    flux            linear: the LLF flux assembled directly from the states, no rounding
+                    (Section 4.2, lambda = sqrt(gH)).
+                    nonlinear, for each side s: 1/h by Algorithm 1, u = round(hu o 1/h),
+                    w = round(hv o 1/h), P1 = round(hu o u), P2 = round(h o h),
+                    F2 = round(P1 + g/2 P2), F3 = round(hu o w), F1 = hu;
+                    lambda by one cross of max(|hu-/h-| + sqrt(g h-), |hu+/h+| + sqrt(g h+));
+                    D_c = round(lambda o (q_c+ - q_c-)); Fhat_c = round((F_c- + F_c+)/2 - D_c/2).
+    finish          Gauss-Legendre sum over the quadrature rows of the second core, and the
+                    difference (T - 1) on the first core (Section 4.1).
+  L_c = -dF_c/dx - dG_c/dy (+ Coriolis source), a concatenation of cores.
+
+SSP-RK3 (Section 4.4): Q1 = F(Qn), Q2 = round(3/4 Qn + 1/4 F(Q1)),
+Qn+1 = round(1/3 Qn + 2/3 F(Q2)), with F(q) = round(q + dt L(q)).  One tolerance eps and
+one rank cap rmax serve every rounding.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import stencils
+from . import fv_grid
+from .tt import TT, add, cross, hadamard, initial_columns, norm, reciprocal, scale, tt_round, \
+    zero_tt
+
+NG = 3
+
+# reflection signs in "normal-first" variable order (q0, q_normal, q_tangential)
+SIGN_NORMAL = (1.0, -1.0, 1.0)
+SIGN_TANGENT = (1.0, 1.0, -1.0)
+
+
+def extend(core: np.ndarray, periodic: bool, sign: float) -> np.ndarray:
+    """Ghost-extend a core along its rows by NG rows per side (wrap, or mirror times sign)."""
+    if periodic:
+        return np.concatenate([core[-NG:], core, core[:NG]], axis=0)
+    return np.concatenate([sign * core[:NG][::-1], core, sign * core[-NG:][::-1]], axis=0)
+
+
+class _Lambda:
+    """Entries max(|m-/h-| + sqrt(g h-), |m+/h+| + sqrt(g h+)) from four TTs."""
+
+    def __init__(self, hm, mm, hp, mp, g):
+        self.t, self.g = (hm, mm, hp, mp), g
+
+    def _f(self, hm, mm, hp, mp):
+        g = self.g
+        return np.maximum(np.abs(mm / hm) + np.sqrt(g * hm), np.abs(mp / hp) + np.sqrt(g * hp))
+
+    def cols(self, J):
+        return self._f(*[X.A @ X.B[J].T for X in self.t])
+
+    def rows(self, I):
+        return self._f(*[X.A[I] @ X.B.T for X in self.t])
+
+
+class _WenoFace:
+    """Algorithm 2 entries: WENO5 Step-1 face value of the cells around face f, column j."""
+
+    def __init__(self, q: TT, periodic, sign, side, n_faces, tab, eps):
+        self.Ae, self.B = extend(q.A, periodic, sign), q.B
+        self.side, self.nf, self.tab, self.eps = side, n_faces, tab, eps
+
+    def _vals(self, rows_of):
+        if self.side < 0:   # right face of cell f-1
+            return {o: rows_of(NG + (-1 + o)) for o in range(-2, 3)}
+        return {o: rows_of(NG + (0 - o)) for o in range(-2, 3)}  # left face of cell f, mirrored
+
+    def cols(self, J):
+        f = np.arange(self.nf)
+        BJ = self.B[J].T
+        vals = self._vals(lambda off: self.Ae[f + off] @ BJ)
+        return fv_grid.recon_point(vals, self.tab, "face", "weno5", self.eps)
+
+    def rows(self, I):
+        I = np.asarray(I)
+        vals = self._vals(lambda off: self.Ae[I + off] @ self.B.T)
+        return fv_grid.recon_point(vals, self.tab, "face", "weno5", self.eps)
+
+
+class _WenoQuad:
+    """Algorithm 3 entries: WENO5 Step-2 value at Gauss point m of cell j, column j*nq + m."""
+
+    def __init__(self, v: TT, periodic, sign, n, tab, eps):
+        self.A, self.Be = v.A, extend(v.B, periodic, sign)
+        self.n, self.tab, self.eps, self.nq = n, tab, eps, tab["nq"]
+
+    def _quad(self, vals):
+        return np.stack([fv_grid.recon_point(vals, self.tab, m, "weno5", self.eps)
+                         for m in range(self.nq)], axis=-1)
+
+    def cols(self, J):
+        J = np.asarray(J)
+        j, m = J // self.nq, J % self.nq
+        vals = {o: self.A @ self.Be[NG + j + o].T for o in range(-2, 3)}
+        allq = self._quad(vals)                              # n_f x |J| x nq
+        return allq[:, np.arange(len(J)), m]
+
+    def rows(self, I):
+        I = np.asarray(I)
+        jj = np.arange(self.n)
+        vals = {o: self.A[I] @ self.Be[NG + jj + o].T for o in range(-2, 3)}
+        return self._quad(vals).reshape(len(I), -1)          # column j*nq + m
+
+
+class TTSolver:
+    def __init__(self, n: int, scheme: str, nonlinear: bool, periodic: bool = True,
+                 g: float = 9.81, H: float = 1.0, f: float = 0.0, eps: float = 1e-10,
+                 rmax: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
+                 cross_kick: int = 4, cross_full: bool = False):
+        self.n, self.scheme, self.nonlinear, self.periodic = n, scheme, nonlinear, periodic
+        self.g, self.H, self.f = g, H, f
+        self.eps, self.rmax, self.K = eps, rmax, taylor_terms
+        self.sweeps, self.kick, self.cross_full = cross_sweeps, cross_kick, cross_full
+        self.dx = 1.0 / n
+        self.tab = stencils.tables(scheme)
+        self.nq = self.tab["nq"]
+        self.nf = n if periodic else n + 1
+        k = self.tab["k"]
+        self.face_w = np.asarray(self.tab["face_full"])       # offsets -k..k, at +1/2
+        self.quad_w = [np.asarray(w) for w in self.tab["quad_full"]]
+        self.k = k
+        self.pivots = {}
+        self.step_index = 0
+        self.stats = {"taylor_terms": [], "taylor_err": [], "ranks": []}
+
+    # -- helpers ---------------------------------------------------------------
+    def rnd(self, X: TT) -> TT:
+        return tt_round(X, self.eps, self.rmax)
+
+    def face_cores(self, A: np.ndarray, sign: float):
+        """(Rf- A, Rf+ A): face values of every column of the core, n_f x r each."""
+        E = extend(A, self.periodic, sign)
+        f = np.arange(self.nf)
+        k = self.k
+        m = sum(self.face_w[o + k] * E[NG + f - 1 + o] for o in range(-k, k + 1))
+        p = sum(self.face_w[o + k] * E[NG + f - o] for o in range(-k, k + 1))
+        return m, p
+
+    def quad_core(self, B: np.ndarray, sign: float) -> np.ndarray:
+        """Gauss-point values of every column, rows j*nq + m, (n*nq) x r."""
+        E = extend(B, self.periodic, sign)
+        j = np.arange(self.n)
+        k = self.k
+        out = np.stack([sum(w[o + k] * E[NG + j + o] for o in range(-k, k + 1))
+                        for w in self.quad_w], axis=1)        # n x nq x r
+        return out.reshape(self.n * self.nq, -1)
+
+    def _cross(self, fun, n1, n2, y0: TT, site: int):
+        if self.cross_full:
+            J0 = np.arange(n2)
+            X, J = cross(fun, n1, n2, J0, self.eps, self.rmax, sweeps=1, kick=0)
+            return X
+        J0 = self.pivots.get(site)
+        if J0 is None:
+            J0 = initial_columns(y0)
+        key = (site << 32) | (self.step_index & 0xFFFFFFFF)
+        X, J = cross(fun, n1, n2, J0, self.eps, self.rmax, self.sweeps, self.kick, key)
+        self.pivots[site] = J
+        return X
+
+    # -- one direction -----------------------------------------------------------
+    def states(self, Q, site_base: int):
+        """Face-quadrature states (minus, plus) of the three variables."""
+        qm, qp = [], []
+        if self.scheme != "weno5":
+            for c, q in enumerate(Q):
+                Am, Ap = self.face_cores(q.A, SIGN_NORMAL[c])
+                Bq = self.quad_core(q.B, SIGN_TANGENT[c])
+                qm.append(TT(Am, Bq))
+                qp.append(TT(Ap, Bq))
+            return qm, qp
+        eps_w = self.dx * self.dx
+        nn = self.n * self.nq
+        for c, q in enumerate(Q):
+            out = []
+            for side_i, side in enumerate((-1, 1)):
+                site = site_base + 16 + c * 4 + side_i
+                v = self._cross(_WenoFace(q, self.periodic, SIGN_NORMAL[c], side, self.nf,
+                                          self.tab, eps_w), self.nf, self.n, q, site)
+                # initial columns for Step 2: v's second core repeated for every Gauss point
+                y0 = TT(v.A, np.repeat(v.B, self.nq, axis=0))
+                w = self._cross(_WenoQuad(v, self.periodic, SIGN_TANGENT[c], self.n, self.tab,
+                                          eps_w), self.nf, nn, y0, site + 2)
+                out.append(w)
+            qm.append(out[0])
+            qp.append(out[1])
+        return qm, qp
+
+    def face_flux(self, Q, site_base: int):
+        """Fhat for the direction whose normal core is the first core: 3 TTs n_f x (n*nq)."""
+        qm, qp = self.states(Q, site_base)
+        if not self.nonlinear:
+            g, H = self.g, self.H
+            c = math.sqrt(g * H)
+            eta_m, u_m, v_m = qm
+            eta_p, u_p, v_p = qp
+            F0 = add([(0.5 * H, u_m), (0.5 * H, u_p), (-0.5 * c, eta_p), (0.5 * c, eta_m)])
+            F1 = add([(0.5 * g, eta_m), (0.5 * g, eta_p), (-0.5 * c, u_p), (0.5 * c, u_m)])
+            F2 = add([(-0.5 * c, v_p), (0.5 * c, v_m)])
+            return [F0, F1, F2]
+        g = self.g
+        F = {}
+        for s, (h, m, t) in (("m", qm), ("p", qp)):
+            rh, err, terms = reciprocal(h, self.eps, self.K, self.rmax)
+            self.stats["taylor_terms"].append(terms)
+            self.stats["taylor_err"].append(err)
+            u = self.rnd(hadamard(m, rh))
+            w = self.rnd(hadamard(t, rh))
+            P1 = self.rnd(hadamard(m, u))
+            P2 = self.rnd(hadamard(h, h))
+            F2 = self.rnd(add([(1.0, P1), (0.5 * g, P2)]))
+            F3 = self.rnd(hadamard(m, w))
+            F[s] = [m, F2, F3]
+        hm, mm = qm[0], qm[1]
+        hp, mp = qp[0], qp[1]
+        y0 = mm if norm(mm) > 0.0 else hm
+        lam = self._cross(_Lambda(hm, mm, hp, mp, g), self.nf, self.n * self.nq, y0, site_base)
+        out = []
+        for c in range(3):
+            dq = add([(1.0, qp[c]), (-1.0, qm[c])])
+            D = self.rnd(hadamard(lam, dq))
+            out.append(self.rnd(add([(0.5, F["m"][c]), (0.5, F["p"][c]), (-0.5, D)])))
+        return out
+
+    def finish(self, Fh: TT) -> TT:
+        """Gauss-Legendre sum on the second core, (T - 1) on the first core."""
+        w = np.asarray(self.tab["gl_weights"])
+        B = np.tensordot(Fh.B.reshape(self.n, self.nq, -1), w, axes=([1], [0]))
+        A = Fh.A
+        dA = (np.roll(A, -1, axis=0) - A) if self.periodic else (A[1:] - A[:-1])
+        return TT(dA, B)
+
+    def L(self, Q, stage: int):
+        """Right-hand side as three TTs (concatenations, not rounded)."""
+        Fx = [self.finish(F) for F in self.face_flux(Q, site_base=(0 * 3 + stage) << 6)]
+        Qy = [Q[0].T(), Q[2].T(), Q[1].T()]
+        Gy = [self.finish(F) for F in self.face_flux(Qy, site_base=(1 * 3 + stage) << 6)]
+        G = [Gy[0].T(), Gy[2].T(), Gy[1].T()]
+        dx = self.dx
+        out = []
+        for c in range(3):
+            terms = [(-1.0 / dx, Fx[c]), (-1.0 / dx, G[c])]
+            if self.f != 0.0 and c == 1:
+                terms.append((self.f, Q[2]))
+            if self.f != 0.0 and c == 2:
+                terms.append((-self.f, Q[1]))
+            out.append(add(terms))
+        return out
+
+    def euler(self, Q, dt: float, stage: int):
+        """F(q) = round(q + dt L(q))."""
+        Lq = self.L(Q, stage)
+        return [self.rnd(add([(1.0, q), (dt, l)])) for q, l in zip(Q, Lq)]
+
+    def step(self, Q, dt: float):
+        Q1 = self.euler(Q, dt, 0)
+        F1 = self.euler(Q1, dt, 1)
+        Q2 = [self.rnd(add([(0.75, q), (0.25, f)])) for q, f in zip(Q, F1)]
+        F2 = self.euler(Q2, dt, 2)
+        Qn = [self.rnd(add([(1.0 / 3.0, q), (2.0 / 3.0, f)])) for q, f in zip(Q, F2)]
+        self.step_index += 1
+        self.stats["ranks"].append([q.rank for q in Qn])
+        return Qn
+
+    def run(self, Q, dt: float, nsteps: int):
+        for _ in range(nsteps):
+            Q = self.step(Q, dt)
+        return Q

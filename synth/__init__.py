@@ -1,0 +1,292 @@
+"""Seeded synthetic initial states for the 2-D shallow water workloads.
+
+This module only produces input data.  It holds none of the solver's arithmetic:
+it evaluates the initial fields, averages them over the cells with a library-grade
+Gauss-Legendre rule (numpy.polynomial.legendre.leggauss), and compresses the
+cell-average matrix into two factors with numpy's LAPACK QR/SVD.  Both the CPU
+oracle and the GPU library receive the very same factors.
+
+Workloads (all on the unit square, g = 9.81):
+
+  linear_gaussian   linear SWE, one Gaussian bump on eta (amplitude 0.01, width 0.05,
+                    centre ~ U[0,1]^2), u = v = 0, periodic.          64 x 64, r 8
+  nonlinear_bumps   nonlinear SWE, h = 1 + 4 Gaussian bumps (amplitude U[0.01,0.1],
+                    width U[0.03,0.1], centres U[0,1]^2), u, v smooth Fourier
+                    fields with |k_x|,|k_y| <= 8 scaled to max |.| = 0.05.  1024^2, r 32
+  dam_break         nonlinear SWE, h = 1 + 0.5 tanh((0.3 - r)/0.01), r = distance
+                    to a centre ~ U[0.3,0.7]^2, u = v = 0, reflective walls. 2048^2, r 64
+
+The random draws are made in a fixed order from numpy.random.default_rng(seed).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+G_DEFAULT = 9.81
+
+
+@dataclasses.dataclass
+class Factored:
+    """A field stored as two factors: field[i, j] = sum_a A[i, a] * B[j, a]."""
+    A: np.ndarray  # (n1, r) float64, rows = x cells
+    B: np.ndarray  # (n2, r) float64, rows = y cells
+
+    @property
+    def rank(self) -> int:
+        return self.A.shape[1]
+
+    def full(self) -> np.ndarray:
+        return self.A @ self.B.T
+
+
+@dataclasses.dataclass
+class State:
+    """Initial state: three conserved variables, each as full cell averages and factors."""
+    name: str
+    n: int
+    nonlinear: bool
+    periodic: bool
+    g: float
+    H0: float
+    fields: list          # three (n, n) cell-average arrays, x index first
+    tt: list              # three Factored
+    dt: float             # CFL 0.4 time step from the initial full fields
+    meta: dict
+
+
+# ---------------------------------------------------------------------------
+# quadrature helpers (input preparation only)
+
+def _gl(npts: int):
+    x, w = np.polynomial.legendre.leggauss(npts)
+    return 0.5 * x, 0.5 * w          # nodes on [-1/2, 1/2], weights summing to 1
+
+
+def cell_avg_1d(fun, n: int, npts: int = 8) -> np.ndarray:
+    """Average of fun(x) over each of n equal cells of [0, 1]."""
+    xg, wg = _gl(npts)
+    h = 1.0 / n
+    centres = (np.arange(n) + 0.5) * h
+    pts = centres[:, None] + h * xg[None, :]
+    return (fun(pts) * wg[None, :]).sum(axis=1)
+
+
+def cell_avg_2d(fun, n: int, npts: int = 3, block: int = 256) -> np.ndarray:
+    """Average of fun(x, y) over each cell of an n x n grid of [0, 1]^2."""
+    xg, wg = _gl(npts)
+    h = 1.0 / n
+    centres = (np.arange(n) + 0.5) * h
+    px = centres[:, None] + h * xg[None, :]          # (n, q)
+    out = np.zeros((n, n))
+    for i0 in range(0, n, block):
+        X = px[i0:i0 + block]                          # (b, q)
+        acc = np.zeros((X.shape[0], n))
+        for a in range(npts):
+            for b in range(npts):
+                acc += wg[a] * wg[b] * fun(X[:, a][:, None], px[:, b][None, :])
+        out[i0:i0 + block] = acc
+    return out
+
+
+def compress(terms_x: np.ndarray, terms_y: np.ndarray, eps: float, rmax: int) -> Factored:
+    """Best rank-k factors of terms_x @ terms_y.T, relative Frobenius tolerance eps, k <= rmax."""
+    qa, ra = np.linalg.qr(terms_x)
+    qb, rb = np.linalg.qr(terms_y)
+    u, s, vt = np.linalg.svd(ra @ rb.T)
+    return _truncate(qa @ u, s, qb @ vt.T, eps, rmax)
+
+
+def compress_full(field: np.ndarray, eps: float, rmax: int) -> Factored:
+    u, s, vt = np.linalg.svd(field, full_matrices=False)
+    return _truncate(u, s, vt.T, eps, rmax)
+
+
+def _truncate(u, s, v, eps, rmax) -> Factored:
+    nrm = math.sqrt(float(np.sum(s * s)))
+    if nrm == 0.0:
+        n1, n2 = u.shape[0], v.shape[0]
+        return Factored(np.zeros((n1, 1)), np.zeros((n2, 1)))
+    tail = np.sqrt(np.cumsum((s * s)[::-1])[::-1])      # tail[k] = ||s[k:]||
+    k = len(s)
+    for kk in range(1, len(s) + 1):
+        t = tail[kk] if kk < len(s) else 0.0
+        if t <= eps * nrm:
+            k = kk
+            break
+    k = min(k, rmax)
+    return Factored(np.ascontiguousarray(u[:, :k] * s[None, :k]), np.ascontiguousarray(v[:, :k]))
+
+
+def _zero(n: int) -> Factored:
+    return Factored(np.zeros((n, 1)), np.zeros((n, 1)))
+
+
+def cfl_dt(fields, nonlinear: bool, g: float, H0: float, n: int, cfl: float = 0.4) -> float:
+    dx = 1.0 / n
+    if nonlinear:
+        h, hu, hv = fields
+        c = np.sqrt(g * h)
+        sx = float(np.max(np.abs(hu / h) + c))
+        sy = float(np.max(np.abs(hv / h) + c))
+    else:
+        c = math.sqrt(g * H0)
+        sx = float(np.max(np.abs(fields[1]))) + c
+        sy = float(np.max(np.abs(fields[2]))) + c
+    return cfl / (sx / dx + sy / dx)
+
+
+# ---------------------------------------------------------------------------
+# periodised Gaussians and Fourier modes as 1-D factor functions
+
+def _pgauss(c: float, w: float):
+    return lambda t: sum(np.exp(-((t - c - m) ** 2) / (2.0 * w * w)) for m in (-1, 0, 1))
+
+
+def linear_gaussian(seed: int = 0, n: int = 64, rmax: int = 8, eps: float = 1e-12,
+                    g: float = G_DEFAULT, H0: float = 1.0) -> State:
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 1.0, size=2)
+    gx = cell_avg_1d(_pgauss(c[0], 0.05), n)
+    gy = cell_avg_1d(_pgauss(c[1], 0.05), n)
+    eta = 0.01 * np.outer(gx, gy)
+    tt_eta = compress((0.01 * gx)[:, None], gy[:, None], eps, rmax)
+    fields = [eta, np.zeros((n, n)), np.zeros((n, n))]
+    dt = cfl_dt(fields, False, g, H0, n)
+    return State("linear_gaussian", n, False, True, g, H0, fields,
+                 [tt_eta, _zero(n), _zero(n)], dt, {"centre": c.tolist(), "seed": seed})
+
+
+def _fourier_terms(rng, kmax: int):
+    """Half-plane set of modes k with |kx|,|ky| <= kmax; returns list of (kx, ky, a, b)."""
+    modes = []
+    for kx in range(0, kmax + 1):
+        for ky in range(-kmax, kmax + 1):
+            if kx == 0 and ky <= 0:
+                continue
+            modes.append((kx, ky))
+    coef = rng.standard_normal(size=(len(modes), 2))
+    return [(kx, ky, coef[t, 0], coef[t, 1]) for t, (kx, ky) in enumerate(modes)]
+
+
+def _fourier_factors(modes, n: int, npts: int = 8):
+    """Write sum a cos(2pi k.x) + b sin(2pi k.x) as separable terms; return (X, Y) factor columns."""
+    two_pi = 2.0 * math.pi
+    colsx, colsy = [], []
+    for kx, ky, a, b in modes:
+        cx = cell_avg_1d(lambda t, k=kx: np.cos(two_pi * k * t), n, npts)
+        sx = cell_avg_1d(lambda t, k=kx: np.sin(two_pi * k * t), n, npts)
+        cy = cell_avg_1d(lambda t, k=ky: np.cos(two_pi * k * t), n, npts)
+        sy = cell_avg_1d(lambda t, k=ky: np.sin(two_pi * k * t), n, npts)
+        # a cos(A+B) + b sin(A+B) = a(cAcB - sAsB) + b(sAcB + cAsB)
+        colsx += [a * cx, -a * sx, b * sx, b * cx]
+        colsy += [cy, sy, cy, sy]
+    return np.stack(colsx, axis=1), np.stack(colsy, axis=1)
+
+
+def _fourier_pointwise(modes):
+    two_pi = 2.0 * math.pi
+
+    def f(x, y):
+        out = 0.0
+        for kx, ky, a, b in modes:
+            ph = two_pi * (kx * x + ky * y)
+            out = out + a * np.cos(ph) + b * np.sin(ph)
+        return out
+    return f
+
+
+def nonlinear_bumps(seed: int = 0, n: int = 1024, rmax: int = 32, eps: float = 1e-10,
+                    g: float = G_DEFAULT, nbumps: int = 4, kmax: int = 8,
+                    vel_amp: float = 0.05) -> State:
+    rng = np.random.default_rng(seed)
+    bumps = []
+    for _ in range(nbumps):
+        a = rng.uniform(0.01, 0.1)
+        w = rng.uniform(0.03, 0.1)
+        cx = rng.uniform(0.0, 1.0)
+        cy = rng.uniform(0.0, 1.0)
+        bumps.append((a, w, cx, cy))
+    modes_u = _fourier_terms(rng, kmax)
+    modes_v = _fourier_terms(rng, kmax)
+
+    # h as separable terms: 1 + sum_k a_k gx_k(x) gy_k(y)
+    hx = [np.ones(n)] + [a * cell_avg_1d(_pgauss(cx, w), n) for a, w, cx, cy in bumps]
+    hy = [np.ones(n)] + [cell_avg_1d(_pgauss(cy, w), n) for a, w, cx, cy in bumps]
+    hX, hY = np.stack(hx, 1), np.stack(hy, 1)
+
+    # u, v: scale so that the largest |cell average| is vel_amp
+    uX, uY = _fourier_factors(modes_u, n)
+    vX, vY = _fourier_factors(modes_v, n)
+    su = vel_amp / float(np.max(np.abs(uX @ uY.T)))
+    sv = vel_amp / float(np.max(np.abs(vX @ vY.T)))
+
+    # hu, hv: cell averages of the pointwise products, term by term (separable)
+    def prod_terms(scale, modes):
+        two_pi = 2.0 * math.pi
+        fx = [lambda t: np.ones_like(t)] + [
+            (lambda t, a=a, w=w, cx=cx: a * _pgauss(cx, w)(t)) for a, w, cx, cy in bumps]
+        fy = [lambda t: np.ones_like(t)] + [
+            (lambda t, w=w, cy=cy: _pgauss(cy, w)(t)) for a, w, cx, cy in bumps]
+        colsx, colsy = [], []
+        for kx, ky, a, b in modes:
+            gxs = [lambda t, k=kx: np.cos(two_pi * k * t), lambda t, k=kx: np.sin(two_pi * k * t)]
+            gys = [lambda t, k=ky: np.cos(two_pi * k * t), lambda t, k=ky: np.sin(two_pi * k * t)]
+            # a(cAcB - sAsB) + b(sAcB + cAsB)
+            combos = [(a, 0, 0), (-a, 1, 1), (b, 1, 0), (b, 0, 1)]
+            for coef, ix, iy in combos:
+                for fxi, fyi in zip(fx, fy):
+                    colsx.append(scale * coef * cell_avg_1d(
+                        lambda t, p=fxi, q=gxs[ix]: p(t) * q(t), n))
+                    colsy.append(cell_avg_1d(lambda t, p=fyi, q=gys[iy]: p(t) * q(t), n))
+        return np.stack(colsx, 1), np.stack(colsy, 1)
+
+    huX, huY = prod_terms(su, modes_u)
+    hvX, hvY = prod_terms(sv, modes_v)
+    h = hX @ hY.T
+    hu = huX @ huY.T
+    hv = hvX @ hvY.T
+    tt = [compress(hX, hY, eps, rmax), compress(huX, huY, eps, rmax), compress(hvX, hvY, eps, rmax)]
+    fields = [h, hu, hv]
+    dt = cfl_dt(fields, True, g, 1.0, n)
+    meta = {"seed": seed, "bumps": bumps, "su": su, "sv": sv,
+            "ranks": [t.rank for t in tt]}
+    return State("nonlinear_bumps", n, True, True, g, 1.0, fields, tt, dt, meta)
+
+
+def dam_break(seed: int = 0, n: int = 2048, rmax: int = 64, eps: float = 1e-8,
+              g: float = G_DEFAULT, width: float = 0.01, radius: float = 0.3) -> State:
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.3, 0.7, size=2)
+
+    def hfun(x, y):
+        r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2)
+        return 1.0 + 0.5 * np.tanh((radius - r) / width)
+    h = cell_avg_2d(hfun, n, npts=3)
+    tt = [compress_full(h, eps, rmax), _zero(n), _zero(n)]
+    fields = [h, np.zeros((n, n)), np.zeros((n, n))]
+    dt = cfl_dt(fields, True, g, 1.0, n)
+    return State("dam_break", n, True, False, g, 1.0, fields, tt, dt,
+                 {"seed": seed, "centre": c.tolist(), "ranks": [t.rank for t in tt]})
+
+
+def random_factored(rng, n1: int, n2: int, r: int, decay: float = 0.5) -> Factored:
+    """Random factors with geometrically decaying column scales (for primitive tests)."""
+    A = rng.standard_normal((n1, r)) * (decay ** np.arange(r))[None, :]
+    B = rng.standard_normal((n2, r))
+    return Factored(A, B)
+
+
+def smooth_factored(rng, n1: int, n2: int, r: int, base: float = 1.0) -> Factored:
+    """Smooth positive-ish field: base + small smooth perturbation, as factors."""
+    x = (np.arange(n1) + 0.5) / n1
+    y = (np.arange(n2) + 0.5) / n2
+    A = [base * np.ones(n1)]
+    B = [np.ones(n2)]
+    for k in range(1, r):
+        a = rng.uniform(-0.05, 0.05) / k
+        A.append(a * np.cos(2 * math.pi * k * x + rng.uniform(0, 2 * math.pi)))
+        B.append(np.cos(2 * math.pi * k * y + rng.uniform(0, 2 * math.pi)))
+    return Factored(np.stack(A, 1), np.stack(B, 1))

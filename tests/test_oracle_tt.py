@@ -1,0 +1,200 @@
+"""Pins for the oracle's tensor-train algebra (Section 3, Algorithm 1) and the TT step."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fv_grid, tt, tt_fv
+
+
+def rand_tt(rng, n1, n2, r, decay=0.6):
+    return tt.TT(rng.standard_normal((n1, r)) * decay ** np.arange(r), rng.standard_normal((n2, r)))
+
+
+def test_round_equals_truncated_svd_of_full_matrix():
+    """For two cores, rounding is the truncated SVD of the full matrix (Eckart-Young)."""
+    rng = np.random.default_rng(0)
+    for n1, n2, r in ((30, 20, 12), (15, 40, 25), (8, 8, 20)):
+        X = rand_tt(rng, n1, n2, r)
+        F = X.full()
+        u, s, vt = np.linalg.svd(F)
+        for eps, rmax in ((1e-3, 100), (1e-8, 5), (0.0, 100)):
+            Y = tt.tt_round(X, eps, rmax)
+            # brute-force rank choice
+            k = 1
+            while k < len(s) and math.sqrt(np.sum(s[k:] ** 2)) > eps * np.linalg.norm(s):
+                k += 1
+            k = min(k, rmax, r)            # at eps = 0 only the r nonzero values count
+            assert Y.rank == k
+            ref = (u[:, :k] * s[:k]) @ vt[:k]
+            assert np.linalg.norm(Y.full() - ref) <= 1e-12 * np.linalg.norm(F)
+            if k < rmax:
+                assert np.linalg.norm(Y.full() - F) <= eps * np.linalg.norm(F) * (1 + 1e-9) + 1e-13
+
+
+def test_round_idempotent_and_zero():
+    rng = np.random.default_rng(1)
+    X = tt.tt_round(rand_tt(rng, 20, 30, 6), 0.0, 100)
+    Y = tt.tt_round(X, 1e-12, 100)
+    assert Y.rank == X.rank
+    assert np.allclose(Y.full(), X.full(), atol=1e-13)
+    Z = tt.tt_round(tt.zero_tt(5, 7), 1e-10, 4)
+    assert Z.rank == 1 and not np.any(Z.full())
+
+
+def test_sum_hadamard_norm_against_elementwise():
+    rng = np.random.default_rng(2)
+    X, Y = rand_tt(rng, 11, 13, 4), rand_tt(rng, 11, 13, 3)
+    assert np.allclose(tt.hadamard(X, Y).full(), X.full() * Y.full(), atol=1e-13)
+    assert tt.hadamard(X, Y).rank == 12
+    S = tt.add([(2.0, X), (-0.5, Y)])
+    assert np.allclose(S.full(), 2 * X.full() - 0.5 * Y.full(), atol=1e-13)
+    assert S.rank == 7
+    shared = tt.TT(X.A * 3, X.B)
+    S2 = tt.add([(1.0, X), (1.0, shared)])
+    assert S2.rank == X.rank
+    assert np.allclose(S2.full(), 4 * X.full(), atol=1e-13)
+    assert abs(tt.tt_sum(X) - X.full().sum()) < 1e-12
+    assert abs(tt.norm(X) - np.linalg.norm(X.full())) < 1e-12
+
+
+def test_reciprocal_special_cases_and_bound():
+    n1, n2 = 12, 9
+    # constant input: x~ = 0, exact after the first term
+    c = tt.TT(np.full((n1, 1), 2.5), np.ones((n2, 1)))
+    y, err, terms = tt.reciprocal(c, 1e-12, 8, 10)
+    assert np.allclose(y.full(), 0.4, atol=1e-15)
+    # eps = 0, no cap: y is exactly the truncated geometric series sum_{k<K} x~^k / xbar
+    rng = np.random.default_rng(4)
+    x = tt.TT(np.concatenate([np.ones((n1, 1)), 0.1 * rng.standard_normal((n1, 2))], 1),
+              np.concatenate([np.ones((n2, 1)), 0.3 * rng.standard_normal((n2, 2))], 1))
+    F = x.full()
+    xbar = F.mean()
+    xt = 1 - F / xbar
+    for K in (2, 4, 6):
+        y, err, terms = tt.reciprocal(x, 0.0, K, 1000)
+        series = sum(xt ** k for k in range(K)) / xbar
+        assert terms == K
+        assert np.allclose(y.full(), series, atol=1e-13)
+        bound = np.abs(xt) ** K / ((1 - np.abs(xt)) * xbar)
+        assert np.all(np.abs(y.full() - 1 / F) <= bound + 1e-13)
+    # with a tolerance the loop stops once ||dy||/sqrt(N) <= eps
+    y, err, terms = tt.reciprocal(x, 1e-6, 50, 1000)
+    assert err <= 1e-6 and terms < 50
+
+
+def _vol(Q, rows):
+    return abs(np.linalg.det(Q[list(rows)]))
+
+
+def test_maxvol_against_brute_force():
+    rng = np.random.default_rng(7)
+    for trial in range(30):
+        n = int(rng.integers(4, 13))
+        r = int(rng.integers(1, 4))
+        Q = np.linalg.qr(rng.standard_normal((n, r)))[0]
+        I = tt.maxvol(Q, tau=1.0 + 1e-12, maxit=500)
+        B = Q @ np.linalg.inv(Q[I])
+        assert np.max(np.abs(B)) <= 1.0 + 1e-9            # dominance
+        assert np.allclose(B[I], np.eye(r), atol=1e-10)
+        best = max(_vol(Q, c) for c in itertools.combinations(range(n), r))
+        if r == 1:
+            assert _vol(Q, I) == pytest.approx(best)        # r = 1: exact argmax
+        # a dominant set is a local maximum: no single swap increases the volume
+        v = _vol(Q, I)
+        for j in range(r):
+            for i in range(n):
+                J = list(I)
+                J[j] = i
+                assert _vol(Q, J) <= v * (1 + 1e-9)
+        assert v >= best / (r ** (r / 2.0)) - 1e-12      # Goreinov et al. bound
+
+
+def test_maxvol_returns_identity_block():
+    rng = np.random.default_rng(8)
+    r = 3
+    A = 0.5 * (2 * rng.random((10, r)) - 1)
+    A[[2, 5, 7]] = np.eye(r)
+    I = tt.maxvol(A, tau=1.0 + 1e-12)
+    assert sorted(I.tolist()) == [2, 5, 7]
+
+
+class _Full:
+    def __init__(self, F):
+        self.F = F
+
+    def cols(self, J):
+        return self.F[:, J]
+
+    def rows(self, I):
+        return self.F[I, :]
+
+
+def test_cross_reproduces_low_rank_and_full_rank():
+    rng = np.random.default_rng(9)
+    X = rand_tt(rng, 40, 35, 5, decay=0.8)
+    F = X.full()
+    Y, J = tt.cross(_Full(F), 40, 35, np.arange(3), 1e-14, 20, sweeps=3, kick=4, key=11)
+    assert np.linalg.norm(Y.full() - F) < 1e-11 * np.linalg.norm(F)
+    G = np.exp(-rng.random((9, 8)))
+    Y, J = tt.cross(_Full(G), 9, 8, np.arange(8), 0.0, 100, sweeps=1, kick=0)
+    assert np.allclose(Y.full(), G, atol=1e-12)
+
+
+def test_splitmix64_reference_outputs():
+    s, a = tt.splitmix64(0)
+    s, b = tt.splitmix64(s)
+    assert a == 0xE220A8397B1DCDAF
+    assert b == 0x6E789E6AA1B965F4
+    k = tt.kick_indices([0, 1, 2], 10, 4, key=123)
+    assert len(set(k)) == 4 and not set(k) & {0, 1, 2}
+    assert k == tt.kick_indices([0, 1, 2], 10, 4, key=123)
+
+
+def _svd_tt(U):
+    u, s, vt = np.linalg.svd(U)
+    return tt.TT(u * s, vt.T)
+
+
+@pytest.mark.parametrize("scheme,nonlinear,periodic", [
+    ("upwind3", False, True), ("upwind5", False, True), ("upwind3", True, False),
+    ("upwind5", True, True), ("upwind5", True, False), ("weno5", True, True), ("weno5", True, False)])
+def test_tt_step_equals_grid_step_at_full_rank(scheme, nonlinear, periodic):
+    """With eps = 0, no rank cap, Taylor run to round-off and full-rank crosses, the TT step
+    is the full-grid step (the whole fixed sequence of TT operations against the definition)."""
+    n = 10
+    x = (np.arange(n) + 0.5) / n
+    if nonlinear:
+        h = 1 + 0.02 * np.outer(np.cos(2 * np.pi * x), np.sin(2 * np.pi * x + 0.3)) \
+            + 0.01 * np.outer(np.sin(4 * np.pi * x), np.ones(n))
+        hu = 0.03 * np.outer(np.sin(2 * np.pi * x + 0.1), np.cos(2 * np.pi * x))
+        hv = 0.02 * np.outer(np.cos(2 * np.pi * x), np.cos(4 * np.pi * x + 0.2))
+        U = [h, hu, hv]
+    else:
+        U = [0.01 * np.outer(np.cos(2 * np.pi * x), np.sin(2 * np.pi * x)),
+             0.01 * np.outer(np.sin(2 * np.pi * x), np.ones(n)),
+             0.001 * np.outer(np.ones(n), np.cos(2 * np.pi * x))]
+    gs = fv_grid.GridSolver(n, scheme, nonlinear, periodic)
+    ts = tt_fv.TTSolver(n, scheme, nonlinear, periodic, eps=0.0, rmax=10 ** 6, taylor_terms=30,
+                        cross_full=True)
+    Ug = gs.step(U, 1e-3)
+    Qt = ts.step([_svd_tt(u) for u in U], 1e-3)
+    for q, u in zip(Qt, Ug):
+        assert np.linalg.norm(q.full() - u) <= 1e-12 * np.linalg.norm(u)
+
+
+def test_linear_gaussian_tt_run_tracks_grid_run():
+    """The 64^2 linear Gaussian at rank cap 8, tol 1e-12: TT compression error stays small."""
+    import synth
+    st = synth.linear_gaussian(seed=0)
+    gs = fv_grid.GridSolver(st.n, "upwind3", False, True, g=st.g, H=st.H0)
+    ts = tt_fv.TTSolver(st.n, "upwind3", False, True, g=st.g, H=st.H0, eps=1e-12, rmax=8)
+    Q = [tt.TT(f.A, f.B) for f in st.tt]
+    U = st.fields
+    for _ in range(10):
+        U = gs.step(U, st.dt)
+        Q = ts.step(Q, st.dt)
+    rel = np.linalg.norm(Q[0].full() - U[0]) / np.linalg.norm(U[0])
+    assert rel < 1e-3
+    assert all(r <= 8 for r in ts.stats["ranks"][-1])
