@@ -1,0 +1,154 @@
+/*
+ * tt_fv.h -- C ABI of the MI355X (gfx950) tensor-train finite-volume library.
+ *
+ * Method: Danis et al., "High-order Tensor-Train Finite Volume Method for Shallow Water
+ * Equations" (arXiv 2408.03483).  Every field is a 2-core tensor train
+ *     X(i1, i2) = sum_a G1(i1, a) * G2(a, i2)          (Section 3.1, 2-D form of the TT)
+ * stored as two column-major device arrays: g1 = G1 (n1 x rank) and g2 = G2^T (n2 x rank).
+ * For a solution field i1 is the x cell and i2 the y cell.
+ *
+ * Conventions for every entry point
+ *   - Pointers inside tt_matrix are DEVICE pointers owned by the caller.  Their column
+ *     capacity `cap` must be at least the rank written into them; the library never
+ *     frees or reallocates them.  Leading dimensions are n1 and n2 (no padding).
+ *   - All work is enqueued on the stream of the tt_ctx (or solver) and the call returns
+ *     after the stream has been synchronised: ranks chosen on the device are read back
+ *     to set tt_matrix.rank.  Outputs may not alias inputs.
+ *   - Temporary device memory comes from the context's arena, allocated once by
+ *     tt_ctx_create / tt_fv_init; no entry point below allocates device memory.
+ *   - Return value: 0 on success, a negative TT_E* code on error (outputs untouched
+ *     or partially written), or a positive bitmask of TT_W* warnings.
+ *     tt_last_error() gives a message for the last failure in the calling thread.
+ */
+#ifndef TT_FV_H
+#define TT_FV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes (negative) */
+#define TT_EINVAL  (-1)   /* bad argument: shape, rank, capacity, parameter out of range   */
+#define TT_ENOMEM  (-2)   /* the context arena is too small for this call                  */
+#define TT_EHIP    (-3)   /* a HIP runtime call failed (message in tt_last_error)          */
+#define TT_ENONFINITE (-4)/* NaN or Inf met in a factorisation                             */
+/* warning bits (positive) */
+#define TT_WRANKCAP  1    /* a rounding hit r_max with a tail above eps                      */
+#define TT_WNOCONV   2    /* the Taylor reciprocal stopped at max_terms with Err > eps       */
+
+typedef struct {
+  int n1, n2;      /* mode sizes (rows of g1, rows of g2)                                  */
+  int rank;        /* current rank: number of valid columns                                */
+  int cap;         /* column capacity of both buffers                                      */
+  double *g1;      /* device, n1 x cap, column-major, first core G1                        */
+  double *g2;      /* device, n2 x cap, column-major, second core transposed (G2^T)        */
+} tt_matrix;
+
+typedef struct tt_ctx tt_ctx;   /* stream + device arena + tuning knobs */
+typedef struct tt_fv tt_fv;     /* solver: parameters, state, context   */
+
+/* Create a context whose work runs on `hip_stream` (a hipStream_t, NULL = default stream)
+ * with a device arena of `arena_bytes` (allocated here, once). */
+int  tt_ctx_create(tt_ctx **out, size_t arena_bytes, void *hip_stream);
+void tt_ctx_destroy(tt_ctx *ctx);
+/* Rounding sketch width (0 = automatic: min(96, 2 r_max + 16)) and power iterations (>= 0). */
+int  tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters);
+
+/* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
+ * eps and rank <= r_max.  x may have any rank <= x->cap; y->cap must be >= r_max.
+ * Returns TT_WRANKCAP when the cap truncated more than eps.  The kept singular values
+ * are written to sigma_out (host, length >= r_max) when not NULL. */
+int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
+             double *sigma_out);
+
+/* Elementwise (Hadamard) product of two TTs on the same index space followed by rounding:
+ * y = round(x o z, eps, r_max).  The product has rank x.rank * z.rank (Section 4.2). */
+int tt_hadamard_round(tt_ctx *ctx, const tt_matrix *x, const tt_matrix *z, double eps,
+                      int r_max, tt_matrix *y);
+
+/* Taylor-series reciprocal, Algorithm 1 of the paper: y ~ 1/x.  max_terms counts the
+ * constant term (at most max_terms - 1 products); the loop also stops when
+ * Err = ||dy||_F / sqrt(n1 n2) <= eps.  err_out / terms_out (host) report the last Err and
+ * the number of terms.  Returns TT_WNOCONV when it stopped at max_terms with Err > eps. */
+int tt_reciprocal(tt_ctx *ctx, const tt_matrix *x, double eps, int max_terms, int r_max,
+                  tt_matrix *y, double *err_out, int *terms_out);
+
+/* Maximum-volume rows of a tall matrix (n x r, n >= r, r <= 96, device, column-major,
+ * leading dimension ldq), as in the maxvol algorithm of Goreinov et al. cited in
+ * Section 3.3: greedy start, then swaps until max |Q Q[I]^-1| <= tau or maxit swaps.
+ * rows_out: host array of r indices. */
+int tt_maxvol(tt_ctx *ctx, const double *q, int n, int r, int ldq, double tau, int maxit,
+              int *rows_out);
+
+/* Cross interpolation (Section 3.3): an alternating skeleton cross with maxvol pivots of
+ * the n1 x n2 matrix whose entries are fn(inputs) (fn is a TT_FN_* id below), started from
+ * the column set J0 (host, nJ0 >= 1 distinct indices < n2), `sweeps` sweeps, `kick` fresh
+ * column indices per non-final sweep from SplitMix64 keyed by `key`, final rounding at
+ * (eps, r_max).  J_out (host, capacity >= r_max + kick * sweeps) receives the column set
+ * of the last sweep, *nJ_out its size.  fparams: see TT_FN_*. */
+#define TT_FN_IDENTITY   0  /* inputs[0] = X; entry X(i,j)                                   */
+#define TT_FN_LLF_LAMBDA 1  /* inputs = h-, m-, h+, m+ (face/quadrature TTs); fparams[0] = g;
+                               entry max(|m-/h-| + sqrt(g h-), |m+/h+| + sqrt(g h+))         */
+#define TT_FN_WENO_FACE_M 2 /* inputs[0] = cell TT v (n x n); entry (f, j): WENO5 value at face
+                               f from the left (cell f-1); fparams = {periodic, sign, eps_w} */
+#define TT_FN_WENO_FACE_P 3 /* as above from the right (cell f), mirrored stencils           */
+#define TT_FN_WENO_QUAD  4  /* inputs[0] = face TT v (n_f x n); entry (f, j*3+m): WENO5 value
+                               at Gauss point m of cell j; fparams = {periodic, sign, eps_w} */
+int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const double *fparams,
+             int n1, int n2, const int *J0, int nJ0, double eps, int r_max, int sweeps,
+             int kick, uint64_t key, tt_matrix *y, int *J_out, int *nJ_out);
+
+/* Linear reconstruction of one core (Section 4.3.1).  core: n x rank cell values (device).
+ * scheme: 3 = Upwind3, 5 = Upwind5.  face_m / face_p (n_f x rank, n_f = n periodic or n + 1
+ * with walls) get the face values from the left / right; quad (n*nq x rank, row j*nq + m)
+ * gets the Gauss-point values.  Ghost cells: periodic wrap, or mirrored with `sign`. */
+int tt_recon_core(tt_ctx *ctx, const double *core, int n, int rank, int scheme, int periodic,
+                  double sign, double *face_m, double *face_p, double *quad);
+
+/* ---------------------------------------------------------------------------------------
+ * Solver: explicit SSP-RK3 of the TT finite-volume scheme (Sections 4.1-4.4).           */
+typedef struct {
+  int n;              /* cells per direction on [0, 1]^2 (dx = dy = 1/n)                  */
+  int nonlinear;      /* 0: (eta, u, v), Section 2.1 linear SWE; 1: (h, hu, hv) nonlinear  */
+  int scheme;         /* 3 Upwind3, 5 Upwind5, 55 WENO5                                    */
+  int periodic;       /* 1 periodic in x and y; 0 reflective walls                         */
+  double g, H0, f;    /* gravity, mean depth (linear), Coriolis parameter                  */
+  double eps;         /* rounding tolerance (relative Frobenius)                           */
+  int r_max;          /* rank cap of every rounding, <= 64                                 */
+  int taylor_terms;   /* Algorithm 1 terms including the constant (nonlinear)              */
+  int cross_sweeps;   /* maxvol cross sweeps                                               */
+  int cross_kick;     /* fresh columns per non-final sweep                                 */
+} tt_fv_params;
+
+typedef struct {
+  long long steps;            /* steps taken                                              */
+  int ranks[3];               /* current state ranks                                      */
+  long long roundings;        /* roundings performed                                      */
+  long long crosses;          /* crosses performed                                        */
+  int last_taylor_terms;      /* terms used by the last reciprocal                        */
+  double last_taylor_err;     /* its final Err                                            */
+  int warnings;               /* OR of TT_W* bits since init                              */
+  double flops;               /* algorithmic flop count since init                        */
+  double bytes;               /* algorithmic HBM bytes since init                         */
+} tt_fv_stats;
+
+/* Copy the three initial TTs (caller's device buffers) into solver-owned state and build
+ * the reconstruction tables.  Allocates its arena once here. */
+int  tt_fv_init(tt_fv **out, const tt_fv_params *p, const tt_matrix q0[3], void *hip_stream,
+                size_t arena_bytes);
+/* Advance nsteps SSP-RK3 steps of size dt. */
+int  tt_fv_step(tt_fv *s, double dt, int nsteps);
+/* Copy the state into caller buffers (cap >= rank). */
+int  tt_fv_get_state(tt_fv *s, tt_matrix q[3]);
+int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
+void tt_fv_destroy(tt_fv *s);
+
+const char *tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_FV_H */

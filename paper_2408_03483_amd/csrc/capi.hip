@@ -1,0 +1,327 @@
+// C ABI entry points (include/tt_fv.h): argument checks, context/arena management and the
+// translation of internal exceptions into return codes.
+#include "common.h"
+
+#include <cmath>
+
+namespace ttfv {
+
+Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream,
+                      size_t arena_bytes);
+void solver_step(Solver *s, double dt, int nsteps);
+void solver_get_state(Solver *s, tt_matrix q[3]);
+void solver_stats(Solver *s, tt_fv_stats *o);
+void solver_destroy(Solver *s);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+Arena::~Arena() {
+  if (base_) (void)hipFree(base_);
+}
+
+void Arena::init(size_t bytes) {
+  TT_REQUIRE(base_ == nullptr, "arena already initialised");
+  HIP_CHECK(hipMalloc(&base_, bytes));
+  cap_ = bytes;
+  top_ = hw_ = 0;
+}
+
+void *Arena::alloc(size_t bytes) {
+  const size_t a = (top_ + 255) & ~(size_t)255;
+  if (a + bytes > cap_)
+    throw Error(TT_ENOMEM, "arena exhausted: need " + std::to_string(a + bytes) + " of " +
+                               std::to_string(cap_) + " bytes");
+  top_ = a + bytes;
+  hw_ = std::max(hw_, top_);
+  return base_ + a;
+}
+
+DTT view(const tt_matrix *m) {
+  DTT t;
+  t.n1 = m->n1;
+  t.n2 = m->n2;
+  t.r = m->rank;
+  t.A = m->g1;
+  t.B = m->g2;
+  return t;
+}
+
+void check_matrix(const tt_matrix *m, const char *what, bool need_rank) {
+  if (!m) throw Error(TT_EINVAL, std::string(what) + ": null tt_matrix");
+  if (m->n1 < 1 || m->n2 < 1) throw Error(TT_EINVAL, std::string(what) + ": bad mode sizes");
+  if (!m->g1 || !m->g2) throw Error(TT_EINVAL, std::string(what) + ": null core pointer");
+  if (need_rank && (m->rank < 1 || m->rank > m->cap))
+    throw Error(TT_EINVAL, std::string(what) + ": rank out of [1, cap]");
+}
+
+}  // namespace ttfv
+
+struct tt_ctx {
+  ttfv::Ctx c;
+};
+
+struct tt_fv {
+  ttfv::Solver *s;
+};
+
+using namespace ttfv;
+
+template <typename F>
+static int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::exception &e) {
+    set_last_error(e.what());
+    return TT_EINVAL;
+  }
+}
+
+extern "C" {
+
+const char *tt_last_error(void) { return g_last_error.c_str(); }
+
+int tt_ctx_create(tt_ctx **out, size_t arena_bytes, void *hip_stream) {
+  return guarded([&]() {
+    TT_REQUIRE(out, "tt_ctx_create: null out");
+    TT_REQUIRE(arena_bytes >= ((size_t)1 << 20), "tt_ctx_create: arena below 1 MiB");
+    tt_ctx *c = new tt_ctx();
+    try {
+      c->c.stream = (hipStream_t)hip_stream;
+      c->c.arena.init(arena_bytes);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+    return 0;
+  });
+}
+
+void tt_ctx_destroy(tt_ctx *ctx) { delete ctx; }
+
+int tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    TT_REQUIRE(width >= 0 && width <= QR_MAXM, "sketch width out of [0, 96]");
+    TT_REQUIRE(power_iters >= 0 && power_iters <= 8, "power_iters out of [0, 8]");
+    ctx->c.sketch_width = width;
+    ctx->c.power_iters = power_iters;
+    return 0;
+  });
+}
+
+int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
+             double *sigma_out) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    check_matrix(x, "tt_round x", true);
+    check_matrix(y, "tt_round y", false);
+    TT_REQUIRE(eps >= 0.0 && r_max >= 1, "tt_round: eps < 0 or r_max < 1");
+    TT_REQUIRE(y->cap >= r_max, "tt_round: y->cap < r_max");
+    TT_REQUIRE(x->n1 == y->n1 && x->n2 == y->n2, "tt_round: shape mismatch");
+    DTT xv = view(x), yv = view(y);
+    std::vector<double> s;
+    const int w = round_tt(ctx->c, xv, eps, r_max, yv, &s);
+    y->rank = yv.r;
+    if (sigma_out)
+      for (size_t i = 0; i < s.size(); ++i) sigma_out[i] = s[i];
+    return w;
+  });
+}
+
+int tt_hadamard_round(tt_ctx *ctx, const tt_matrix *x, const tt_matrix *z, double eps, int r_max,
+                      tt_matrix *y) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    check_matrix(x, "tt_hadamard_round x", true);
+    check_matrix(z, "tt_hadamard_round z", true);
+    check_matrix(y, "tt_hadamard_round y", false);
+    TT_REQUIRE(x->n1 == z->n1 && x->n2 == z->n2 && x->n1 == y->n1 && x->n2 == y->n2,
+               "tt_hadamard_round: shape mismatch");
+    TT_REQUIRE(y->cap >= r_max && r_max >= 1 && eps >= 0.0, "tt_hadamard_round: bad cap/eps");
+    Ctx &c = ctx->c;
+    Scope sc(c.arena);
+    const int R = x->rank * z->rank;
+    DTT p{x->n1, x->n2, R, c.arena.dalloc((size_t)x->n1 * R), c.arena.dalloc((size_t)x->n2 * R)};
+    khatri_rao(c, p.A, x->n1, x->g1, x->rank, z->g1, z->rank);
+    khatri_rao(c, p.B, x->n2, x->g2, x->rank, z->g2, z->rank);
+    DTT yv = view(y);
+    const int w = round_tt(c, p, eps, r_max, yv, nullptr);
+    y->rank = yv.r;
+    return w;
+  });
+}
+
+int tt_reciprocal(tt_ctx *ctx, const tt_matrix *x, double eps, int max_terms, int r_max,
+                  tt_matrix *y, double *err_out, int *terms_out) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    check_matrix(x, "tt_reciprocal x", true);
+    check_matrix(y, "tt_reciprocal y", false);
+    TT_REQUIRE(x->n1 == y->n1 && x->n2 == y->n2, "tt_reciprocal: shape mismatch");
+    TT_REQUIRE(max_terms >= 1 && r_max >= 1 && eps >= 0.0 && y->cap >= r_max,
+               "tt_reciprocal: bad max_terms / r_max / eps / cap");
+    DTT xv = view(x), yv = view(y);
+    const int w = reciprocal_tt(ctx->c, xv, eps, max_terms, r_max, yv, err_out, terms_out);
+    y->rank = yv.r;
+    return w;
+  });
+}
+
+int tt_maxvol(tt_ctx *ctx, const double *q, int n, int r, int ldq, double tau, int maxit,
+              int *rows_out) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && q && rows_out, "tt_maxvol: null argument");
+    TT_REQUIRE(r >= 1 && r <= 96 && n >= r && ldq >= n, "tt_maxvol: bad shape");
+    TT_REQUIRE(tau >= 1.0 && maxit >= 0, "tt_maxvol: tau < 1 or maxit < 0");
+    std::vector<int> I = maxvol_host(ctx->c, q, n, r, ldq, tau, maxit);
+    for (int i = 0; i < r; ++i) rows_out[i] = I[i];
+    return 0;
+  });
+}
+
+int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const double *fparams,
+             int n1, int n2, const int *J0, int nJ0, double eps, int r_max, int sweeps, int kick,
+             uint64_t key, tt_matrix *y, int *J_out, int *nJ_out) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && inputs && J0 && y, "tt_cross: null argument");
+    check_matrix(y, "tt_cross y", false);
+    TT_REQUIRE(y->n1 == n1 && y->n2 == n2 && y->cap >= r_max, "tt_cross: bad output");
+    TT_REQUIRE(r_max >= 1 && r_max <= 64 && eps >= 0.0 && sweeps >= 1 && kick >= 0,
+               "tt_cross: bad r_max / eps / sweeps / kick");
+    TT_REQUIRE(nJ0 >= 1, "tt_cross: empty J0");
+    std::vector<int> J(J0, J0 + nJ0);
+    for (int j : J) TT_REQUIRE(j >= 0 && j < n2, "tt_cross: J0 index out of range");
+    Ctx &c = ctx->c;
+    Scope sc(c.arena);
+    static WenoTables wt = derive_weno_tables();
+    FiberSpec fs;
+    fs.fn = fn;
+    fs.wt = &wt;
+    switch (fn) {
+      case TT_FN_IDENTITY:
+        TT_REQUIRE(n_inputs == 1, "identity: one input");
+        check_matrix(&inputs[0], "input", true);
+        TT_REQUIRE(inputs[0].n1 == n1 && inputs[0].n2 == n2, "identity: input shape");
+        fs.n_in = 1;
+        fs.in[0] = {inputs[0].g1, inputs[0].g2, n1, n2, inputs[0].rank};
+        break;
+      case TT_FN_LLF_LAMBDA:
+        TT_REQUIRE(n_inputs == 4 && fparams, "lambda: four inputs and g");
+        for (int t = 0; t < 4; ++t) {
+          check_matrix(&inputs[t], "input", true);
+          TT_REQUIRE(inputs[t].n1 == n1 && inputs[t].n2 == n2, "lambda: input shape");
+          fs.in[t] = {inputs[t].g1, inputs[t].g2, n1, n2, inputs[t].rank};
+        }
+        fs.n_in = 4;
+        fs.g = fparams[0];
+        break;
+      case TT_FN_WENO_FACE_M:
+      case TT_FN_WENO_FACE_P: {
+        TT_REQUIRE(n_inputs == 1 && fparams, "weno face: one input and params");
+        const tt_matrix &v = inputs[0];
+        check_matrix(&v, "input", true);
+        const bool per = fparams[0] != 0.0;
+        TT_REQUIRE(v.n2 == n2 && n1 == (per ? v.n1 : v.n1 + 1) && v.n1 >= 3,
+                   "weno face: shapes (n_f x n from an n x n input)");
+        double *Ae = c.arena.dalloc((size_t)(v.n1 + 6) * v.rank);
+        ghost_extend(c, v.g1, v.n1, v.rank, per, fparams[1], Ae);
+        fs.n_in = 1;
+        fs.in[0] = {Ae, v.g2, v.n1 + 6, v.n2, v.rank};
+        fs.eps_w = fparams[2];
+        break;
+      }
+      case TT_FN_WENO_QUAD: {
+        TT_REQUIRE(n_inputs == 1 && fparams, "weno quad: one input and params");
+        const tt_matrix &v = inputs[0];
+        check_matrix(&v, "input", true);
+        TT_REQUIRE(v.n1 == n1 && n2 == 3 * v.n2 && v.n2 >= 3, "weno quad: shapes (n_f x 3n)");
+        double *Be = c.arena.dalloc((size_t)(v.n2 + 6) * v.rank);
+        ghost_extend(c, v.g2, v.n2, v.rank, fparams[0] != 0.0, fparams[1], Be);
+        fs.n_in = 1;
+        fs.in[0] = {v.g1, Be, v.n1, v.n2 + 6, v.rank};
+        fs.eps_w = fparams[2];
+        fs.nq = 3;
+        break;
+      }
+      default:
+        throw Error(TT_EINVAL, "tt_cross: unknown fn id");
+    }
+    DTT yv = view(y);
+    std::vector<int> Jo;
+    const int w = cross_tt(c, fs, n1, n2, J, eps, r_max, sweeps, kick, key, yv, &Jo);
+    y->rank = yv.r;
+    if (J_out)
+      for (size_t i = 0; i < Jo.size(); ++i) J_out[i] = Jo[i];
+    if (nJ_out) *nJ_out = (int)Jo.size();
+    return w;
+  });
+}
+
+int tt_recon_core(tt_ctx *ctx, const double *core, int n, int rank, int scheme, int periodic,
+                  double sign, double *face_m, double *face_p, double *quad) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && core, "tt_recon_core: null argument");
+    TT_REQUIRE(n >= 3 && rank >= 1, "tt_recon_core: n >= 3 and rank >= 1");
+    TT_REQUIRE(scheme == 3 || scheme == 5, "tt_recon_core: scheme must be 3 or 5");
+    StencilSet st = derive_stencils(scheme);
+    const int nf = periodic ? n : n + 1;
+    if (face_m && face_p)
+      recon_face(ctx->c, core, n, rank, periodic != 0, sign, st, face_m, face_p, nf);
+    if (quad) recon_quad(ctx->c, core, n, rank, periodic != 0, sign, st, quad);
+    ctx->c.sync();
+    return 0;
+  });
+}
+
+int tt_fv_init(tt_fv **out, const tt_fv_params *p, const tt_matrix q0[3], void *hip_stream,
+               size_t arena_bytes) {
+  return guarded([&]() {
+    TT_REQUIRE(out, "tt_fv_init: null out");
+    for (int v = 0; v < 3; ++v) check_matrix(&q0[v], "tt_fv_init q0", true);
+    Solver *s = solver_create(p, q0, hip_stream, arena_bytes);
+    *out = new tt_fv{s};
+    return 0;
+  });
+}
+
+int tt_fv_step(tt_fv *s, double dt, int nsteps) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null solver");
+    solver_step(s->s, dt, nsteps);
+    tt_fv_stats st{};
+    solver_stats(s->s, &st);
+    return st.warnings & (TT_WRANKCAP | TT_WNOCONV);
+  });
+}
+
+int tt_fv_get_state(tt_fv *s, tt_matrix q[3]) {
+  return guarded([&]() {
+    TT_REQUIRE(s && q, "null argument");
+    solver_get_state(s->s, q);
+    return 0;
+  });
+}
+
+int tt_fv_get_stats(tt_fv *s, tt_fv_stats *out) {
+  return guarded([&]() {
+    TT_REQUIRE(s && out, "null argument");
+    solver_stats(s->s, out);
+    return 0;
+  });
+}
+
+void tt_fv_destroy(tt_fv *s) {
+  if (!s) return;
+  solver_destroy(s->s);
+  delete s;
+}
+
+}  // extern "C"

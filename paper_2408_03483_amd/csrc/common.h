@@ -1,0 +1,189 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tt_fv.h"
+
+namespace ttfv {
+
+// ---------------------------------------------------------------------------------------
+// errors: internal code throws, the C ABI layer converts to return codes
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &m);
+
+#define HIP_CHECK(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      throw ::ttfv::Error(TT_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
+  } while (0)
+
+#define TT_REQUIRE(cond, msg)                                                             \
+  do {                                                                                    \
+    if (!(cond)) throw ::ttfv::Error(TT_EINVAL, msg);                                     \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------
+// device arena: one hipMalloc at creation, stack-like sub-allocation afterwards
+
+class Arena {
+ public:
+  Arena() = default;
+  ~Arena();
+  void init(size_t bytes);
+  void *alloc(size_t bytes);                 // 256-byte aligned
+  double *dalloc(size_t n) { return static_cast<double *>(alloc(n * sizeof(double))); }
+  int *ialloc(size_t n) { return static_cast<int *>(alloc(n * sizeof(int))); }
+  size_t mark() const { return top_; }
+  void release(size_t m) { top_ = m; }
+  size_t capacity() const { return cap_; }
+  size_t high_water() const { return hw_; }
+
+ private:
+  char *base_ = nullptr;
+  size_t cap_ = 0, top_ = 0, hw_ = 0;
+};
+
+struct Scope {  // releases everything allocated after construction
+  Arena &a;
+  size_t m;
+  explicit Scope(Arena &ar) : a(ar), m(ar.mark()) {}
+  ~Scope() { a.release(m); }
+};
+
+// ---------------------------------------------------------------------------------------
+// a device TT: X = A * B^T, A: n1 x r (ld n1), B: n2 x r (ld n2), column-major
+
+struct DTT {
+  int n1 = 0, n2 = 0, r = 0;
+  double *A = nullptr, *B = nullptr;
+};
+
+struct Counters {
+  long long roundings = 0, crosses = 0, extra_power_iters = 0;
+  double flops = 0, bytes = 0;
+  int warnings = 0;
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  Arena arena;
+  int sketch_width = 0;     // 0: automatic
+  int power_iters = 1;
+  double *host_pinned = nullptr;   // small pinned staging buffer for read-backs
+  size_t host_pinned_n = 0;
+  Counters cnt;
+  void sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
+};
+
+struct Solver;
+
+// ---------------------------------------------------------------------------------------
+// launchers (kernels.hip)
+
+void fill_gauss(Ctx &c, double *O, int rows, int cols, int ld, uint64_t seed);
+void copy_scale(Ctx &c, double *dst, int ldd, const double *src, int lds, int rows, int cols,
+                double alpha);
+void axpby(Ctx &c, double *dst, int ldd, const double *x, int ldx, double a, const double *y,
+           int ldy, double b, int rows, int cols);
+void fill_value(Ctx &c, double *dst, int ld, int rows, int cols, double v);
+void khatri_rao(Ctx &c, double *out, int n, const double *X, int rx, const double *Y, int ry);
+void colsum(Ctx &c, const double *A, int n, int r, int ld, double *out);
+void gather_rows(Ctx &c, double *dst, int ldd, const double *src, int lds, const int *rows_dev,
+                 int nrows, int cols);
+// dst (cols x rows) = src^T (src: rows x cols)
+void transpose(Ctx &c, double *dst, int ldd, const double *src, int lds, int rows, int cols);
+
+struct StencilSet {          // weights of the combined linear stencils, offsets -k..k
+  int k = 0, nq = 0;
+  double face[5] = {0};      // value at the right face (x0 = +1/2)
+  double quad[3][5] = {{0}}; // value at Gauss point m
+  double gw[3] = {0};        // Gauss-Legendre weights (sum 1)
+};
+void recon_face(Ctx &c, const double *A, int n, int r, bool periodic, double sign,
+                const StencilSet &st, double *Am, double *Ap, int nf);
+void recon_quad(Ctx &c, const double *B, int n, int r, bool periodic, double sign,
+                const StencilSet &st, double *Bq);
+void quad_sum(Ctx &c, const double *Bq, int n, int nq, int r, const StencilSet &st, double *Bo);
+void face_diff(Ctx &c, const double *A, int nf, int n, int r, bool periodic, double scale,
+               double *Ao, int ldo);
+void ghost_extend(Ctx &c, const double *A, int n, int r, bool periodic, double sign,
+                  double *E);
+
+// gemm.hip: C = alpha * op(A) * B + beta * C, op = identity or transpose
+void gemm(Ctx &c, bool transA, int M, int N, int K, double alpha, const double *A, int lda,
+          const double *B, int ldb, double beta, double *C, int ldc);
+void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, const double *A,
+           int lda, const double *B, int ldb, double beta, double *C, int ldc);
+
+// tsqr.hip: Q (n x m, ldq) and R (m x m, ldr) of Y (n x m, n >= m, m <= 96)
+constexpr int QR_MAXM = 96;
+int qr_max_cols();   // largest m the device's LDS allows (<= QR_MAXM)
+void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, double *R,
+          int ldr);
+
+// jacobi.hip
+// One-sided Jacobi on M (m x m, ld m, m <= 96): writes U*Sigma columns sorted by norm into
+// US (m x m) and the norms into sig (device, m).
+void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig);
+// inverse of a small square matrix (m <= 96) with partial pivoting
+void small_inverse(Ctx &c, const double *M, int m, int ldm, double *Minv);
+// normalise the first k columns of US by sig into U
+void normalise_cols(Ctx &c, const double *US, const double *sig, int m, int k, double *U);
+
+// cross.hip
+void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int maxit,
+                int *rows_dev);
+
+struct WenoTables {          // candidate stencils and weights for WENO5 (k = 2)
+  double face_C[3][3];       // Step 1 candidate r, cell j-r+l, at +1/2
+  double face_d[3];          // ideal weights
+  double quad_C[3][3][3];    // Step 2, Gauss point m
+  double quad_g[3][3];       // linear weights (m = 0, 2); m = 1: unused
+  double gp[3], gm[3];       // normalised split weights at m = 1
+  double sp, sm;             // sigma+-
+};
+struct FiberInput {
+  const double *A; const double *B; int lda, ldb, r;
+};
+struct FiberSpec {
+  int fn = 0;
+  int n_in = 0;
+  FiberInput in[4];
+  double g = 0, eps_w = 0;
+  int nq = 3;
+  const WenoTables *wt = nullptr;   // host table, copied into the kernel arguments
+};
+// entries fn(i, j) for i in [0,n1), j in J (|J| = nj) into out (n1 x nj, ld n1)
+void fiber_cols(Ctx &c, const FiberSpec &fs, int n1, const int *J_dev, int nj, double *out);
+// entries fn(i, j) for i in I, j in [0,n2) into outT (n2 x ni, ld n2): transposed rows
+void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, double *outT);
+
+// tt_ops.hip (host algorithms)
+int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
+void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out);
+int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, double *err,
+                  int *terms);
+std::vector<int> maxvol_host(Ctx &c, const double *Q, int n, int r, int ldq, double tau,
+                             int maxit);
+int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, double eps,
+             int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out);
+uint64_t splitmix64_next(uint64_t &state);
+std::vector<int> kick_indices(const std::vector<int> &have, int n, int count, uint64_t key);
+
+// stencil derivation (stencils.cpp part of fv.hip)
+StencilSet derive_stencils(int scheme);
+WenoTables derive_weno_tables();
+
+}  // namespace ttfv

@@ -1,0 +1,281 @@
+// Cross interpolation kernels (Section 3.3): maxvol row selection and fiber evaluation.
+//
+// maxvol (Goreinov et al., cited in Section 3.3) on an orthonormal basis Q (n x r):
+//   start: greedy rows -- repeatedly the row of largest residual norm, whose direction is
+//          then projected out of every row (a pivoted QR of Q^T); for an orthonormal basis
+//          this start does not depend on which basis of the column space is given;
+//   swaps: B = Q Q[I]^-1; while max |B_ij| > tau, row i replaces the j-th chosen row and B
+//          gets the rank-one correction B -= B(:,j) (B(i,:) - e_j) / B_ij.
+//   Ties in every argmax go to the smallest row, then the smallest column.
+// Fibers: the entries of the matrix being interpolated are pointwise functions of one or
+// more TTs, evaluated as rank-r dot products of core rows (with ghost-extended cores for
+// the shifted WENO stencils), so a column or row fiber never materialises a full field.
+#include "common.h"
+
+#include <algorithm>
+
+namespace ttfv {
+namespace {
+
+constexpr int NT = 1024;
+
+struct Best {
+  double v;
+  int i, j;
+};
+
+__device__ __forceinline__ bool better(const Best &a, const Best &b) {
+  if (a.v != b.v) return a.v > b.v;
+  if (a.i != b.i) return a.i < b.i;
+  return a.j < b.j;
+}
+
+__device__ Best block_best(Best b, Best *red) {
+  const int tid = threadIdx.x;
+  red[tid] = b;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s && better(red[tid + s], red[tid])) red[tid] = red[tid + s];
+    __syncthreads();
+  }
+  Best r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// greedy start: R (n x r, workspace copy of Q) is destroyed; rows -> rows_dev
+__global__ __launch_bounds__(NT) void k_greedy(double *__restrict__ R, int n, int r, int ldr,
+                                               int *__restrict__ rows_dev) {
+  __shared__ Best red[NT];
+  __shared__ double v[128];
+  for (int t = 0; t < r; ++t) {
+    Best b{-1.0, n, 0};
+    for (int i = threadIdx.x; i < n; i += NT) {
+      double s = 0.0;
+      for (int c = 0; c < r; ++c) {
+        const double x = R[i + (size_t)c * ldr];
+        s += x * x;
+      }
+      Best cand{s, i, 0};
+      if (better(cand, b)) b = cand;
+    }
+    Best w = block_best(b, red);
+    const int is = w.i;
+    const double inv = w.v > 0.0 ? 1.0 / sqrt(w.v) : 0.0;
+    for (int c = threadIdx.x; c < r; c += NT) v[c] = R[is + (size_t)c * ldr] * inv;
+    if (threadIdx.x == 0) rows_dev[t] = is;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) {
+      double d = 0.0;
+      for (int c = 0; c < r; ++c) d += R[i + (size_t)c * ldr] * v[c];
+      for (int c = 0; c < r; ++c) R[i + (size_t)c * ldr] -= d * v[c];
+    }
+    __syncthreads();
+  }
+}
+
+// swap iterations on B = Q Q[I]^-1 (n x r, ld n)
+__global__ __launch_bounds__(NT) void k_maxvol_swaps(double *__restrict__ B, int n, int r,
+                                                     double tau, int maxit,
+                                                     int *__restrict__ rows_dev) {
+  __shared__ Best red[NT];
+  __shared__ double bi[128];
+  for (int it = 0; it < maxit; ++it) {
+    Best b{-1.0, n, r};
+    for (int i = threadIdx.x; i < n; i += NT)
+      for (int c = 0; c < r; ++c) {
+        Best cand{fabs(B[i + (size_t)c * n]), i, c};
+        if (better(cand, b)) b = cand;
+      }
+    Best w = block_best(b, red);
+    if (w.v <= tau) break;
+    const int is = w.i, js = w.j;
+    const double piv = B[is + (size_t)js * n];
+    for (int c = threadIdx.x; c < r; c += NT)
+      bi[c] = (B[is + (size_t)c * n] - (c == js ? 1.0 : 0.0)) / piv;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) {
+      const double bj = B[i + (size_t)js * n];
+      for (int c = 0; c < r; ++c) B[i + (size_t)c * n] -= bj * bi[c];
+    }
+    if (threadIdx.x == 0) rows_dev[js] = is;
+    __syncthreads();
+  }
+}
+
+// --- pointwise functions -----------------------------------------------------------------
+
+struct WenoArgs {
+  WenoTables t;
+  double eps;
+};
+
+__device__ __forceinline__ void smoothness(const double *v, double *beta) {
+  // v[0..4] = cells c-2 .. c+2
+  const double a = v[2] - 2 * v[3] + v[4], b = 3 * v[2] - 4 * v[3] + v[4];
+  const double c = v[1] - 2 * v[2] + v[3], d = v[1] - v[3];
+  const double e = v[0] - 2 * v[1] + v[2], f = v[0] - 4 * v[1] + 3 * v[2];
+  beta[0] = 13.0 / 12.0 * a * a + 0.25 * b * b;
+  beta[1] = 13.0 / 12.0 * c * c + 0.25 * d * d;
+  beta[2] = 13.0 / 12.0 * e * e + 0.25 * f * f;
+}
+
+__device__ __forceinline__ double weno_combine(const double (*C)[3], const double *gam,
+                                               const double *beta, const double *v, double eps) {
+  double cand[3], al[3], s = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    double acc = 0.0;
+    for (int l = 0; l < 3; ++l) acc += C[r][l] * v[2 - r + l];
+    cand[r] = acc;
+    const double be = beta[r] + eps;
+    al[r] = gam[r] / (be * be);
+    s += al[r];
+  }
+  return (al[0] * cand[0] + al[1] * cand[1] + al[2] * cand[2]) / s;
+}
+
+__device__ double weno_face(const WenoArgs &w, const double *v) {
+  double beta[3];
+  smoothness(v, beta);
+  return weno_combine(w.t.face_C, w.t.face_d, beta, v, w.eps);
+}
+
+__device__ double weno_quad(const WenoArgs &w, const double *v, int m) {
+  double beta[3];
+  smoothness(v, beta);
+  if (m == 1) {
+    const double up = weno_combine(w.t.quad_C[1], w.t.gp, beta, v, w.eps);
+    const double um = weno_combine(w.t.quad_C[1], w.t.gm, beta, v, w.eps);
+    return w.t.sp * up - w.t.sm * um;
+  }
+  return weno_combine(w.t.quad_C[m], w.t.quad_g[m], beta, v, w.eps);
+}
+
+__device__ __forceinline__ double dotrow(const double *A, int lda, int ia, const double *B,
+                                         int ldb, int ib, int r) {
+  double s = 0.0;
+  for (int a = 0; a < r; ++a) s += A[ia + (size_t)a * lda] * B[ib + (size_t)a * ldb];
+  return s;
+}
+
+struct FibArgs {
+  int fn, n_in;
+  FiberInput in[4];
+  double g;
+  int nq;
+};
+
+__device__ double fiber_entry(const FibArgs &f, const WenoArgs &w, int i, int j) {
+  switch (f.fn) {
+    case TT_FN_IDENTITY:
+      return dotrow(f.in[0].A, f.in[0].lda, i, f.in[0].B, f.in[0].ldb, j, f.in[0].r);
+    case TT_FN_LLF_LAMBDA: {
+      double x[4];
+      for (int t = 0; t < 4; ++t)
+        x[t] = dotrow(f.in[t].A, f.in[t].lda, i, f.in[t].B, f.in[t].ldb, j, f.in[t].r);
+      const double lm = fabs(x[1] / x[0]) + sqrt(f.g * x[0]);
+      const double lp = fabs(x[3] / x[2]) + sqrt(f.g * x[2]);
+      return fmax(lm, lp);
+    }
+    case TT_FN_WENO_FACE_M:
+    case TT_FN_WENO_FACE_P: {
+      // first core ghost-extended by 3 rows: cell q is row q + 3
+      double v[5];
+      for (int o = -2; o <= 2; ++o) {
+        const int cell = (f.fn == TT_FN_WENO_FACE_M) ? (i - 1 + o) : (i - o);
+        v[o + 2] = dotrow(f.in[0].A, f.in[0].lda, cell + 3, f.in[0].B, f.in[0].ldb, j, f.in[0].r);
+      }
+      return weno_face(w, v);
+    }
+    case TT_FN_WENO_QUAD: {
+      // second core ghost-extended by 3 rows; column j = cell * nq + point
+      const int cell = j / f.nq, m = j - cell * f.nq;
+      double v[5];
+      for (int o = -2; o <= 2; ++o)
+        v[o + 2] = dotrow(f.in[0].A, f.in[0].lda, i, f.in[0].B, f.in[0].ldb, cell + o + 3,
+                          f.in[0].r);
+      return weno_quad(w, v, m);
+    }
+  }
+  return 0.0;
+}
+
+__global__ void k_fiber_cols(FibArgs f, WenoArgs w, int n1, const int *__restrict__ J, int nj,
+                             double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (i >= n1 || t >= nj) return;
+  out[i + (size_t)t * n1] = fiber_entry(f, w, i, J[t]);
+}
+
+__global__ void k_fiber_rows(FibArgs f, WenoArgs w, int n2, const int *__restrict__ I, int ni,
+                             double *__restrict__ outT) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (j >= n2 || t >= ni) return;
+  outT[j + (size_t)t * n2] = fiber_entry(f, w, I[t], j);
+}
+
+FibArgs make_args(const FiberSpec &fs) {
+  FibArgs a{};
+  a.fn = fs.fn;
+  a.n_in = fs.n_in;
+  for (int t = 0; t < 4; ++t) a.in[t] = fs.in[t];
+  a.g = fs.g;
+  a.nq = fs.nq;
+  return a;
+}
+
+WenoArgs make_weno(const FiberSpec &fs) {
+  WenoArgs w{};
+  if (fs.wt) w.t = *fs.wt;
+  w.eps = fs.eps_w;
+  return w;
+}
+
+double fiber_cost(const FiberSpec &fs) {
+  double r = 0;
+  for (int t = 0; t < fs.n_in; ++t) r += fs.in[t].r;
+  if (fs.fn == TT_FN_WENO_FACE_M || fs.fn == TT_FN_WENO_FACE_P || fs.fn == TT_FN_WENO_QUAD)
+    return 2.0 * 5 * r + 70.0;
+  return 2.0 * r + 10.0;
+}
+
+}  // namespace
+
+void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int maxit,
+                int *rows_dev) {
+  TT_REQUIRE(r >= 1 && r <= 96 && n >= r, "maxvol: need n >= r, 1 <= r <= 96");
+  Scope sc(c.arena);
+  double *R = c.arena.dalloc((size_t)n * r);
+  copy_scale(c, R, n, Q, ldq, n, r, 1.0);
+  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(NT), 0, c.stream, R, n, r, n, rows_dev);
+  // B = Q Q[I]^-1
+  double *QI = c.arena.dalloc((size_t)r * r);
+  double *QIinv = c.arena.dalloc((size_t)r * r);
+  double *B = c.arena.dalloc((size_t)n * r);
+  gather_rows(c, QI, r, Q, ldq, rows_dev, r, r);
+  small_inverse(c, QI, r, r, QIinv);
+  gemm(c, false, n, r, r, 1.0, Q, ldq, QIinv, r, 0.0, B, n);
+  hipLaunchKernelGGL(k_maxvol_swaps, dim3(1), dim3(NT), 0, c.stream, B, n, r, tau, maxit,
+                     rows_dev);
+  c.cnt.flops += 3.0 * n * r * r;
+}
+
+void fiber_cols(Ctx &c, const FiberSpec &fs, int n1, const int *J_dev, int nj, double *out) {
+  if (nj <= 0) return;
+  hipLaunchKernelGGL(k_fiber_cols, dim3((n1 + 255) / 256, nj), dim3(256), 0, c.stream,
+                     make_args(fs), make_weno(fs), n1, J_dev, nj, out);
+  c.cnt.flops += fiber_cost(fs) * n1 * nj;
+  c.cnt.bytes += 8.0 * n1 * nj;
+}
+
+void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, double *outT) {
+  if (ni <= 0) return;
+  hipLaunchKernelGGL(k_fiber_rows, dim3((n2 + 255) / 256, ni), dim3(256), 0, c.stream,
+                     make_args(fs), make_weno(fs), n2, I_dev, ni, outT);
+  c.cnt.flops += fiber_cost(fs) * n2 * ni;
+  c.cnt.bytes += 8.0 * n2 * ni;
+}
+
+}  // namespace ttfv

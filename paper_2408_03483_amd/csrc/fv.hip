@@ -1,0 +1,477 @@
+// The TT finite-volume step (Section 4) on the GPU.
+//
+// One right-hand side L(Q) (Sections 4.1-4.3), for the x direction; the y direction is
+// the same sequence on the transposed TTs with the momenta swapped, so the normal
+// momentum is always the second variable:
+//   reconstruction  Upwind: face stencils on the first core, Gauss-point stencils on the
+//                   second core, minus/plus states share the second core (Section 4.3.1).
+//                   WENO5: Algorithm 2 (two crosses over the five x-shifted copies) and
+//                   Algorithm 3 (two crosses over five y-shifts, all Gauss points at once on
+//                   the merged column index j*nq + m) (Section 4.3.2).
+//   flux            linear: LLF assembled directly, never rounded (Section 4.2).
+//                   nonlinear, per side: 1/h by Algorithm 1, u = round(hu o 1/h),
+//                   w = round(hv o 1/h), P1 = round(hu o u), P2 = round(h o h),
+//                   F2 = round(P1 + g/2 P2), F3 = round(hu o w); lambda by one cross of
+//                   max(|hu-/h-| + sqrt(g h-), |hu+/h+| + sqrt(g h+));
+//                   D_c = round(lambda o (q_c+ - q_c-)), Fhat_c = round((F- + F+)/2 - D_c/2).
+//   finish          Gauss-Legendre sum on the second core, (T - 1) on the first (Section 4.1).
+// SSP-RK3 (Section 4.4): Q1 = F(Qn), Q2 = round(3/4 Qn + 1/4 F(Q1)),
+// Qn+1 = round(1/3 Qn + 2/3 F(Q2)), F(q) = round(q + dt L(q)).
+//
+// Every TT of the step lives in the solver's arena; ranks are known on the host after each
+// rounding (one stream synchronisation per rounding), so every launch has its exact shape.
+#include "common.h"
+#include "pool.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+
+namespace ttfv {
+
+namespace {
+const double SIGN_NORMAL[3] = {1.0, -1.0, 1.0};
+const double SIGN_TANGENT[3] = {1.0, 1.0, -1.0};
+}  // namespace
+
+struct Solver {
+  tt_fv_params p{};
+  Ctx c;                       // caller's stream; owns the state and phase outputs
+  std::unique_ptr<Pool> pool;  // worker streams for independent chains
+  StencilSet st;
+  WenoTables wt{};
+  int n = 0, nf = 0, nq = 0;
+  bool periodic = true;
+  DTT Q[3];
+  std::map<int, std::vector<int>> piv;
+  std::mutex mu;               // guards piv and the Taylor statistics
+  long long step_index = 0;
+  int last_terms = 0;
+  double last_err = 0.0;
+  int *rep_idx = nullptr;      // row j*nq + m -> j
+
+  static DTT alloc(Ctx &w, int n1, int n2, int cap) {
+    DTT t;
+    t.n1 = n1;
+    t.n2 = n2;
+    t.r = 0;
+    t.A = w.arena.dalloc((size_t)n1 * std::max(cap, 1));
+    t.B = w.arena.dalloc((size_t)n2 * std::max(cap, 1));
+    return t;
+  }
+
+  DTT rnd(Ctx &w, const DTT &x) {
+    DTT y = alloc(w, x.n1, x.n2, p.r_max);
+    round_tt(w, x, p.eps, p.r_max, y, nullptr);
+    return y;
+  }
+
+  static DTT transposed(const DTT &x) {
+    DTT t;
+    t.n1 = x.n2;
+    t.n2 = x.n1;
+    t.r = x.r;
+    t.A = x.B;
+    t.B = x.A;
+    return t;
+  }
+
+  // sum of coefficient * TT; terms whose second cores are the same buffer add their first cores
+  static DTT add(Ctx &w, const std::vector<std::pair<double, DTT>> &terms) {
+    struct G {
+      std::vector<std::pair<double, const DTT *>> parts;
+      const double *B;
+      int r;
+    };
+    std::vector<G> groups;
+    for (auto &t : terms) {
+      bool found = false;
+      for (auto &g : groups)
+        if (g.B == t.second.B && g.r == t.second.r) {
+          g.parts.push_back({t.first, &t.second});
+          found = true;
+          break;
+        }
+      if (!found) groups.push_back({{{t.first, &t.second}}, t.second.B, t.second.r});
+    }
+    int R = 0;
+    for (auto &g : groups) R += g.r;
+    const int n1 = terms[0].second.n1, n2 = terms[0].second.n2;
+    DTT out = alloc(w, n1, n2, R);
+    out.r = R;
+    int off = 0;
+    for (auto &g : groups) {
+      double *dA = out.A + (size_t)n1 * off;
+      copy_scale(w, dA, n1, g.parts[0].second->A, n1, n1, g.r, g.parts[0].first);
+      for (size_t k = 1; k < g.parts.size(); ++k)
+        axpby(w, dA, n1, dA, n1, 1.0, g.parts[k].second->A, n1, g.parts[k].first, n1, g.r);
+      copy_scale(w, out.B + (size_t)n2 * off, n2, g.B, n2, n2, g.r, 1.0);
+      off += g.r;
+    }
+    return out;
+  }
+
+  static DTT had(Ctx &w, const DTT &x, const DTT &y) {
+    const int R = x.r * y.r;
+    DTT out = alloc(w, x.n1, x.n2, R);
+    out.r = R;
+    khatri_rao(w, out.A, x.n1, x.A, x.r, y.A, y.r);
+    khatri_rao(w, out.B, x.n2, x.B, x.r, y.B, y.r);
+    return out;
+  }
+
+  static double norm2(Ctx &w, const DTT &x) {
+    Scope sc(w.arena);
+    double *ga = w.arena.dalloc((size_t)x.r * x.r), *gb = w.arena.dalloc((size_t)x.r * x.r);
+    gemm(w, true, x.r, x.r, x.n1, 1.0, x.A, x.n1, x.A, x.n1, 0.0, ga, x.r);
+    gemm(w, true, x.r, x.r, x.n2, 1.0, x.B, x.n2, x.B, x.n2, 0.0, gb, x.r);
+    std::vector<double> ha((size_t)x.r * x.r), hb((size_t)x.r * x.r);
+    HIP_CHECK(hipMemcpyAsync(ha.data(), ga, ha.size() * 8, hipMemcpyDeviceToHost, w.stream));
+    HIP_CHECK(hipMemcpyAsync(hb.data(), gb, hb.size() * 8, hipMemcpyDeviceToHost, w.stream));
+    w.sync();
+    double s = 0.0;
+    for (size_t i = 0; i < ha.size(); ++i) s += ha[i] * hb[i];
+    return std::max(s, 0.0);
+  }
+
+  static std::vector<int> initial_columns(Ctx &w, const DTT &y0) {
+    Scope sc(w.arena);
+    const int m = std::min(y0.r, y0.n2);
+    double *Qb = w.arena.dalloc((size_t)y0.n2 * std::max(m, 1));
+    int k = 0;
+    orth(w, y0.B, y0.n2, y0.r, y0.n2, 1e-13, Qb, &k);
+    if (k == 0) return {0};
+    return maxvol_host(w, Qb, y0.n2, k, y0.n2, 1.05, 100);
+  }
+
+  // cross into the preallocated `out` (capacity r_max)
+  void cross(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y0, int site, DTT &out) {
+    std::vector<int> J0;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = piv.find(site);
+      if (it != piv.end()) J0 = it->second;
+    }
+    if (J0.empty()) J0 = initial_columns(w, y0);
+    const uint64_t key = ((uint64_t)site << 32) | (uint64_t)(step_index & 0xFFFFFFFFll);
+    std::vector<int> J;
+    cross_tt(w, fs, n1, n2, J0, p.eps, p.r_max, p.cross_sweeps, p.cross_kick, key, out, &J);
+    std::lock_guard<std::mutex> lk(mu);
+    piv[site] = J;
+  }
+
+  // ---- reconstruction -------------------------------------------------------------
+  void states_upwind(Ctx &w, const DTT *Qv, DTT *qm, DTT *qp) {
+    for (int v = 0; v < 3; ++v) {
+      const DTT &q = Qv[v];
+      DTT m = alloc(w, nf, n * nq, q.r);
+      DTT pl = m;
+      pl.A = w.arena.dalloc((size_t)nf * q.r);
+      m.r = pl.r = q.r;
+      recon_face(w, q.A, n, q.r, periodic, SIGN_NORMAL[v], st, m.A, pl.A, nf);
+      recon_quad(w, q.B, n, q.r, periodic, SIGN_TANGENT[v], st, m.B);   // shared second core
+      qm[v] = m;
+      qp[v] = pl;
+    }
+  }
+
+  // Algorithms 2 and 3 for one variable and one side, into `out` (n_f x n*nq, cap r_max)
+  void weno_state(Ctx &w, const DTT &q, int v, int side, int site_base, DTT &out) {
+    const double eps_w = (1.0 / n) * (1.0 / n);
+    const int site = site_base + 16 + v * 4 + side;
+    double *Ae = w.arena.dalloc((size_t)(n + 6) * q.r);
+    ghost_extend(w, q.A, n, q.r, periodic, SIGN_NORMAL[v], Ae);
+    FiberSpec f1;
+    f1.fn = side == 0 ? TT_FN_WENO_FACE_M : TT_FN_WENO_FACE_P;
+    f1.n_in = 1;
+    f1.in[0] = {Ae, q.B, n + 6, n, q.r};
+    f1.eps_w = eps_w;
+    f1.wt = &wt;
+    DTT vt = alloc(w, nf, n, p.r_max);
+    cross(w, f1, nf, n, q, site, vt);
+    DTT y0 = alloc(w, nf, n * nq, vt.r);
+    y0.r = vt.r;
+    copy_scale(w, y0.A, nf, vt.A, nf, nf, vt.r, 1.0);
+    gather_rows(w, y0.B, n * nq, vt.B, n, rep_idx, n * nq, vt.r);
+    double *Be = w.arena.dalloc((size_t)(n + 6) * vt.r);
+    ghost_extend(w, vt.B, n, vt.r, periodic, SIGN_TANGENT[v], Be);
+    FiberSpec f2;
+    f2.fn = TT_FN_WENO_QUAD;
+    f2.n_in = 1;
+    f2.in[0] = {vt.A, Be, nf, n + 6, vt.r};
+    f2.eps_w = eps_w;
+    f2.nq = nq;
+    f2.wt = &wt;
+    cross(w, f2, nf, n * nq, y0, site + 2, out);
+  }
+
+  // ---- nonlinear flux pieces ----------------------------------------------------------
+  // one side: 1/h (Algorithm 1), u, w, P1, P2 -> F2 = round(P1 + g/2 P2), F3 = round(m o w)
+  void side_fluxes(Ctx &w, const DTT &h, const DTT &m, const DTT &t, DTT &F2, DTT &F3) {
+    DTT rh = alloc(w, h.n1, h.n2, p.r_max);
+    double err = 0;
+    int terms = 0;
+    reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      last_err = err;
+      last_terms = terms;
+    }
+    DTT u = rnd(w, had(w, m, rh));
+    DTT wv = rnd(w, had(w, t, rh));
+    DTT P1 = rnd(w, had(w, m, u));
+    DTT P2 = rnd(w, had(w, h, h));
+    round_tt(w, add(w, {{1.0, P1}, {0.5 * p.g, P2}}), p.eps, p.r_max, F2, nullptr);
+    round_tt(w, had(w, m, wv), p.eps, p.r_max, F3, nullptr);
+  }
+
+  DTT finish(Ctx &w, const DTT &Fh, DTT &o) {
+    o.r = Fh.r;
+    face_diff(w, Fh.A, nf, n, Fh.r, periodic, 1.0, o.A, n);
+    quad_sum(w, Fh.B, n, nq, Fh.r, st, o.B);
+    return o;
+  }
+
+  // dF[d][v] (n x n, cap r_max): flux differences of both directions, d = 0 x, d = 1 y
+  // (the y result is in transposed orientation)
+  void fluxes(const DTT (*QD)[3], int stage, DTT (*dF)[3]) {
+    const int sb[2] = {(0 * 3 + stage) << 6, (1 * 3 + stage) << 6};
+    DTT qm[2][3], qp[2][3];
+    if (p.scheme != 55) {
+      for (int d = 0; d < 2; ++d) states_upwind(c, QD[d], qm[d], qp[d]);
+      c.sync();
+    } else {
+      for (int d = 0; d < 2; ++d)
+        for (int v = 0; v < 3; ++v) {
+          qm[d][v] = alloc(c, nf, n * nq, p.r_max);
+          qp[d][v] = alloc(c, nf, n * nq, p.r_max);
+        }
+      c.sync();
+      std::vector<Pool::Task> tasks;
+      for (int d = 0; d < 2; ++d)
+        for (int v = 0; v < 3; ++v)
+          for (int side = 0; side < 2; ++side)
+            tasks.push_back([this, &QD, &qm, &qp, &sb, d, v, side](Ctx &w) {
+              weno_state(w, QD[d][v], v, side, sb[d], side == 0 ? qm[d][v] : qp[d][v]);
+            });
+      pool->run(std::move(tasks));
+    }
+    if (!p.nonlinear) {
+      const double g = p.g, H = p.H0, cw = std::sqrt(g * H);
+      for (int d = 0; d < 2; ++d) {
+        DTT Fh[3];
+        Fh[0] = add(c, {{0.5 * H, qm[d][1]}, {0.5 * H, qp[d][1]}, {-0.5 * cw, qp[d][0]},
+                        {0.5 * cw, qm[d][0]}});
+        Fh[1] = add(c, {{0.5 * g, qm[d][0]}, {0.5 * g, qp[d][0]}, {-0.5 * cw, qp[d][1]},
+                        {0.5 * cw, qm[d][1]}});
+        Fh[2] = add(c, {{-0.5 * cw, qp[d][2]}, {0.5 * cw, qm[d][2]}});
+        for (int v = 0; v < 3; ++v) {
+          dF[d][v] = alloc(c, n, n, Fh[v].r);
+          finish(c, Fh[v], dF[d][v]);
+        }
+      }
+      return;
+    }
+    // phase A: per direction and side, the reciprocal and the flux products
+    DTT F[2][2][3];
+    for (int d = 0; d < 2; ++d)
+      for (int s = 0; s < 2; ++s) {
+        F[d][s][0] = s == 0 ? qm[d][1] : qp[d][1];
+        F[d][s][1] = alloc(c, nf, n * nq, p.r_max);
+        F[d][s][2] = alloc(c, nf, n * nq, p.r_max);
+      }
+    DTT lam[2];
+    for (int d = 0; d < 2; ++d) lam[d] = alloc(c, nf, n * nq, p.r_max);
+    c.sync();
+    {
+      std::vector<Pool::Task> tasks;
+      for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < 2; ++s)
+          tasks.push_back([this, &qm, &qp, &F, d, s](Ctx &w) {
+            const DTT *q = s == 0 ? qm[d] : qp[d];
+            side_fluxes(w, q[0], q[1], q[2], F[d][s][1], F[d][s][2]);
+          });
+      // phase A also carries the two lambda crosses (independent of the products)
+      for (int d = 0; d < 2; ++d)
+        tasks.push_back([this, &qm, &qp, &lam, &sb, d](Ctx &w) {
+          const DTT &y0 = norm2(w, qm[d][1]) > 0.0 ? qm[d][1] : qm[d][0];
+          FiberSpec fl;
+          fl.fn = TT_FN_LLF_LAMBDA;
+          fl.n_in = 4;
+          const DTT *in[4] = {&qm[d][0], &qm[d][1], &qp[d][0], &qp[d][1]};
+          for (int k = 0; k < 4; ++k) fl.in[k] = {in[k]->A, in[k]->B, in[k]->n1, in[k]->n2, in[k]->r};
+          fl.g = p.g;
+          cross(w, fl, nf, n * nq, y0, sb[d], lam[d]);
+        });
+      pool->run(std::move(tasks));
+    }
+    // phase B: dissipation, LLF flux and finish, per direction and variable
+    for (int d = 0; d < 2; ++d)
+      for (int v = 0; v < 3; ++v) dF[d][v] = alloc(c, n, n, p.r_max);
+    {
+      std::vector<Pool::Task> tasks;
+      for (int d = 0; d < 2; ++d)
+        for (int v = 0; v < 3; ++v)
+          tasks.push_back([this, &qm, &qp, &F, &lam, &dF, d, v](Ctx &w) {
+            DTT dq = add(w, {{1.0, qp[d][v]}, {-1.0, qm[d][v]}});
+            DTT D = rnd(w, had(w, lam[d], dq));
+            DTT Fh = rnd(w, add(w, {{0.5, F[d][0][v]}, {0.5, F[d][1][v]}, {-0.5, D}}));
+            finish(w, Fh, dF[d][v]);
+          });
+      pool->run(std::move(tasks));
+    }
+  }
+
+  // out[v] = round(Q[v] + dt L(Q)[v]); out buffers allocated by the caller (cap r_max)
+  void euler(const DTT *Qv, double dt, int stage, DTT *out) {
+    Scope sc(c.arena);
+    DTT QD[2][3] = {{Qv[0], Qv[1], Qv[2]},
+                    {transposed(Qv[0]), transposed(Qv[2]), transposed(Qv[1])}};
+    DTT dF[2][3];
+    fluxes(QD, stage, dF);
+    DTT G[3] = {transposed(dF[1][0]), transposed(dF[1][2]), transposed(dF[1][1])};
+    const double dx = 1.0 / n;
+    std::vector<Pool::Task> tasks;
+    for (int v = 0; v < 3; ++v)
+      tasks.push_back([this, Qv, &dF, &G, dt, dx, out, v](Ctx &w) {
+        std::vector<std::pair<double, DTT>> terms{{1.0, Qv[v]}, {-dt / dx, dF[0][v]},
+                                                  {-dt / dx, G[v]}};
+        if (p.f != 0.0 && v == 1) terms.push_back({dt * p.f, Qv[2]});
+        if (p.f != 0.0 && v == 2) terms.push_back({-dt * p.f, Qv[1]});
+        round_tt(w, add(w, terms), p.eps, p.r_max, out[v], nullptr);
+      });
+    c.sync();
+    pool->run(std::move(tasks));
+  }
+
+  void combine(const DTT *A, double a, const DTT *B, double b, DTT *out) {
+    std::vector<Pool::Task> tasks;
+    for (int v = 0; v < 3; ++v)
+      tasks.push_back([this, A, B, a, b, out, v](Ctx &w) {
+        round_tt(w, add(w, {{a, A[v]}, {b, B[v]}}), p.eps, p.r_max, out[v], nullptr);
+      });
+    c.sync();
+    pool->run(std::move(tasks));
+  }
+
+  void step(double dt) {
+    Scope sc(c.arena);
+    DTT Q1[3], F1[3], Q2[3], F2[3], Qn[3];
+    for (int v = 0; v < 3; ++v) {
+      Q1[v] = alloc(c, n, n, p.r_max);
+      F1[v] = alloc(c, n, n, p.r_max);
+      Q2[v] = alloc(c, n, n, p.r_max);
+      F2[v] = alloc(c, n, n, p.r_max);
+      Qn[v] = alloc(c, n, n, p.r_max);
+    }
+    euler(Q, dt, 0, Q1);
+    euler(Q1, dt, 1, F1);
+    combine(Q, 0.75, F1, 0.25, Q2);
+    euler(Q2, dt, 2, F2);
+    combine(Q, 1.0 / 3.0, F2, 2.0 / 3.0, Qn);
+    for (int v = 0; v < 3; ++v) {
+      copy_scale(c, Q[v].A, n, Qn[v].A, n, n, Qn[v].r, 1.0);
+      copy_scale(c, Q[v].B, n, Qn[v].B, n, n, Qn[v].r, 1.0);
+      Q[v].r = Qn[v].r;
+    }
+    c.sync();
+    ++step_index;
+  }
+};
+
+Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream,
+                      size_t arena_bytes) {
+  TT_REQUIRE(p && q0, "tt_fv_init: null argument");
+  TT_REQUIRE(p->n >= 6, "tt_fv_init: n must be >= 6");
+  TT_REQUIRE(p->scheme == 3 || p->scheme == 5 || p->scheme == 55, "tt_fv_init: bad scheme");
+  TT_REQUIRE(p->r_max >= 1 && p->r_max <= 64, "tt_fv_init: r_max must be in [1, 64]");
+  TT_REQUIRE(p->eps >= 0.0, "tt_fv_init: eps < 0");
+  TT_REQUIRE(!p->nonlinear || p->taylor_terms >= 1, "tt_fv_init: taylor_terms < 1");
+  TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
+             "tt_fv_init: bad cross parameters");
+  for (int v = 0; v < 3; ++v) {
+    TT_REQUIRE(q0[v].n1 == p->n && q0[v].n2 == p->n, "tt_fv_init: state shape != n x n");
+    TT_REQUIRE(q0[v].rank >= 1 && q0[v].rank <= p->r_max, "tt_fv_init: state rank out of range");
+    TT_REQUIRE(q0[v].g1 && q0[v].g2, "tt_fv_init: null core");
+  }
+  Solver *s = new Solver();
+  try {
+    s->p = *p;
+    s->c.stream = (hipStream_t)stream;
+    const size_t ab = arena_bytes ? arena_bytes : ((size_t)4 << 30);
+    s->c.arena.init(ab);
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    s->pool = std::make_unique<Pool>(4, ab, dev);
+    s->st = derive_stencils(p->scheme == 3 ? 3 : 5);
+    s->wt = derive_weno_tables();
+    s->n = p->n;
+    s->nq = s->st.nq;
+    s->periodic = p->periodic != 0;
+    s->nf = s->periodic ? p->n : p->n + 1;
+    for (int v = 0; v < 3; ++v) {
+      s->Q[v] = Solver::alloc(s->c, p->n, p->n, p->r_max);
+      s->Q[v].r = q0[v].rank;
+      HIP_CHECK(hipMemcpyAsync(s->Q[v].A, q0[v].g1, (size_t)p->n * q0[v].rank * 8,
+                               hipMemcpyDeviceToDevice, s->c.stream));
+      HIP_CHECK(hipMemcpyAsync(s->Q[v].B, q0[v].g2, (size_t)p->n * q0[v].rank * 8,
+                               hipMemcpyDeviceToDevice, s->c.stream));
+    }
+    std::vector<int> rep((size_t)p->n * s->nq);
+    for (int j = 0; j < p->n; ++j)
+      for (int m = 0; m < s->nq; ++m) rep[(size_t)j * s->nq + m] = j;
+    s->rep_idx = s->c.arena.ialloc(rep.size());
+    HIP_CHECK(hipMemcpyAsync(s->rep_idx, rep.data(), rep.size() * sizeof(int),
+                             hipMemcpyHostToDevice, s->c.stream));
+    s->c.sync();
+  } catch (...) {
+    delete s;
+    throw;
+  }
+  return s;
+}
+
+void solver_step(Solver *s, double dt, int nsteps) {
+  TT_REQUIRE(nsteps >= 0 && std::isfinite(dt), "tt_fv_step: bad dt or nsteps");
+  for (int k = 0; k < nsteps; ++k) s->step(dt);
+}
+
+void solver_get_state(Solver *s, tt_matrix q[3]) {
+  for (int v = 0; v < 3; ++v) {
+    TT_REQUIRE(q[v].n1 == s->n && q[v].n2 == s->n && q[v].cap >= s->Q[v].r,
+               "tt_fv_get_state: output too small");
+    HIP_CHECK(hipMemcpyAsync(q[v].g1, s->Q[v].A, (size_t)s->n * s->Q[v].r * 8,
+                             hipMemcpyDeviceToDevice, s->c.stream));
+    HIP_CHECK(hipMemcpyAsync(q[v].g2, s->Q[v].B, (size_t)s->n * s->Q[v].r * 8,
+                             hipMemcpyDeviceToDevice, s->c.stream));
+    q[v].rank = s->Q[v].r;
+  }
+  s->c.sync();
+}
+
+void solver_stats(Solver *s, tt_fv_stats *o) {
+  o->steps = s->step_index;
+  for (int v = 0; v < 3; ++v) o->ranks[v] = s->Q[v].r;
+  Counters t = s->c.cnt;
+  for (int i = 0; i < s->pool->size(); ++i) {
+    const Counters &w = s->pool->ctx(i).cnt;
+    t.roundings += w.roundings;
+    t.crosses += w.crosses;
+    t.flops += w.flops;
+    t.bytes += w.bytes;
+    t.warnings |= w.warnings;
+    t.extra_power_iters += w.extra_power_iters;
+  }
+  o->roundings = t.roundings;
+  o->crosses = t.crosses;
+  o->last_taylor_terms = s->last_terms;
+  o->last_taylor_err = s->last_err;
+  o->warnings = t.warnings;
+  o->flops = t.flops;
+  o->bytes = t.bytes;
+}
+
+void solver_destroy(Solver *s) { delete s; }
+
+}  // namespace ttfv

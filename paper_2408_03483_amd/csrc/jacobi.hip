@@ -1,0 +1,214 @@
+// Small dense factorizations kept in one workgroup's LDS:
+//  * one-sided (Hestenes) Jacobi SVD of the m x m core matrix of a rounding (Section 3.2
+//    truncates the SVD of G1 R): columns are rotated pairwise until mutually orthogonal,
+//    giving U * Sigma column by column; a round-robin schedule makes the m/2 pair rotations
+//    of a round independent, one wavefront per pair;
+//  * Gauss-Jordan inverse with partial pivoting (skeleton of the cross, maxvol start).
+#include "common.h"
+#include "wave.h"
+
+#include <algorithm>
+
+namespace ttfv {
+namespace {
+
+constexpr int NT = 1024;
+constexpr int WAVES = NT / 64;
+
+// One group of 16 lanes (a DPP row) per column pair: column entries i = lane + 16 r.
+// Columns whose squared norm is below 1e-34 ||M||_F^2 are left alone (numerical zeros).
+template <int RS>
+__global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int m,
+                                               double *__restrict__ US,
+                                               double *__restrict__ sig, int max_sweeps) {
+  extern __shared__ double sm[];
+  const int mm = (m + 1) & ~1;
+  double *S = sm;                               // mm columns of m rows
+  double *nrm = sm + (size_t)mm * m;            // mm norms
+  __shared__ int rotated;
+  __shared__ double fro_part[NT / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  double part = 0.0;
+  for (int idx = threadIdx.x; idx < mm * m; idx += NT) {
+    const double v = (idx < m * m) ? M[idx] : 0.0;
+    S[idx] = v;
+    part += v * v;
+  }
+  part = wave_sum(part);
+  if (lane == 0) fro_part[wave] = part;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int w = 0; w < NT / 64; ++w) fro2 += fro_part[w];
+  const double tiny = 1e-34 * fro2;
+  const double tol = sqrt((double)m) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int t = 0; t < mm - 1; ++t) {
+      for (int k = gid; k < mm / 2; k += NT / 16) {
+        const int a = (k + t) % (mm - 1);
+        const int b = (k == 0) ? (mm - 1) : ((mm - 1 - k + t) % (mm - 1));
+        const int p = min(a, b), q = max(a, b);
+        double *cp = S + (size_t)p * m, *cq = S + (size_t)q * m;
+        double xp[RS], xq[RS];
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+          const int i = gl + 16 * r;
+          xp[r] = i < m ? cp[i] : 0.0;
+          xq[r] = i < m ? cq[i] : 0.0;
+          acc[0] += xp[r] * xp[r];
+          acc[1] += xq[r] * xq[r];
+          acc[2] += xp[r] * xq[r];
+        }
+        row16_sum_n<3>(acc);
+        const double al = acc[0], be = acc[1], ga = acc[2];
+        if (al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+#pragma unroll
+          for (int r = 0; r < RS; ++r) {
+            const int i = gl + 16 * r;
+            if (i < m) {
+              cp[i] = c * xp[r] - s * xq[r];
+              cq[i] = s * xp[r] + c * xq[r];
+            }
+          }
+          if (gl == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  // norms
+  for (int cidx = wave; cidx < mm; cidx += NT / 64) {
+    const double *cc = S + (size_t)cidx * m;
+    double x0 = lane < m ? cc[lane] : 0.0, x1 = lane + 64 < m ? cc[lane + 64] : 0.0;
+    double s2 = wave_sum(x0 * x0 + x1 * x1);
+    if (lane == 0) nrm[cidx] = sqrt(s2);
+  }
+  __syncthreads();
+  // rank by (norm desc, index asc) over the first m columns (the pad column is zero)
+  for (int i = threadIdx.x; i < m; i += NT) {
+    int rk = 0;
+    const double ni = nrm[i];
+    for (int j = 0; j < m; ++j) {
+      const double nj = nrm[j];
+      rk += (nj > ni) || (nj == ni && j < i);
+    }
+    sig[rk] = ni;
+    for (int r = 0; r < m; ++r) US[(size_t)rk * m + r] = S[(size_t)i * m + r];
+  }
+}
+
+// Gauss-Jordan inverse of an m x m matrix (m <= 96) with partial pivoting
+__global__ __launch_bounds__(NT) void k_inverse(const double *__restrict__ M, int m, int ldm,
+                                                double *__restrict__ Minv) {
+  extern __shared__ double sm[];
+  const int w = 2 * m;
+  double *T = sm;                    // row-major m x 2m
+  __shared__ int piv;
+  __shared__ double pv;
+  for (int idx = threadIdx.x; idx < m * w; idx += NT) {
+    const int i = idx / w, j = idx - i * w;
+    T[idx] = j < m ? M[i + (size_t)j * ldm] : (j - m == i ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    if (threadIdx.x == 0) {
+      int best = j;
+      double bv = fabs(T[(size_t)j * w + j]);
+      for (int i = j + 1; i < m; ++i) {
+        const double v = fabs(T[(size_t)i * w + j]);
+        if (v > bv) { bv = v; best = i; }
+      }
+      piv = best;
+    }
+    __syncthreads();
+    const int pr = piv;
+    if (pr != j)
+      for (int c = threadIdx.x; c < w; c += NT) {
+        const double tmp = T[(size_t)j * w + c];
+        T[(size_t)j * w + c] = T[(size_t)pr * w + c];
+        T[(size_t)pr * w + c] = tmp;
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) pv = T[(size_t)j * w + j];
+    __syncthreads();
+    const double inv = 1.0 / pv;
+    for (int c = threadIdx.x; c < w; c += NT) T[(size_t)j * w + c] *= inv;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < m * w; idx += NT) {
+      const int i = idx / w, c = idx - i * w;
+      if (i == j) continue;
+      const double f = T[(size_t)i * w + j];
+      if (c != j) T[idx] -= f * T[(size_t)j * w + c];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += NT)
+      if (i != j) T[(size_t)i * w + j] = 0.0;
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * m; idx += NT) {
+    const int i = idx % m, j = idx / m;
+    Minv[i + (size_t)j * m] = T[(size_t)i * w + m + j];
+  }
+}
+
+__global__ void k_normalise(const double *__restrict__ US, const double *__restrict__ sig, int m,
+                            int k, double *__restrict__ U) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * k) return;
+  const int c = idx / m;
+  const double s = sig[c];
+  U[idx] = s > 0.0 ? US[idx] / s : 0.0;
+}
+
+template <typename K>
+void set_lds(K kern, size_t bytes) {
+  HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+}
+
+}  // namespace
+
+void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
+  TT_REQUIRE(m >= 1 && m <= 128, "jacobi_svd: m out of range");
+  const int mm = (m + 1) & ~1;
+  const size_t lds = ((size_t)mm * m + mm) * sizeof(double);
+  if (m <= 32) {
+    set_lds(k_jacobi<2>, lds);
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+  } else if (m <= 64) {
+    set_lds(k_jacobi<4>, lds);
+    hipLaunchKernelGGL(k_jacobi<4>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+  } else if (m <= 96) {
+    set_lds(k_jacobi<6>, lds);
+    hipLaunchKernelGGL(k_jacobi<6>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+  } else {
+    set_lds(k_jacobi<8>, lds);
+    hipLaunchKernelGGL(k_jacobi<8>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+  }
+  c.cnt.flops += 22.0 * m * m * m;
+}
+
+void small_inverse(Ctx &c, const double *M, int m, int ldm, double *Minv) {
+  TT_REQUIRE(m >= 1 && m <= 128, "small_inverse: m out of range");
+  const size_t lds = (size_t)m * 2 * m * sizeof(double);
+  set_lds(k_inverse, lds);
+  hipLaunchKernelGGL(k_inverse, dim3(1), dim3(NT), lds, c.stream, M, m, ldm, Minv);
+  c.cnt.flops += 2.0 * m * m * m;
+}
+
+void normalise_cols(Ctx &c, const double *US, const double *sig, int m, int k, double *U) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_normalise, dim3((m * k + 255) / 256), dim3(256), 0, c.stream, US, sig, m, k,
+                     U);
+}
+
+}  // namespace ttfv

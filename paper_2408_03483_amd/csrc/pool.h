@@ -1,0 +1,116 @@
+// Task executor for independent chains of TT operations: a fixed set of worker threads,
+// each owning a HIP stream (non-blocking, default priority) and a device arena.  A task
+// receives its worker's context, enqueues work on that stream, and the worker synchronises
+// the stream before the task counts as done, so results are visible to every stream once
+// run() returns.
+#pragma once
+#include <condition_variable>
+#include <deque>
+#include <exception>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+namespace ttfv {
+
+class Pool {
+ public:
+  using Task = std::function<void(Ctx &)>;
+
+  Pool(int nworkers, size_t arena_bytes, int device) {
+    for (int i = 0; i < nworkers; ++i) {
+      auto c = std::make_unique<Ctx>();
+      HIP_CHECK(hipSetDevice(device));
+      HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->arena.init(arena_bytes);
+      ctx_.push_back(std::move(c));
+    }
+    for (int i = 0; i < nworkers; ++i)
+      threads_.emplace_back([this, i, device]() { loop(i, device); });
+  }
+
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto &t : threads_) t.join();
+    for (auto &c : ctx_)
+      if (c->stream) (void)hipStreamDestroy(c->stream);
+  }
+
+  int size() const { return (int)ctx_.size(); }
+  Ctx &ctx(int i) { return *ctx_[i]; }
+
+  // Run all tasks and wait; the first exception raised by a task is rethrown here.
+  void run(std::vector<Task> tasks) {
+    if (tasks.empty()) return;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (auto &t : tasks) q_.push_back(std::move(t));
+      pending_ += (int)tasks.size();
+      err_ = nullptr;
+    }
+    cv_.notify_all();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [this] { return pending_ == 0; });
+    if (err_) {
+      std::exception_ptr e = err_;
+      err_ = nullptr;
+      std::rethrow_exception(e);
+    }
+  }
+
+  void set_sketch(int width, int power_iters) {
+    for (auto &c : ctx_) {
+      c->sketch_width = width;
+      c->power_iters = power_iters;
+    }
+  }
+
+ private:
+  void loop(int i, int device) {
+    (void)hipSetDevice(device);
+    for (;;) {
+      Task t;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [this] { return stop_ || !q_.empty(); });
+        if (stop_ && q_.empty()) return;
+        t = std::move(q_.front());
+        q_.pop_front();
+      }
+      std::exception_ptr e = nullptr;
+      try {
+        Scope sc(ctx_[i]->arena);
+        t(*ctx_[i]);
+        ctx_[i]->sync();
+      } catch (...) {
+        e = std::current_exception();
+        (void)hipStreamSynchronize(ctx_[i]->stream);
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (e && !err_) err_ = e;
+        --pending_;
+      }
+      done_.notify_all();
+    }
+  }
+
+  std::vector<std::unique_ptr<Ctx>> ctx_;
+  std::vector<std::thread> threads_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  std::deque<Task> q_;
+  int pending_ = 0;
+  bool stop_ = false;
+  std::exception_ptr err_;
+};
+
+}  // namespace ttfv

@@ -1,0 +1,404 @@
+// Host-side TT algorithms built from the device kernels: rounding (Section 3.2),
+// the Taylor reciprocal (Algorithm 1), and the alternating maxvol cross (Section 3.3).
+//
+// Rounding of X = A B^T (rank R) to (eps, rmax):
+//   * R small (R <= sketch width and both modes): QR of both cores, M = Ra Rb^T, SVD of M
+//     (the two-core form of orthogonalise-then-truncated-SVD);
+//   * R large (e.g. Hadamard products, R = r_x r_y): a randomized range finder (Halko,
+//     Martinsson and Tropp 2011) replaces the R x R SVD: Y = X Omega with a Gaussian
+//     Omega of `width` columns (default 2 rmax), `power_iters` subspace iterations, Qa = orth(Y),
+//     W = X^T Qa = Qb Rb, M = Rb^T; SVD of M.  Only GEMMs touch the n x R cores; the
+//     factorizations are of width <= 96.
+//   The rank k is the smallest with sqrt(sum_{i>=k} s_i^2) <= eps ||s|| capped at rmax.
+//   Output gauge: A' = Qa U_k (orthonormal columns), B' = Qb M^T U_k (carries Sigma).
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <unordered_set>
+
+namespace ttfv {
+
+namespace {
+
+std::vector<double> to_host(Ctx &c, const double *dev, size_t n) {
+  std::vector<double> h(n);
+  if (n) HIP_CHECK(hipMemcpyAsync(h.data(), dev, n * sizeof(double), hipMemcpyDeviceToHost,
+                                  c.stream));
+  c.sync();
+  return h;
+}
+
+int trunc_rank(const std::vector<double> &s, double eps, int rmax, bool *capped) {
+  const int m = (int)s.size();
+  std::vector<double> tail(m + 1, 0.0);
+  for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
+  const double thr = eps * eps * tail[0];
+  int k = m;
+  for (int kk = 1; kk <= m; ++kk)
+    if (tail[kk] <= thr) { k = kk; break; }
+  k = std::max(1, std::min(k, rmax));
+  if (capped) *capped = (k < m) && (tail[k] > thr);
+  return k;
+}
+
+void zero_tt(Ctx &c, DTT &y) {
+  fill_value(c, y.A, y.n1, y.n1, 1, 0.0);
+  fill_value(c, y.B, y.n2, y.n2, 1, 0.0);
+  y.r = 1;
+}
+
+uint64_t g_sketch_seed = 0x5EED5EED12345ull;
+
+}  // namespace
+
+int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig_out) {
+  TT_REQUIRE(x.r >= 1 && rmax >= 1, "round: empty input or rmax < 1");
+  TT_REQUIRE(x.n1 == y.n1 && x.n2 == y.n2, "round: shape mismatch");
+  c.cnt.roundings++;
+  Scope sc(c.arena);
+  const int n1 = x.n1, n2 = x.n2, R = x.r;
+  const int qmax = qr_max_cols();
+  int width = c.sketch_width > 0 ? c.sketch_width : std::min(QR_MAXM, std::max(2 * rmax, 16));
+  width = std::min(width, qmax);
+  const int mn = std::min(n1, n2);
+
+  const double *Qa = nullptr, *Qb = nullptr;
+  double *M = nullptr;
+  double *US = nullptr, *sg = nullptr;   // SVD of M once computed
+  int m = 0;
+  if (R <= width && R <= mn) {
+    m = R;
+    double *qa = c.arena.dalloc((size_t)n1 * m), *ra = c.arena.dalloc((size_t)m * m);
+    double *qb = c.arena.dalloc((size_t)n2 * m), *rb = c.arena.dalloc((size_t)m * m);
+    tsqr(c, x.A, n1, m, n1, qa, n1, ra, m);
+    tsqr(c, x.B, n2, m, n2, qb, n2, rb, m);
+    M = c.arena.dalloc((size_t)m * m);
+    gemm2(c, false, true, m, m, m, 1.0, ra, m, rb, m, 0.0, M, m);     // Ra Rb^T
+    Qa = qa;
+    Qb = qb;
+  } else if (mn <= width && mn <= qmax) {
+    // tiny modes: materialise the full matrix on the smaller side
+    if (n2 <= n1) {
+      // X = (A B^T) I: A' = A B^T (n1 x n2), B' = I (n2 x n2)
+      m = n2;
+      double *F = c.arena.dalloc((size_t)n1 * n2);
+      gemm2(c, false, true, n1, n2, R, 1.0, x.A, n1, x.B, n2, 0.0, F, n1);
+      double *qa = c.arena.dalloc((size_t)n1 * m), *ra = c.arena.dalloc((size_t)m * m);
+      tsqr(c, F, n1, m, n1, qa, n1, ra, m);
+      double *qb = c.arena.dalloc((size_t)n2 * m);
+      fill_value(c, qb, n2, n2, m, 0.0);
+      {
+        std::vector<double> eye((size_t)m * m, 0.0);
+        for (int i = 0; i < m; ++i) eye[(size_t)i * m + i] = 1.0;
+        HIP_CHECK(hipMemcpyAsync(qb, eye.data(), eye.size() * 8, hipMemcpyHostToDevice, c.stream));
+        c.sync();
+      }
+      M = ra;
+      Qa = qa;
+      Qb = qb;
+    } else {
+      m = n1;
+      double *F = c.arena.dalloc((size_t)n2 * n1);                  // X^T = B A^T
+      gemm2(c, false, true, n2, n1, R, 1.0, x.B, n2, x.A, n1, 0.0, F, n2);
+      double *qb = c.arena.dalloc((size_t)n2 * m), *rb = c.arena.dalloc((size_t)m * m);
+      tsqr(c, F, n2, m, n2, qb, n2, rb, m);
+      double *qa = c.arena.dalloc((size_t)n1 * m);
+      {
+        std::vector<double> eye((size_t)m * m, 0.0);
+        for (int i = 0; i < m; ++i) eye[(size_t)i * m + i] = 1.0;
+        HIP_CHECK(hipMemcpyAsync(qa, eye.data(), eye.size() * 8, hipMemcpyHostToDevice, c.stream));
+        c.sync();
+      }
+      M = c.arena.dalloc((size_t)m * m);
+      transpose(c, M, m, rb, m, m, m);                               // X = I Rb^T Qb^T
+      Qa = qa;
+      Qb = qb;
+    }
+  } else {
+    // randomized range finder with subspace iterations; more iterations are run while the
+    // estimated contraction (s_m / s_k)^(2q+1) of the discarded directions is above 1e-13
+    m = std::min(width, mn);
+    double *Om = c.arena.dalloc((size_t)n2 * m);
+    fill_gauss(c, Om, n2, m, n2, g_sketch_seed + (uint64_t)c.cnt.roundings * 0x9E3779B9ull);
+    double *T = c.arena.dalloc((size_t)R * m);
+    double *Y = c.arena.dalloc((size_t)n1 * m);
+    double *Z = c.arena.dalloc((size_t)n2 * m);
+    double *qa = c.arena.dalloc((size_t)n1 * m), *qz = c.arena.dalloc((size_t)n2 * m);
+    double *qb = c.arena.dalloc((size_t)n2 * m), *rb = c.arena.dalloc((size_t)m * m);
+    double *rtmp = c.arena.dalloc((size_t)m * m);
+    M = c.arena.dalloc((size_t)m * m);
+    gemm(c, true, R, m, n2, 1.0, x.B, n2, Om, n2, 0.0, T, R);          // B^T Omega
+    gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);          // Y = X Omega
+    int q = 0;
+    const int qlim = std::max(c.power_iters, 8);
+    for (;;) {
+      for (; q < c.power_iters; ++q) {
+        tsqr(c, Y, n1, m, n1, qa, n1, rtmp, m);
+        gemm(c, true, R, m, n1, 1.0, x.A, n1, qa, n1, 0.0, T, R);      // A^T Qy
+        gemm(c, false, n2, m, R, 1.0, x.B, n2, T, R, 0.0, Z, n2);      // X^T Qy
+        tsqr(c, Z, n2, m, n2, qz, n2, rtmp, m);
+        gemm(c, true, R, m, n2, 1.0, x.B, n2, qz, n2, 0.0, T, R);      // B^T Qz
+        gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);      // Y = X Qz
+      }
+      tsqr(c, Y, n1, m, n1, qa, n1, rtmp, m);
+      gemm(c, true, R, m, n1, 1.0, x.A, n1, qa, n1, 0.0, T, R);        // A^T Qa
+      gemm(c, false, n2, m, R, 1.0, x.B, n2, T, R, 0.0, Z, n2);        // W = X^T Qa
+      tsqr(c, Z, n2, m, n2, qb, n2, rb, m);                            // W = Qb Rb
+      transpose(c, M, m, rb, m, m, m);                                 // X ~ Qa Rb^T Qb^T
+      if (q >= qlim) break;
+      // singular values of Rb estimate those of X on the captured subspace
+      if (!US) {
+        US = c.arena.dalloc((size_t)m * m);
+        sg = c.arena.dalloc((size_t)m);
+      }
+      jacobi_svd(c, M, m, US, sg);
+      std::vector<double> s = to_host(c, sg, m);
+      if (s[0] == 0.0) break;
+      const int k = trunc_rank(s, eps, rmax, nullptr);
+      if (k >= m) break;
+      const double ratio = s[m - 1] / s[k - 1];
+      if (std::pow(ratio, 2 * q + 1) <= 1e-13) break;
+      US = nullptr;   // basis changes below: the SVD must be recomputed
+      // one more subspace iteration from the current basis: Y = X (X^T Qa) = X Z
+      tsqr(c, Z, n2, m, n2, qz, n2, rtmp, m);
+      gemm(c, true, R, m, n2, 1.0, x.B, n2, qz, n2, 0.0, T, R);
+      gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);
+      ++q;
+      c.cnt.extra_power_iters++;
+    }
+    Qa = qa;
+    Qb = qb;
+  }
+  // SVD of the m x m core
+  if (!US) {
+    US = c.arena.dalloc((size_t)m * m);
+    sg = c.arena.dalloc((size_t)m);
+    jacobi_svd(c, M, m, US, sg);
+  }
+  std::vector<double> s = to_host(c, sg, m);
+  for (double v : s)
+    if (!std::isfinite(v)) throw Error(TT_ENONFINITE, "round: non-finite singular value");
+  int warn = 0;
+  if (s[0] == 0.0) {
+    zero_tt(c, y);
+    if (sig_out) sig_out->assign(1, 0.0);
+    return 0;
+  }
+  bool capped = false;
+  const int k = trunc_rank(s, eps, rmax, &capped);
+  if (capped) warn |= TT_WRANKCAP;
+  double *U = c.arena.dalloc((size_t)m * k);
+  normalise_cols(c, US, sg, m, k, U);
+  double *W = c.arena.dalloc((size_t)m * k);
+  gemm(c, true, m, k, m, 1.0, M, m, U, m, 0.0, W, m);                  // M^T U_k
+  gemm(c, false, n1, k, m, 1.0, Qa, n1, U, m, 0.0, y.A, n1);
+  gemm(c, false, n2, k, m, 1.0, Qb, n2, W, m, 0.0, y.B, n2);
+  y.r = k;
+  if (sig_out) sig_out->assign(s.begin(), s.begin() + k);
+  c.cnt.warnings |= warn;
+  return warn;
+}
+
+void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out) {
+  Scope sc(c.arena);
+  TT_REQUIRE(m >= 1, "orth: no columns");
+  if (m <= n) {
+    TT_REQUIRE(m <= qr_max_cols(), "orth: too many columns");
+    double *q = c.arena.dalloc((size_t)n * m), *r = c.arena.dalloc((size_t)m * m);
+    tsqr(c, C, n, m, ldc, q, n, r, m);
+    double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc(m);
+    jacobi_svd(c, r, m, US, sg);
+    std::vector<double> s = to_host(c, sg, m);
+    int k = 0;
+    if (s[0] > 0.0)
+      while (k < m && s[k] > drop * s[0]) ++k;
+    *k_out = k;
+    if (k == 0) return;
+    double *U = c.arena.dalloc((size_t)m * k);
+    normalise_cols(c, US, sg, m, k, U);
+    gemm(c, false, n, k, m, 1.0, q, n, U, m, 0.0, Q, n);
+    return;
+  }
+  // wide: range(C) = range(R^T) where C^T = Qt Rt
+  TT_REQUIRE(n <= qr_max_cols(), "orth: too many rows");
+  double *Ct = c.arena.dalloc((size_t)m * n);
+  transpose(c, Ct, m, C, ldc, n, m);
+  double *qt = c.arena.dalloc((size_t)m * n), *rt = c.arena.dalloc((size_t)n * n);
+  tsqr(c, Ct, m, n, m, qt, m, rt, n);
+  double *Rt = c.arena.dalloc((size_t)n * n);
+  transpose(c, Rt, n, rt, n, n, n);
+  double *US = c.arena.dalloc((size_t)n * n), *sg = c.arena.dalloc(n);
+  jacobi_svd(c, Rt, n, US, sg);
+  std::vector<double> s = to_host(c, sg, n);
+  int k = 0;
+  if (s[0] > 0.0)
+    while (k < n && s[k] > drop * s[0]) ++k;
+  *k_out = k;
+  if (k == 0) return;
+  normalise_cols(c, US, sg, n, k, Q);
+}
+
+int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, double *err_out,
+                  int *terms_out) {
+  TT_REQUIRE(K >= 1, "reciprocal: max_terms < 1");
+  Scope sc(c.arena);
+  const int n1 = x.n1, n2 = x.n2;
+  const double N = (double)n1 * (double)n2;
+  // x_avg = sum(x) / N, sum(x) = (1^T A)(B^T 1)
+  double *cs = c.arena.dalloc(2 * (size_t)x.r);
+  colsum(c, x.A, n1, x.r, n1, cs);
+  colsum(c, x.B, n2, x.r, n2, cs + x.r);
+  std::vector<double> h = to_host(c, cs, 2 * (size_t)x.r);
+  double total = 0.0;
+  for (int a = 0; a < x.r; ++a) total += h[a] * h[x.r + a];
+  const double xavg = total / N;
+  TT_REQUIRE(xavg != 0.0 && std::isfinite(xavg), "reciprocal: mean of x is zero or not finite");
+  // x~ = round(1 - x / x_avg)
+  const int cap = std::max(rmax, 1);
+  DTT xt{n1, n2, 0, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+  {
+    Scope s2(c.arena);
+    DTT t{n1, n2, x.r + 1, c.arena.dalloc((size_t)n1 * (x.r + 1)),
+          c.arena.dalloc((size_t)n2 * (x.r + 1))};
+    fill_value(c, t.A, n1, n1, 1, 1.0);
+    fill_value(c, t.B, n2, n2, 1, 1.0);
+    copy_scale(c, t.A + n1, n1, x.A, n1, n1, x.r, -1.0 / xavg);
+    copy_scale(c, t.B + n2, n2, x.B, n2, n2, x.r, 1.0);
+    round_tt(c, t, eps, rmax, xt, nullptr);
+  }
+  DTT dy{n1, n2, 1, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+  DTT dy2{n1, n2, 0, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+  fill_value(c, dy.A, n1, n1, 1, 1.0);
+  fill_value(c, dy.B, n2, n2, 1, 1.0);
+  // y is accumulated in the caller's buffers; start at 1
+  fill_value(c, y.A, n1, n1, 1, 1.0);
+  fill_value(c, y.B, n2, n2, 1, 1.0);
+  y.r = 1;
+  double err = 1.0;
+  int terms = 1, warn = 0;
+  while (err > eps && terms < K) {
+    Scope s3(c.arena);
+    const int R = dy.r * xt.r;
+    DTT p{n1, n2, R, c.arena.dalloc((size_t)n1 * R), c.arena.dalloc((size_t)n2 * R)};
+    khatri_rao(c, p.A, n1, dy.A, dy.r, xt.A, xt.r);
+    khatri_rao(c, p.B, n2, dy.B, dy.r, xt.B, xt.r);
+    std::vector<double> sdy;
+    warn |= round_tt(c, p, eps, rmax, dy2, &sdy);
+    std::swap(dy, dy2);
+    const int Rs = y.r + dy.r;
+    DTT s{n1, n2, Rs, c.arena.dalloc((size_t)n1 * Rs), c.arena.dalloc((size_t)n2 * Rs)};
+    copy_scale(c, s.A, n1, y.A, n1, n1, y.r, 1.0);
+    copy_scale(c, s.A + (size_t)n1 * y.r, n1, dy.A, n1, n1, dy.r, 1.0);
+    copy_scale(c, s.B, n2, y.B, n2, n2, y.r, 1.0);
+    copy_scale(c, s.B + (size_t)n2 * y.r, n2, dy.B, n2, n2, dy.r, 1.0);
+    warn |= round_tt(c, s, eps, rmax, y, nullptr);
+    double nrm2 = 0.0;
+    for (double v : sdy) nrm2 += v * v;
+    err = std::sqrt(nrm2) / std::sqrt(N);
+    ++terms;
+  }
+  copy_scale(c, y.A, n1, y.A, n1, n1, y.r, 1.0 / xavg);
+  if (err > eps) warn |= TT_WNOCONV;
+  if (err_out) *err_out = err;
+  if (terms_out) *terms_out = terms;
+  c.cnt.warnings |= warn;
+  return warn;
+}
+
+std::vector<int> maxvol_host(Ctx &c, const double *Q, int n, int r, int ldq, double tau,
+                             int maxit) {
+  Scope sc(c.arena);
+  int *rows = c.arena.ialloc(r);
+  maxvol_dev(c, Q, n, r, ldq, tau, maxit, rows);
+  std::vector<int> h(r);
+  HIP_CHECK(hipMemcpyAsync(h.data(), rows, r * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  c.sync();
+  return h;
+}
+
+uint64_t splitmix64_next(uint64_t &state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+std::vector<int> kick_indices(const std::vector<int> &have_v, int n, int count, uint64_t key) {
+  std::unordered_set<int> have(have_v.begin(), have_v.end());
+  std::vector<int> out;
+  uint64_t state = key;
+  int tries = 0;
+  while ((int)out.size() < count && (int)have.size() < n && tries < 64 * (count + 1)) {
+    const uint64_t z = splitmix64_next(state);
+    const int idx = (int)(z % (uint64_t)n);
+    ++tries;
+    if (!have.count(idx)) {
+      have.insert(idx);
+      out.push_back(idx);
+    }
+  }
+  return out;
+}
+
+int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, double eps,
+             int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out) {
+  TT_REQUIRE(!J.empty(), "cross: empty starting column set");
+  TT_REQUIRE(sweeps >= 1, "cross: sweeps < 1");
+  c.cnt.crosses++;
+  Scope sc(c.arena);
+  const int jcap = std::max((int)J.size(), rmax) + kick * sweeps + 1;
+  const int qmax = qr_max_cols();
+  TT_REQUIRE(jcap <= qmax + kick * sweeps + 1, "cross: rank too large");
+  int *Jd = c.arena.ialloc(jcap);
+  int *Id = c.arena.ialloc(jcap);
+  double *C = c.arena.dalloc((size_t)n1 * jcap);
+  double *Qc = c.arena.dalloc((size_t)n1 * jcap);
+  double *RwT = c.arena.dalloc((size_t)n2 * jcap);
+  double *Qr = c.arena.dalloc((size_t)n2 * jcap);
+  std::vector<int> I;
+  int rc = 0;
+  for (int s = 0; s < sweeps; ++s) {
+    TT_REQUIRE((int)J.size() <= qmax, "cross: column set exceeds the factorization width");
+    HIP_CHECK(hipMemcpyAsync(Jd, J.data(), J.size() * sizeof(int), hipMemcpyHostToDevice,
+                             c.stream));
+    fiber_cols(c, fs, n1, Jd, (int)J.size(), C);
+    orth(c, C, n1, (int)J.size(), n1, 1e-13, Qc, &rc);
+    if (rc == 0) {
+      zero_tt(c, y);
+      if (J_out) *J_out = J;
+      return 0;
+    }
+    I = maxvol_host(c, Qc, n1, rc, n1, 1.05, 100);
+    HIP_CHECK(hipMemcpyAsync(Id, I.data(), I.size() * sizeof(int), hipMemcpyHostToDevice,
+                             c.stream));
+    fiber_rows(c, fs, n2, Id, rc, RwT);
+    if (s == sweeps - 1) break;
+    int rr = 0;
+    orth(c, RwT, n2, rc, n2, 1e-13, Qr, &rr);
+    if (rr == 0) {
+      zero_tt(c, y);
+      if (J_out) *J_out = J;
+      return 0;
+    }
+    J = maxvol_host(c, Qr, n2, rr, n2, 1.05, 100);
+    if ((int)J.size() < rmax && kick > 0) {
+      std::vector<int> extra = kick_indices(J, n2, std::min(kick, rmax - (int)J.size()),
+                                            key + 1000003ull * (uint64_t)(s + 1));
+      J.insert(J.end(), extra.begin(), extra.end());
+    }
+  }
+  // skeleton: G1 = Qc Qc[I]^-1, G2^T = RwT
+  double *QI = c.arena.dalloc((size_t)rc * rc), *QIi = c.arena.dalloc((size_t)rc * rc);
+  gather_rows(c, QI, rc, Qc, n1, Id, rc, rc);
+  small_inverse(c, QI, rc, rc, QIi);
+  double *G1 = c.arena.dalloc((size_t)n1 * rc);
+  gemm(c, false, n1, rc, rc, 1.0, Qc, n1, QIi, rc, 0.0, G1, n1);
+  DTT sk{n1, n2, rc, G1, RwT};
+  const int w = round_tt(c, sk, eps, rmax, y, nullptr);
+  if (J_out) *J_out = J;
+  return w;
+}
+
+}  // namespace ttfv

@@ -1,0 +1,305 @@
+"""Python binding of libttfv.so (include/tt_fv.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm).  A core of n rows and capacity `cap`
+is a contiguous torch tensor of shape (cap, n): column a of the column-major n x cap core
+is row a of the tensor.  Every computation runs in the HIP library; if the library cannot
+be loaded, or no GPU is present, the calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libttfv.so")
+
+TT_FN_IDENTITY = 0
+TT_FN_LLF_LAMBDA = 1
+TT_FN_WENO_FACE_M = 2
+TT_FN_WENO_FACE_P = 3
+TT_FN_WENO_QUAD = 4
+
+TT_WRANKCAP = 1
+TT_WNOCONV = 2
+
+
+class TTMatrixC(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("rank", ctypes.c_int),
+                ("cap", ctypes.c_int), ("g1", ctypes.c_void_p), ("g2", ctypes.c_void_p)]
+
+
+class ParamsC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("nonlinear", ctypes.c_int), ("scheme", ctypes.c_int),
+                ("periodic", ctypes.c_int), ("g", ctypes.c_double), ("H0", ctypes.c_double),
+                ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
+                ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
+                ("cross_kick", ctypes.c_int)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_longlong), ("ranks", ctypes.c_int * 3),
+                ("roundings", ctypes.c_longlong), ("crosses", ctypes.c_longlong),
+                ("last_taylor_terms", ctypes.c_int), ("last_taylor_err", ctypes.c_double),
+                ("warnings", ctypes.c_int), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_round",
+           "tt_hadamard_round", "tt_reciprocal", "tt_maxvol", "tt_cross", "tt_recon_core",
+           "tt_fv_init", "tt_fv_step", "tt_fv_get_state", "tt_fv_get_stats", "tt_fv_destroy",
+           "tt_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libttfv.so and declare its signatures (no GPU needed for this step)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libttfv.so not built ({path}); run paper_2408_03483_amd.build")
+    L = ctypes.CDLL(path)
+    P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    pM = ctypes.POINTER(TTMatrixC)
+    L.tt_last_error.restype = ctypes.c_char_p
+    L.tt_ctx_create.argtypes = [ctypes.POINTER(P), S, P]
+    L.tt_ctx_destroy.argtypes = [P]
+    L.tt_ctx_destroy.restype = None
+    L.tt_ctx_set_sketch.argtypes = [P, I, I]
+    L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
+    L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
+    L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
+    L.tt_maxvol.argtypes = [P, P, I, I, I, D, I, ctypes.POINTER(I)]
+    L.tt_cross.argtypes = [P, I, pM, I, ctypes.POINTER(D), I, I, ctypes.POINTER(I), I, D, I, I,
+                           I, ctypes.c_uint64, pM, ctypes.POINTER(I), ctypes.POINTER(I)]
+    L.tt_recon_core.argtypes = [P, P, I, I, I, I, D, P, P, P]
+    L.tt_fv_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(ParamsC), pM, P, S]
+    L.tt_fv_step.argtypes = [P, D, I]
+    L.tt_fv_get_state.argtypes = [P, pM]
+    L.tt_fv_get_stats.argtypes = [P, ctypes.POINTER(StatsC)]
+    L.tt_fv_destroy.argtypes = [P]
+    L.tt_fv_destroy.restype = None
+    for name in EXPORTS:
+        if not hasattr(L, name):
+            raise RuntimeError(f"libttfv.so lacks {name}")
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the TT-FV library runs on the GPU only")
+    return torch
+
+
+def _check(code: int, what: str) -> int:
+    if code < 0:
+        msg = _lib.tt_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed ({code}): {msg}")
+    return code
+
+
+class DeviceTT:
+    """Two device cores: g1 (cap, n1), g2 (cap, n2) float64 tensors (column-major cores)."""
+
+    def __init__(self, n1: int, n2: int, cap: int, device="cuda"):
+        torch = _torch()
+        self.n1, self.n2, self.cap, self.rank = n1, n2, cap, 0
+        self.g1 = torch.zeros((cap, n1), dtype=torch.float64, device=device)
+        self.g2 = torch.zeros((cap, n2), dtype=torch.float64, device=device)
+
+    @classmethod
+    def from_factors(cls, A: np.ndarray, B: np.ndarray, cap: Optional[int] = None,
+                     device="cuda") -> "DeviceTT":
+        torch = _torch()
+        r = A.shape[1]
+        t = cls(A.shape[0], B.shape[0], max(cap or r, r), device)
+        t.g1[:r] = torch.from_numpy(np.ascontiguousarray(A.T)).to(device)
+        t.g2[:r] = torch.from_numpy(np.ascontiguousarray(B.T)).to(device)
+        t.rank = r
+        return t
+
+    def c(self) -> TTMatrixC:
+        return TTMatrixC(self.n1, self.n2, self.rank, self.cap, self.g1.data_ptr(),
+                         self.g2.data_ptr())
+
+    def factors(self):
+        A = self.g1[:self.rank].T.cpu().numpy().copy()
+        B = self.g2[:self.rank].T.cpu().numpy().copy()
+        return A, B
+
+    def full(self) -> np.ndarray:
+        A, B = self.factors()
+        return A @ B.T
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Ctx:
+    def __init__(self, arena_bytes: int = 1 << 30, stream=None):
+        L = load_library()
+        _torch()
+        self._stream = stream
+        self.h = ctypes.c_void_p()
+        _check(L.tt_ctx_create(ctypes.byref(self.h), arena_bytes, _stream_ptr(stream)),
+               "tt_ctx_create")
+
+    def close(self):
+        if self.h:
+            _lib.tt_ctx_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tt_ctx_create(arena_bytes: int = 1 << 30, stream=None) -> Ctx:
+    return Ctx(arena_bytes, stream)
+
+
+def tt_ctx_set_sketch(ctx: Ctx, width: int, power_iters: int) -> None:
+    _check(_lib.tt_ctx_set_sketch(ctx.h, width, power_iters), "tt_ctx_set_sketch")
+
+
+def tt_round(ctx: Ctx, x: DeviceTT, eps: float, r_max: int, y: DeviceTT):
+    xc, yc = x.c(), y.c()
+    sig = (ctypes.c_double * max(r_max, 1))()
+    w = _check(_lib.tt_round(ctx.h, ctypes.byref(xc), eps, r_max, ctypes.byref(yc), sig),
+               "tt_round")
+    y.rank = yc.rank
+    return w, np.array(sig[:y.rank])
+
+
+def tt_hadamard_round(ctx: Ctx, x: DeviceTT, z: DeviceTT, eps: float, r_max: int,
+                      y: DeviceTT) -> int:
+    xc, zc, yc = x.c(), z.c(), y.c()
+    w = _check(_lib.tt_hadamard_round(ctx.h, ctypes.byref(xc), ctypes.byref(zc), eps, r_max,
+                                      ctypes.byref(yc)), "tt_hadamard_round")
+    y.rank = yc.rank
+    return w
+
+
+def tt_reciprocal(ctx: Ctx, x: DeviceTT, eps: float, max_terms: int, r_max: int, y: DeviceTT):
+    xc, yc = x.c(), y.c()
+    err = ctypes.c_double()
+    terms = ctypes.c_int()
+    w = _check(_lib.tt_reciprocal(ctx.h, ctypes.byref(xc), eps, max_terms, r_max,
+                                  ctypes.byref(yc), ctypes.byref(err), ctypes.byref(terms)),
+               "tt_reciprocal")
+    y.rank = yc.rank
+    return w, err.value, terms.value
+
+
+def tt_maxvol(ctx: Ctx, q, tau: float = 1.05, maxit: int = 100) -> np.ndarray:
+    """q: torch float64 (r, n) tensor = column-major n x r basis."""
+    r, n = q.shape
+    rows = (ctypes.c_int * r)()
+    _check(_lib.tt_maxvol(ctx.h, ctypes.c_void_p(q.data_ptr()), n, r, n, tau, maxit, rows),
+           "tt_maxvol")
+    return np.array(rows[:], dtype=np.int64)
+
+
+def tt_cross(ctx: Ctx, fn: int, inputs: Sequence[DeviceTT], fparams: Sequence[float], n1: int,
+             n2: int, J0: Sequence[int], eps: float, r_max: int, sweeps: int, kick: int,
+             key: int, y: DeviceTT):
+    arr = (TTMatrixC * len(inputs))(*[t.c() for t in inputs])
+    fp = (ctypes.c_double * max(1, len(fparams)))(*fparams)
+    J = (ctypes.c_int * len(J0))(*[int(j) for j in J0])
+    jcap = len(J0) + r_max + kick * sweeps + 8
+    Jo = (ctypes.c_int * jcap)()
+    nJ = ctypes.c_int()
+    yc = y.c()
+    w = _check(_lib.tt_cross(ctx.h, fn, arr, len(inputs), fp, n1, n2, J, len(J0), eps, r_max,
+                             sweeps, kick, ctypes.c_uint64(key & 0xFFFFFFFFFFFFFFFF),
+                             ctypes.byref(yc), Jo, ctypes.byref(nJ)), "tt_cross")
+    y.rank = yc.rank
+    return w, np.array(Jo[:nJ.value], dtype=np.int64)
+
+
+def tt_recon_core(ctx: Ctx, core, scheme: int, periodic: bool, sign: float = 1.0):
+    """core: torch (r, n).  Returns (face_m, face_p, quad) torch tensors (r, n_f) and (r, n*nq)."""
+    torch = _torch()
+    r, n = core.shape
+    nf = n if periodic else n + 1
+    nq = 2 if scheme == 3 else 3
+    fm = torch.empty((r, nf), dtype=torch.float64, device=core.device)
+    fp = torch.empty((r, nf), dtype=torch.float64, device=core.device)
+    q = torch.empty((r, n * nq), dtype=torch.float64, device=core.device)
+    _check(_lib.tt_recon_core(ctx.h, ctypes.c_void_p(core.data_ptr()), n, r, scheme,
+                              1 if periodic else 0, sign, ctypes.c_void_p(fm.data_ptr()),
+                              ctypes.c_void_p(fp.data_ptr()), ctypes.c_void_p(q.data_ptr())),
+           "tt_recon_core")
+    return fm, fp, q
+
+
+SCHEMES = {"upwind3": 3, "upwind5": 5, "weno5": 55}
+
+
+class Solver:
+    def __init__(self, h, params: ParamsC, ctx_stream):
+        self.h, self.params, self._stream = h, params, ctx_stream
+
+    def close(self):
+        if self.h:
+            _lib.tt_fv_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequence[DeviceTT],
+               g: float = 9.81, H0: float = 1.0, f: float = 0.0, eps: float = 1e-10,
+               r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
+               cross_kick: int = 4, stream=None, arena_bytes: int = 4 << 30) -> Solver:
+    L = load_library()
+    _torch()
+    p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
+                r_max, taylor_terms, cross_sweeps, cross_kick)
+    arr = (TTMatrixC * 3)(*[t.c() for t in q0])
+    h = ctypes.c_void_p()
+    _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
+           "tt_fv_init")
+    return Solver(h, p, stream)
+
+
+def tt_fv_step(s: Solver, dt: float, nsteps: int = 1) -> int:
+    return _check(_lib.tt_fv_step(s.h, dt, nsteps), "tt_fv_step")
+
+
+def tt_fv_get_state(s: Solver) -> List[DeviceTT]:
+    n, cap = s.params.n, s.params.r_max
+    out = [DeviceTT(n, n, cap) for _ in range(3)]
+    arr = (TTMatrixC * 3)(*[t.c() for t in out])
+    _check(_lib.tt_fv_get_state(s.h, arr), "tt_fv_get_state")
+    for t, c in zip(out, arr):
+        t.rank = c.rank
+    return out
+
+
+def tt_fv_get_stats(s: Solver) -> dict:
+    st = StatsC()
+    _check(_lib.tt_fv_get_stats(s.h, ctypes.byref(st)), "tt_fv_get_stats")
+    return {"steps": st.steps, "ranks": list(st.ranks), "roundings": st.roundings,
+            "crosses": st.crosses, "last_taylor_terms": st.last_taylor_terms,
+            "last_taylor_err": st.last_taylor_err, "warnings": st.warnings,
+            "flops": st.flops, "bytes": st.bytes}
+
+
+def tt_fv_destroy(s: Solver) -> None:
+    s.close()

@@ -1,0 +1,218 @@
+"""GPU parity of each TT primitive against the CPU oracle (called through the C ABI)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import tt as ott
+from oracle import tt_fv as otf
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_03483_amd import ttfv
+    ttfv.load_library()
+    return ttfv
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.tt_ctx_create(1 << 30)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def decaying_tt(rng, n1, n2, r, decay=0.7):
+    A = rng.standard_normal((n1, r)) * decay ** np.arange(r)
+    B = rng.standard_normal((n2, r))
+    return A, B
+
+
+@pytest.mark.parametrize("scheme", [3, 5])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_recon_core_parity(lib, ctx, scheme, periodic):
+    import torch
+    _say(f"recon scheme={scheme} periodic={periodic}")
+    rng = np.random.default_rng(0)
+    n, r = 333, 7
+    core = rng.standard_normal((n, r))
+    sign = -1.0
+    fm, fp, q = lib.tt_recon_core(ctx, torch.from_numpy(core.T.copy()).cuda(), scheme, periodic,
+                                  sign)
+    name = {3: "upwind3", 5: "upwind5"}[scheme]
+    s = otf.TTSolver(n, name, True, periodic)
+    m_ref, p_ref = s.face_cores(core, sign)
+    q_ref = s.quad_core(core, sign)
+    assert np.max(np.abs(fm.T.cpu().numpy() - m_ref)) < 1e-14
+    assert np.max(np.abs(fp.T.cpu().numpy() - p_ref)) < 1e-14
+    assert np.max(np.abs(q.T.cpu().numpy() - q_ref)) < 1e-14
+
+
+@pytest.mark.parametrize("n1,n2,r,eps,rmax", [
+    (300, 200, 20, 1e-10, 32),      # exact path, rank from tolerance
+    (1000, 3000, 40, 1e-10, 8),     # exact path, cap binds
+    (1000, 3000, 300, 1e-10, 32),   # randomized path (R > sketch width)
+    (777, 1531, 1024, 1e-12, 16),   # randomized path, ragged sizes
+    (50, 40, 200, 0.0, 64),         # tiny modes: materialised
+])
+def test_round_parity(lib, ctx, n1, n2, r, eps, rmax):
+    _say(f"round {n1}x{n2} r={r} eps={eps} rmax={rmax}")
+    rng = np.random.default_rng(1)
+    A, B = decaying_tt(rng, n1, n2, r, decay=0.8)
+    x = lib.DeviceTT.from_factors(A, B)
+    y = lib.DeviceTT(n1, n2, rmax)
+    w, sig = lib.tt_round(ctx, x, eps, rmax, y)
+    ref = ott.tt_round(ott.TT(A, B), eps, rmax)
+    assert y.rank == ref.rank
+    F = A @ B.T
+    assert rel(y.full(), ref.full()) < 1e-10
+    # singular values of the kept part agree with the exact ones
+    s_ref = np.linalg.svd(ref.A, compute_uv=False) * 0 + np.linalg.norm(ref.A, axis=0)
+    assert np.allclose(sig, s_ref, rtol=1e-9, atol=1e-12 * np.linalg.norm(F))
+
+
+def test_hadamard_round_parity(lib, ctx):
+    _say("hadamard")
+    rng = np.random.default_rng(2)
+    n1, n2 = 1024, 3072
+    x = np.linspace(0, 1, n1)[:, None]
+    y = np.linspace(0, 1, n2)[:, None]
+    k1 = np.arange(1, 25)[None, :]
+    A1 = np.cos(np.pi * k1 * x) * (0.6 ** k1)
+    B1 = np.sin(np.pi * k1 * y + 0.3)
+    A2 = np.cos(np.pi * k1 * x + 0.1) * (0.5 ** k1)
+    B2 = np.cos(np.pi * k1 * y)
+    X = lib.DeviceTT.from_factors(A1, B1)
+    Z = lib.DeviceTT.from_factors(A2, B2)
+    Y = lib.DeviceTT(n1, n2, 32)
+    lib.tt_hadamard_round(ctx, X, Z, 1e-10, 32, Y)
+    ref = ott.tt_round(ott.hadamard(ott.TT(A1, B1), ott.TT(A2, B2)), 1e-10, 32)
+    assert Y.rank == ref.rank
+    assert rel(Y.full(), ref.full()) < 1e-10
+
+
+def test_reciprocal_parity(lib, ctx):
+    _say("reciprocal")
+    import synth
+    rng = np.random.default_rng(3)
+    f = synth.smooth_factored(rng, 900, 2700, 6, base=1.0)
+    X = lib.DeviceTT.from_factors(f.A, f.B)
+    Y = lib.DeviceTT(900, 2700, 32)
+    w, err, terms = lib.tt_reciprocal(ctx, X, 1e-10, 8, 32, Y)
+    ref, err_r, terms_r = ott.reciprocal(ott.TT(f.A, f.B), 1e-10, 8, 32)
+    assert terms == terms_r
+    assert abs(err - err_r) <= 1e-6 * err_r + 1e-15
+    assert rel(Y.full(), ref.full()) < 1e-10
+
+
+def test_maxvol_parity(lib, ctx):
+    import torch
+    _say("maxvol")
+    rng = np.random.default_rng(4)
+    for n, r in ((1000, 16), (3001, 40), (64, 64), (200, 1)):
+        Q = np.linalg.qr(rng.standard_normal((n, r)))[0]
+        I = lib.tt_maxvol(ctx, torch.from_numpy(Q.T.copy()).cuda(), 1.05, 100)
+        I_ref = ott.maxvol(Q, 1.05, 100)
+        assert sorted(I.tolist()) == sorted(I_ref.tolist())
+        B = Q @ np.linalg.inv(Q[I])
+        assert np.max(np.abs(B)) <= 1.05 + 1e-12
+
+
+def test_cross_identity_reproduces_low_rank(lib, ctx):
+    _say("cross identity")
+    rng = np.random.default_rng(5)
+    A, B = decaying_tt(rng, 700, 900, 6, decay=0.9)
+    X = lib.DeviceTT.from_factors(A, B)
+    Y = lib.DeviceTT(700, 900, 16)
+    w, J = lib.tt_cross(ctx, lib.TT_FN_IDENTITY, [X], [], 700, 900, [0, 1, 2], 1e-13, 16, 3, 4,
+                        7, Y)
+    assert rel(Y.full(), A @ B.T) < 1e-11
+
+
+def test_cross_lambda_parity(lib, ctx):
+    _say("cross lambda")
+    import synth
+    rng = np.random.default_rng(6)
+    n1, n2 = 256, 768
+    fh = synth.smooth_factored(rng, n1, n2, 5, base=1.0)
+    fm = synth.smooth_factored(rng, n1, n2, 7, base=0.0)
+    fh2 = synth.smooth_factored(rng, n1, n2, 5, base=1.0)
+    fm2 = synth.smooth_factored(rng, n1, n2, 7, base=0.0)
+    T = [ott.TT(f.A, f.B) for f in (fh, fm, fh2, fm2)]
+    D = [lib.DeviceTT.from_factors(f.A, f.B) for f in (fh, fm, fh2, fm2)]
+    g = 9.81
+    fun = otf._Lambda(T[0], T[1], T[2], T[3], g)
+    J0 = ott.initial_columns(T[1])
+    ref, J_ref = ott.cross(fun, n1, n2, J0, 1e-10, 32, 3, 4, key=99)
+    Y = lib.DeviceTT(n1, n2, 32)
+    w, J = lib.tt_cross(ctx, lib.TT_FN_LLF_LAMBDA, D, [g], n1, n2, J0.tolist(), 1e-10, 32, 3, 4,
+                        99, Y)
+    assert sorted(J.tolist()) == sorted(J_ref.tolist())
+    assert Y.rank == ref.rank
+    assert rel(Y.full(), ref.full()) < 1e-9
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_cross_weno_parity(lib, ctx, periodic):
+    _say(f"cross weno periodic={periodic}")
+    from oracle import stencils
+    rng = np.random.default_rng(7)
+    n = 96
+    x = (np.arange(n) + 0.5) / n
+    h = 1 + 0.5 * np.tanh((0.3 - np.sqrt((x[:, None] - 0.45) ** 2 + (x[None, :] - 0.55) ** 2))
+                         / 0.05)
+    u, s, vt = np.linalg.svd(h)
+    k = int(np.sum(s > 1e-10 * s[0]))
+    q = ott.TT(u[:, :k] * s[:k], vt[:k].T)
+    tab = stencils.tables("weno5")
+    nf = n if periodic else n + 1
+    eps_w = (1.0 / n) ** 2
+    sign = -1.0
+    for side, fn in ((-1, lib.TT_FN_WENO_FACE_M), (1, lib.TT_FN_WENO_FACE_P)):
+        fun = otf._WenoFace(q, periodic, sign, side, nf, tab, eps_w)
+        J0 = ott.initial_columns(q)
+        ref, J_ref = ott.cross(fun, nf, n, J0, 1e-10, 64, 3, 4, key=5)
+        Y = lib.DeviceTT(nf, n, 64)
+        X = lib.DeviceTT.from_factors(q.A, q.B)
+        w, J = lib.tt_cross(ctx, fn, [X], [1.0 if periodic else 0.0, sign, eps_w], nf, n,
+                            J0.tolist(), 1e-10, 64, 3, 4, 5, Y)
+        assert rel(Y.full(), ref.full()) < 1e-8
+    # step 2 on a face TT
+    v = ott.TT(rng.standard_normal((nf, 4)) * 0.1 + 1.0, np.cos(np.outer(x, np.arange(4))))
+    fun = otf._WenoQuad(v, periodic, sign, n, tab, eps_w)
+    y0 = ott.TT(v.A, np.repeat(v.B, 3, axis=0))
+    J0 = ott.initial_columns(y0)
+    ref, _ = ott.cross(fun, nf, 3 * n, J0, 1e-10, 64, 3, 4, key=9)
+    Y = lib.DeviceTT(nf, 3 * n, 64)
+    X = lib.DeviceTT.from_factors(v.A, v.B)
+    w, J = lib.tt_cross(ctx, lib.TT_FN_WENO_QUAD, [X], [1.0 if periodic else 0.0, sign, eps_w],
+                        nf, 3 * n, J0.tolist(), 1e-10, 64, 3, 4, 9, Y)
+    assert rel(Y.full(), ref.full()) < 1e-8
+
+
+def test_error_paths(lib, ctx):
+    _say("errors")
+    X = lib.DeviceTT(10, 10, 2)
+    X.rank = 3                      # rank above capacity
+    Y = lib.DeviceTT(10, 10, 4)
+    with pytest.raises(RuntimeError, match="rank"):
+        lib.tt_round(ctx, X, 1e-10, 4, Y)
+    X.rank = 1
+    with pytest.raises(RuntimeError, match="cap"):
+        lib.tt_round(ctx, X, 1e-10, 8, Y)
