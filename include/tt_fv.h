@@ -54,7 +54,8 @@ typedef struct tt_fv tt_fv;     /* solver: parameters, state, context   */
  * with a device arena of `arena_bytes` (allocated here, once). */
 int  tt_ctx_create(tt_ctx **out, size_t arena_bytes, void *hip_stream);
 void tt_ctx_destroy(tt_ctx *ctx);
-/* Rounding sketch width (0 = automatic: min(96, 2 r_max + 16)) and power iterations (>= 0). */
+/* Rounding sketch width (0 = automatic: min(96, max(2 r_max, 16))) and the number of
+ * subspace iterations always run (>= 0; more are added while the sketch has not converged). */
 int  tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters);
 
 /* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
@@ -133,6 +134,10 @@ typedef struct {
   int warnings;               /* OR of TT_W* bits since init                              */
   double flops;               /* algorithmic flop count since init                        */
   double bytes;               /* algorithmic HBM bytes since init                         */
+  double timed_ms;            /* event-timed duration of the timed kernel family          */
+  long long timed_launches;   /* its launches since tt_fv_time_kernel                     */
+  double timed_flops;         /* its algorithmic flops                                    */
+  double timed_bytes;         /* its algorithmic bytes                                    */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build
@@ -144,6 +149,10 @@ int  tt_fv_step(tt_fv *s, double dt, int nsteps);
 /* Copy the state into caller buffers (cap >= rank). */
 int  tt_fv_get_state(tt_fv *s, tt_matrix q[3]);
 int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
+/* Time every launch of one kernel family with HIP events on the stream it runs on (name:
+ * "jacobi", "tsqr_leaf_qr", "tsqr_node_qr", "tsqr_node_apply", "tsqr_leaf_apply", "gemm",
+ * "maxvol_greedy"; NULL or "" switches timing off) and reset the timed_* statistics. */
+int  tt_fv_time_kernel(tt_fv *s, const char *name);
 void tt_fv_destroy(tt_fv *s);
 
 const char *tt_last_error(void);

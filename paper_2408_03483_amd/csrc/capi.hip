@@ -12,6 +12,7 @@ void solver_step(Solver *s, double dt, int nsteps);
 void solver_get_state(Solver *s, tt_matrix q[3]);
 void solver_stats(Solver *s, tt_fv_stats *o);
 void solver_destroy(Solver *s);
+void solver_time_kernel(Solver *s, const char *name);
 
 namespace {
 thread_local std::string g_last_error;
@@ -38,6 +39,55 @@ void *Arena::alloc(size_t bytes) {
   top_ = a + bytes;
   hw_ = std::max(hw_, top_);
   return base_ + a;
+}
+
+void Ctx::sync() {
+  HIP_CHECK(hipStreamSynchronize(stream));
+  for (size_t i = 0; i < timer.pending.size(); ++i) {
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, timer.pending[i].first, timer.pending[i].second));
+    timer.ms += ms;
+    timer.flops += timer.pending_flops[i];
+    timer.bytes += timer.pending_bytes[i];
+    timer.launches++;
+    timer.spare.push_back(timer.pending[i]);
+  }
+  timer.pending.clear();
+  timer.pending_flops.clear();
+  timer.pending_bytes.clear();
+}
+
+Ctx::~Ctx() {
+  for (auto &e : timer.spare) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto &e : timer.pending) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+}
+
+TimedLaunch::TimedLaunch(Ctx &ctx, const char *name, double flops, double bytes)
+    : c(ctx), on(!ctx.timer.name.empty() && ctx.timer.name == name) {
+  if (!on) return;
+  if (c.timer.spare.empty()) {
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    c.timer.spare.push_back({a, b});
+  }
+  ev = c.timer.spare.back();
+  c.timer.spare.pop_back();
+  HIP_CHECK(hipEventRecord(ev.first, c.stream));
+  c.timer.pending_flops.push_back(flops);
+  c.timer.pending_bytes.push_back(bytes);
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (!on) return;
+  (void)hipEventRecord(ev.second, c.stream);
+  c.timer.pending.push_back(ev);
 }
 
 DTT view(const tt_matrix *m) {
@@ -306,6 +356,14 @@ int tt_fv_get_state(tt_fv *s, tt_matrix q[3]) {
   return guarded([&]() {
     TT_REQUIRE(s && q, "null argument");
     solver_get_state(s->s, q);
+    return 0;
+  });
+}
+
+int tt_fv_time_kernel(tt_fv *s, const char *name) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null solver");
+    solver_time_kernel(s->s, name ? name : "");
     return 0;
   });
 }

@@ -76,15 +76,34 @@ struct Counters {
   int warnings = 0;
 };
 
+// Optional event timing of one kernel family: launches of the family named in `name` are
+// bracketed by HIP events on their own stream; pairs are resolved at the next sync.
+struct KernelTimer {
+  std::string name;                         // empty: off
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, spare;
+  std::vector<double> pending_flops, pending_bytes;
+  double ms = 0, flops = 0, bytes = 0;
+  long long launches = 0;
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   Arena arena;
   int sketch_width = 0;     // 0: automatic
   int power_iters = 1;
-  double *host_pinned = nullptr;   // small pinned staging buffer for read-backs
-  size_t host_pinned_n = 0;
   Counters cnt;
-  void sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
+  KernelTimer timer;
+  void sync();
+  ~Ctx();
+};
+
+// RAII bracket around one launch: records events when `name` is the timed family
+struct TimedLaunch {
+  Ctx &c;
+  bool on;
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  TimedLaunch(Ctx &ctx, const char *name, double flops, double bytes);
+  ~TimedLaunch();
 };
 
 struct Solver;

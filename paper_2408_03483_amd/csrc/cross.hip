@@ -249,7 +249,10 @@ void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int 
   Scope sc(c.arena);
   double *R = c.arena.dalloc((size_t)n * r);
   copy_scale(c, R, n, Q, ldq, n, r, 1.0);
-  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(NT), 0, c.stream, R, n, r, n, rows_dev);
+  {
+    TimedLaunch tl(c, "maxvol_greedy", 4.0 * n * r * r, 8.0 * 3.0 * n * r);
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(NT), 0, c.stream, R, n, r, n, rows_dev);
+  }
   // B = Q Q[I]^-1
   double *QI = c.arena.dalloc((size_t)r * r);
   double *QIinv = c.arena.dalloc((size_t)r * r);

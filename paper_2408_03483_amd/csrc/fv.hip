@@ -470,6 +470,31 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->warnings = t.warnings;
   o->flops = t.flops;
   o->bytes = t.bytes;
+  KernelTimer *tm[8];
+  int nt = 0;
+  tm[nt++] = &s->c.timer;
+  for (int i = 0; i < s->pool->size(); ++i) tm[nt++] = &s->pool->ctx(i).timer;
+  o->timed_ms = 0;
+  o->timed_launches = 0;
+  o->timed_flops = 0;
+  o->timed_bytes = 0;
+  for (int i = 0; i < nt; ++i) {
+    o->timed_ms += tm[i]->ms;
+    o->timed_launches += tm[i]->launches;
+    o->timed_flops += tm[i]->flops;
+    o->timed_bytes += tm[i]->bytes;
+  }
+}
+
+void solver_time_kernel(Solver *s, const char *name) {
+  std::vector<Ctx *> cs{&s->c};
+  for (int i = 0; i < s->pool->size(); ++i) cs.push_back(&s->pool->ctx(i));
+  for (Ctx *c : cs) {
+    c->sync();
+    c->timer.name = name;
+    c->timer.ms = c->timer.flops = c->timer.bytes = 0;
+    c->timer.launches = 0;
+  }
 }
 
 void solver_destroy(Solver *s) { delete s; }

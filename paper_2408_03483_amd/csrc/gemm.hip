@@ -140,8 +140,11 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
   int kchunk = (K + S - 1) / S;
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   S = (K + kchunk - 1) / kchunk;
-  c.cnt.flops += 2.0 * M * N * K;
-  c.cnt.bytes += 8.0 * ((double)M * K + (double)K * N + (double)M * N);
+  const double fl = 2.0 * M * N * K;
+  const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
+  c.cnt.flops += fl;
+  c.cnt.bytes += by;
+  TimedLaunch tl(c, "gemm", fl, by);
   if (S == 1) {
     dispatch(c, transA, transB, dim3(tm, tn, 1), M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C,
              ldc, nullptr);

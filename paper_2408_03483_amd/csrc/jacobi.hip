@@ -181,6 +181,7 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
   TT_REQUIRE(m >= 1 && m <= 128, "jacobi_svd: m out of range");
   const int mm = (m + 1) & ~1;
   const size_t lds = ((size_t)mm * m + mm) * sizeof(double);
+  TimedLaunch tl(c, "jacobi", 22.0 * m * m * m, 8.0 * (2.0 * m * m + m));
   if (m <= 32) {
     set_lds(k_jacobi<2>, lds);
     hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);

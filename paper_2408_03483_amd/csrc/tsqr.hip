@@ -341,8 +341,13 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
   double *Vleaf = c.arena.dalloc((size_t)nleaf * bmax * m);
   double *tleaf = c.arena.dalloc((size_t)nleaf * m);
   double *Rleaf = c.arena.dalloc((size_t)nleaf * m * m);
-  hipLaunchKernelGGL((k_leaf_qr<RS, CS>), dim3(nleaf), dim3(NT), 0, c.stream, Y, n, m, ldy, nleaf,
-                     bmax, Vleaf, tleaf, Rleaf);
+  const double mm3 = (double)m * m * m;
+  {
+    TimedLaunch tl(c, "tsqr_leaf_qr", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
+                   8.0 * (2.0 * n * m + (double)nleaf * m * m));
+    hipLaunchKernelGGL((k_leaf_qr<RS, CS>), dim3(nleaf), dim3(NT), 0, c.stream, Y, n, m, ldy,
+                       nleaf, bmax, Vleaf, tleaf, Rleaf);
+  }
   const int levels = (int)pl.cnt.size() - 1;
   std::vector<double *> Vl(levels + 1, nullptr), tl(levels + 1, nullptr), Rl(levels + 1, nullptr);
   Rl[0] = Rleaf;
@@ -351,6 +356,9 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
     Vl[l] = c.arena.dalloc((size_t)cout * arity * m * m);
     tl[l] = c.arena.dalloc((size_t)cout * m);
     Rl[l] = c.arena.dalloc((size_t)cout * m * m);
+    const double rows_l = (double)pl.cnt[l - 1] * m;
+    TimedLaunch tq(c, "tsqr_node_qr", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * cout,
+                   8.0 * (2.0 * rows_l * m + (double)cout * m * m));
     hipLaunchKernelGGL((k_node_qr<RS, CS>), dim3(cout), dim3(NT), 0, c.stream, Rl[l - 1],
                        pl.cnt[l - 1], m, arity, Vl[l], tl[l], Rl[l]);
   }
@@ -363,6 +371,9 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
   for (int l = levels; l >= 1; --l) {
     const size_t lds = ((size_t)arity * m * m + m) * sizeof(double);
     set_lds(k_node_apply<RS, CS>, lds);
+    const double rows_l = (double)pl.cnt[l - 1] * m;
+    TimedLaunch ta(c, "tsqr_node_apply", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * pl.cnt[l],
+                   8.0 * (2.0 * rows_l * m + (double)pl.cnt[l] * m * m));
     hipLaunchKernelGGL((k_node_apply<RS, CS>), dim3(pl.cnt[l]), dim3(NT), lds, c.stream, Vl[l],
                        tl[l], pl.cnt[l - 1], m, arity, Zin, Z[which]);
     Zin = Z[which];
@@ -370,6 +381,8 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
   }
   const size_t lds = ((size_t)bmax * m + m) * sizeof(double);
   set_lds(k_leaf_apply<RS, CS>, lds);
+  TimedLaunch tl2(c, "tsqr_leaf_apply", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
+                  8.0 * (2.0 * n * m + (double)nleaf * m * m));
   hipLaunchKernelGGL((k_leaf_apply<RS, CS>), dim3(nleaf), dim3(NT), lds, c.stream, Vleaf, tleaf,
                      n, m, nleaf, bmax, Zin, Q, ldq);
 }

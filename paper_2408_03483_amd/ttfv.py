@@ -44,13 +44,15 @@ class StatsC(ctypes.Structure):
                 ("roundings", ctypes.c_longlong), ("crosses", ctypes.c_longlong),
                 ("last_taylor_terms", ctypes.c_int), ("last_taylor_err", ctypes.c_double),
                 ("warnings", ctypes.c_int), ("flops", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("timed_ms", ctypes.c_double),
+                ("timed_launches", ctypes.c_longlong), ("timed_flops", ctypes.c_double),
+                ("timed_bytes", ctypes.c_double)]
 
 
 EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_round",
            "tt_hadamard_round", "tt_reciprocal", "tt_maxvol", "tt_cross", "tt_recon_core",
            "tt_fv_init", "tt_fv_step", "tt_fv_get_state", "tt_fv_get_stats", "tt_fv_destroy",
-           "tt_last_error"]
+           "tt_fv_time_kernel", "tt_last_error"]
 
 _lib = None
 
@@ -81,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_fv_step.argtypes = [P, D, I]
     L.tt_fv_get_state.argtypes = [P, pM]
     L.tt_fv_get_stats.argtypes = [P, ctypes.POINTER(StatsC)]
+    L.tt_fv_time_kernel.argtypes = [P, ctypes.c_char_p]
     L.tt_fv_destroy.argtypes = [P]
     L.tt_fv_destroy.restype = None
     for name in EXPORTS:
@@ -298,7 +301,13 @@ def tt_fv_get_stats(s: Solver) -> dict:
     return {"steps": st.steps, "ranks": list(st.ranks), "roundings": st.roundings,
             "crosses": st.crosses, "last_taylor_terms": st.last_taylor_terms,
             "last_taylor_err": st.last_taylor_err, "warnings": st.warnings,
-            "flops": st.flops, "bytes": st.bytes}
+            "flops": st.flops, "bytes": st.bytes, "timed_ms": st.timed_ms,
+            "timed_launches": st.timed_launches, "timed_flops": st.timed_flops,
+            "timed_bytes": st.timed_bytes}
+
+
+def tt_fv_time_kernel(s: Solver, name: Optional[str]) -> None:
+    _check(_lib.tt_fv_time_kernel(s.h, (name or "").encode()), "tt_fv_time_kernel")
 
 
 def tt_fv_destroy(s: Solver) -> None:
