@@ -37,7 +37,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle step")
-    ap.add_argument("--timed-kernel", default="tsqr_node_qr")
+    ap.add_argument("--timed-kernel", default="jacobi",
+                    help="kernel family timed with HIP events ('' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
@@ -92,14 +93,16 @@ def main():
 
     for _ in range(max(args.warmup - 1, 0)):
         ttfv.tt_fv_step(s, st.dt, 1)
-    ttfv.tt_fv_time_kernel(s, args.timed_kernel)
+    if args.timed_kernel:
+        ttfv.tt_fv_time_kernel(s, args.timed_kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ttfv.tt_fv_step(s, st.dt, args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stats = ttfv.tt_fv_get_stats(s)
-    ttfv.tt_fv_time_kernel(s, None)
+    if args.timed_kernel:
+        ttfv.tt_fv_time_kernel(s, None)
     value = n * n * args.steps / elapsed
 
     roof = None

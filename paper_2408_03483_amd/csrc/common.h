@@ -90,7 +90,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   Arena arena;
   int sketch_width = 0;     // 0: automatic
-  int power_iters = 1;
+  int power_iters = 1;      // subspace iterations always run; more are added on demand
   Counters cnt;
   KernelTimer timer;
   void sync();

@@ -30,33 +30,54 @@ __device__ __forceinline__ bool better(const Best &a, const Best &b) {
   return a.j < b.j;
 }
 
-__device__ Best block_best(Best b, Best *red) {
-  const int tid = threadIdx.x;
-  red[tid] = b;
-  __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s && better(red[tid + s], red[tid])) red[tid] = red[tid + s];
-    __syncthreads();
+__device__ __forceinline__ Best wave_best(Best b) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    Best o;
+    o.v = __shfl_xor(b.v, off, 64);
+    o.i = __shfl_xor(b.i, off, 64);
+    o.j = __shfl_xor(b.j, off, 64);
+    if (better(o, b)) b = o;
   }
-  Best r = red[0];
+  return b;
+}
+
+// argmax over the block under the total order `better` (so the result is unique)
+__device__ Best block_best(Best b, Best *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  b = wave_best(b);
+  if (lane == 0) red[wave] = b;
+  __syncthreads();
+  if (wave == 0) {
+    Best x = lane < NT / 64 ? red[lane] : Best{-1.0, 0x7fffffff, 0x7fffffff};
+    x = wave_best(x);
+    if (lane == 0) red[NT / 64] = x;
+  }
+  __syncthreads();
+  Best r = red[NT / 64];
   __syncthreads();
   return r;
 }
 
-// greedy start: R (n x r, workspace copy of Q) is destroyed; rows -> rows_dev
+// greedy start: R (n x r, workspace copy of Q) is destroyed; rows -> rows_dev.
+// nrm (n doubles of workspace) holds the current squared residual norm of every row.
 __global__ __launch_bounds__(NT) void k_greedy(double *__restrict__ R, int n, int r, int ldr,
+                                               double *__restrict__ nrm,
                                                int *__restrict__ rows_dev) {
-  __shared__ Best red[NT];
+  __shared__ Best red[NT / 64 + 1];
   __shared__ double v[128];
+  for (int i = threadIdx.x; i < n; i += NT) {
+    double s = 0.0;
+    for (int c = 0; c < r; ++c) {
+      const double x = R[i + (size_t)c * ldr];
+      s += x * x;
+    }
+    nrm[i] = s;
+  }
   for (int t = 0; t < r; ++t) {
     Best b{-1.0, n, 0};
     for (int i = threadIdx.x; i < n; i += NT) {
-      double s = 0.0;
-      for (int c = 0; c < r; ++c) {
-        const double x = R[i + (size_t)c * ldr];
-        s += x * x;
-      }
-      Best cand{s, i, 0};
+      Best cand{nrm[i], i, 0};
       if (better(cand, b)) b = cand;
     }
     Best w = block_best(b, red);
@@ -68,7 +89,13 @@ __global__ __launch_bounds__(NT) void k_greedy(double *__restrict__ R, int n, in
     for (int i = threadIdx.x; i < n; i += NT) {
       double d = 0.0;
       for (int c = 0; c < r; ++c) d += R[i + (size_t)c * ldr] * v[c];
-      for (int c = 0; c < r; ++c) R[i + (size_t)c * ldr] -= d * v[c];
+      double s = 0.0;
+      for (int c = 0; c < r; ++c) {
+        const double x = R[i + (size_t)c * ldr] - d * v[c];
+        R[i + (size_t)c * ldr] = x;
+        s += x * x;
+      }
+      nrm[i] = s;
     }
     __syncthreads();
   }
@@ -78,7 +105,7 @@ __global__ __launch_bounds__(NT) void k_greedy(double *__restrict__ R, int n, in
 __global__ __launch_bounds__(NT) void k_maxvol_swaps(double *__restrict__ B, int n, int r,
                                                      double tau, int maxit,
                                                      int *__restrict__ rows_dev) {
-  __shared__ Best red[NT];
+  __shared__ Best red[NT / 64 + 1];
   __shared__ double bi[128];
   for (int it = 0; it < maxit; ++it) {
     Best b{-1.0, n, r};
@@ -248,10 +275,11 @@ void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int 
   TT_REQUIRE(r >= 1 && r <= 96 && n >= r, "maxvol: need n >= r, 1 <= r <= 96");
   Scope sc(c.arena);
   double *R = c.arena.dalloc((size_t)n * r);
+  double *nrm = c.arena.dalloc((size_t)n);
   copy_scale(c, R, n, Q, ldq, n, r, 1.0);
   {
     TimedLaunch tl(c, "maxvol_greedy", 4.0 * n * r * r, 8.0 * 3.0 * n * r);
-    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(NT), 0, c.stream, R, n, r, n, rows_dev);
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(NT), 0, c.stream, R, n, r, n, nrm, rows_dev);
   }
   // B = Q Q[I]^-1
   double *QI = c.arena.dalloc((size_t)r * r);

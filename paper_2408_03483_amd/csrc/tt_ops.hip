@@ -157,6 +157,12 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       if (s[0] == 0.0) break;
       const int k = trunc_rank(s, eps, rmax, nullptr);
       if (k >= m) break;
+      // (a) the sketch reached round-off: beyond m - p the captured spectrum is below
+      //     1e-14 s_0, so with oversampling p the range error is at that level;
+      // (b) otherwise the subspace iteration has contracted the discarded directions by
+      //     (s_m / s_k)^(2q+1) <= 1e-13.
+      const int pover = std::max(8, m / 4);
+      if (m - pover > k && s[m - pover] <= 1e-14 * s[0]) break;
       const double ratio = s[m - 1] / s[k - 1];
       if (std::pow(ratio, 2 * q + 1) <= 1e-13) break;
       US = nullptr;   // basis changes below: the SVD must be recomputed
