@@ -98,6 +98,8 @@ int tt_maxvol(tt_ctx *ctx, const double *q, int n, int r, int ldq, double tau, i
 #define TT_FN_WENO_FACE_P 3 /* as above from the right (cell f), mirrored stencils           */
 #define TT_FN_WENO_QUAD  4  /* inputs[0] = face TT v (n_f x n); entry (f, j*3+m): WENO5 value
                                at Gauss point m of cell j; fparams = {periodic, sign, eps_w} */
+#define TT_FN_RECIP      5  /* inputs[0] = X; entry 1 / X(i,j) (the cross alternative to
+                               Algorithm 1 that Section 4.2 names)                          */
 int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const double *fparams,
              int n1, int n2, const int *J0, int nJ0, double eps, int r_max, int sweeps,
              int kick, uint64_t key, tt_matrix *y, int *J_out, int *nJ_out);
@@ -122,6 +124,7 @@ typedef struct {
   int taylor_terms;   /* Algorithm 1 terms including the constant (nonlinear)              */
   int cross_sweeps;   /* maxvol cross sweeps                                               */
   int cross_kick;     /* fresh columns per non-final sweep                                 */
+  int recip;          /* 1/h: 0 = Taylor series (Algorithm 1), 1 = cross of 1/x            */
 } tt_fv_params;
 
 typedef struct {

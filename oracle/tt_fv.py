@@ -17,7 +17,8 @@ One evaluation of L(Q) (Sections 4.1-4.3):
                     once on the merged column index j*nq + m) (Section 4.3.2).
     flux            linear: the LLF flux assembled directly from the states, no rounding
                     (Section 4.2, lambda = sqrt(gH)).
-                    nonlinear, for each side s: 1/h by Algorithm 1, u = round(hu o 1/h),
+                    nonlinear, for each side s: 1/h by Algorithm 1 (or by a cross of 1/x, the alternative
+                    Section 4.2 names), u = round(hu o 1/h),
                     w = round(hv o 1/h), P1 = round(hu o u), P2 = round(h o h),
                     F2 = round(P1 + g/2 P2), F3 = round(hu o w), F1 = hu;
                     lambda by one cross of max(|hu-/h-| + sqrt(g h-), |hu+/h+| + sqrt(g h+));
@@ -70,6 +71,19 @@ class _Lambda:
 
     def rows(self, I):
         return self._f(*[X.A[I] @ X.B.T for X in self.t])
+
+
+class _Recip:
+    """Entries 1/x of one TT (the cross alternative to Algorithm 1 named in Section 4.2)."""
+
+    def __init__(self, x: TT):
+        self.x = x
+
+    def cols(self, J):
+        return 1.0 / (self.x.A @ self.x.B[J].T)
+
+    def rows(self, I):
+        return 1.0 / (self.x.A[I] @ self.x.B.T)
 
 
 class _WenoFace:
@@ -125,11 +139,12 @@ class TTSolver:
     def __init__(self, n: int, scheme: str, nonlinear: bool, periodic: bool = True,
                  g: float = 9.81, H: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                  rmax: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
-                 cross_kick: int = 4, cross_full: bool = False):
+                 cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor"):
         self.n, self.scheme, self.nonlinear, self.periodic = n, scheme, nonlinear, periodic
         self.g, self.H, self.f = g, H, f
         self.eps, self.rmax, self.K = eps, rmax, taylor_terms
         self.sweeps, self.kick, self.cross_full = cross_sweeps, cross_kick, cross_full
+        self.recip = recip
         self.dx = 1.0 / n
         self.tab = stencils.tables(scheme)
         self.nq = self.tab["nq"]
@@ -219,10 +234,13 @@ class TTSolver:
             return [F0, F1, F2]
         g = self.g
         F = {}
-        for s, (h, m, t) in (("m", qm), ("p", qp)):
-            rh, err, terms = reciprocal(h, self.eps, self.K, self.rmax)
-            self.stats["taylor_terms"].append(terms)
-            self.stats["taylor_err"].append(err)
+        for si, (s, (h, m, t)) in enumerate((("m", qm), ("p", qp))):
+            if self.recip == "cross":
+                rh = self._cross(_Recip(h), self.nf, self.n * self.nq, h, site_base + 8 + si)
+            else:
+                rh, err, terms = reciprocal(h, self.eps, self.K, self.rmax)
+                self.stats["taylor_terms"].append(terms)
+                self.stats["taylor_err"].append(err)
             u = self.rnd(hadamard(m, rh))
             w = self.rnd(hadamard(t, rh))
             P1 = self.rnd(hadamard(m, u))

@@ -257,7 +257,8 @@ int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const d
     fs.wt = &wt;
     switch (fn) {
       case TT_FN_IDENTITY:
-        TT_REQUIRE(n_inputs == 1, "identity: one input");
+      case TT_FN_RECIP:
+        TT_REQUIRE(n_inputs == 1, "identity/recip: one input");
         check_matrix(&inputs[0], "input", true);
         TT_REQUIRE(inputs[0].n1 == n1 && inputs[0].n2 == n2, "identity: input shape");
         fs.n_in = 1;

@@ -196,6 +196,8 @@ __device__ double fiber_entry(const FibArgs &f, const WenoArgs &w, int i, int j)
   switch (f.fn) {
     case TT_FN_IDENTITY:
       return dotrow(f.in[0].A, f.in[0].lda, i, f.in[0].B, f.in[0].ldb, j, f.in[0].r);
+    case TT_FN_RECIP:
+      return 1.0 / dotrow(f.in[0].A, f.in[0].lda, i, f.in[0].B, f.in[0].ldb, j, f.in[0].r);
     case TT_FN_LLF_LAMBDA: {
       double x[4];
       for (int t = 0; t < 4; ++t)

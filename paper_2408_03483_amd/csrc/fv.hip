@@ -9,7 +9,8 @@
 //                   Algorithm 3 (two crosses over five y-shifts, all Gauss points at once on
 //                   the merged column index j*nq + m) (Section 4.3.2).
 //   flux            linear: LLF assembled directly, never rounded (Section 4.2).
-//                   nonlinear, per side: 1/h by Algorithm 1, u = round(hu o 1/h),
+//                   nonlinear, per side: 1/h by Algorithm 1 or by a cross of 1/x (the
+//                   alternative Section 4.2 names), u = round(hu o 1/h),
 //                   w = round(hv o 1/h), P1 = round(hu o u), P2 = round(h o h),
 //                   F2 = round(P1 + g/2 P2), F3 = round(hu o w); lambda by one cross of
 //                   max(|hu-/h-| + sqrt(g h-), |hu+/h+| + sqrt(g h+));
@@ -208,12 +209,19 @@ struct Solver {
 
   // ---- nonlinear flux pieces ----------------------------------------------------------
   // one side: 1/h (Algorithm 1), u, w, P1, P2 -> F2 = round(P1 + g/2 P2), F3 = round(m o w)
-  void side_fluxes(Ctx &w, const DTT &h, const DTT &m, const DTT &t, DTT &F2, DTT &F3) {
+  void side_fluxes(Ctx &w, const DTT &h, const DTT &m, const DTT &t, int recip_site, DTT &F2,
+                   DTT &F3) {
     DTT rh = alloc(w, h.n1, h.n2, p.r_max);
-    double err = 0;
-    int terms = 0;
-    reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms);
-    {
+    if (p.recip == 1) {
+      FiberSpec fr;
+      fr.fn = TT_FN_RECIP;
+      fr.n_in = 1;
+      fr.in[0] = {h.A, h.B, h.n1, h.n2, h.r};
+      cross(w, fr, h.n1, h.n2, h, recip_site, rh);
+    } else {
+      double err = 0;
+      int terms = 0;
+      reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms);
       std::lock_guard<std::mutex> lk(mu);
       last_err = err;
       last_terms = terms;
@@ -288,9 +296,9 @@ struct Solver {
       std::vector<Pool::Task> tasks;
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s)
-          tasks.push_back([this, &qm, &qp, &F, d, s](Ctx &w) {
+          tasks.push_back([this, &qm, &qp, &F, &sb, d, s](Ctx &w) {
             const DTT *q = s == 0 ? qm[d] : qp[d];
-            side_fluxes(w, q[0], q[1], q[2], F[d][s][1], F[d][s][2]);
+            side_fluxes(w, q[0], q[1], q[2], sb[d] + 8 + s, F[d][s][1], F[d][s][2]);
           });
       // phase A also carries the two lambda crosses (independent of the products)
       for (int d = 0; d < 2; ++d)
@@ -387,7 +395,11 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   TT_REQUIRE(p->scheme == 3 || p->scheme == 5 || p->scheme == 55, "tt_fv_init: bad scheme");
   TT_REQUIRE(p->r_max >= 1 && p->r_max <= 64, "tt_fv_init: r_max must be in [1, 64]");
   TT_REQUIRE(p->eps >= 0.0, "tt_fv_init: eps < 0");
-  TT_REQUIRE(!p->nonlinear || p->taylor_terms >= 1, "tt_fv_init: taylor_terms < 1");
+  TT_REQUIRE(!p->nonlinear || p->taylor_terms >= 1 || p->recip == 1,
+             "tt_fv_init: taylor_terms < 1");
+  TT_REQUIRE(p->recip == 0 || p->recip == 1, "tt_fv_init: recip must be 0 or 1");
+  TT_REQUIRE(p->recip == 0 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
+             "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   for (int v = 0; v < 3; ++v) {

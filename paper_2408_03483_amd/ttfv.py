@@ -21,6 +21,7 @@ TT_FN_LLF_LAMBDA = 1
 TT_FN_WENO_FACE_M = 2
 TT_FN_WENO_FACE_P = 3
 TT_FN_WENO_QUAD = 4
+TT_FN_RECIP = 5
 
 TT_WRANKCAP = 1
 TT_WNOCONV = 2
@@ -36,7 +37,7 @@ class ParamsC(ctypes.Structure):
                 ("periodic", ctypes.c_int), ("g", ctypes.c_double), ("H0", ctypes.c_double),
                 ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
-                ("cross_kick", ctypes.c_int)]
+                ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):
@@ -269,11 +270,12 @@ class Solver:
 def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequence[DeviceTT],
                g: float = 9.81, H0: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
-               cross_kick: int = 4, stream=None, arena_bytes: int = 4 << 30) -> Solver:
+               cross_kick: int = 4, recip: str = "taylor", stream=None,
+               arena_bytes: int = 4 << 30) -> Solver:
     L = load_library()
     _torch()
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
-                r_max, taylor_terms, cross_sweeps, cross_kick)
+                r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),

@@ -198,3 +198,22 @@ def test_linear_gaussian_tt_run_tracks_grid_run():
     rel = np.linalg.norm(Q[0].full() - U[0]) / np.linalg.norm(U[0])
     assert rel < 1e-3
     assert all(r <= 8 for r in ts.stats["ranks"][-1])
+
+
+@pytest.mark.parametrize("scheme", ["upwind5", "weno5"])
+def test_tt_step_with_cross_reciprocal_equals_grid_step(scheme):
+    """1/h by a full-rank cross of 1/x (Section 4.2's alternative to Algorithm 1) reproduces the
+    grid step on a dam break with walls, where the Taylor series would diverge."""
+    import synth
+    st = synth.dam_break(seed=1, n=12, rmax=12, eps=0.0, width=0.1)
+    U = st.fields
+    xt = 1 - U[0] / U[0].mean()
+    assert np.max(np.abs(xt)) > 0.3
+    gs = fv_grid.GridSolver(12, scheme, True, False)
+    ts = tt_fv.TTSolver(12, scheme, True, False, eps=0.0, rmax=10 ** 6, cross_full=True,
+                        recip="cross")
+    Ug = gs.step(U, 1e-3)
+    Qt = ts.step([_svd_tt(u) for u in U], 1e-3)
+    for q, u in zip(Qt, Ug):
+        if np.linalg.norm(u) > 0:
+            assert np.linalg.norm(q.full() - u) <= 1e-11 * np.linalg.norm(Ug[0])
