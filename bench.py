@@ -13,6 +13,16 @@ the host, is the cpu_baseline.  The dominant kernel is timed live with HIP event
 streams it runs on, which gives the roofline line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--timed-kernel NAME]
+                    [--workload bumps1024 | dambreak2048 | ensemble] [--members 64]
+
+Other workloads (not the headline line): dambreak2048 = WENO5 through maxvol crosses, 1/h by
+cross, walls, rank cap 64, tol 1e-8; ensemble = independent nonlinear members of 256^2,
+512^2 or 1024^2 cells with rank caps 8..48 advanced together on shared worker streams,
+reported against the same members stepped one at a time.
+
+Independent chains of TT operations run on several HIP streams; the runtime maps streams to
+GPU_MAX_HW_QUEUES hardware queues (4 by default), which would serialise them, so this script
+raises it before HIP starts.
 """
 import argparse
 import json
@@ -23,6 +33,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+if "--workload" in sys.argv and "ensemble" in sys.argv:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+else:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA peak"
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector (no MFMA used by this kernel)
@@ -39,6 +53,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle step")
     ap.add_argument("--timed-kernel", default="jacobi",
                     help="kernel family timed with HIP events ('' = none)")
+    ap.add_argument("--workload", default="bumps1024",
+                    choices=["bumps1024", "dambreak2048", "ensemble"])
+    ap.add_argument("--members", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
@@ -53,6 +70,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "ensemble":
+        return ensemble(args)
+    if args.workload == "dambreak2048":
+        return dambreak(args)
     n, rmax, eps, K = args.n, 32, 1e-10, 8
     st = synth.nonlinear_bumps(seed=0, n=n, rmax=rmax, eps=eps)
     dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
@@ -129,6 +150,138 @@ def main():
     }
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def _roofline(stats, kernel, elapsed):
+    if not stats["timed_launches"] or stats["timed_ms"] <= 0:
+        return None
+    avg_ms = stats["timed_ms"] / stats["timed_launches"]
+    fl = stats["timed_flops"] / stats["timed_launches"]
+    achieved = fl / (avg_ms * 1e-3) / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved,
+            "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+            "avg_launch_us": avg_ms * 1e3, "launches": stats["timed_launches"],
+            "share_of_step": stats["timed_ms"] / (elapsed * 1e3), "alg_flops_per_launch": fl}
+
+
+def dambreak(args):
+    """WENO5 dam break, 2048^2, walls, rank cap 64, tol 1e-8, 1/h by cross."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2408_03483_amd import ttfv
+    n, rmax, eps = 2048, 64, 1e-8
+    st = synth.dam_break(seed=0, n=n, rmax=rmax, eps=eps)
+    dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+    s = ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
+                        recip="cross")
+    for _ in range(args.warmup):
+        ttfv.tt_fv_step(s, st.dt, 1)
+    if args.timed_kernel:
+        ttfv.tt_fv_time_kernel(s, args.timed_kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ttfv.tt_fv_step(s, st.dt, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = ttfv.tt_fv_get_stats(s)
+    out = {"metric": METRIC, "value": n * n * args.steps / elapsed, "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"dam_break_weno5_{n}", "grid": f"{n}x{n}", "scheme": "weno5",
+                      "bc": "walls", "r_max": rmax, "eps": eps, "reciprocal": "cross",
+                      "cross_sweeps": 3, "seed": 0},
+           "roofline": _roofline(stats, args.timed_kernel, elapsed), "cpu_baseline": None,
+           "ranks": stats["ranks"], "crosses": stats["crosses"]}
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+def ensemble(args):
+    """Independent nonlinear members advanced together; the (workers, concurrency) pair is
+    picked by timing one step of each candidate on the first eight members."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2408_03483_amd import ttfv
+    M = args.members
+    rng = np.random.default_rng(2024)
+    sizes = [int(x) for x in rng.choice([256, 512, 1024], size=M)]
+    ranks = [int(x) for x in rng.integers(8, 49, size=M)]
+    states = []
+    for m in range(M):
+        states.append(synth.nonlinear_bumps(seed=1000 + m, n=sizes[m], rmax=ranks[m], eps=1e-10))
+        if m % 8 == 7:
+            print(f"[ensemble] generated {m + 1}/{M} members", file=sys.stderr, flush=True)
+    cells = float(sum(n * n for n in sizes))
+
+    def make(idx, workers):
+        out = []
+        for m in idx:
+            st, r = states[m], ranks[m]
+            dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=r) for f in st.tt]
+            out.append(ttfv.tt_fv_init(st.n, "upwind5", True, True, dev, g=st.g, eps=1e-10,
+                                       r_max=r, taylor_terms=8, workers=workers,
+                                       arena_bytes=1 << 28))
+        return out
+
+    # members one at a time (each with its own worker streams)
+    alone = make(range(M), 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m, s in enumerate(alone):
+        ttfv.tt_fv_step(s, states[m].dt, 1)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    ref = [[q.full() for q in ttfv.tt_fv_get_state(s)] for s in alone[:4]]
+    for s in alone:
+        s.close()
+    # autotune (workers, concurrency) on the first 8 members
+    best = None
+    for workers, conc in ((8, 8), (12, 16), (16, 32)):
+        ens = ttfv.tt_ens_create(workers=workers, arena_bytes_per_worker=1 << 30)
+        mem = make(range(min(8, M)), -1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ttfv.tt_ens_step(ens, mem, [states[m].dt for m in range(len(mem))], 1, conc)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        for s in mem:
+            s.close()
+        ens.close()
+        if best is None or t < best[0]:
+            best = (t, workers, conc)
+    _, workers, conc = best
+    ens = ttfv.tt_ens_create(workers=workers, arena_bytes_per_worker=1 << 30)
+    mem = make(range(M), -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ttfv.tt_ens_step(ens, mem, [st.dt for st in states], args.steps, conc)
+    torch.cuda.synchronize()
+    t_ens = (time.perf_counter() - t0) / args.steps
+    # after `steps` ensemble steps the members are ahead of the one-step references, so the
+    # equality check is made on a fresh ensemble of the first four members for one step
+    for s in mem:
+        s.close()
+    mem4 = make(range(min(4, M)), -1)
+    ttfv.tt_ens_step(ens, mem4, [states[m].dt for m in range(len(mem4))], 1, conc)
+    same = all(np.array_equal(q.full(), r) for s, rr in zip(mem4, ref)
+               for q, r in zip(ttfv.tt_fv_get_state(s), rr))
+    for s in mem4:
+        s.close()
+    ens.close()
+    out = {"metric": METRIC, "value": cells / t_ens, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 0, "ms_per_step": t_ens * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"ensemble_{M}", "members": M, "sizes": sizes,
+                      "r_max": ranks, "eps": 1e-10, "scheme": "upwind5",
+                      "autotuned": {"workers": workers, "concurrency": conc}},
+           "sequential": {"value": cells / t_seq, "s_per_step": t_seq},
+           "speedup_vs_sequential": t_seq / t_ens, "members_equal_alone": bool(same)}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

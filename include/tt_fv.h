@@ -125,6 +125,8 @@ typedef struct {
   int cross_sweeps;   /* maxvol cross sweeps                                               */
   int cross_kick;     /* fresh columns per non-final sweep                                 */
   int recip;          /* 1/h: 0 = Taylor series (Algorithm 1), 1 = cross of 1/x            */
+  int workers;        /* own worker streams: 0 = default (6), k = k, -1 = none (the solver
+                         then steps only inside an ensemble, tt_ens_step)                 */
 } tt_fv_params;
 
 typedef struct {
@@ -157,6 +159,18 @@ int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
  * "maxvol_greedy"; NULL or "" switches timing off) and reset the timed_* statistics. */
 int  tt_fv_time_kernel(tt_fv *s, const char *name);
 void tt_fv_destroy(tt_fv *s);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched ensemble: independent solvers advanced together.  Their independent chains of TT
+ * operations share one pool of `workers` worker streams; `concurrency` host threads take
+ * the members in decreasing cost order (n r_max^4, longest first) and step each one.  A
+ * member's result is the same as stepping it alone.  Members must not be stepped
+ * elsewhere during the call. */
+typedef struct tt_ens tt_ens;
+int  tt_ens_create(tt_ens **out, int workers, size_t arena_bytes_per_worker);
+int  tt_ens_step(tt_ens *e, tt_fv *const *members, int count, const double *dts, int nsteps,
+                 int concurrency);
+void tt_ens_destroy(tt_ens *e);
 
 const char *tt_last_error(void);
 

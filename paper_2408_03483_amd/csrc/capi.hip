@@ -13,6 +13,11 @@ void solver_get_state(Solver *s, tt_matrix q[3]);
 void solver_stats(Solver *s, tt_fv_stats *o);
 void solver_destroy(Solver *s);
 void solver_time_kernel(Solver *s, const char *name);
+struct Ensemble;
+Ensemble *ensemble_create(int workers, size_t arena_bytes);
+void ensemble_destroy(Ensemble *e);
+void ensemble_step(Ensemble *e, Solver *const *members, int count, const double *dts,
+                   int nsteps, int concurrency);
 
 namespace {
 thread_local std::string g_last_error;
@@ -116,6 +121,10 @@ struct tt_ctx {
 
 struct tt_fv {
   ttfv::Solver *s;
+};
+
+struct tt_ens {
+  ttfv::Ensemble *e;
 };
 
 using namespace ttfv;
@@ -375,6 +384,42 @@ int tt_fv_get_stats(tt_fv *s, tt_fv_stats *out) {
     solver_stats(s->s, out);
     return 0;
   });
+}
+
+int tt_ens_create(tt_ens **out, int workers, size_t arena_bytes_per_worker) {
+  return guarded([&]() {
+    TT_REQUIRE(out, "tt_ens_create: null out");
+    Ensemble *e = ensemble_create(workers, arena_bytes_per_worker);
+    *out = new tt_ens{e};
+    return 0;
+  });
+}
+
+int tt_ens_step(tt_ens *e, tt_fv *const *members, int count, const double *dts, int nsteps,
+                int concurrency) {
+  return guarded([&]() {
+    TT_REQUIRE(e && members && count >= 1, "tt_ens_step: null argument");
+    TT_REQUIRE(nsteps >= 0, "tt_ens_step: nsteps < 0");
+    std::vector<Solver *> m(count);
+    for (int i = 0; i < count; ++i) {
+      TT_REQUIRE(members[i], "tt_ens_step: null member");
+      m[i] = members[i]->s;
+    }
+    ensemble_step(e->e, m.data(), count, dts, nsteps, concurrency);
+    int w = 0;
+    for (int i = 0; i < count; ++i) {
+      tt_fv_stats st{};
+      solver_stats(m[i], &st);
+      w |= st.warnings & (TT_WRANKCAP | TT_WNOCONV);
+    }
+    return w;
+  });
+}
+
+void tt_ens_destroy(tt_ens *e) {
+  if (!e) return;
+  ensemble_destroy(e->e);
+  delete e;
 }
 
 void tt_fv_destroy(tt_fv *s) {

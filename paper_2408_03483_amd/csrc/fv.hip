@@ -28,6 +28,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <thread>
 
 namespace ttfv {
 
@@ -39,7 +40,8 @@ const double SIGN_TANGENT[3] = {1.0, 1.0, -1.0};
 struct Solver {
   tt_fv_params p{};
   Ctx c;                       // caller's stream; owns the state and phase outputs
-  std::unique_ptr<Pool> pool;  // worker streams for independent chains
+  std::unique_ptr<Pool> pool;  // own worker streams for independent chains (may be empty)
+  Pool *exec = nullptr;        // pool the phases run on: the own pool or an ensemble's
   StencilSet st;
   WenoTables wt{};
   int n = 0, nf = 0, nq = 0;
@@ -263,7 +265,7 @@ struct Solver {
             tasks.push_back([this, &QD, &qm, &qp, &sb, d, v, side](Ctx &w) {
               weno_state(w, QD[d][v], v, side, sb[d], side == 0 ? qm[d][v] : qp[d][v]);
             });
-      pool->run(std::move(tasks));
+      exec->run(std::move(tasks));
     }
     if (!p.nonlinear) {
       const double g = p.g, H = p.H0, cw = std::sqrt(g * H);
@@ -312,7 +314,7 @@ struct Solver {
           fl.g = p.g;
           cross(w, fl, nf, n * nq, y0, sb[d], lam[d]);
         });
-      pool->run(std::move(tasks));
+      exec->run(std::move(tasks));
     }
     // phase B: dissipation, LLF flux and finish, per direction and variable
     for (int d = 0; d < 2; ++d)
@@ -327,7 +329,7 @@ struct Solver {
             DTT Fh = rnd(w, add(w, {{0.5, F[d][0][v]}, {0.5, F[d][1][v]}, {-0.5, D}}));
             finish(w, Fh, dF[d][v]);
           });
-      pool->run(std::move(tasks));
+      exec->run(std::move(tasks));
     }
   }
 
@@ -350,7 +352,7 @@ struct Solver {
         round_tt(w, add(w, terms), p.eps, p.r_max, out[v], nullptr);
       });
     c.sync();
-    pool->run(std::move(tasks));
+    exec->run(std::move(tasks));
   }
 
   void combine(const DTT *A, double a, const DTT *B, double b, DTT *out) {
@@ -360,7 +362,7 @@ struct Solver {
         round_tt(w, add(w, {{a, A[v]}, {b, B[v]}}), p.eps, p.r_max, out[v], nullptr);
       });
     c.sync();
-    pool->run(std::move(tasks));
+    exec->run(std::move(tasks));
   }
 
   void step(double dt) {
@@ -398,6 +400,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   TT_REQUIRE(!p->nonlinear || p->taylor_terms >= 1 || p->recip == 1,
              "tt_fv_init: taylor_terms < 1");
   TT_REQUIRE(p->recip == 0 || p->recip == 1, "tt_fv_init: recip must be 0 or 1");
+  TT_REQUIRE(p->workers >= -1 && p->workers <= 16, "tt_fv_init: workers must be in [-1, 16]");
   TT_REQUIRE(p->recip == 0 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
@@ -415,7 +418,11 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->c.arena.init(ab);
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
-    s->pool = std::make_unique<Pool>(4, ab, dev);
+    const int nw = p->workers == 0 ? 6 : p->workers;
+    if (nw > 0) {
+      s->pool = std::make_unique<Pool>(nw, ab, dev);
+      s->exec = s->pool.get();
+    }
     s->st = derive_stencils(p->scheme == 3 ? 3 : 5);
     s->wt = derive_weno_tables();
     s->n = p->n;
@@ -446,7 +453,79 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
 
 void solver_step(Solver *s, double dt, int nsteps) {
   TT_REQUIRE(nsteps >= 0 && std::isfinite(dt), "tt_fv_step: bad dt or nsteps");
+  TT_REQUIRE(s->exec, "tt_fv_step: solver made with workers = -1 steps only inside an ensemble");
   for (int k = 0; k < nsteps; ++k) s->step(dt);
+}
+
+// ---- ensemble: members share one pool; host threads take members in cost order --------
+struct Ensemble {
+  std::unique_ptr<Pool> pool;
+};
+
+Ensemble *ensemble_create(int workers, size_t arena_bytes) {
+  TT_REQUIRE(workers >= 1 && workers <= 32, "tt_ens_create: workers must be in [1, 32]");
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  Ensemble *e = new Ensemble();
+  e->pool = std::make_unique<Pool>(workers, arena_bytes ? arena_bytes : ((size_t)1 << 30), dev);
+  return e;
+}
+
+void ensemble_destroy(Ensemble *e) { delete e; }
+
+void ensemble_step(Ensemble *e, Solver *const *members, int count, const double *dts,
+                   int nsteps, int concurrency) {
+  TT_REQUIRE(count >= 1 && members && dts, "tt_ens_step: no members");
+  TT_REQUIRE(concurrency >= 1 && concurrency <= 256, "tt_ens_step: concurrency in [1, 256]");
+  for (int i = 0; i < count; ++i) {
+    TT_REQUIRE(members[i], "tt_ens_step: null member");
+    TT_REQUIRE(std::isfinite(dts[i]), "tt_ens_step: bad dt");
+  }
+  // longest-processing-time first: a Hadamard rounding costs ~ n r^4
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const double r = members[i]->p.r_max, n = members[i]->n;
+    return n * r * r * r * r;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<Pool *> saved(count);
+  for (int i = 0; i < count; ++i) {
+    saved[i] = members[i]->exec;
+    members[i]->exec = e->pool.get();
+  }
+  std::mutex qm;
+  size_t next = 0;
+  std::exception_ptr err;
+  auto worker = [&]() {
+    for (;;) {
+      int idx;
+      {
+        std::lock_guard<std::mutex> lk(qm);
+        if (next >= order.size() || err) return;
+        idx = order[next++];
+      }
+      try {
+        for (int k = 0; k < nsteps; ++k) members[idx]->step(dts[idx]);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(qm);
+        if (!err) err = std::current_exception();
+        return;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  const int nt = std::min(concurrency, count);
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, dev]() {
+      (void)hipSetDevice(dev);
+      worker();
+    });
+  for (auto &t : th) t.join();
+  for (int i = 0; i < count; ++i) members[i]->exec = saved[i];
+  if (err) std::rethrow_exception(err);
 }
 
 void solver_get_state(Solver *s, tt_matrix q[3]) {
@@ -466,7 +545,8 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->steps = s->step_index;
   for (int v = 0; v < 3; ++v) o->ranks[v] = s->Q[v].r;
   Counters t = s->c.cnt;
-  for (int i = 0; i < s->pool->size(); ++i) {
+  const int npool = s->pool ? s->pool->size() : 0;
+  for (int i = 0; i < npool; ++i) {
     const Counters &w = s->pool->ctx(i).cnt;
     t.roundings += w.roundings;
     t.crosses += w.crosses;
@@ -485,7 +565,7 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   KernelTimer *tm[8];
   int nt = 0;
   tm[nt++] = &s->c.timer;
-  for (int i = 0; i < s->pool->size(); ++i) tm[nt++] = &s->pool->ctx(i).timer;
+  for (int i = 0; i < npool && nt < 8; ++i) tm[nt++] = &s->pool->ctx(i).timer;
   o->timed_ms = 0;
   o->timed_launches = 0;
   o->timed_flops = 0;
@@ -500,7 +580,7 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
 
 void solver_time_kernel(Solver *s, const char *name) {
   std::vector<Ctx *> cs{&s->c};
-  for (int i = 0; i < s->pool->size(); ++i) cs.push_back(&s->pool->ctx(i));
+  for (int i = 0; s->pool && i < s->pool->size(); ++i) cs.push_back(&s->pool->ctx(i));
   for (Ctx *c : cs) {
     c->sync();
     c->timer.name = name;

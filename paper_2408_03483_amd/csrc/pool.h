@@ -47,23 +47,21 @@ class Pool {
   int size() const { return (int)ctx_.size(); }
   Ctx &ctx(int i) { return *ctx_[i]; }
 
-  // Run all tasks and wait; the first exception raised by a task is rethrown here.
+  // Run all tasks and wait; the first exception raised by a task is rethrown here.  Several
+  // threads may call run() at once (an ensemble of solvers shares one pool); each call waits
+  // only for its own tasks.
   void run(std::vector<Task> tasks) {
     if (tasks.empty()) return;
+    Group g;
+    g.pending = (int)tasks.size();
     {
       std::lock_guard<std::mutex> lk(mu_);
-      for (auto &t : tasks) q_.push_back(std::move(t));
-      pending_ += (int)tasks.size();
-      err_ = nullptr;
+      for (auto &t : tasks) q_.push_back({std::move(t), &g});
     }
     cv_.notify_all();
     std::unique_lock<std::mutex> lk(mu_);
-    done_.wait(lk, [this] { return pending_ == 0; });
-    if (err_) {
-      std::exception_ptr e = err_;
-      err_ = nullptr;
-      std::rethrow_exception(e);
-    }
+    g.cv.wait(lk, [&g] { return g.pending == 0; });
+    if (g.err) std::rethrow_exception(g.err);
   }
 
   void set_sketch(int width, int power_iters) {
@@ -74,43 +72,45 @@ class Pool {
   }
 
  private:
+  struct Group {
+    int pending = 0;
+    std::exception_ptr err;
+    std::condition_variable cv;
+  };
+
   void loop(int i, int device) {
     (void)hipSetDevice(device);
     for (;;) {
-      Task t;
+      std::pair<Task, Group *> item;
       {
         std::unique_lock<std::mutex> lk(mu_);
         cv_.wait(lk, [this] { return stop_ || !q_.empty(); });
         if (stop_ && q_.empty()) return;
-        t = std::move(q_.front());
+        item = std::move(q_.front());
         q_.pop_front();
       }
       std::exception_ptr e = nullptr;
       try {
         Scope sc(ctx_[i]->arena);
-        t(*ctx_[i]);
+        item.first(*ctx_[i]);
         ctx_[i]->sync();
       } catch (...) {
         e = std::current_exception();
         (void)hipStreamSynchronize(ctx_[i]->stream);
       }
-      {
-        std::lock_guard<std::mutex> lk(mu_);
-        if (e && !err_) err_ = e;
-        --pending_;
-      }
-      done_.notify_all();
+      std::lock_guard<std::mutex> lk(mu_);
+      Group *g = item.second;
+      if (e && !g->err) g->err = e;
+      if (--g->pending == 0) g->cv.notify_all();
     }
   }
 
   std::vector<std::unique_ptr<Ctx>> ctx_;
   std::vector<std::thread> threads_;
   std::mutex mu_;
-  std::condition_variable cv_, done_;
-  std::deque<Task> q_;
-  int pending_ = 0;
+  std::condition_variable cv_;
+  std::deque<std::pair<Task, Group *>> q_;
   bool stop_ = false;
-  std::exception_ptr err_;
 };
 
 }  // namespace ttfv

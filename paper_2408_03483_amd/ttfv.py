@@ -37,7 +37,7 @@ class ParamsC(ctypes.Structure):
                 ("periodic", ctypes.c_int), ("g", ctypes.c_double), ("H0", ctypes.c_double),
                 ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
-                ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int)]
+                ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):
@@ -53,7 +53,8 @@ class StatsC(ctypes.Structure):
 EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_round",
            "tt_hadamard_round", "tt_reciprocal", "tt_maxvol", "tt_cross", "tt_recon_core",
            "tt_fv_init", "tt_fv_step", "tt_fv_get_state", "tt_fv_get_stats", "tt_fv_destroy",
-           "tt_fv_time_kernel", "tt_last_error"]
+           "tt_fv_time_kernel", "tt_ens_create", "tt_ens_step", "tt_ens_destroy",
+           "tt_last_error"]
 
 _lib = None
 
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH):
     L.tt_fv_time_kernel.argtypes = [P, ctypes.c_char_p]
     L.tt_fv_destroy.argtypes = [P]
     L.tt_fv_destroy.restype = None
+    L.tt_ens_create.argtypes = [ctypes.POINTER(P), I, S]
+    L.tt_ens_step.argtypes = [P, ctypes.POINTER(P), I, ctypes.POINTER(D), I, I]
+    L.tt_ens_destroy.argtypes = [P]
+    L.tt_ens_destroy.restype = None
     for name in EXPORTS:
         if not hasattr(L, name):
             raise RuntimeError(f"libttfv.so lacks {name}")
@@ -270,12 +275,13 @@ class Solver:
 def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequence[DeviceTT],
                g: float = 9.81, H0: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
-               cross_kick: int = 4, recip: str = "taylor", stream=None,
+               cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
                arena_bytes: int = 4 << 30) -> Solver:
     L = load_library()
     _torch()
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
-                r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0)
+                r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
+                workers)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -314,3 +320,38 @@ def tt_fv_time_kernel(s: Solver, name: Optional[str]) -> None:
 
 def tt_fv_destroy(s: Solver) -> None:
     s.close()
+
+
+class Ensemble:
+    def __init__(self, workers: int = 8, arena_bytes_per_worker: int = 1 << 30):
+        L = load_library()
+        _torch()
+        self.h = ctypes.c_void_p()
+        _check(L.tt_ens_create(ctypes.byref(self.h), workers, arena_bytes_per_worker),
+               "tt_ens_create")
+
+    def close(self):
+        if self.h:
+            _lib.tt_ens_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tt_ens_create(workers: int = 8, arena_bytes_per_worker: int = 1 << 30) -> Ensemble:
+    return Ensemble(workers, arena_bytes_per_worker)
+
+
+def tt_ens_step(e: Ensemble, members: Sequence[Solver], dts: Sequence[float], nsteps: int = 1,
+                concurrency: int = 8) -> int:
+    hs = (ctypes.c_void_p * len(members))(*[m.h.value for m in members])
+    d = (ctypes.c_double * len(members))(*dts)
+    return _check(_lib.tt_ens_step(e.h, hs, len(members), d, nsteps, concurrency), "tt_ens_step")
+
+
+def tt_ens_destroy(e: Ensemble) -> None:
+    e.close()
