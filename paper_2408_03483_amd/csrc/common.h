@@ -91,6 +91,7 @@ struct Ctx {
   Arena arena;
   int sketch_width = 0;     // 0: automatic
   int power_iters = 1;      // subspace iterations always run; more are added on demand
+  bool fp32 = false;        // core contractions (GEMM, face-splitting products, TSQR) in FP32
   Counters cnt;
   KernelTimer timer;
   void sync();

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
   double part = 0.0;
-  for (int idx = threadIdx.x; idx < mm * m; idx += NT) {
+  const int nt = blockDim.x;
+  for (int idx = threadIdx.x; idx < mm * m; idx += nt) {
     const double v = (idx < m * m) ? M[idx] : 0.0;
     S[idx] = v;
     part += v * v;
@@ -39,14 +40,15 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   if (lane == 0) fro_part[wave] = part;
   __syncthreads();
   double fro2 = 0.0;
-  for (int w = 0; w < NT / 64; ++w) fro2 += fro_part[w];
+  for (int w = 0; w < nt / 64; ++w) fro2 += fro_part[w];
   const double tiny = 1e-34 * fro2;
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
+  const double tol2 = tol * tol;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int t = 0; t < mm - 1; ++t) {
-      for (int k = gid; k < mm / 2; k += NT / 16) {
+      for (int k = gid; k < mm / 2; k += nt / 16) {
         const int a = (k + t) % (mm - 1);
         const int b = (k == 0) ? (mm - 1) : ((mm - 1 - k + t) % (mm - 1));
         const int p = min(a, b), q = max(a, b);
@@ -64,10 +66,10 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
         }
         row16_sum_n<3>(acc);
         const double al = acc[0], be = acc[1], ga = acc[2];
-        if (al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
+        if (al > tiny && be > tiny && ga * ga > tol2 * al * be) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+          const double c = rsqrt(1.0 + tt * tt), s = c * tt;
 #pragma unroll
           for (int r = 0; r < RS; ++r) {
             const int i = gl + 16 * r;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
     if (!any) break;
   }
   // norms
-  for (int cidx = wave; cidx < mm; cidx += NT / 64) {
+  for (int cidx = wave; cidx < mm; cidx += nt / 64) {
     const double *cc = S + (size_t)cidx * m;
     double x0 = lane < m ? cc[lane] : 0.0, x1 = lane + 64 < m ? cc[lane + 64] : 0.0;
     double s2 = wave_sum(x0 * x0 + x1 * x1);
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   }
   __syncthreads();
   // rank by (norm desc, index asc) over the first m columns (the pad column is zero)
-  for (int i = threadIdx.x; i < m; i += NT) {
+  for (int i = threadIdx.x; i < m; i += nt) {
     int rk = 0;
     const double ni = nrm[i];
     for (int j = 0; j < m; ++j) {
@@ -182,18 +184,19 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
   const int mm = (m + 1) & ~1;
   const size_t lds = ((size_t)mm * m + mm) * sizeof(double);
   TimedLaunch tl(c, "jacobi", 22.0 * m * m * m, 8.0 * (2.0 * m * m + m));
+  const int nthreads = std::min(NT, std::max(64, ((mm / 2) * 16 + 63) / 64 * 64));
   if (m <= 32) {
     set_lds(k_jacobi<2>, lds);
-    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
   } else if (m <= 64) {
     set_lds(k_jacobi<4>, lds);
-    hipLaunchKernelGGL(k_jacobi<4>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+    hipLaunchKernelGGL(k_jacobi<4>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
   } else if (m <= 96) {
     set_lds(k_jacobi<6>, lds);
-    hipLaunchKernelGGL(k_jacobi<6>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+    hipLaunchKernelGGL(k_jacobi<6>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
   } else {
     set_lds(k_jacobi<8>, lds);
-    hipLaunchKernelGGL(k_jacobi<8>, dim3(1), dim3(NT), lds, c.stream, M, m, US, sig, 40);
+    hipLaunchKernelGGL(k_jacobi<8>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
   }
   c.cnt.flops += 22.0 * m * m * m;
 }

@@ -30,55 +30,55 @@ constexpr int MAXROWS = 256; // rows of a block held in registers (16 lanes x RS
 
 // Householder QR of the register panel x (LAPACK-style reflectors: R on and above the
 // diagonal, v below it, v_j(j) = 1).  vbuf: 2 * 16 * RS doubles of LDS, taus: m doubles.
-template <int RS, int CS>
-__device__ void qr_regs(double (&x)[CS][RS], int rows, int m, double *vbuf, double *taus) {
+template <typename T, int RS, int CS>
+__device__ void qr_regs(T (&x)[CS][RS], int rows, int m, T *vbuf, T *taus) {
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
   for (int j = 0; j < m; ++j) {
-    double *vb = vbuf + (j & 1) * (16 * RS);
+    T *vb = vbuf + (j & 1) * (16 * RS);
     const int og = j % NG, os = j / NG;
     if (gid == og) {
 #pragma unroll
       for (int s = 0; s < CS; ++s) {
         if (s != os) continue;
-        double red[2] = {0.0, 0.0};
+        T red[2] = {T(0), T(0)};
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
           const int i = gl + 16 * r;
-          const double v = x[s][r];
+          const T v = x[s][r];
           if (i > j && i < rows) red[0] += v * v;
           if (i == j) red[1] += v;
         }
         row16_sum_n<2>(red);
-        const double ss = red[0], alpha = red[1];
-        double t = 0.0, scal = 0.0, beta = alpha;
-        if (ss > 0.0) {
-          const double nrm = sqrt(alpha * alpha + ss);
-          beta = alpha >= 0.0 ? -nrm : nrm;
+        const T ss = red[0], alpha = red[1];
+        T t = T(0), scal = T(0), beta = alpha;
+        if (ss > T(0)) {
+          const T nrm = sqrt(alpha * alpha + ss);
+          beta = alpha >= T(0) ? -nrm : nrm;
           t = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
+          scal = T(1) / (alpha - beta);
         }
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
           const int i = gl + 16 * r;
-          double v = x[s][r];
+          T v = x[s][r];
           if (i > j && i < rows) v *= scal;
           if (i == j) v = beta;
           x[s][r] = v;
-          vb[i] = (i > j && i < rows) ? v : (i == j ? 1.0 : 0.0);
+          vb[i] = (i > j && i < rows) ? v : (i == j ? T(1) : T(0));
         }
         if (gl == 0) taus[j] = t;
       }
     }
     __syncthreads();
-    const double t = taus[j];
-    if (t != 0.0) {
-      double v[RS];
+    const T t = taus[j];
+    if (t != T(0)) {
+      T v[RS];
 #pragma unroll
       for (int r = 0; r < RS; ++r) v[r] = vb[gl + 16 * r];
-      double d[CS];
+      T d[CS];
 #pragma unroll
       for (int s = 0; s < CS; ++s) {
-        double acc = 0.0;
+        T acc = T(0);
 #pragma unroll
         for (int r = 0; r < RS; ++r) acc += v[r] * x[s][r];
         d[s] = acc;
@@ -88,7 +88,7 @@ __device__ void qr_regs(double (&x)[CS][RS], int rows, int m, double *vbuf, doub
       for (int s = 0; s < CS; ++s) {
         const int c = gid + NG * s;
         if (c <= j || c >= m) continue;
-        const double du = t * d[s];
+        const T du = t * d[s];
 #pragma unroll
         for (int r = 0; r < RS; ++r) x[s][r] -= du * v[r];
       }
@@ -99,24 +99,23 @@ __device__ void qr_regs(double (&x)[CS][RS], int rows, int m, double *vbuf, doub
 
 // Apply H_0 ... H_{m-1} (V in LDS, rows x m, ld rows; taus) to the register panel x;
 // reflectors run m-1 .. 0.  No barriers: V is read-only here.
-template <int RS, int CS>
-__device__ void apply_regs(const double *V, const double *taus, int rows, int m,
-                           double (&x)[CS][RS]) {
+template <typename T, int RS, int CS>
+__device__ void apply_regs(const T *V, const T *taus, int rows, int m, T (&x)[CS][RS]) {
   const int gl = threadIdx.x & 15;
   for (int j = m - 1; j >= 0; --j) {
-    const double t = taus[j];
-    if (t == 0.0) continue;
-    const double *vj = V + (size_t)j * rows;
-    double v[RS];
+    const T t = taus[j];
+    if (t == T(0)) continue;
+    const T *vj = V + (size_t)j * rows;
+    T v[RS];
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int i = gl + 16 * r;
-      v[r] = (i < rows && i >= j) ? (i == j ? 1.0 : vj[i]) : 0.0;
+      v[r] = (i < rows && i >= j) ? (i == j ? T(1) : vj[i]) : T(0);
     }
-    double d[CS];
+    T d[CS];
 #pragma unroll
     for (int s = 0; s < CS; ++s) {
-      double acc = 0.0;
+      T acc = T(0);
 #pragma unroll
       for (int r = 0; r < RS; ++r) acc += v[r] * x[s][r];
       d[s] = acc;
@@ -124,7 +123,7 @@ __device__ void apply_regs(const double *V, const double *taus, int rows, int m,
     row16_sum_n<CS>(d);
 #pragma unroll
     for (int s = 0; s < CS; ++s) {
-      const double du = t * d[s];
+      const T du = t * d[s];
 #pragma unroll
       for (int r = 0; r < RS; ++r) x[s][r] -= du * v[r];
     }
@@ -137,28 +136,28 @@ __device__ __forceinline__ void leaf_range(int L, int n, int nleaf, int &start, 
   rows = end - start;
 }
 
-template <int RS, int CS>
+template <typename T, int RS, int CS>
 __global__ __launch_bounds__(NT) void k_leaf_qr(const double *__restrict__ Y, int n, int m,
                                                 int ldy, int nleaf, int bmax,
-                                                double *__restrict__ V, double *__restrict__ tau,
-                                                double *__restrict__ R) {
-  __shared__ double vbuf[2 * 16 * RS];
-  __shared__ double taus[128];
+                                                T *__restrict__ V, T *__restrict__ tau,
+                                                T *__restrict__ R) {
+  __shared__ T vbuf[2 * 16 * RS];
+  __shared__ T taus[128];
   const int L = blockIdx.x;
   int start, rows;
   leaf_range(L, n, nleaf, start, rows);
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  double x[CS][RS];
+  T x[CS][RS];
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int c = gid + NG * s, i = gl + 16 * r;
-      x[s][r] = (c < m && i < rows) ? Y[(size_t)(start + i) + (size_t)c * ldy] : 0.0;
+      x[s][r] = (c < m && i < rows) ? T(Y[(size_t)(start + i) + (size_t)c * ldy]) : T(0);
     }
-  qr_regs<RS, CS>(x, rows, m, vbuf, taus);
-  double *VL = V + (size_t)L * bmax * m;
-  double *RL = R + (size_t)L * m * m;
+  qr_regs<T, RS, CS>(x, rows, m, vbuf, taus);
+  T *VL = V + (size_t)L * bmax * m;
+  T *RL = R + (size_t)L * m * m;
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
@@ -166,45 +165,44 @@ __global__ __launch_bounds__(NT) void k_leaf_qr(const double *__restrict__ Y, in
       const int c = gid + NG * s, i = gl + 16 * r;
       if (c >= m) continue;
       if (i < rows) VL[i + (size_t)c * bmax] = x[s][r];
-      if (i < m) RL[i + (size_t)c * m] = (i <= c) ? x[s][r] : 0.0;
+      if (i < m) RL[i + (size_t)c * m] = (i <= c) ? x[s][r] : T(0);
     }
   for (int c = threadIdx.x; c < m; c += NT) tau[(size_t)L * m + c] = taus[c];
 }
 
 // Combine up to `arity` child triangles (m x m each) of the level below.
-template <int RS, int CS>
-__global__ __launch_bounds__(NT) void k_node_qr(const double *__restrict__ Rin, int cnt_in, int m,
-                                                int arity, double *__restrict__ V,
-                                                double *__restrict__ tau,
-                                                double *__restrict__ Rout) {
-  __shared__ double vbuf[2 * 16 * RS];
-  __shared__ double taus[128];
+template <typename T, int RS, int CS>
+__global__ __launch_bounds__(NT) void k_node_qr(const T *__restrict__ Rin, int cnt_in, int m,
+                                                int arity, T *__restrict__ V,
+                                                T *__restrict__ tau, T *__restrict__ Rout) {
+  __shared__ T vbuf[2 * 16 * RS];
+  __shared__ T taus[128];
   const int k = blockIdx.x;
   const int c0 = k * arity;
   const int nch = min(arity, cnt_in - c0);
   const int rows = nch * m;
-  double *Ro = Rout + (size_t)k * m * m;
+  T *Ro = Rout + (size_t)k * m * m;
   if (nch == 1) {
     for (int idx = threadIdx.x; idx < m * m; idx += NT) Ro[idx] = Rin[(size_t)c0 * m * m + idx];
     return;
   }
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  double x[CS][RS];
+  T x[CS][RS];
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int c = gid + NG * s, i = gl + 16 * r;
-      double v = 0.0;
+      T v = T(0);
       if (c < m && i < rows) {
         const int ch = i / m, ii = i - ch * m;
         v = Rin[(size_t)(c0 + ch) * m * m + ii + (size_t)c * m];
       }
       x[s][r] = v;
     }
-  qr_regs<RS, CS>(x, rows, m, vbuf, taus);
+  qr_regs<T, RS, CS>(x, rows, m, vbuf, taus);
   const int ldv = arity * m;
-  double *Vk = V + (size_t)k * ldv * m;
+  T *Vk = V + (size_t)k * ldv * m;
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
@@ -212,20 +210,20 @@ __global__ __launch_bounds__(NT) void k_node_qr(const double *__restrict__ Rin, 
       const int c = gid + NG * s, i = gl + 16 * r;
       if (c >= m) continue;
       if (i < rows) Vk[i + (size_t)c * ldv] = x[s][r];
-      if (i < m) Ro[i + (size_t)c * m] = (i <= c) ? x[s][r] : 0.0;
+      if (i < m) Ro[i + (size_t)c * m] = (i <= c) ? x[s][r] : T(0);
     }
   for (int c = threadIdx.x; c < m; c += NT) tau[(size_t)k * m + c] = taus[c];
 }
 
 // Top-down: slab Zin[k] (m x m) of node k -> slabs Zout[c0 .. c0+nch-1] of its children.
 // Zin == nullptr means the identity slab (root).
-template <int RS, int CS>
-__global__ __launch_bounds__(NT) void k_node_apply(const double *__restrict__ V,
-                                                   const double *__restrict__ tau, int cnt_in,
-                                                   int m, int arity,
-                                                   const double *__restrict__ Zin,
-                                                   double *__restrict__ Zout) {
-  extern __shared__ double sm[];
+template <typename T, int RS, int CS>
+__global__ __launch_bounds__(NT) void k_node_apply(const T *__restrict__ V,
+                                                   const T *__restrict__ tau, int cnt_in,
+                                                   int m, int arity, const T *__restrict__ Zin,
+                                                   T *__restrict__ Zout) {
+  extern __shared__ __align__(8) unsigned char smraw[];
+  T *sm = reinterpret_cast<T *>(smraw);
   const int k = blockIdx.x;
   const int c0 = k * arity;
   const int nch = min(arity, cnt_in - c0);
@@ -233,32 +231,32 @@ __global__ __launch_bounds__(NT) void k_node_apply(const double *__restrict__ V,
   if (nch == 1) {
     for (int idx = threadIdx.x; idx < m * m; idx += NT) {
       const int i = idx % m, c = idx / m;
-      Zout[(size_t)c0 * m * m + idx] = Zin ? Zin[(size_t)k * m * m + idx] : (i == c ? 1.0 : 0.0);
+      Zout[(size_t)c0 * m * m + idx] = Zin ? Zin[(size_t)k * m * m + idx] : T(i == c ? 1 : 0);
     }
     return;
   }
   const int ldv = arity * m;
-  double *Vs = sm;
-  double *ts = sm + (size_t)rows * m;
-  const double *Vk = V + (size_t)k * ldv * m;
+  T *Vs = sm;
+  T *ts = sm + (size_t)rows * m;
+  const T *Vk = V + (size_t)k * ldv * m;
   for (int idx = threadIdx.x; idx < rows * m; idx += NT) {
     const int i = idx % rows, c = idx / rows;
     Vs[i + (size_t)c * rows] = Vk[i + (size_t)c * ldv];
   }
   for (int c = threadIdx.x; c < m; c += NT) ts[c] = tau[(size_t)k * m + c];
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  double x[CS][RS];
+  T x[CS][RS];
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int c = gid + NG * s, i = gl + 16 * r;
-      double v = 0.0;
-      if (c < m && i < m) v = Zin ? Zin[(size_t)k * m * m + i + (size_t)c * m] : (i == c ? 1.0 : 0.0);
+      T v = T(0);
+      if (c < m && i < m) v = Zin ? Zin[(size_t)k * m * m + i + (size_t)c * m] : T(i == c ? 1 : 0);
       x[s][r] = v;
     }
   __syncthreads();
-  apply_regs<RS, CS>(Vs, ts, rows, m, x);
+  apply_regs<T, RS, CS>(Vs, ts, rows, m, x);
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
@@ -270,43 +268,43 @@ __global__ __launch_bounds__(NT) void k_node_apply(const double *__restrict__ V,
     }
 }
 
-template <int RS, int CS>
-__global__ __launch_bounds__(NT) void k_leaf_apply(const double *__restrict__ V,
-                                                   const double *__restrict__ tau, int n, int m,
-                                                   int nleaf, int bmax,
-                                                   const double *__restrict__ Z,
+template <typename T, int RS, int CS>
+__global__ __launch_bounds__(NT) void k_leaf_apply(const T *__restrict__ V,
+                                                   const T *__restrict__ tau, int n, int m,
+                                                   int nleaf, int bmax, const T *__restrict__ Z,
                                                    double *__restrict__ Q, int ldq) {
-  extern __shared__ double sm[];
+  extern __shared__ __align__(8) unsigned char smraw[];
+  T *sm = reinterpret_cast<T *>(smraw);
   const int L = blockIdx.x;
   int start, rows;
   leaf_range(L, n, nleaf, start, rows);
-  double *Vs = sm;
-  double *ts = sm + (size_t)rows * m;
-  const double *VL = V + (size_t)L * bmax * m;
+  T *Vs = sm;
+  T *ts = sm + (size_t)rows * m;
+  const T *VL = V + (size_t)L * bmax * m;
   for (int idx = threadIdx.x; idx < rows * m; idx += NT) {
     const int i = idx % rows, c = idx / rows;
     Vs[i + (size_t)c * rows] = VL[i + (size_t)c * bmax];
   }
   for (int c = threadIdx.x; c < m; c += NT) ts[c] = tau[(size_t)L * m + c];
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  double x[CS][RS];
+  T x[CS][RS];
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int c = gid + NG * s, i = gl + 16 * r;
-      double v = 0.0;
-      if (c < m && i < m) v = Z ? Z[(size_t)L * m * m + i + (size_t)c * m] : (i == c ? 1.0 : 0.0);
+      T v = T(0);
+      if (c < m && i < m) v = Z ? Z[(size_t)L * m * m + i + (size_t)c * m] : T(i == c ? 1 : 0);
       x[s][r] = v;
     }
   __syncthreads();
-  apply_regs<RS, CS>(Vs, ts, rows, m, x);
+  apply_regs<T, RS, CS>(Vs, ts, rows, m, x);
 #pragma unroll
   for (int s = 0; s < CS; ++s)
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       const int c = gid + NG * s, i = gl + 16 * r;
-      if (c < m && i < rows) Q[(size_t)(start + i) + (size_t)c * ldq] = x[s][r];
+      if (c < m && i < rows) Q[(size_t)(start + i) + (size_t)c * ldq] = double(x[s][r]);
     }
 }
 
@@ -333,58 +331,85 @@ struct Plan {
   std::vector<int> cnt;
 };
 
-template <int RS, int CS>
+__global__ void k_to_double(const float *__restrict__ a, double *__restrict__ b, int n, int ldb,
+                            int rows) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  b[(idx % rows) + (size_t)(idx / rows) * ldb] = a[idx];
+}
+
+template <typename T, int RS, int CS>
 void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int ldq, double *R,
               int ldr) {
   const int n = pl.n, m = pl.m, nleaf = pl.nleaf, bmax = pl.bmax, arity = pl.arity;
   Scope sc(c.arena);
-  double *Vleaf = c.arena.dalloc((size_t)nleaf * bmax * m);
-  double *tleaf = c.arena.dalloc((size_t)nleaf * m);
-  double *Rleaf = c.arena.dalloc((size_t)nleaf * m * m);
+  auto talloc = [&](size_t k) { return reinterpret_cast<T *>(c.arena.alloc(k * sizeof(T))); };
+  T *Vleaf = talloc((size_t)nleaf * bmax * m);
+  T *tleaf = talloc((size_t)nleaf * m);
+  T *Rleaf = talloc((size_t)nleaf * m * m);
   const double mm3 = (double)m * m * m;
   {
     TimedLaunch tl(c, "tsqr_leaf_qr", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
                    8.0 * (2.0 * n * m + (double)nleaf * m * m));
-    hipLaunchKernelGGL((k_leaf_qr<RS, CS>), dim3(nleaf), dim3(NT), 0, c.stream, Y, n, m, ldy,
+    hipLaunchKernelGGL((k_leaf_qr<T, RS, CS>), dim3(nleaf), dim3(NT), 0, c.stream, Y, n, m, ldy,
                        nleaf, bmax, Vleaf, tleaf, Rleaf);
   }
   const int levels = (int)pl.cnt.size() - 1;
-  std::vector<double *> Vl(levels + 1, nullptr), tl(levels + 1, nullptr), Rl(levels + 1, nullptr);
+  std::vector<T *> Vl(levels + 1, nullptr), tl(levels + 1, nullptr), Rl(levels + 1, nullptr);
   Rl[0] = Rleaf;
   for (int l = 1; l <= levels; ++l) {
     const int cout = pl.cnt[l];
-    Vl[l] = c.arena.dalloc((size_t)cout * arity * m * m);
-    tl[l] = c.arena.dalloc((size_t)cout * m);
-    Rl[l] = c.arena.dalloc((size_t)cout * m * m);
+    Vl[l] = talloc((size_t)cout * arity * m * m);
+    tl[l] = talloc((size_t)cout * m);
+    Rl[l] = talloc((size_t)cout * m * m);
     const double rows_l = (double)pl.cnt[l - 1] * m;
     TimedLaunch tq(c, "tsqr_node_qr", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * cout,
                    8.0 * (2.0 * rows_l * m + (double)cout * m * m));
-    hipLaunchKernelGGL((k_node_qr<RS, CS>), dim3(cout), dim3(NT), 0, c.stream, Rl[l - 1],
+    hipLaunchKernelGGL((k_node_qr<T, RS, CS>), dim3(cout), dim3(NT), 0, c.stream, Rl[l - 1],
                        pl.cnt[l - 1], m, arity, Vl[l], tl[l], Rl[l]);
   }
-  copy_scale(c, R, ldr, Rl[levels], m, m, m, 1.0);
+  if (sizeof(T) == sizeof(double)) {
+    copy_scale(c, R, ldr, reinterpret_cast<const double *>(Rl[levels]), m, m, m, 1.0);
+  } else {
+    hipLaunchKernelGGL(k_to_double, dim3((m * m + 255) / 256), dim3(256), 0, c.stream,
+                       reinterpret_cast<const float *>(Rl[levels]), R, m * m, ldr, m);
+  }
   size_t zmax = 0;
   for (int v : pl.cnt) zmax = std::max(zmax, (size_t)v);
-  double *Z[2] = {c.arena.dalloc(zmax * m * m), c.arena.dalloc(zmax * m * m)};
-  const double *Zin = nullptr;
+  T *Z[2] = {talloc(zmax * m * m), talloc(zmax * m * m)};
+  const T *Zin = nullptr;
   int which = 0;
   for (int l = levels; l >= 1; --l) {
-    const size_t lds = ((size_t)arity * m * m + m) * sizeof(double);
-    set_lds(k_node_apply<RS, CS>, lds);
+    const size_t lds = ((size_t)arity * m * m + m) * sizeof(T);
+    set_lds(k_node_apply<T, RS, CS>, lds);
     const double rows_l = (double)pl.cnt[l - 1] * m;
     TimedLaunch ta(c, "tsqr_node_apply", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * pl.cnt[l],
                    8.0 * (2.0 * rows_l * m + (double)pl.cnt[l] * m * m));
-    hipLaunchKernelGGL((k_node_apply<RS, CS>), dim3(pl.cnt[l]), dim3(NT), lds, c.stream, Vl[l],
+    hipLaunchKernelGGL((k_node_apply<T, RS, CS>), dim3(pl.cnt[l]), dim3(NT), lds, c.stream, Vl[l],
                        tl[l], pl.cnt[l - 1], m, arity, Zin, Z[which]);
     Zin = Z[which];
     which ^= 1;
   }
-  const size_t lds = ((size_t)bmax * m + m) * sizeof(double);
-  set_lds(k_leaf_apply<RS, CS>, lds);
+  const size_t lds = ((size_t)bmax * m + m) * sizeof(T);
+  set_lds(k_leaf_apply<T, RS, CS>, lds);
   TimedLaunch tl2(c, "tsqr_leaf_apply", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
                   8.0 * (2.0 * n * m + (double)nleaf * m * m));
-  hipLaunchKernelGGL((k_leaf_apply<RS, CS>), dim3(nleaf), dim3(NT), lds, c.stream, Vleaf, tleaf,
-                     n, m, nleaf, bmax, Zin, Q, ldq);
+  hipLaunchKernelGGL((k_leaf_apply<T, RS, CS>), dim3(nleaf), dim3(NT), lds, c.stream, Vleaf,
+                     tleaf, n, m, nleaf, bmax, Zin, Q, ldq);
+}
+
+template <typename T>
+void dispatch_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, int rs, int cs, double *Q,
+                   int ldq, double *R, int ldr) {
+  if (cs == 1) {
+    if (rs <= 2) run_tsqr<T, 2, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
+    else if (rs <= 4) run_tsqr<T, 4, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
+    else if (rs <= 8) run_tsqr<T, 8, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
+    else run_tsqr<T, 16, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
+  } else {
+    if (rs <= 8) run_tsqr<T, 8, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
+    else run_tsqr<T, 16, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
+  }
 }
 
 }  // namespace
@@ -410,15 +435,10 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
   TT_REQUIRE(rowsmax <= MAXROWS, "tsqr: block too tall");
   const int rs = (rowsmax + 15) / 16;
   const int cs = (m + NG - 1) / NG;
-  if (cs == 1) {
-    if (rs <= 2) run_tsqr<2, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
-    else if (rs <= 4) run_tsqr<4, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
-    else if (rs <= 8) run_tsqr<8, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
-    else run_tsqr<16, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
-  } else {
-    if (rs <= 8) run_tsqr<8, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
-    else run_tsqr<16, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
-  }
+  if (c.fp32)
+    dispatch_tsqr<float>(c, Y, ldy, pl, rs, cs, Q, ldq, R, ldr);
+  else
+    dispatch_tsqr<double>(c, Y, ldy, pl, rs, cs, Q, ldq, R, ldr);
   c.cnt.flops += 4.0 * n * m * m;
   c.cnt.bytes += 8.0 * 3.0 * n * m;
 }

@@ -54,8 +54,13 @@ namespace ttfv {
 // Sum over the 16 lanes of a DPP row, returned in every lane of the row: four row_ror
 // steps (8, 4, 2, 1).  Every lane adds the same pairs in the same tree, so all 16 lanes
 // hold bitwise-identical results.
-template <int N>
-__device__ __forceinline__ void row16_sum_n(double (&v)[N]) {
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void row16_sum_n(T (&v)[N]) {
 #pragma unroll
   for (int k = 0; k < N; ++k) v[k] += dpp_shift<0x128>(v[k]);   // row_ror:8
 #pragma unroll
