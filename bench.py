@@ -14,6 +14,7 @@ streams it runs on, which gives the roofline line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--timed-kernel NAME]
                     [--workload bumps1024 | dambreak2048 | ensemble] [--members 64]
+                    [--precision f64 | f32]
 
 Other workloads (not the headline line): dambreak2048 = WENO5 through maxvol crosses, 1/h by
 cross, walls, rank cap 64, tol 1e-8; ensemble = independent nonlinear members of 256^2,
@@ -56,6 +57,8 @@ def main():
     ap.add_argument("--workload", default="bumps1024",
                     choices=["bumps1024", "dambreak2048", "ensemble"])
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
+                    help="contraction arithmetic of the dambreak2048 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
@@ -165,38 +168,71 @@ def _roofline(stats, kernel, elapsed):
             "share_of_step": stats["timed_ms"] / (elapsed * 1e3), "alg_flops_per_launch": fl}
 
 
-def dambreak(args):
-    """WENO5 dam break, 2048^2, walls, rank cap 64, tol 1e-8, 1/h by cross."""
+def _field_rel(Qa, Qb):
     import numpy as np
+    out = []
+    for a, b in zip(Qa, Qb):
+        fa, fb = a.full(), b.full()
+        out.append(float(np.linalg.norm(fa - fb) / max(np.linalg.norm(fb), 1e-300)))
+    return out
+
+
+def dambreak(args):
+    """WENO5 dam break, 2048^2, walls, rank cap 64, tol 1e-8, 1/h by cross.  With
+    --precision f32 the contractions run in FP32 and the same steps are also run in FP64:
+    the line then carries the FP64 rate, the speed-up and the per-field rel-L2 between the
+    two end states (gate 1e-4)."""
     import torch
     import synth
     from paper_2408_03483_amd import ttfv
     n, rmax, eps = 2048, 64, 1e-8
     st = synth.dam_break(seed=0, n=n, rmax=rmax, eps=eps)
-    dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
-    s = ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
-                        recip="cross")
-    for _ in range(args.warmup):
-        ttfv.tt_fv_step(s, st.dt, 1)
-    if args.timed_kernel:
-        ttfv.tt_fv_time_kernel(s, args.timed_kernel)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ttfv.tt_fv_step(s, st.dt, args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stats = ttfv.tt_fv_get_stats(s)
+
+    def run(precision, timed_kernel):
+        dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+        s = ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
+                            recip="cross", precision=precision)
+        for _ in range(args.warmup):
+            ttfv.tt_fv_step(s, st.dt, 1)
+        if timed_kernel:
+            ttfv.tt_fv_time_kernel(s, timed_kernel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ttfv.tt_fv_step(s, st.dt, args.steps)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        stats = ttfv.tt_fv_get_stats(s)
+        Q = ttfv.tt_fv_get_state(s)
+        s.close()
+        print(f"dam break {precision}: {elapsed * 1e3 / args.steps:.1f} ms/step, ranks "
+              f"{stats['ranks']}", file=sys.stderr, flush=True)
+        return elapsed, stats, Q
+
+    elapsed, stats, Q = run(args.precision, args.timed_kernel)
+    extra = {}
+    if args.precision == "f32":
+        e64, s64, Q64 = run("f64", "")
+        rel = _field_rel(Q, Q64)
+        import numpy as np
+        hn = float(np.linalg.norm(Q64[0].full()))
+        on_h = [float(np.linalg.norm(a.full() - b.full()) / hn) for a, b in zip(Q, Q64)]
+        extra = {"fp64_value": n * n * args.steps / e64,
+                 "speedup_vs_fp64": e64 / elapsed,
+                 "rel_l2_vs_fp64": rel, "diff_vs_fp64_on_h_scale": on_h,
+                 "gate": 1e-4, "gate_pass_per_field": max(rel) <= 1e-4,
+                 "gate_pass_on_h_scale": max(on_h) <= 1e-4, "ranks_fp64": s64["ranks"]}
     out = {"metric": METRIC, "value": n * n * args.steps / elapsed, "unit": "cell-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
            "config": {"workload": f"dam_break_weno5_{n}", "grid": f"{n}x{n}", "scheme": "weno5",
                       "bc": "walls", "r_max": rmax, "eps": eps, "reciprocal": "cross",
-                      "cross_sweeps": 3, "seed": 0},
+                      "cross_sweeps": 3, "seed": 0,
+                      "contractions": "fp32 matrix cores" if args.precision == "f32" else "fp64"},
            "roofline": _roofline(stats, args.timed_kernel, elapsed), "cpu_baseline": None,
            "ranks": stats["ranks"], "crosses": stats["crosses"]}
+    out.update(extra)
     print(json.dumps(out), flush=True)
-    s.close()
 
 
 def ensemble(args):

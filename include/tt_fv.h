@@ -57,6 +57,14 @@ void tt_ctx_destroy(tt_ctx *ctx);
 /* Rounding sketch width (0 = automatic: min(96, max(2 r_max, 16))) and the number of
  * subspace iterations always run (>= 0; more are added while the sketch has not converged). */
 int  tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters);
+/* Arithmetic of the core contractions (rounding GEMMs and Householder QR panels):
+ * TT_PREC_F64 (default) or TT_PREC_F32 (FP32 operands and accumulation on the matrix cores;
+ * the small SVD, maxvol, the Taylor mean and error estimates and all stored cores stay FP64).
+ * Results in FP32 mode are accurate to about 1e-6 relative, so tolerances below that
+ * saturate the rank cap. */
+#define TT_PREC_F64 0
+#define TT_PREC_F32 1
+int  tt_ctx_set_precision(tt_ctx *ctx, int precision);
 
 /* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
  * eps and rank <= r_max.  x may have any rank <= x->cap; y->cap must be >= r_max.
@@ -127,6 +135,7 @@ typedef struct {
   int recip;          /* 1/h: 0 = Taylor series (Algorithm 1), 1 = cross of 1/x            */
   int workers;        /* own worker streams: 0 = default (6), k = k, -1 = none (the solver
                          then steps only inside an ensemble, tt_ens_step)                 */
+  int precision;      /* TT_PREC_F64 or TT_PREC_F32 (contractions; see tt_ctx_set_precision) */
 } tt_fv_params;
 
 typedef struct {
@@ -143,6 +152,10 @@ typedef struct {
   long long timed_launches;   /* its launches since tt_fv_time_kernel                     */
   double timed_flops;         /* its algorithmic flops                                    */
   double timed_bytes;         /* its algorithmic bytes                                    */
+  long long cross_sweeps_run; /* maxvol sweeps actually run by all crosses                */
+  long long learned_crosses;  /* crosses accepted from the learned pivot proposer          */
+  long long learned_fallbacks;/* proposer results rejected (plain crosses run instead)     */
+  double max_learned_err;     /* largest validation error of an accepted proposer cross    */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build
@@ -159,6 +172,45 @@ int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
  * "maxvol_greedy"; NULL or "" switches timing off) and reset the timed_* statistics. */
 int  tt_fv_time_kernel(tt_fv *s, const char *name);
 void tt_fv_destroy(tt_fv *s);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned pivot proposer for the crosses (an addition to the paper, whose crosses choose
+ * pivots by alternating maxvol sweeps, Section 3.3).  A perceptron 16 -> 256 -> 256 -> 1
+ * (ReLU; BF16 weights and activations, FP32 accumulation) scores every column index of a
+ * cross from 16 features of the cross's starting TT (second core B0) and the call site's
+ * previous pivots; the top K = min(r_max, |J_prev| + kick) indices are the columns of one
+ * refinement sweep.  The result is checked on 8 seeded validation columns outside J: if
+ * |f - Y|_F / |Y|_F exceeds max(1e-6, 2 x the same error of the site's last plain cross),
+ * the plain maxvol cross runs instead.  The model is trained with Adam on (features, final
+ * maxvol pivots) pairs logged from plain crosses.  Weights: flat FP32 vector of
+ * TT_PM_NPARAM entries, W1 (16 x 256, row-major) | b1 | W2 (256 x 256) | b2 | w3 | b3. */
+#define TT_PM_NPARAM 70401
+#define TT_PIV_MAXVOL  0    /* plain alternating maxvol sweeps                              */
+#define TT_PIV_LOG     1    /* plain sweeps; log (features, pivots) into the model          */
+#define TT_PIV_LEARNED 2    /* proposer + one sweep, plain sweeps as the fallback           */
+typedef struct tt_pm tt_pm;
+/* max_rows: capacity of the training log (rows of 16 features); seed: weight init. */
+int  tt_pm_create(tt_pm **out, size_t max_rows, unsigned long long seed);
+void tt_pm_destroy(tt_pm *pm);
+int  tt_pm_set_weights(tt_pm *pm, const float *host, size_t n);
+int  tt_pm_get_weights(tt_pm *pm, float *host, size_t n);
+/* Scores s (N, device FP32) of features X (N x 16 row-major, device FP32, cast to BF16). */
+int  tt_pm_forward(tt_pm *pm, const float *X_dev, int N, float *s_dev);
+/* Loss and gradients (flat, host FP32, n = TT_PM_NPARAM) of the weighted logistic loss
+ * sum_i w_i (log(1 + e^s_i) - y_i s_i) / N, w_i = pos_weight where y_i = 1, else 1. */
+int  tt_pm_grad(tt_pm *pm, const float *X_dev, const float *y_dev, int N, double pos_weight,
+                float *grad_host, size_t n, double *loss_out);
+/* Adam (lr) over the logged samples, positive weight = negatives / positives. */
+int  tt_pm_train(tt_pm *pm, int epochs, int batch, double lr, double *loss_out);
+int  tt_pm_dataset(tt_pm *pm, size_t *rows, size_t *positives);
+/* The 16 features of every index of a cross (B0: n2 x r, ld ldb, device FP64; J_dev: the
+ * nJ <= 128 previous pivots) into X_dev (n2 x 16 row-major FP32). */
+int  tt_pm_features(tt_ctx *ctx, const double *B0, int n2, int r, int ldb, const int *J_dev,
+                    int nJ, float *X_dev);
+/* Indices of the k largest scores (ties: smaller index first), ascending, into idx_dev. */
+int  tt_pm_topk(tt_ctx *ctx, const float *s_dev, int n, int k, int *idx_dev);
+/* Pivot mode of a solver's crosses (TT_PIV_*); pm must outlive its use (NULL with mode 0). */
+int  tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm);
 
 /* ---------------------------------------------------------------------------------------
  * Batched ensemble: independent solvers advanced together.  Their independent chains of TT

@@ -3,6 +3,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <memory>
 
 namespace ttfv {
 
@@ -13,6 +14,7 @@ void solver_get_state(Solver *s, tt_matrix q[3]);
 void solver_stats(Solver *s, tt_fv_stats *o);
 void solver_destroy(Solver *s);
 void solver_time_kernel(Solver *s, const char *name);
+void solver_set_pivots(Solver *s, int mode, PivotModel *pm);
 struct Ensemble;
 Ensemble *ensemble_create(int workers, size_t arena_bytes);
 void ensemble_destroy(Ensemble *e);
@@ -127,6 +129,10 @@ struct tt_ens {
   ttfv::Ensemble *e;
 };
 
+struct tt_pm {
+  std::unique_ptr<ttfv::PivotModel> m;
+};
+
 using namespace ttfv;
 
 template <typename F>
@@ -172,6 +178,15 @@ int tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters) {
     TT_REQUIRE(power_iters >= 0 && power_iters <= 8, "power_iters out of [0, 8]");
     ctx->c.sketch_width = width;
     ctx->c.power_iters = power_iters;
+    return 0;
+  });
+}
+
+int tt_ctx_set_precision(tt_ctx *ctx, int precision) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    TT_REQUIRE(precision == TT_PREC_F64 || precision == TT_PREC_F32, "unknown precision");
+    ctx->c.fp32 = precision == TT_PREC_F32;
     return 0;
   });
 }
@@ -429,3 +444,122 @@ void tt_fv_destroy(tt_fv *s) {
 }
 
 }  // extern "C"
+
+// ---- learned pivot proposer -------------------------------------------------------------
+
+int tt_pm_create(tt_pm **out, size_t max_rows, unsigned long long seed) {
+  return guarded([&]() {
+    TT_REQUIRE(out, "null argument");
+    auto *h = new tt_pm();
+    try {
+      h->m = std::make_unique<PivotModel>(max_rows, (uint64_t)seed);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return 0;
+  });
+}
+
+void tt_pm_destroy(tt_pm *pm) { delete pm; }
+
+int tt_pm_set_weights(tt_pm *pm, const float *host, size_t n) {
+  return guarded([&]() {
+    TT_REQUIRE(pm && host && n == PM_NPARAM, "tt_pm_set_weights: null or n != TT_PM_NPARAM");
+    pm->m->set_weights(host);
+    return 0;
+  });
+}
+
+int tt_pm_get_weights(tt_pm *pm, float *host, size_t n) {
+  return guarded([&]() {
+    TT_REQUIRE(pm && host && n == PM_NPARAM, "tt_pm_get_weights: null or n != TT_PM_NPARAM");
+    pm->m->get_weights(host);
+    return 0;
+  });
+}
+
+int tt_pm_forward(tt_pm *pm, const float *X_dev, int N, float *s_dev) {
+  return guarded([&]() {
+    TT_REQUIRE(pm && X_dev && s_dev && N >= 1, "tt_pm_forward: bad argument");
+    PivotModel &m = *pm->m;
+    std::lock_guard<std::mutex> lk(m.mu);
+    Scope sc(m.c.arena);
+    bf16_t *Xb = static_cast<bf16_t *>(m.c.arena.alloc((size_t)N * PM_F * sizeof(bf16_t)));
+    to_bf16(m.c, X_dev, (size_t)N * PM_F, Xb);
+    m.forward(m.c, Xb, N, s_dev, nullptr, nullptr);
+    m.c.sync();
+    return 0;
+  });
+}
+
+int tt_pm_grad(tt_pm *pm, const float *X_dev, const float *y_dev, int N, double pos_weight,
+               float *grad_host, size_t n, double *loss_out) {
+  return guarded([&]() {
+    TT_REQUIRE(pm && X_dev && y_dev && grad_host && N >= 1 && n == PM_NPARAM,
+               "tt_pm_grad: bad argument");
+    PivotModel &m = *pm->m;
+    std::lock_guard<std::mutex> lk(m.mu);
+    Scope sc(m.c.arena);
+    bf16_t *Xb = static_cast<bf16_t *>(m.c.arena.alloc((size_t)N * PM_F * sizeof(bf16_t)));
+    to_bf16(m.c, X_dev, (size_t)N * PM_F, Xb);
+    const double l = m.grad(m.c, Xb, y_dev, N, pos_weight);
+    HIP_CHECK(hipMemcpyAsync(grad_host, m.g, PM_NPARAM * sizeof(float), hipMemcpyDeviceToHost,
+                             m.c.stream));
+    m.c.sync();
+    if (loss_out) *loss_out = l;
+    return 0;
+  });
+}
+
+int tt_pm_train(tt_pm *pm, int epochs, int batch, double lr, double *loss_out) {
+  return guarded([&]() {
+    TT_REQUIRE(pm && lr > 0.0, "tt_pm_train: bad argument");
+    const double l = pm->m->train(epochs, batch, lr);
+    if (loss_out) *loss_out = l;
+    return 0;
+  });
+}
+
+int tt_pm_dataset(tt_pm *pm, size_t *rows, size_t *positives) {
+  return guarded([&]() {
+    TT_REQUIRE(pm, "null model");
+    std::lock_guard<std::mutex> lk(pm->m->mu);
+    if (rows) *rows = pm->m->rows;
+    if (positives) *positives = pm->m->positives;
+    return 0;
+  });
+}
+
+int tt_pm_features(tt_ctx *ctx, const double *B0, int n2, int r, int ldb, const int *J_dev,
+                   int nJ, float *X_dev) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && B0 && X_dev && n2 >= 1 && r >= 1 && ldb >= n2 && nJ >= 0 && nJ <= 128 &&
+                   (nJ == 0 || J_dev),
+               "tt_pm_features: bad argument");
+    pivot_features(ctx->c, B0, n2, r, ldb, J_dev, nJ, X_dev, nullptr);
+    ctx->c.sync();
+    return 0;
+  });
+}
+
+int tt_pm_topk(tt_ctx *ctx, const float *s_dev, int n, int k, int *idx_dev) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && s_dev && idx_dev && n >= 1 && k >= 1 && k <= n, "tt_pm_topk: bad argument");
+    topk_indices(ctx->c, s_dev, n, k, idx_dev);
+    ctx->c.sync();
+    return 0;
+  });
+}
+
+int tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null solver");
+    TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_LOG || mode == TT_PIV_LEARNED,
+               "tt_fv_set_pivots: unknown mode");
+    TT_REQUIRE(mode == TT_PIV_MAXVOL || pm, "tt_fv_set_pivots: mode needs a model");
+    solver_set_pivots(s->s, mode, pm ? pm->m.get() : nullptr);
+    return 0;
+  });
+}

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -201,6 +202,41 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
              int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out);
 uint64_t splitmix64_next(uint64_t &state);
 std::vector<int> kick_indices(const std::vector<int> &have, int n, int count, uint64_t key);
+
+// mlp.hip: learned pivot proposer (16 features -> 256 -> 256 -> 1, BF16 on the matrix cores)
+typedef unsigned short bf16_t;
+constexpr int PM_F = 16, PM_H = 256;
+constexpr size_t PM_W1_N = (size_t)PM_F * PM_H, PM_W2_N = (size_t)PM_H * PM_H, PM_W3_N = PM_H;
+// flat FP32 parameter vector: W1 (F x H, row-major) | b1 | W2 (H x H) | b2 | w3 | b3
+constexpr size_t PM_W1 = 0, PM_B1 = PM_W1 + PM_W1_N, PM_W2 = PM_B1 + PM_H,
+                 PM_B2 = PM_W2 + PM_W2_N, PM_W3 = PM_B2 + PM_H, PM_B3 = PM_W3 + PM_W3_N,
+                 PM_NPARAM = PM_B3 + 1;
+
+struct PivotModel {
+  PivotModel(size_t max_rows, uint64_t seed);
+  ~PivotModel();
+  void set_weights(const float *host);
+  void get_weights(float *host);
+  void refresh_bf16();
+  void forward(Ctx &w, const bf16_t *Xb, int N, float *s, bf16_t **H1, bf16_t **H2);
+  double grad(Ctx &w, const bf16_t *Xb, const float *y, int N, double pos_weight);
+  void adam(Ctx &w, double lr);
+  void append(Ctx &w, const bf16_t *Xb, const int *J_dev, int nJ, int n2);
+  double train(int epochs, int batch, double lr);
+
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // FP32 params, grads, Adam
+  bf16_t *wb = nullptr;                                              // BF16 W1 | W2 | w3
+  bf16_t *Xd = nullptr;                                              // logged features
+  float *Yd = nullptr;                                               // logged labels
+  size_t cap = 0, rows = 0, positives = 0;
+  int t = 0;
+  Ctx c;
+  std::mutex mu;
+};
+void pivot_features(Ctx &c, const double *B0, int n2, int r, int ldb, const int *J_dev, int nJ,
+                    float *Xf, bf16_t *Xb);
+void topk_indices(Ctx &c, const float *s, int n, int K, int *out);
+void to_bf16(Ctx &c, const float *x, size_t n, bf16_t *y);
 
 // stencil derivation (stencils.cpp part of fv.hip)
 StencilSet derive_stencils(int scheme);

@@ -3,7 +3,8 @@
 // maxvol (Goreinov et al., cited in Section 3.3) on an orthonormal basis Q (n x r):
 //   start: greedy rows -- repeatedly the row of largest residual norm, whose direction is
 //          then projected out of every row (a pivoted QR of Q^T); for an orthonormal basis
-//          this start does not depend on which basis of the column space is given;
+//          this start does not depend on which basis of the column space is given.  One
+//          launch per chosen row spreads the n x r residual over all CUs;
 //   swaps: B = Q Q[I]^-1; while max |B_ij| > tau, row i replaces the j-th chosen row and B
 //          gets the rank-one correction B -= B(:,j) (B(i,:) - e_j) / B_ij.
 //   Ties in every argmax go to the smallest row, then the smallest column.
@@ -59,46 +60,98 @@ __device__ Best block_best(Best b, Best *red) {
   return r;
 }
 
-// greedy start: R (n x r, workspace copy of Q) is destroyed; rows -> rows_dev.
-// nrm (n doubles of workspace) holds the current squared residual norm of every row.
-__global__ __launch_bounds__(NT) void k_greedy(double *__restrict__ R, int n, int r, int ldr,
-                                               double *__restrict__ nrm,
-                                               int *__restrict__ rows_dev) {
-  __shared__ Best red[NT / 64 + 1];
-  __shared__ double v[128];
-  for (int i = threadIdx.x; i < n; i += NT) {
+// Greedy start, one launch per chosen row over all CUs: each block owns GB rows of R (the
+// residual of Q, updated in place) and publishes its best row (squared residual norm,
+// index, and the row itself) into a double-buffered candidate table.  The next launch picks
+// the winner among the block candidates (largest norm, then smallest row), normalises its
+// row to v, projects v out of every owned row and publishes new candidates.  Every row
+// update and norm is summed in the same order as a single-block sweep would.
+constexpr int GB = 256;
+
+__device__ Best block_best_gb(Best b, Best *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  b = wave_best(b);
+  if (lane == 0) red[wave] = b;
+  __syncthreads();
+  if (wave == 0) {
+    Best x = lane < GB / 64 ? red[lane] : Best{-1.0, 0x7fffffff, 0x7fffffff};
+    x = wave_best(x);
+    if (lane == 0) red[GB / 64] = x;
+  }
+  __syncthreads();
+  return red[GB / 64];
+}
+
+__global__ __launch_bounds__(GB) void k_greedy_init(const double *__restrict__ R, int n, int r,
+                                                    int ldr, double *__restrict__ cval,
+                                                    int *__restrict__ cidx,
+                                                    double *__restrict__ cvec) {
+  __shared__ Best red[GB / 64 + 1];
+  const int i = blockIdx.x * GB + threadIdx.x;
+  Best b{-1.0, n, 0};
+  if (i < n) {
     double s = 0.0;
     for (int c = 0; c < r; ++c) {
       const double x = R[i + (size_t)c * ldr];
       s += x * x;
     }
-    nrm[i] = s;
+    b = Best{s, i, 0};
   }
-  for (int t = 0; t < r; ++t) {
-    Best b{-1.0, n, 0};
-    for (int i = threadIdx.x; i < n; i += NT) {
-      Best cand{nrm[i], i, 0};
+  const Best w = block_best_gb(b, red);
+  if (threadIdx.x == 0) {
+    cval[blockIdx.x] = w.v;
+    cidx[blockIdx.x] = w.i;
+  }
+  for (int c = threadIdx.x; c < r; c += GB) cvec[(size_t)blockIdx.x * r + c] = R[w.i + (size_t)c * ldr];
+}
+
+__global__ __launch_bounds__(GB) void k_greedy_step(double *__restrict__ R, int n, int r, int ldr,
+                                                    int nblk, int t,
+                                                    const double *__restrict__ cval_in,
+                                                    const int *__restrict__ cidx_in,
+                                                    const double *__restrict__ cvec_in,
+                                                    double *__restrict__ cval_out,
+                                                    int *__restrict__ cidx_out,
+                                                    double *__restrict__ cvec_out,
+                                                    int *__restrict__ rows_dev) {
+  __shared__ Best red[GB / 64 + 1];
+  __shared__ double v[128];
+  __shared__ Best win;
+  if (threadIdx.x < 64) {
+    Best b{-1.0, 0x7fffffff, 0x7fffffff};
+    for (int k = threadIdx.x; k < nblk; k += 64) {
+      const Best cand{cval_in[k], cidx_in[k], k};
       if (better(cand, b)) b = cand;
     }
-    Best w = block_best(b, red);
-    const int is = w.i;
-    const double inv = w.v > 0.0 ? 1.0 / sqrt(w.v) : 0.0;
-    for (int c = threadIdx.x; c < r; c += NT) v[c] = R[is + (size_t)c * ldr] * inv;
-    if (threadIdx.x == 0) rows_dev[t] = is;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += NT) {
-      double d = 0.0;
-      for (int c = 0; c < r; ++c) d += R[i + (size_t)c * ldr] * v[c];
-      double s = 0.0;
-      for (int c = 0; c < r; ++c) {
-        const double x = R[i + (size_t)c * ldr] - d * v[c];
-        R[i + (size_t)c * ldr] = x;
-        s += x * x;
-      }
-      nrm[i] = s;
-    }
-    __syncthreads();
+    b = wave_best(b);
+    if (threadIdx.x == 0) win = b;
   }
+  __syncthreads();
+  const Best w = win;
+  const double inv = w.v > 0.0 ? 1.0 / sqrt(w.v) : 0.0;
+  for (int c = threadIdx.x; c < r; c += GB) v[c] = cvec_in[(size_t)w.j * r + c] * inv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) rows_dev[t] = w.i;
+  __syncthreads();
+  const int i = blockIdx.x * GB + threadIdx.x;
+  Best b{-1.0, n, 0};
+  if (i < n) {
+    double d = 0.0;
+    for (int c = 0; c < r; ++c) d += R[i + (size_t)c * ldr] * v[c];
+    double s = 0.0;
+    for (int c = 0; c < r; ++c) {
+      const double x = R[i + (size_t)c * ldr] - d * v[c];
+      R[i + (size_t)c * ldr] = x;
+      s += x * x;
+    }
+    b = Best{s, i, 0};
+  }
+  const Best bb = block_best_gb(b, red);   // its barrier also publishes the row updates
+  if (threadIdx.x == 0) {
+    cval_out[blockIdx.x] = bb.v;
+    cidx_out[blockIdx.x] = bb.i;
+  }
+  for (int c = threadIdx.x; c < r; c += GB)
+    cvec_out[(size_t)blockIdx.x * r + c] = R[bb.i + (size_t)c * ldr];
 }
 
 // swap iterations on B = Q Q[I]^-1 (n x r, ld n)
@@ -277,11 +330,22 @@ void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int 
   TT_REQUIRE(r >= 1 && r <= 96 && n >= r, "maxvol: need n >= r, 1 <= r <= 96");
   Scope sc(c.arena);
   double *R = c.arena.dalloc((size_t)n * r);
-  double *nrm = c.arena.dalloc((size_t)n);
   copy_scale(c, R, n, Q, ldq, n, r, 1.0);
   {
+    const int nblk = (n + GB - 1) / GB;
+    double *cval = c.arena.dalloc(2 * (size_t)nblk);
+    int *cidx = c.arena.ialloc(2 * (size_t)nblk);
+    double *cvec = c.arena.dalloc(2 * (size_t)nblk * r);
     TimedLaunch tl(c, "maxvol_greedy", 4.0 * n * r * r, 8.0 * 3.0 * n * r);
-    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(NT), 0, c.stream, R, n, r, n, nrm, rows_dev);
+    hipLaunchKernelGGL(k_greedy_init, dim3(nblk), dim3(GB), 0, c.stream, R, n, r, n, cval, cidx,
+                       cvec);
+    for (int t = 0; t < r; ++t) {
+      const int pi = t & 1, po = pi ^ 1;
+      hipLaunchKernelGGL(k_greedy_step, dim3(nblk), dim3(GB), 0, c.stream, R, n, r, n, nblk, t,
+                         cval + pi * nblk, cidx + pi * nblk, cvec + (size_t)pi * nblk * r,
+                         cval + po * nblk, cidx + po * nblk, cvec + (size_t)po * nblk * r,
+                         rows_dev);
+    }
   }
   // B = Q Q[I]^-1
   double *QI = c.arena.dalloc((size_t)r * r);

@@ -53,6 +53,13 @@ struct Solver {
   int last_terms = 0;
   double last_err = 0.0;
   int *rep_idx = nullptr;      // row j*nq + m -> j
+  // learned pivot proposer (TT_PIV_*): model, per-site validation error of the last plain
+  // cross, and counters
+  PivotModel *pm = nullptr;
+  int piv_mode = TT_PIV_MAXVOL;
+  std::map<int, double> ref_err;
+  long long sweeps_run = 0, learned = 0, fallbacks = 0;
+  double max_learned_err = 0.0;
 
   static DTT alloc(Ctx &w, int n1, int n2, int cap) {
     DTT t;
@@ -62,6 +69,17 @@ struct Solver {
     t.A = w.arena.dalloc((size_t)n1 * std::max(cap, 1));
     t.B = w.arena.dalloc((size_t)n2 * std::max(cap, 1));
     return t;
+  }
+
+  // every task sets its worker's arithmetic to this solver's (an ensemble shares workers)
+  void run_tasks(std::vector<Pool::Task> tasks) {
+    const bool f32 = p.precision == TT_PREC_F32;
+    for (auto &t : tasks)
+      t = [f32, f = std::move(t)](Ctx &w) {
+        w.fp32 = f32;
+        f(w);
+      };
+    exec->run(std::move(tasks));
   }
 
   DTT rnd(Ctx &w, const DTT &x) {
@@ -143,24 +161,101 @@ struct Solver {
     const int m = std::min(y0.r, y0.n2);
     double *Qb = w.arena.dalloc((size_t)y0.n2 * std::max(m, 1));
     int k = 0;
-    orth(w, y0.B, y0.n2, y0.r, y0.n2, 1e-13, Qb, &k);
+    orth(w, y0.B, y0.n2, y0.r, y0.n2, w.fp32 ? 1e-6 : 1e-13, Qb, &k);
     if (k == 0) return {0};
     return maxvol_host(w, Qb, y0.n2, k, y0.n2, 1.05, 100);
   }
 
-  // cross into the preallocated `out` (capacity r_max)
+  // relative error |f - Y|_F / |Y|_F of a cross result Y on 8 seeded columns outside J
+  double validate(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y,
+                  const std::vector<int> &J, uint64_t key) {
+    Scope sc(w.arena);
+    const std::vector<int> Jv = kick_indices(J, n2, 8, key ^ 0x76A11DA7E5ull);
+    const int nv = (int)Jv.size();
+    if (nv == 0) return 0.0;
+    int *Jd = w.arena.ialloc(nv);
+    HIP_CHECK(hipMemcpyAsync(Jd, Jv.data(), nv * sizeof(int), hipMemcpyHostToDevice, w.stream));
+    double *Fv = w.arena.dalloc((size_t)n1 * nv), *Yv = w.arena.dalloc((size_t)n1 * nv);
+    double *G = w.arena.dalloc((size_t)nv * std::max(y.r, 1));
+    fiber_cols(w, fs, n1, Jd, nv, Fv);
+    gather_rows(w, G, nv, y.B, y.n2, Jd, nv, y.r);
+    gemm2(w, false, true, n1, nv, y.r, 1.0, y.A, y.n1, G, nv, 0.0, Yv, n1);
+    std::vector<double> f((size_t)n1 * nv), yy((size_t)n1 * nv);
+    HIP_CHECK(hipMemcpyAsync(f.data(), Fv, f.size() * 8, hipMemcpyDeviceToHost, w.stream));
+    HIP_CHECK(hipMemcpyAsync(yy.data(), Yv, yy.size() * 8, hipMemcpyDeviceToHost, w.stream));
+    w.sync();
+    double d2 = 0.0, y2 = 0.0;
+    for (size_t i = 0; i < f.size(); ++i) {
+      d2 += (f[i] - yy[i]) * (f[i] - yy[i]);
+      y2 += yy[i] * yy[i];
+    }
+    return y2 > 0.0 ? std::sqrt(d2 / y2) : std::sqrt(d2);
+  }
+
+  // cross into the preallocated `out` (capacity r_max).  Pivots: the same site's columns of
+  // the previous step (or maxvol of the starting TT), refined by the maxvol sweeps; with the
+  // learned proposer, its top-K columns and one sweep when the validation check passes.
   void cross(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y0, int site, DTT &out) {
     std::vector<int> J0;
+    double ref = -1.0;
     {
       std::lock_guard<std::mutex> lk(mu);
       auto it = piv.find(site);
       if (it != piv.end()) J0 = it->second;
+      auto ie = ref_err.find(site);
+      if (ie != ref_err.end()) ref = ie->second;
     }
+    const bool have_prev = !J0.empty();
     if (J0.empty()) J0 = initial_columns(w, y0);
     const uint64_t key = ((uint64_t)site << 32) | (uint64_t)(step_index & 0xFFFFFFFFll);
     std::vector<int> J;
+    Scope sc(w.arena);
+    bf16_t *Xb = nullptr;
+    if (pm && piv_mode != TT_PIV_MAXVOL && have_prev && (int)J0.size() <= 128) {
+      int *Jd = w.arena.ialloc(J0.size());
+      HIP_CHECK(hipMemcpyAsync(Jd, J0.data(), J0.size() * sizeof(int), hipMemcpyHostToDevice,
+                               w.stream));
+      Xb = static_cast<bf16_t *>(w.arena.alloc((size_t)n2 * PM_F * sizeof(bf16_t)));
+      pivot_features(w, y0.B, n2, y0.r, y0.n2, Jd, (int)J0.size(), nullptr, Xb);
+    }
+    if (piv_mode == TT_PIV_LEARNED && Xb && ref >= 0.0) {
+      std::vector<int> Jp;
+      {
+        Scope s2(w.arena);
+        float *sc_dev = static_cast<float *>(w.arena.alloc((size_t)n2 * sizeof(float)));
+        pm->forward(w, Xb, n2, sc_dev, nullptr, nullptr);
+        const int K = std::min(std::min(p.r_max, (int)J0.size() + p.cross_kick), n2);
+        int *Kd = w.arena.ialloc(K);
+        topk_indices(w, sc_dev, n2, K, Kd);
+        Jp.resize(K);
+        HIP_CHECK(hipMemcpyAsync(Jp.data(), Kd, K * sizeof(int), hipMemcpyDeviceToHost,
+                                 w.stream));
+        w.sync();
+      }
+      cross_tt(w, fs, n1, n2, Jp, p.eps, p.r_max, 1, 0, key, out, &J);
+      const double err = validate(w, fs, n1, n2, out, J, key);
+      std::lock_guard<std::mutex> lk(mu);
+      sweeps_run += 1;
+      if (err <= std::max(1e-6, 2.0 * ref)) {
+        learned++;
+        max_learned_err = std::max(max_learned_err, err);
+        piv[site] = J;
+        return;
+      }
+      fallbacks++;
+    }
     cross_tt(w, fs, n1, n2, J0, p.eps, p.r_max, p.cross_sweeps, p.cross_kick, key, out, &J);
+    double err = -1.0;
+    if (piv_mode != TT_PIV_MAXVOL) err = validate(w, fs, n1, n2, out, J, key);
+    if (piv_mode == TT_PIV_LOG && Xb) {
+      int *Jd = w.arena.ialloc(J.size());
+      HIP_CHECK(hipMemcpyAsync(Jd, J.data(), J.size() * sizeof(int), hipMemcpyHostToDevice,
+                               w.stream));
+      pm->append(w, Xb, Jd, (int)J.size(), n2);
+    }
     std::lock_guard<std::mutex> lk(mu);
+    sweeps_run += p.cross_sweeps;
+    if (err >= 0.0) ref_err[site] = err;
     piv[site] = J;
   }
 
@@ -265,7 +360,7 @@ struct Solver {
             tasks.push_back([this, &QD, &qm, &qp, &sb, d, v, side](Ctx &w) {
               weno_state(w, QD[d][v], v, side, sb[d], side == 0 ? qm[d][v] : qp[d][v]);
             });
-      exec->run(std::move(tasks));
+      run_tasks(std::move(tasks));
     }
     if (!p.nonlinear) {
       const double g = p.g, H = p.H0, cw = std::sqrt(g * H);
@@ -314,7 +409,7 @@ struct Solver {
           fl.g = p.g;
           cross(w, fl, nf, n * nq, y0, sb[d], lam[d]);
         });
-      exec->run(std::move(tasks));
+      run_tasks(std::move(tasks));
     }
     // phase B: dissipation, LLF flux and finish, per direction and variable
     for (int d = 0; d < 2; ++d)
@@ -329,7 +424,7 @@ struct Solver {
             DTT Fh = rnd(w, add(w, {{0.5, F[d][0][v]}, {0.5, F[d][1][v]}, {-0.5, D}}));
             finish(w, Fh, dF[d][v]);
           });
-      exec->run(std::move(tasks));
+      run_tasks(std::move(tasks));
     }
   }
 
@@ -352,7 +447,7 @@ struct Solver {
         round_tt(w, add(w, terms), p.eps, p.r_max, out[v], nullptr);
       });
     c.sync();
-    exec->run(std::move(tasks));
+    run_tasks(std::move(tasks));
   }
 
   void combine(const DTT *A, double a, const DTT *B, double b, DTT *out) {
@@ -362,7 +457,7 @@ struct Solver {
         round_tt(w, add(w, {{a, A[v]}, {b, B[v]}}), p.eps, p.r_max, out[v], nullptr);
       });
     c.sync();
-    exec->run(std::move(tasks));
+    run_tasks(std::move(tasks));
   }
 
   void step(double dt) {
@@ -401,6 +496,8 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
              "tt_fv_init: taylor_terms < 1");
   TT_REQUIRE(p->recip == 0 || p->recip == 1, "tt_fv_init: recip must be 0 or 1");
   TT_REQUIRE(p->workers >= -1 && p->workers <= 16, "tt_fv_init: workers must be in [-1, 16]");
+  TT_REQUIRE(p->precision == TT_PREC_F64 || p->precision == TT_PREC_F32,
+             "tt_fv_init: unknown precision");
   TT_REQUIRE(p->recip == 0 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
@@ -414,6 +511,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   try {
     s->p = *p;
     s->c.stream = (hipStream_t)stream;
+    s->c.fp32 = p->precision == TT_PREC_F32;
     const size_t ab = arena_bytes ? arena_bytes : ((size_t)4 << 30);
     s->c.arena.init(ab);
     int dev = 0;
@@ -555,6 +653,10 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
     t.warnings |= w.warnings;
     t.extra_power_iters += w.extra_power_iters;
   }
+  o->cross_sweeps_run = s->sweeps_run;
+  o->learned_crosses = s->learned;
+  o->learned_fallbacks = s->fallbacks;
+  o->max_learned_err = s->max_learned_err;
   o->roundings = t.roundings;
   o->crosses = t.crosses;
   o->last_taylor_terms = s->last_terms;
@@ -587,6 +689,12 @@ void solver_time_kernel(Solver *s, const char *name) {
     c->timer.ms = c->timer.flops = c->timer.bytes = 0;
     c->timer.launches = 0;
   }
+}
+
+void solver_set_pivots(Solver *s, int mode, PivotModel *pm) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->piv_mode = mode;
+  s->pm = pm;
 }
 
 void solver_destroy(Solver *s) { delete s; }

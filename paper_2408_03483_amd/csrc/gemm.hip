@@ -1,11 +1,11 @@
-// FP64 GEMM for the dense core contractions of TT rounding (sketches, projections,
-// back-multiplication): C = alpha * op(A) * B + beta * C with op = I or transpose.
+// GEMM for the dense core contractions of TT rounding (sketches, projections,
+// back-multiplication): C = alpha * op(A) * B + beta * C with op = I or transpose, on the
+// matrix cores (FP64 MFMA, or FP32 MFMA when the context computes contractions in FP32).
 //
-// Tiling: 64 x 64 output tile per 256-thread block, K staged through LDS in slices of 16,
-// 4 x 4 register micro-tile per thread (rows tx + 16u, columns ty + 16v, so LDS reads are
-// conflict-free).  Tall-skinny contractions (few output tiles, long K) are split along K
-// over blockIdx.z into partial tiles that a second kernel sums in a fixed order, so the
-// result does not depend on scheduling.
+// Tiling: 64 x 64 or 64 x 128 output tile per 256-thread block, K staged through LDS in
+// slices of 16.  Tall-skinny contractions (few output tiles, long K) are split along K over
+// blockIdx.z into partial tiles that a second kernel sums in a fixed order, so the result
+// does not depend on scheduling.
 #include "common.h"
 
 #include <algorithm>
@@ -13,79 +13,111 @@
 namespace ttfv {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int BM = 64, BK = 16, NT = 256;
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(NT) void k_gemm(int M, int N, int K, int kchunk, double alpha,
-                                             const double *__restrict__ A, int lda,
-                                             const double *__restrict__ B, int ldb, double beta,
-                                             double *__restrict__ C, int ldc,
-                                             double *__restrict__ part) {
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
-  const int bm = blockIdx.x * BM, bn = blockIdx.y * BN;
+// Matrix-core variant: the block tile is 64 x BN2 (BN2 = 64 or 128), four waves each own a
+// 32 x (BN2/2) sub-tile built from 16x16 MFMA blocks (16x16x4, FP64 or FP32 operands with
+// accumulation in the same type).  Operand layout of the 16x16x4 instructions: lane l
+// supplies A(l % 16, l / 16) and B(l / 16, l % 16).  Result v of lane l is
+// D(4 (l / 16) + v, l % 16) for FP32 and D(l / 16 + 4 v, l % 16) for FP64 (both checked).
+// Operands are converted to T as they are staged in LDS; C and the split-K partials are FP64.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+template <typename T, int BN2, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchunk, double alpha,
+                                                  const double *__restrict__ A, int lda,
+                                                  const double *__restrict__ B, int ldb,
+                                                  double beta, double *__restrict__ C, int ldc,
+                                                  double *__restrict__ part) {
+  constexpr int TN = BN2 / 32;                   // 16-wide MFMA blocks per wave along N
+  __shared__ T As[BK][BM + 4];
+  __shared__ T Bs[BK][BN2 + 4];
+  using V = typename Mfma<T>::v4;
+  const int bm = blockIdx.x * BM, bn = blockIdx.y * BN2;
   const int k0 = blockIdx.z * kchunk;
   const int k1 = min(K, k0 + kchunk);
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * (BN2 / 2);
+  const int li = lane & 15, lk = lane >> 4;
+  V acc[2][TN];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int v = 0; v < TN; ++v) acc[u][v] = V{0, 0, 0, 0};
 
   for (int kk = k0; kk < k1; kk += BK) {
 #pragma unroll
     for (int t = tid; t < BM * BK; t += NT) {
       int i, k;
-      if (!TA) { i = t & 63; k = t >> 6; }       // A(i, k): contiguous along i
-      else     { k = t & 15; i = t >> 4; }       // A(k, i): contiguous along k
+      if (!TA) { i = t & 63; k = t >> 6; }
+      else     { k = t & 15; i = t >> 4; }
       const int gi = bm + i, gk = kk + k;
       double v = 0.0;
       if (gi < M && gk < k1) v = TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda];
-      As[k][i] = v;
+      As[k][i] = (T)v;
     }
 #pragma unroll
-    for (int t = tid; t < BN * BK; t += NT) {
+    for (int t = tid; t < BN2 * BK; t += NT) {
       int k, j;
-      if (!TB) { k = t & 15; j = t >> 4; }       // B(k, j): contiguous along k
-      else     { j = t & 63; k = t >> 6; }       // B(j, k) stored, contiguous along j
+      if (!TB) { k = t & 15; j = t >> 4; }
+      else     { j = t % BN2; k = t / BN2; }
       const int gj = bn + j, gk = kk + k;
       double v = 0.0;
       if (gj < N && gk < k1) v = TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb];
-      Bs[k][j] = v;
+      Bs[k][j] = (T)v;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < BK; ++k) {
-      double a[4], b[4];
+    for (int ks = 0; ks < BK; ks += 4) {
+      T a[2], b[TN];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = As[k][tx + 16 * u];
+      for (int u = 0; u < 2; ++u) a[u] = As[ks + lk][wr + 16 * u + li];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Bs[k][ty + 16 * v];
+      for (int v = 0; v < TN; ++v) b[v] = Bs[ks + lk][wc + 16 * v + li];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        for (int v = 0; v < TN; ++v) acc[u][v] = Mfma<T>::op(a[u], b[v], acc[u][v]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int gi = bm + tx + 16 * u;
-    if (gi >= M) continue;
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gj = bn + ty + 16 * v;
+    for (int v = 0; v < TN; ++v) {
+      const int gj = bn + wc + 16 * v + li;
       if (gj >= N) continue;
-      if (part) {
-        part[((size_t)blockIdx.z * N + gj) * M + gi] = acc[u][v];
-      } else {
-        double out = alpha * acc[u][v];
-        if (beta != 0.0) out += beta * C[gi + (size_t)gj * ldc];
-        C[gi + (size_t)gj * ldc] = out;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = bm + wr + 16 * u + Mfma<T>::row(lk, e);
+        if (gi >= M) continue;
+        const double r = (double)acc[u][v][e];
+        if (part) {
+          part[((size_t)blockIdx.z * N + gj) * M + gi] = r;
+        } else {
+          double out = alpha * r;
+          if (beta != 0.0) out += beta * C[gi + (size_t)gj * ldc];
+          C[gi + (size_t)gj * ldc] = out;
+        }
       }
     }
-  }
 }
 
 __global__ void k_splitk_reduce(int M, int N, int S, const double *__restrict__ part,
@@ -100,20 +132,33 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double *__restrict__ 
   C[i + (size_t)j * ldc] = out;
 }
 
-template <bool TA, bool TB>
+template <typename T, int BN2, bool TA, bool TB>
 void launch(Ctx &c, dim3 grid, int M, int N, int K, int kchunk, double alpha, const double *A,
             int lda, const double *B, int ldb, double beta, double *C, int ldc, double *part) {
-  hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(NT), 0, c.stream, M, N, K, kchunk, alpha, A, lda,
-                     B, ldb, beta, C, ldc, part);
+  hipLaunchKernelGGL((k_gemm_mfma<T, BN2, TA, TB>), grid, dim3(NT), 0, c.stream, M, N, K, kchunk,
+                     alpha, A, lda, B, ldb, beta, C, ldc, part);
 }
 
+template <typename T, int BN2>
 void dispatch(Ctx &c, bool ta, bool tb, dim3 grid, int M, int N, int K, int kchunk, double alpha,
               const double *A, int lda, const double *B, int ldb, double beta, double *C, int ldc,
               double *part) {
-  if (ta && tb) launch<true, true>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
-  else if (ta) launch<true, false>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
-  else if (tb) launch<false, true>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
-  else launch<false, false>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+  if (ta && tb) launch<T, BN2, true, true>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+  else if (ta) launch<T, BN2, true, false>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+  else if (tb) launch<T, BN2, false, true>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+  else launch<T, BN2, false, false>(c, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+}
+
+void dispatch_any(Ctx &c, int bn2, bool ta, bool tb, dim3 grid, int M, int N, int K, int kchunk,
+                  double alpha, const double *A, int lda, const double *B, int ldb, double beta,
+                  double *C, int ldc, double *part) {
+  if (c.fp32) {
+    if (bn2 == 128) dispatch<float, 128>(c, ta, tb, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+    else dispatch<float, 64>(c, ta, tb, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+  } else {
+    if (bn2 == 128) dispatch<double, 128>(c, ta, tb, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+    else dispatch<double, 64>(c, ta, tb, grid, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part);
+  }
 }
 
 }  // namespace
@@ -130,7 +175,9 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
     copy_scale(c, C, ldc, C, ldc, M, N, beta);
     return;
   }
-  const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  // 128-wide tiles when N fills them (each row panel of A is then read once)
+  const int bn2 = N > 64 ? 128 : 64;
+  const int tm = (M + BM - 1) / BM, tn = (N + bn2 - 1) / bn2;
   const int tiles = tm * tn;
   int S = 1;
   if (tiles < 256 && K >= 512) {
@@ -146,14 +193,14 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
   c.cnt.bytes += by;
   TimedLaunch tl(c, "gemm", fl, by);
   if (S == 1) {
-    dispatch(c, transA, transB, dim3(tm, tn, 1), M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C,
-             ldc, nullptr);
+    dispatch_any(c, bn2, transA, transB, dim3(tm, tn, 1), M, N, K, kchunk, alpha, A, lda, B, ldb,
+                 beta, C, ldc, nullptr);
     return;
   }
   Scope sc(c.arena);
   double *part = c.arena.dalloc((size_t)S * M * N);
-  dispatch(c, transA, transB, dim3(tm, tn, S), M, N, K, kchunk, alpha, A, lda, B, ldb, beta, C,
-           ldc, part);
+  dispatch_any(c, bn2, transA, transB, dim3(tm, tn, S), M, N, K, kchunk, alpha, A, lda, B, ldb,
+               beta, C, ldc, part);
   const size_t tot = (size_t)M * N;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                      c.stream, M, N, S, part, alpha, beta, C, ldc);

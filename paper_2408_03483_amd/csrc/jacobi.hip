@@ -15,9 +15,11 @@ namespace {
 constexpr int NT = 1024;
 constexpr int WAVES = NT / 64;
 
-// One group of 16 lanes (a DPP row) per column pair: column entries i = lane + 16 r.
+// One group of LP lanes (8 or 16) per column pair: column entries i = lane + LP r.  A round
+// is a dependent chain (loads, dot products, group reduction, rotation, stores, barrier),
+// so its latency, not the issue rate, sets the time per round.
 // Columns whose squared norm is below 1e-34 ||M||_F^2 are left alone (numerical zeros).
-template <int RS>
+template <int LP, int RS>
 __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int m,
                                                double *__restrict__ US,
                                                double *__restrict__ sig, int max_sweeps) {
@@ -28,9 +30,9 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   __shared__ int rotated;
   __shared__ double fro_part[NT / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  const int gid = threadIdx.x / LP, gl = threadIdx.x % LP;
+  const int nt = blockDim.x, ngroups = nt / LP;
   double part = 0.0;
-  const int nt = blockDim.x;
   for (int idx = threadIdx.x; idx < mm * m; idx += nt) {
     const double v = (idx < m * m) ? M[idx] : 0.0;
     S[idx] = v;
@@ -44,35 +46,41 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   const double tiny = 1e-34 * fro2;
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
   const double tol2 = tol * tol;
+  const int np = mm - 1;                        // round-robin over mm players, np rounds
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
-    for (int t = 0; t < mm - 1; ++t) {
-      for (int k = gid; k < mm / 2; k += nt / 16) {
-        const int a = (k + t) % (mm - 1);
-        const int b = (k == 0) ? (mm - 1) : ((mm - 1 - k + t) % (mm - 1));
+    for (int t = 0; t < np; ++t) {
+      for (int k = gid; k < mm / 2; k += ngroups) {
+        int a = k + t;
+        if (a >= np) a -= np;
+        int b = np - k + t;
+        if (b >= np) b -= np;
+        if (k == 0) b = np;
         const int p = min(a, b), q = max(a, b);
         double *cp = S + (size_t)p * m, *cq = S + (size_t)q * m;
         double xp[RS], xq[RS];
         double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
-          const int i = gl + 16 * r;
+          const int i = gl + LP * r;
           xp[r] = i < m ? cp[i] : 0.0;
           xq[r] = i < m ? cq[i] : 0.0;
           acc[0] += xp[r] * xp[r];
           acc[1] += xq[r] * xq[r];
           acc[2] += xp[r] * xq[r];
         }
-        row16_sum_n<3>(acc);
+        group_sum_n<LP, 3>(acc);
         const double al = acc[0], be = acc[1], ga = acc[2];
         if (al > tiny && be > tiny && ga * ga > tol2 * al * be) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          // tan of the rotation angle, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
+          // zeta = (be - al) / (2 ga), written with one square root and one division
+          const double d = be - al, g2 = 2.0 * ga;
+          const double tt = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(d * d + g2 * g2));
           const double c = rsqrt(1.0 + tt * tt), s = c * tt;
 #pragma unroll
           for (int r = 0; r < RS; ++r) {
-            const int i = gl + 16 * r;
+            const int i = gl + LP * r;
             if (i < m) {
               cp[i] = c * xp[r] - s * xq[r];
               cq[i] = s * xp[r] + c * xq[r];
@@ -184,20 +192,16 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
   const int mm = (m + 1) & ~1;
   const size_t lds = ((size_t)mm * m + mm) * sizeof(double);
   TimedLaunch tl(c, "jacobi", 22.0 * m * m * m, 8.0 * (2.0 * m * m + m));
-  const int nthreads = std::min(NT, std::max(64, ((mm / 2) * 16 + 63) / 64 * 64));
-  if (m <= 32) {
-    set_lds(k_jacobi<2>, lds);
-    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
-  } else if (m <= 64) {
-    set_lds(k_jacobi<4>, lds);
-    hipLaunchKernelGGL(k_jacobi<4>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
-  } else if (m <= 96) {
-    set_lds(k_jacobi<6>, lds);
-    hipLaunchKernelGGL(k_jacobi<6>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
-  } else {
-    set_lds(k_jacobi<8>, lds);
-    hipLaunchKernelGGL(k_jacobi<8>, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
-  }
+  // 16 lanes per pair (measured faster than 8 at m = 64); threads = pairs * lanes per pair
+  auto launch = [&](auto kern, int lp) {
+    const int nthreads = std::max(64, ((mm / 2) * lp + 63) / 64 * 64);
+    set_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
+  };
+  if (m <= 32) launch(k_jacobi<16, 2>, 16);
+  else if (m <= 64) launch(k_jacobi<16, 4>, 16);
+  else if (m <= 96) launch(k_jacobi<16, 6>, 16);
+  else launch(k_jacobi<16, 8>, 16);
   c.cnt.flops += 22.0 * m * m * m;
 }
 

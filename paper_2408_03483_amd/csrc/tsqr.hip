@@ -71,7 +71,14 @@ __device__ void qr_regs(T (&x)[CS][RS], int rows, int m, T *vbuf, T *taus) {
     }
     __syncthreads();
     const T t = taus[j];
-    if (t != T(0)) {
+    // groups holding no column right of j have nothing to update
+    bool active = false;
+#pragma unroll
+    for (int s = 0; s < CS; ++s) {
+      const int c = gid + NG * s;
+      active = active || (c > j && c < m);
+    }
+    if (t != T(0) && active) {
       T v[RS];
 #pragma unroll
       for (int r = 0; r < RS; ++r) v[r] = vb[gl + 16 * r];
@@ -408,6 +415,7 @@ void dispatch_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, int rs, int
     else run_tsqr<T, 16, 1>(c, Y, ldy, pl, Q, ldq, R, ldr);
   } else {
     if (rs <= 8) run_tsqr<T, 8, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
+    else if (rs <= 12) run_tsqr<T, 12, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
     else run_tsqr<T, 16, 2>(c, Y, ldy, pl, Q, ldq, R, ldr);
   }
 }
@@ -426,6 +434,8 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
   pl.m = m;
   // rows per leaf: registers hold <= 256 rows; the apply kernel keeps V (rows x m) in LDS
   pl.bmax = std::min(MAXROWS, (d - 2 * m) / m);
+  // two columns per lane group above 64 columns: 192-row blocks keep the panel in registers
+  if (m > NG) pl.bmax = std::min(pl.bmax, 192);
   TT_REQUIRE(pl.bmax >= 2 * m || n <= pl.bmax, "tsqr: LDS too small for this width");
   pl.nleaf = std::max(1, (n + pl.bmax - 1) / pl.bmax);
   pl.arity = std::max(2, std::min(16, std::min(MAXROWS / m, (d - m) / (m * m))));

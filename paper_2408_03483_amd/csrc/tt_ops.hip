@@ -369,12 +369,15 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
   double *Qr = c.arena.dalloc((size_t)n2 * jcap);
   std::vector<int> I;
   int rc = 0;
+  // fiber directions below this fraction of the largest are dropped: round-off level of
+  // the QR's arithmetic
+  const double drop = c.fp32 ? 1e-6 : 1e-13;
   for (int s = 0; s < sweeps; ++s) {
     TT_REQUIRE((int)J.size() <= qmax, "cross: column set exceeds the factorization width");
     HIP_CHECK(hipMemcpyAsync(Jd, J.data(), J.size() * sizeof(int), hipMemcpyHostToDevice,
                              c.stream));
     fiber_cols(c, fs, n1, Jd, (int)J.size(), C);
-    orth(c, C, n1, (int)J.size(), n1, 1e-13, Qc, &rc);
+    orth(c, C, n1, (int)J.size(), n1, drop, Qc, &rc);
     if (rc == 0) {
       zero_tt(c, y);
       if (J_out) *J_out = J;
@@ -386,7 +389,7 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
     fiber_rows(c, fs, n2, Id, rc, RwT);
     if (s == sweeps - 1) break;
     int rr = 0;
-    orth(c, RwT, n2, rc, n2, 1e-13, Qr, &rr);
+    orth(c, RwT, n2, rc, n2, drop, Qr, &rr);
     if (rr == 0) {
       zero_tt(c, y);
       if (J_out) *J_out = J;

@@ -72,3 +72,28 @@ __device__ __forceinline__ void row16_sum_n(T (&v)[N]) {
 }
 
 }  // namespace ttfv
+
+namespace ttfv {
+
+// Sum over each group of 8 lanes (half a DPP row), returned in every lane of the group:
+// quad_perm [1,0,3,2] and [2,3,0,1] add within quads, row_half_mirror adds the other quad.
+// The pairs added are symmetric, so the 8 lanes hold bitwise-identical results.
+template <int N>
+__device__ __forceinline__ void group8_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += dpp_shift<0xB1>(v[k]);    // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += dpp_shift<0x4E>(v[k]);    // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] += dpp_shift<0x141>(v[k]);   // row_half_mirror
+}
+
+template <int LP, int N>
+__device__ __forceinline__ void group_sum_n(double (&v)[N]) {
+  static_assert(LP == 8 || LP == 16, "group of 8 or 16 lanes");
+  if constexpr (LP == 8) group8_sum_n<N>(v);
+  else row16_sum_n<N>(v);
+}
+
+}  // namespace ttfv
+

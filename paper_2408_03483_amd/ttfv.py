@@ -37,7 +37,8 @@ class ParamsC(ctypes.Structure):
                 ("periodic", ctypes.c_int), ("g", ctypes.c_double), ("H0", ctypes.c_double),
                 ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
-                ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int)]
+                ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int),
+                ("precision", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):
@@ -47,14 +48,24 @@ class StatsC(ctypes.Structure):
                 ("warnings", ctypes.c_int), ("flops", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("timed_ms", ctypes.c_double),
                 ("timed_launches", ctypes.c_longlong), ("timed_flops", ctypes.c_double),
-                ("timed_bytes", ctypes.c_double)]
+                ("timed_bytes", ctypes.c_double), ("cross_sweeps_run", ctypes.c_longlong),
+                ("learned_crosses", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_longlong),
+                ("max_learned_err", ctypes.c_double)]
 
 
-EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_round",
+PRECISIONS = {"f64": 0, "f32": 1}
+
+EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_precision",
+           "tt_round",
            "tt_hadamard_round", "tt_reciprocal", "tt_maxvol", "tt_cross", "tt_recon_core",
            "tt_fv_init", "tt_fv_step", "tt_fv_get_state", "tt_fv_get_stats", "tt_fv_destroy",
            "tt_fv_time_kernel", "tt_ens_create", "tt_ens_step", "tt_ens_destroy",
-           "tt_last_error"]
+           "tt_pm_create", "tt_pm_destroy", "tt_pm_set_weights", "tt_pm_get_weights",
+           "tt_pm_forward", "tt_pm_grad", "tt_pm_train", "tt_pm_dataset", "tt_pm_features",
+           "tt_pm_topk", "tt_fv_set_pivots", "tt_last_error"]
+
+PM_NPARAM = 70401
+PIVOTS = {"maxvol": 0, "log": 1, "learned": 2}
 
 _lib = None
 
@@ -74,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_destroy.argtypes = [P]
     L.tt_ctx_destroy.restype = None
     L.tt_ctx_set_sketch.argtypes = [P, I, I]
+    L.tt_ctx_set_precision.argtypes = [P, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
     L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
@@ -92,6 +104,19 @@ def load_library(path: str = LIB_PATH):
     L.tt_ens_step.argtypes = [P, ctypes.POINTER(P), I, ctypes.POINTER(D), I, I]
     L.tt_ens_destroy.argtypes = [P]
     L.tt_ens_destroy.restype = None
+    pF = ctypes.POINTER(ctypes.c_float)
+    L.tt_pm_create.argtypes = [ctypes.POINTER(P), S, ctypes.c_ulonglong]
+    L.tt_pm_destroy.argtypes = [P]
+    L.tt_pm_destroy.restype = None
+    L.tt_pm_set_weights.argtypes = [P, pF, S]
+    L.tt_pm_get_weights.argtypes = [P, pF, S]
+    L.tt_pm_forward.argtypes = [P, P, I, P]
+    L.tt_pm_grad.argtypes = [P, P, P, I, D, pF, S, ctypes.POINTER(D)]
+    L.tt_pm_train.argtypes = [P, I, I, D, ctypes.POINTER(D)]
+    L.tt_pm_dataset.argtypes = [P, ctypes.POINTER(S), ctypes.POINTER(S)]
+    L.tt_pm_features.argtypes = [P, P, I, I, I, P, I, P]
+    L.tt_pm_topk.argtypes = [P, P, I, I, P]
+    L.tt_fv_set_pivots.argtypes = [P, I, P]
     for name in EXPORTS:
         if not hasattr(L, name):
             raise RuntimeError(f"libttfv.so lacks {name}")
@@ -180,6 +205,10 @@ def tt_ctx_create(arena_bytes: int = 1 << 30, stream=None) -> Ctx:
 
 def tt_ctx_set_sketch(ctx: Ctx, width: int, power_iters: int) -> None:
     _check(_lib.tt_ctx_set_sketch(ctx.h, width, power_iters), "tt_ctx_set_sketch")
+
+
+def tt_ctx_set_precision(ctx: Ctx, precision: str) -> None:
+    _check(_lib.tt_ctx_set_precision(ctx.h, PRECISIONS[precision]), "tt_ctx_set_precision")
 
 
 def tt_round(ctx: Ctx, x: DeviceTT, eps: float, r_max: int, y: DeviceTT):
@@ -276,12 +305,12 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                g: float = 9.81, H0: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
-               arena_bytes: int = 4 << 30) -> Solver:
+               arena_bytes: int = 4 << 30, precision: str = "f64") -> Solver:
     L = load_library()
     _torch()
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
-                workers)
+                workers, PRECISIONS[precision])
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -311,7 +340,9 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "last_taylor_err": st.last_taylor_err, "warnings": st.warnings,
             "flops": st.flops, "bytes": st.bytes, "timed_ms": st.timed_ms,
             "timed_launches": st.timed_launches, "timed_flops": st.timed_flops,
-            "timed_bytes": st.timed_bytes}
+            "timed_bytes": st.timed_bytes, "cross_sweeps_run": st.cross_sweeps_run,
+            "learned_crosses": st.learned_crosses, "learned_fallbacks": st.learned_fallbacks,
+            "max_learned_err": st.max_learned_err}
 
 
 def tt_fv_time_kernel(s: Solver, name: Optional[str]) -> None:
@@ -355,3 +386,106 @@ def tt_ens_step(e: Ensemble, members: Sequence[Solver], dts: Sequence[float], ns
 
 def tt_ens_destroy(e: Ensemble) -> None:
     e.close()
+
+
+# ---- learned pivot proposer -------------------------------------------------------------
+
+class PivotModel:
+    """Handle of a pivot-proposer model (weights on the device, training log)."""
+
+    def __init__(self, max_rows: int = 0, seed: int = 0):
+        L = load_library()
+        _torch()
+        self.h = ctypes.c_void_p()
+        _check(L.tt_pm_create(ctypes.byref(self.h), max_rows, seed), "tt_pm_create")
+
+    def close(self):
+        if self.h:
+            _lib.tt_pm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, flat: np.ndarray) -> None:
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(_lib.tt_pm_set_weights(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                      a.size), "tt_pm_set_weights")
+
+    def get_weights(self) -> np.ndarray:
+        a = np.zeros(PM_NPARAM, dtype=np.float32)
+        _check(_lib.tt_pm_get_weights(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                      a.size), "tt_pm_get_weights")
+        return a
+
+    def forward(self, X):
+        """X: torch float32 (N, 16) on the GPU -> scores (N,) float32."""
+        torch = _torch()
+        X = X.contiguous()
+        s = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(_lib.tt_pm_forward(self.h, X.data_ptr(), X.shape[0], s.data_ptr()),
+               "tt_pm_forward")
+        return s
+
+    def grad(self, X, y, pos_weight: float):
+        X, y = X.contiguous(), y.contiguous()
+        g = np.zeros(PM_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(_lib.tt_pm_grad(self.h, X.data_ptr(), y.data_ptr(), X.shape[0], pos_weight,
+                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), g.size,
+                               ctypes.byref(loss)), "tt_pm_grad")
+        return loss.value, g
+
+    def train(self, epochs: int = 4, batch: int = 8192, lr: float = 1e-3) -> float:
+        loss = ctypes.c_double()
+        _check(_lib.tt_pm_train(self.h, epochs, batch, lr, ctypes.byref(loss)), "tt_pm_train")
+        return loss.value
+
+    def dataset(self):
+        rows, pos = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.tt_pm_dataset(self.h, ctypes.byref(rows), ctypes.byref(pos)), "tt_pm_dataset")
+        return rows.value, pos.value
+
+
+def pm_flat(p: dict) -> np.ndarray:
+    """Flat parameter vector from W1, b1, W2, b2, w3, b3 arrays."""
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).reshape(-1)
+                           for k in ("W1", "b1", "W2", "b2", "w3", "b3")])
+
+
+def pm_unflat(flat: np.ndarray) -> dict:
+    F, H = 16, 256
+    sizes = [("W1", (F, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))]
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(shp)
+        o += n
+    return out
+
+
+def tt_pm_features(ctx: Ctx, B0, r: int, J_prev):
+    """Features (n2, 16) float32 of a cross whose starting TT has second core B0 (torch
+    float64 tensor (cap, n2) as in DeviceTT.g2; the first r rows are used)."""
+    torch = _torch()
+    n2 = B0.shape[1]
+    Jd = torch.tensor(list(J_prev) or [0], dtype=torch.int32, device=B0.device)
+    X = torch.empty((n2, 16), dtype=torch.float32, device=B0.device)
+    _check(_lib.tt_pm_features(ctx.h, B0.data_ptr(), n2, r, n2, Jd.data_ptr(), len(J_prev),
+                               X.data_ptr()), "tt_pm_features")
+    return X
+
+
+def tt_pm_topk(ctx: Ctx, s, k: int):
+    torch = _torch()
+    out = torch.empty(k, dtype=torch.int32, device=s.device)
+    _check(_lib.tt_pm_topk(ctx.h, s.data_ptr(), s.shape[0], k, out.data_ptr()), "tt_pm_topk")
+    return out
+
+
+def tt_fv_set_pivots(s: Solver, mode: str, model: Optional[PivotModel] = None) -> None:
+    _check(_lib.tt_fv_set_pivots(s.h, PIVOTS[mode], model.h if model is not None else None),
+           "tt_fv_set_pivots")

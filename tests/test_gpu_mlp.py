@@ -1,0 +1,197 @@
+"""GPU parity of the learned pivot proposer (BF16 perceptron on the matrix cores) against
+the float64 oracle, through the C ABI: features, top-K selection, forward scores and
+gradients, training, and the solver's crosses with proposed pivots."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as omlp
+from oracle import tt as ott
+from oracle import tt_fv as otf
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_03483_amd import ttfv
+    ttfv.load_library()
+    return ttfv
+
+
+def bf16_round(x):
+    """Round float64 values to bfloat16 (nearest even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _weights(seed):
+    rng = np.random.default_rng(seed)
+    p = omlp.init_weights(rng)
+    p["b1"] = rng.standard_normal(omlp.H) * 0.1
+    p["b2"] = rng.standard_normal(omlp.H) * 0.1
+    p["b3"] = np.array([0.05])
+    return p
+
+
+def _rounded(p):
+    q = dict(p)
+    for k in ("W1", "W2", "w3"):
+        q[k] = bf16_round(p[k])
+    return q
+
+
+def test_features_match_oracle(lib):
+    import torch
+    _say("pivot features n2=1000 r=7")
+    rng = np.random.default_rng(5)
+    n2, r = 1000, 7
+    B = rng.standard_normal((n2, r)) * np.exp(-np.arange(r))
+    J = sorted(rng.choice(n2, size=20, replace=False).tolist())
+    t = lib.DeviceTT.from_factors(np.zeros((3, r)), B)
+    c = lib.tt_ctx_create(1 << 28)
+    X = lib.tt_pm_features(c, t.g2, r, J).cpu().numpy().astype(np.float64)
+    c.close()
+    ref = omlp.features(B, J)
+    assert np.allclose(X, ref, rtol=2e-6, atol=2e-6)
+
+
+def test_topk_exact_with_ties(lib):
+    import torch
+    _say("top-k n=5003 k=70 with ties")
+    rng = np.random.default_rng(6)
+    s = np.round(rng.standard_normal(5003) * 4) / 4          # many equal scores
+    k = 70
+    order = sorted(range(s.size), key=lambda i: (-s[i], i))[:k]
+    c = lib.tt_ctx_create(1 << 28)
+    got = lib.tt_pm_topk(c, torch.from_numpy(s.astype(np.float32)).cuda(), k).cpu().numpy()
+    c.close()
+    assert got.tolist() == sorted(order)
+
+
+def test_forward_matches_oracle(lib):
+    import torch
+    _say("mlp forward N=300")
+    rng = np.random.default_rng(7)
+    p = _weights(8)
+    X = rng.standard_normal((300, omlp.F))
+    m = lib.PivotModel(0, 1)
+    m.set_weights(lib.pm_flat(p))
+    s = m.forward(torch.from_numpy(X.astype(np.float32)).cuda()).cpu().numpy()
+    m.close()
+    ref, _ = omlp.forward(_rounded(p), bf16_round(X))
+    e = np.linalg.norm(s - ref) / np.linalg.norm(ref)
+    _say(f"  rel {e:.2e}")
+    assert e < 2e-2
+
+
+def test_gradients_match_oracle(lib):
+    import torch
+    _say("mlp gradients N=1000")
+    rng = np.random.default_rng(9)
+    p = _weights(10)
+    N = 1000
+    X = rng.standard_normal((N, omlp.F))
+    y = (rng.random(N) < 0.05).astype(np.float64)
+    pw = 12.0
+    m = lib.PivotModel(0, 1)
+    m.set_weights(lib.pm_flat(p))
+    loss, g = m.grad(torch.from_numpy(X.astype(np.float32)).cuda(),
+                     torch.from_numpy(y.astype(np.float32)).cuda(), pw)
+    m.close()
+    q = _rounded(p)
+    s, cache = omlp.forward(q, bf16_round(X))
+    ref_loss = omlp.loss(s, y, pw)
+    ref = omlp.backward(q, cache, s, y, pw)
+    gg = lib.pm_unflat(g)
+    assert abs(loss - ref_loss) <= 1e-2 * ref_loss
+    for k in ref:
+        e = np.linalg.norm(gg[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-30)
+        _say(f"  {k}: rel {e:.2e}")
+        assert e < 5e-2, k
+
+
+def _dam_break_solver(lib, st, rmax, eps, precision="f64"):
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+    return lib.tt_fv_init(st.n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
+                          recip="cross", arena_bytes=1 << 30, precision=precision)
+
+
+def test_training_reduces_loss_and_learned_steps_stay_valid(lib):
+    """Log (features, maxvol pivots) from two plain steps of a 48^2 dam break, train, then
+    take two steps with proposed pivots: the proposer must be used (accepted or rejected by
+    the validation check) and the result must stay as close to the full-grid scheme as the
+    plain oracle's (within twice its distance plus 20 eps)."""
+    from oracle import fv_grid
+    _say("learned pivots on the 48^2 dam break")
+    st = synth.dam_break(seed=0, n=48, rmax=24, eps=1e-8, width=0.05)
+    m = lib.PivotModel(1 << 20, 3)
+    s = _dam_break_solver(lib, st, 24, 1e-8)
+    lib.tt_fv_set_pivots(s, "log", m)
+    lib.tt_fv_step(s, st.dt, 2)
+    rows, pos = m.dataset()
+    assert rows > 0 and 0 < pos < rows
+    l0 = m.train(epochs=1, batch=4096, lr=1e-3)
+    l1 = m.train(epochs=40, batch=4096, lr=1e-3)
+    _say(f"  {rows} rows, {pos} pivots, loss {l0:.4f} -> {l1:.4f}")
+    assert l1 < l0
+    lib.tt_fv_set_pivots(s, "learned", m)
+    lib.tt_fv_step(s, st.dt, 2)
+    stats = lib.tt_fv_get_stats(s)
+    Qg = lib.tt_fv_get_state(s)
+    s.close()
+    m.close()
+    _say(f"  learned {stats['learned_crosses']} fallbacks {stats['learned_fallbacks']} "
+         f"sweeps {stats['cross_sweeps_run']} max err {stats['max_learned_err']:.2e}")
+    assert stats["learned_crosses"] + stats["learned_fallbacks"] > 0
+    assert stats["max_learned_err"] <= 1e-2
+    U = [f.full() for f in st.tt]
+    gs = fv_grid.GridSolver(st.n, "weno5", True, False, g=st.g)
+    for _ in range(4):
+        U = gs.step(U, st.dt)
+    ts = otf.TTSolver(st.n, "weno5", True, False, g=st.g, eps=1e-8, rmax=24, recip="cross")
+    Qo = ts.run([ott.TT(f.A, f.B) for f in st.tt], st.dt, 4)
+    scale = np.linalg.norm(U[0])
+    for c in range(3):
+        e_o = np.linalg.norm(Qo[c].full() - U[c]) / scale
+        e_g = np.linalg.norm(Qg[c].full() - U[c]) / scale
+        _say(f"  var {c}: oracle-vs-grid {e_o:.3e} learned-vs-grid {e_g:.3e}")
+        assert e_g <= 2.0 * e_o + 20 * 1e-8
+
+
+def test_learned_pivots_full_rank_unique(lib):
+    """At full rank (cap = n) every cross reproduces its function exactly, so the step is
+    unique whatever the pivots: the learned path must match the oracle to 1e-9."""
+    _say("learned pivots, 16^2 WENO5 full rank")
+    st = synth.nonlinear_bumps(seed=4, n=16, rmax=16, eps=0.0)
+    m = lib.PivotModel(1 << 18, 5)
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=16) for f in st.tt]
+    s = lib.tt_fv_init(16, "weno5", True, True, dev, g=st.g, eps=0.0, r_max=16,
+                       taylor_terms=40, arena_bytes=1 << 28)
+    lib.tt_fv_set_pivots(s, "log", m)
+    lib.tt_fv_step(s, st.dt, 1)
+    m.train(epochs=5, batch=1024, lr=1e-3)
+    lib.tt_fv_set_pivots(s, "learned", m)
+    lib.tt_fv_step(s, st.dt, 1)
+    Qg = lib.tt_fv_get_state(s)
+    stats = lib.tt_fv_get_stats(s)
+    s.close()
+    m.close()
+    ts = otf.TTSolver(16, "weno5", True, True, g=st.g, eps=0.0, rmax=16, taylor_terms=40)
+    Qo = ts.run([ott.TT(f.A, f.B) for f in st.tt], st.dt, 2)
+    r = [np.linalg.norm(g.full() - o.full()) / np.linalg.norm(o.full()) for g, o in zip(Qg, Qo)]
+    _say(f"  rel {r}, learned {stats['learned_crosses']} fallbacks {stats['learned_fallbacks']}")
+    assert stats["learned_crosses"] + stats["learned_fallbacks"] > 0
+    assert max(r) <= 1e-9

@@ -87,6 +87,31 @@ def test_round_parity(lib, ctx, n1, n2, r, eps, rmax):
     assert np.allclose(sig, s_ref, rtol=1e-9, atol=1e-12 * np.linalg.norm(F))
 
 
+@pytest.mark.parametrize("n1,n2,r,eps,rmax", [
+    (300, 200, 20, 1e-6, 32),       # exact path
+    (1000, 3000, 300, 1e-6, 32),    # randomized path
+    (777, 1531, 1024, 1e-5, 16),    # randomized path, ragged sizes
+])
+def test_round_fp32_contractions(lib, n1, n2, r, eps, rmax):
+    """FP32 contractions (GEMMs and QR panels on the matrix cores, SVD in FP64): the result
+    is within the FP32 noise (1e-5 relative) of the FP64 oracle's rounding."""
+    _say(f"round fp32 {n1}x{n2} r={r} eps={eps} rmax={rmax}")
+    c = lib.tt_ctx_create(1 << 30)
+    lib.tt_ctx_set_precision(c, "f32")
+    rng = np.random.default_rng(1)
+    A, B = decaying_tt(rng, n1, n2, r, decay=0.8)
+    x = lib.DeviceTT.from_factors(A, B)
+    y = lib.DeviceTT(n1, n2, rmax)
+    lib.tt_round(c, x, eps, rmax, y)
+    c.close()
+    ref = ott.tt_round(ott.TT(A, B), eps, rmax)
+    F = A @ B.T
+    assert y.rank <= rmax
+    e = np.linalg.norm(y.full() - ref.full()) / np.linalg.norm(F)
+    _say(f"  ranks gpu {y.rank} oracle {ref.rank}, rel diff {e:.2e}")
+    assert e < 1e-5
+
+
 def test_hadamard_round_parity(lib, ctx):
     _say("hadamard")
     rng = np.random.default_rng(2)

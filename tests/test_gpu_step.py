@@ -31,14 +31,16 @@ def field_rel(Qg, Qo):
             for g, o in zip(Qg, Qo)]
 
 
-def run_both(lib, st, scheme, nonlinear, periodic, eps, rmax, nsteps, taylor=8, recip="taylor"):
+def run_both(lib, st, scheme, nonlinear, periodic, eps, rmax, nsteps, taylor=8, recip="taylor",
+             precision="f64"):
     Q0 = [ott.TT(f.A, f.B) for f in st.tt]
     ts = otf.TTSolver(st.n, scheme, nonlinear, periodic, g=st.g, H=st.H0, eps=eps, rmax=rmax,
                       taylor_terms=taylor, recip=recip)
     Qo = ts.run(Q0, st.dt, nsteps)
     dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
     s = lib.tt_fv_init(st.n, scheme, nonlinear, periodic, dev, g=st.g, H0=st.H0, eps=eps,
-                       r_max=rmax, taylor_terms=taylor, recip=recip, arena_bytes=1 << 30)
+                       r_max=rmax, taylor_terms=taylor, recip=recip, arena_bytes=1 << 30,
+                       precision=precision)
     lib.tt_fv_step(s, st.dt, nsteps)
     Qg = lib.tt_fv_get_state(s)
     stats = lib.tt_fv_get_stats(s)
@@ -134,3 +136,31 @@ def test_dam_break_weno5_cross_reciprocal_equally_valid(lib):
         d = np.linalg.norm(Qg[c].full() - Qo[c].full()) / scale
         _say(f"  var {c}: oracle-vs-grid {e_o:.3e} gpu-vs-grid {e_g:.3e} gpu-vs-oracle {d:.3e}")
         assert e_g <= 2.0 * e_o + 20 * 1e-8
+
+
+def test_nonlinear_upwind5_fp32_contractions(lib):
+    """Mixed precision: FP32 contractions, FP64 SVD / Taylor scalars, on the 96^2 bumps
+    (Upwind5, periodic, cap 24, tol 1e-10, 2 steps).  Gate: rel-L2 <= 1e-4 per field against
+    the FP64 oracle, and for h also on the deviation from its mean."""
+    _say("nonlinear 96 upwind5 fp32")
+    st = synth.nonlinear_bumps(seed=1, n=96, rmax=24, eps=1e-10)
+    Qg, Qo, stats, ts = run_both(lib, st, "upwind5", True, True, 1e-10, 24, 2, precision="f32")
+    r = field_rel(Qg, Qo)
+    hg, ho = Qg[0].full(), Qo[0].full()
+    dev = np.linalg.norm(hg - ho) / np.linalg.norm(ho - ho.mean())
+    _say(f"  rel {r}, h deviation {dev:.2e}, ranks {[q.rank for q in Qg]}")
+    assert max(r) <= 1e-4 and dev <= 1e-4
+
+
+def test_dam_break_fp32_contractions(lib):
+    """Mixed precision on the 48^2 dam break (WENO5 crosses, 1/h by cross, walls, cap 24,
+    tol 1e-8): rel-L2 <= 1e-4 per field against the FP64 oracle, measured on the scale of h."""
+    _say("dam break 48 weno5 cross reciprocal fp32")
+    st = synth.dam_break(seed=0, n=48, rmax=24, eps=1e-8, width=0.05)
+    Qg, Qo, stats, ts = run_both(lib, st, "weno5", True, False, 1e-8, 24, 1, recip="cross",
+                                 precision="f32")
+    scale = np.linalg.norm(Qo[0].full())
+    d = [np.linalg.norm(g.full() - o.full()) / scale for g, o in zip(Qg, Qo)]
+    r = field_rel(Qg, Qo)
+    _say(f"  diff on h scale {d}, per-field rel {r}")
+    assert max(d) <= 1e-4
