@@ -178,10 +178,10 @@ void tt_fv_destroy(tt_fv *s);
  * pivots by alternating maxvol sweeps, Section 3.3).  A perceptron 16 -> 256 -> 256 -> 1
  * (ReLU; BF16 weights and activations, FP32 accumulation) scores every column index of a
  * cross from 16 features of the cross's starting TT (second core B0) and the call site's
- * previous pivots; the top K = min(r_max, |J_prev| + kick) indices are the columns of one
- * refinement sweep.  The result is checked on 8 seeded validation columns outside J: if
- * |f - Y|_F / |Y|_F exceeds max(1e-6, 2 x the same error of the site's last plain cross),
- * the plain maxvol cross runs instead.  The model is trained with Adam on (features, final
+ * previous pivots; the previous pivots together with the top K = min(r_max, |J_prev| + kick)
+ * indices (at most 96 columns) are the columns of one refinement sweep.  The result is checked on 16 seeded validation columns outside J: if
+ * |f - Y|_F / |Y|_F exceeds max(1e-6, the same error of the site's last plain cross), the
+ * plain maxvol cross runs instead.  The model is trained with Adam on (features, final
  * maxvol pivots) pairs logged from plain crosses.  Weights: flat FP32 vector of
  * TT_PM_NPARAM entries, W1 (16 x 256, row-major) | b1 | W2 (256 x 256) | b2 | w3 | b3. */
 #define TT_PM_NPARAM 70401

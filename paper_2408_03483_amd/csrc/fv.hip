@@ -166,11 +166,11 @@ struct Solver {
     return maxvol_host(w, Qb, y0.n2, k, y0.n2, 1.05, 100);
   }
 
-  // relative error |f - Y|_F / |Y|_F of a cross result Y on 8 seeded columns outside J
+  // relative error |f - Y|_F / |Y|_F of a cross result Y on 16 seeded columns outside J
   double validate(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y,
                   const std::vector<int> &J, uint64_t key) {
     Scope sc(w.arena);
-    const std::vector<int> Jv = kick_indices(J, n2, 8, key ^ 0x76A11DA7E5ull);
+    const std::vector<int> Jv = kick_indices(J, n2, 16, key ^ 0x76A11DA7E5ull);
     const int nv = (int)Jv.size();
     if (nv == 0) return 0.0;
     int *Jd = w.arena.ialloc(nv);
@@ -227,16 +227,22 @@ struct Solver {
         const int K = std::min(std::min(p.r_max, (int)J0.size() + p.cross_kick), n2);
         int *Kd = w.arena.ialloc(K);
         topk_indices(w, sc_dev, n2, K, Kd);
-        Jp.resize(K);
-        HIP_CHECK(hipMemcpyAsync(Jp.data(), Kd, K * sizeof(int), hipMemcpyDeviceToHost,
+        std::vector<int> top(K);
+        HIP_CHECK(hipMemcpyAsync(top.data(), Kd, K * sizeof(int), hipMemcpyDeviceToHost,
                                  w.stream));
         w.sync();
+        // the previous pivots, then the proposals they miss, up to the factorization width
+        Jp = J0;
+        for (int j : top) {
+          if ((int)Jp.size() >= qr_max_cols()) break;
+          if (std::find(J0.begin(), J0.end(), j) == J0.end()) Jp.push_back(j);
+        }
       }
       cross_tt(w, fs, n1, n2, Jp, p.eps, p.r_max, 1, 0, key, out, &J);
       const double err = validate(w, fs, n1, n2, out, J, key);
       std::lock_guard<std::mutex> lk(mu);
       sweeps_run += 1;
-      if (err <= std::max(1e-6, 2.0 * ref)) {
+      if (err <= std::max(1e-6, ref)) {
         learned++;
         max_learned_err = std::max(max_learned_err, err);
         piv[site] = J;
