@@ -13,13 +13,16 @@ the host, is the cpu_baseline.  The dominant kernel is timed live with HIP event
 streams it runs on, which gives the roofline line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--timed-kernel NAME]
-                    [--workload bumps1024 | dambreak2048 | ensemble] [--members 64]
-                    [--precision f64 | f32]
+                    [--workload bumps1024 | dambreak2048 | ensemble | learned4096]
+                    [--members 64] [--precision f64 | f32] [--learned-n 4096]
 
 Other workloads (not the headline line): dambreak2048 = WENO5 through maxvol crosses, 1/h by
-cross, walls, rank cap 64, tol 1e-8; ensemble = independent nonlinear members of 256^2,
-512^2 or 1024^2 cells with rank caps 8..48 advanced together on shared worker streams,
-reported against the same members stepped one at a time.
+cross, walls, rank cap 64, tol 1e-8 (with --precision f32 also run in FP64 for the
+speed-up and the difference); ensemble = independent nonlinear members of 256^2, 512^2 or
+1024^2 cells with rank caps 8..48 advanced together on shared worker streams, reported
+against the same members stepped one at a time; learned4096 = the dam break on 4096^2 with
+crosses whose columns come from the learned pivot proposer (trained on pivots logged from
+the same run's warm-up steps), reported against plain maxvol crosses from the same state.
 
 Independent chains of TT operations run on several HIP streams; the runtime maps streams to
 GPU_MAX_HW_QUEUES hardware queues (4 by default), which would serialise them, so this script
@@ -40,7 +43,7 @@ else:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA peak"
-PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector (no MFMA used by this kernel)
+PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector (the timed kernels run on VALU)
 PEAK_HBM_GBS = 8000.0
 PARITY_GATE = 1e-9
 
@@ -52,13 +55,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle step")
-    ap.add_argument("--timed-kernel", default="jacobi",
+    ap.add_argument("--timed-kernel", default="tsqr_node_apply",
                     help="kernel family timed with HIP events ('' = none)")
     ap.add_argument("--workload", default="bumps1024",
-                    choices=["bumps1024", "dambreak2048", "ensemble"])
+                    choices=["bumps1024", "dambreak2048", "ensemble", "learned4096"])
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
-                    help="contraction arithmetic of the dambreak2048 workload")
+                    help="contraction arithmetic of the dambreak2048 / learned4096 workloads")
+    ap.add_argument("--learned-n", type=int, default=4096, help="grid of learned4096")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
@@ -77,6 +81,8 @@ def main():
         return ensemble(args)
     if args.workload == "dambreak2048":
         return dambreak(args)
+    if args.workload == "learned4096":
+        return learned(args)
     n, rmax, eps, K = args.n, 32, 1e-10, 8
     st = synth.nonlinear_bumps(seed=0, n=n, rmax=rmax, eps=eps)
     dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
@@ -232,6 +238,86 @@ def dambreak(args):
            "roofline": _roofline(stats, args.timed_kernel, elapsed), "cpu_baseline": None,
            "ranks": stats["ranks"], "crosses": stats["crosses"]}
     out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def learned(args):
+    """Dam break on learned_n^2 (WENO5, walls, rank cap 64, tol 1e-8, 1/h by cross): plain
+    maxvol crosses against crosses with learned pivots.  Both runs take `warmup` untimed steps
+    (the learned run logs (features, maxvol pivots) from the second of them and then trains
+    the proposer) and `steps` timed steps from there."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2408_03483_amd import ttfv
+    n, rmax, eps = args.learned_n, 64, 1e-8
+    W = max(2, args.warmup)
+    st = synth.dam_break(seed=0, n=n, rmax=rmax, eps=eps)
+    print(f"learned: {n}^2 initial state ready", file=sys.stderr, flush=True)
+
+    def make():
+        dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+        return ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
+                               recip="cross", precision=args.precision)
+
+    def timed(s):
+        s0 = ttfv.tt_fv_get_stats(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ttfv.tt_fv_step(s, st.dt, args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s1 = ttfv.tt_fv_get_stats(s)
+        d = {k: s1[k] - s0[k] for k in ("crosses", "cross_sweeps_run", "learned_crosses",
+                                         "learned_fallbacks")}
+        return el, d, s1
+
+    sp = make()
+    ttfv.tt_fv_step(sp, st.dt, W)
+    e_plain, d_plain, _ = timed(sp)
+    Qp = ttfv.tt_fv_get_state(sp)
+    sp.close()
+    print(f"learned: plain {e_plain * 1e3 / args.steps:.0f} ms/step", file=sys.stderr, flush=True)
+
+    m = ttfv.PivotModel(1 << 23, 0)
+    sl = make()
+    ttfv.tt_fv_set_pivots(sl, "log", m)
+    ttfv.tt_fv_step(sl, st.dt, W)
+    rows, pos = m.dataset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = m.train(epochs=30, batch=16384, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    ttfv.tt_fv_set_pivots(sl, "learned", m)
+    e_l, d_l, s_l = timed(sl)
+    Ql = ttfv.tt_fv_get_state(sl)
+    sl.close()
+    m.close()
+    print(f"learned: learned {e_l * 1e3 / args.steps:.0f} ms/step", file=sys.stderr, flush=True)
+    hn = float(np.linalg.norm(Qp[0].full()))
+    rel = _field_rel(Ql, Qp)
+    on_h = [float(np.linalg.norm(a.full() - b.full()) / hn) for a, b in zip(Ql, Qp)]
+    tried = d_l["learned_crosses"] + d_l["learned_fallbacks"]
+    out = {"metric": METRIC, "value": n * n * args.steps / e_l, "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": W,
+           "ms_per_step": e_l * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+           "data": "synthetic",
+           "config": {"workload": f"dam_break_weno5_{n}_learned_pivots", "grid": f"{n}x{n}",
+                      "scheme": "weno5", "bc": "walls", "r_max": rmax, "eps": eps,
+                      "reciprocal": "cross", "cross_sweeps": 3, "seed": 0,
+                      "pivot_model": "16-256-256-1 bf16, trained on the warm-up steps' pivots"},
+           "roofline": None, "cpu_baseline": None,
+           "plain_value": n * n * args.steps / e_plain,
+           "speedup_vs_plain": e_plain / e_l,
+           "sweeps_per_cross_plain": d_plain["cross_sweeps_run"] / max(d_plain["crosses"], 1),
+           "sweeps_per_cross_learned": d_l["cross_sweeps_run"] / max(d_l["crosses"], 1),
+           "learned_accepted": d_l["learned_crosses"], "fallbacks": d_l["learned_fallbacks"],
+           "fallback_rate": d_l["learned_fallbacks"] / max(tried, 1),
+           "max_accepted_validation_err": s_l["max_learned_err"],
+           "rel_l2_vs_plain": rel, "diff_vs_plain_on_h_scale": on_h,
+           "train": {"rows": rows, "pivots": pos, "epochs": 30, "loss": loss,
+                     "seconds": t_train}}
     print(json.dumps(out), flush=True)
 
 
