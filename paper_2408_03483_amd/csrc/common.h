@@ -148,7 +148,8 @@ void gemm(Ctx &c, bool transA, int M, int N, int K, double alpha, const double *
 void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, const double *A,
            int lda, const double *B, int ldb, double beta, double *C, int ldc);
 
-// tsqr.hip: Q (n x m, ldq) and R (m x m, ldr) of Y (n x m, n >= m, m <= 96)
+// tsqr.hip: Q (n x m, ldq) and R (m x m, ldr) of Y (n x m, n >= m, m <= 96); Q == nullptr
+// forms R only
 constexpr int QR_MAXM = 96;
 int qr_max_cols();   // largest m the device's LDS allows (<= QR_MAXM)
 void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, double *R,

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   const int mm = (m + 1) & ~1;
   double *S = sm;                               // mm columns of m rows
   double *nrm = sm + (size_t)mm * m;            // mm norms
+  double *cn = nrm + mm;                        // squared column norms during the sweeps
   __shared__ int rotated;
   __shared__ double fro_part[NT / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -49,6 +50,20 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   const int np = mm - 1;                        // round-robin over mm players, np rounds
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
+    // exact squared norms at the start of each sweep; within a sweep they follow the
+    // rotations (a' = a - t g, b' = b + t g), so a round reduces only the cross product
+    for (int col = gid; col < mm; col += ngroups) {
+      const double *cc = S + (size_t)col * m;
+      double acc[1] = {0.0};
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        const int i = gl + LP * r;
+        const double x = i < m ? cc[i] : 0.0;
+        acc[0] += x * x;
+      }
+      group_sum_n<LP, 1>(acc);
+      if (gl == 0) cn[col] = acc[0];
+    }
     __syncthreads();
     for (int t = 0; t < np; ++t) {
       for (int k = gid; k < mm / 2; k += ngroups) {
@@ -60,18 +75,16 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
         const int p = min(a, b), q = max(a, b);
         double *cp = S + (size_t)p * m, *cq = S + (size_t)q * m;
         double xp[RS], xq[RS];
-        double acc[3] = {0.0, 0.0, 0.0};
+        double acc[1] = {0.0};
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
           const int i = gl + LP * r;
           xp[r] = i < m ? cp[i] : 0.0;
           xq[r] = i < m ? cq[i] : 0.0;
-          acc[0] += xp[r] * xp[r];
-          acc[1] += xq[r] * xq[r];
-          acc[2] += xp[r] * xq[r];
+          acc[0] += xp[r] * xq[r];
         }
-        group_sum_n<LP, 3>(acc);
-        const double al = acc[0], be = acc[1], ga = acc[2];
+        group_sum_n<LP, 1>(acc);
+        const double al = cn[p], be = cn[q], ga = acc[0];
         if (al > tiny && be > tiny && ga * ga > tol2 * al * be) {
           // tan of the rotation angle, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
           // zeta = (be - al) / (2 ga), written with one square root and one division
@@ -86,7 +99,11 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
               cq[i] = s * xp[r] + c * xq[r];
             }
           }
-          if (gl == 0) rotated = 1;
+          if (gl == 0) {
+            cn[p] = al - tt * ga;
+            cn[q] = be + tt * ga;
+            rotated = 1;
+          }
         }
       }
       __syncthreads();
@@ -190,7 +207,7 @@ void set_lds(K kern, size_t bytes) {
 void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
   TT_REQUIRE(m >= 1 && m <= 128, "jacobi_svd: m out of range");
   const int mm = (m + 1) & ~1;
-  const size_t lds = ((size_t)mm * m + mm) * sizeof(double);
+  const size_t lds = ((size_t)mm * m + 2 * mm) * sizeof(double);
   TimedLaunch tl(c, "jacobi", 22.0 * m * m * m, 8.0 * (2.0 * m * m + m));
   // 16 lanes per pair (measured faster than 8 at m = 64); threads = pairs * lanes per pair
   auto launch = [&](auto kern, int lp) {

@@ -381,6 +381,7 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
     hipLaunchKernelGGL(k_to_double, dim3((m * m + 255) / 256), dim3(256), 0, c.stream,
                        reinterpret_cast<const float *>(Rl[levels]), R, m * m, ldr, m);
   }
+  if (!Q) return;                      // R only: no top-down pass
   size_t zmax = 0;
   for (int v : pl.cnt) zmax = std::max(zmax, (size_t)v);
   T *Z[2] = {talloc(zmax * m * m), talloc(zmax * m * m)};

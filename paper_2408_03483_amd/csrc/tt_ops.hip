@@ -64,19 +64,26 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   const int mn = std::min(n1, n2);
 
   const double *Qa = nullptr, *Qb = nullptr;
+  // The second output core is Qb M^T U_k.  Qb is only formed for tiny modes: on the exact
+  // path Qb M^T = Qb Rb Ra^T = x.B Ra^T, and on the range finder Qb M^T = Qb Rb = W with
+  // W = X^T Qa, so those paths need only the R factor of the second QR.
+  const double *Bsrc = nullptr, *Ra_exact = nullptr;
+  int bsrc_cols = 0;
   double *M = nullptr;
   double *US = nullptr, *sg = nullptr;   // SVD of M once computed
   int m = 0;
   if (R <= width && R <= mn) {
     m = R;
     double *qa = c.arena.dalloc((size_t)n1 * m), *ra = c.arena.dalloc((size_t)m * m);
-    double *qb = c.arena.dalloc((size_t)n2 * m), *rb = c.arena.dalloc((size_t)m * m);
+    double *rb = c.arena.dalloc((size_t)m * m);
     tsqr(c, x.A, n1, m, n1, qa, n1, ra, m);
-    tsqr(c, x.B, n2, m, n2, qb, n2, rb, m);
+    tsqr(c, x.B, n2, m, n2, nullptr, 0, rb, m);                        // R only
     M = c.arena.dalloc((size_t)m * m);
     gemm2(c, false, true, m, m, m, 1.0, ra, m, rb, m, 0.0, M, m);     // Ra Rb^T
     Qa = qa;
-    Qb = qb;
+    Bsrc = x.B;
+    bsrc_cols = m;
+    Ra_exact = ra;
   } else if (mn <= width && mn <= qmax) {
     // tiny modes: materialise the full matrix on the smaller side
     if (n2 <= n1) {
@@ -129,7 +136,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
     double *Y = c.arena.dalloc((size_t)n1 * m);
     double *Z = c.arena.dalloc((size_t)n2 * m);
     double *qa = c.arena.dalloc((size_t)n1 * m), *qz = c.arena.dalloc((size_t)n2 * m);
-    double *qb = c.arena.dalloc((size_t)n2 * m), *rb = c.arena.dalloc((size_t)m * m);
+    double *rb = c.arena.dalloc((size_t)m * m);
     double *rtmp = c.arena.dalloc((size_t)m * m);
     M = c.arena.dalloc((size_t)m * m);
     gemm(c, true, R, m, n2, 1.0, x.B, n2, Om, n2, 0.0, T, R);          // B^T Omega
@@ -148,7 +155,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       tsqr(c, Y, n1, m, n1, qa, n1, rtmp, m);
       gemm(c, true, R, m, n1, 1.0, x.A, n1, qa, n1, 0.0, T, R);        // A^T Qa
       gemm(c, false, n2, m, R, 1.0, x.B, n2, T, R, 0.0, Z, n2);        // W = X^T Qa
-      tsqr(c, Z, n2, m, n2, qb, n2, rb, m);                            // W = Qb Rb
+      tsqr(c, Z, n2, m, n2, nullptr, 0, rb, m);                        // W = Qb Rb (R only)
       transpose(c, M, m, rb, m, m, m);                                 // X ~ Qa Rb^T Qb^T
       if (q >= qlim) break;
       // singular values of Rb estimate those of X on the captured subspace
@@ -178,7 +185,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       c.cnt.extra_power_iters++;
     }
     Qa = qa;
-    Qb = qb;
+    Bsrc = Z;
+    bsrc_cols = m;
   }
   // SVD of the m x m core
   if (!US) {
@@ -200,10 +208,18 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   if (capped) warn |= TT_WRANKCAP;
   double *U = c.arena.dalloc((size_t)m * k);
   normalise_cols(c, US, sg, m, k, U);
-  double *W = c.arena.dalloc((size_t)m * k);
-  gemm(c, true, m, k, m, 1.0, M, m, U, m, 0.0, W, m);                  // M^T U_k
   gemm(c, false, n1, k, m, 1.0, Qa, n1, U, m, 0.0, y.A, n1);
-  gemm(c, false, n2, k, m, 1.0, Qb, n2, W, m, 0.0, y.B, n2);
+  if (Bsrc && !Ra_exact) {
+    gemm(c, false, n2, k, bsrc_cols, 1.0, Bsrc, n2, U, m, 0.0, y.B, n2);  // W U_k
+  } else {
+    double *W = c.arena.dalloc((size_t)m * k);
+    if (Ra_exact)
+      gemm(c, true, m, k, m, 1.0, Ra_exact, m, U, m, 0.0, W, m);        // Ra^T U_k
+    else
+      gemm(c, true, m, k, m, 1.0, M, m, U, m, 0.0, W, m);               // M^T U_k
+    gemm(c, false, n2, k, bsrc_cols ? bsrc_cols : m, 1.0, Bsrc ? Bsrc : Qb, n2, W, m, 0.0, y.B,
+         n2);
+  }
   y.r = k;
   if (sig_out) sig_out->assign(s.begin(), s.begin() + k);
   c.cnt.warnings |= warn;
