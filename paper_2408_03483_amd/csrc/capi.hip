@@ -64,7 +64,21 @@ void Ctx::sync() {
   timer.pending_bytes.clear();
 }
 
+constexpr int kTileCounters = 16384;
+
+int *Ctx::tile_counters() {
+  if (!tile_cnt) {
+    HIP_CHECK(hipMalloc(&tile_cnt, kTileCounters * sizeof(int)));
+    HIP_CHECK(hipMemsetAsync(tile_cnt, 0, kTileCounters * sizeof(int), stream));
+  }
+  return tile_cnt;
+}
+
 Ctx::~Ctx() {
+  if (tile_cnt) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(tile_cnt);
+  }
   for (auto &e : timer.spare) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);

@@ -95,6 +95,8 @@ struct Ctx {
   bool fp32 = false;        // core contractions (GEMM, face-splitting products, TSQR) in FP32
   Counters cnt;
   KernelTimer timer;
+  int *tile_cnt = nullptr;  // zeroed per-tile arrival counters of split-K GEMMs (this stream)
+  int *tile_counters();     // allocates them on first use
   void sync();
   ~Ctx();
 };
@@ -158,7 +160,8 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
 // jacobi.hip
 // One-sided Jacobi on M (m x m, ld m, m <= 96): writes U*Sigma columns sorted by norm into
 // US (m x m) and the norms into sig (device, m).
-void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig);
+// trans: M holds the transpose of the matrix to decompose
+void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans = false);
 // inverse of a small square matrix (m <= 96) with partial pivoting
 void small_inverse(Ctx &c, const double *M, int m, int ldm, double *Minv);
 // normalise the first k columns of US by sig into U

@@ -4,8 +4,8 @@
 //
 // Tiling: 64 x 64 or 64 x 128 output tile per 256-thread block, K staged through LDS in
 // slices of 16.  Tall-skinny contractions (few output tiles, long K) are split along K over
-// blockIdx.z into partial tiles that a second kernel sums in a fixed order, so the result
-// does not depend on scheduling.
+// blockIdx.z into partial tiles; the last block to finish a tile (arrival counter) sums its
+// partials in z order, so the result does not depend on scheduling.
 #include "common.h"
 
 #include <algorithm>
@@ -45,7 +45,8 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
                                                   const double *__restrict__ A, int lda,
                                                   const double *__restrict__ B, int ldb,
                                                   double beta, double *__restrict__ C, int ldc,
-                                                  double *__restrict__ part) {
+                                                  double *__restrict__ part,
+                                                  int *__restrict__ tile_cnt) {
   constexpr int TN = BN2 / 32;                   // 16-wide MFMA blocks per wave along N
   __shared__ T As[BK][BM + 4];
   __shared__ T Bs[BK][BN2 + 4];
@@ -118,25 +119,39 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
         }
       }
     }
-}
-
-__global__ void k_splitk_reduce(int M, int N, int S, const double *__restrict__ part,
-                                double alpha, double beta, double *__restrict__ C, int ldc) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)M * N) return;
-  const int i = (int)(idx % M), j = (int)(idx / M);
-  double s = 0.0;
-  for (int z = 0; z < S; ++z) s += part[((size_t)z * N + j) * M + i];
-  double out = alpha * s;
-  if (beta != 0.0) out += beta * C[i + (size_t)j * ldc];
-  C[i + (size_t)j * ldc] = out;
+  if (!part) return;
+  // split-K: the last block to finish this output tile sums the partials in z order (the
+  // result does not depend on which block that is) and resets the tile's counter
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const int tile = blockIdx.x + blockIdx.y * gridDim.x;
+    const int prev = atomicAdd(&tile_cnt[tile], 1);
+    is_last = prev == (int)gridDim.z - 1;
+    if (is_last) atomicExch(&tile_cnt[tile], 0);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int S = gridDim.z;
+  for (int t = tid; t < BM * BN2; t += NT) {
+    const int gi = bm + (t % BM), gj = bn + (t / BM);
+    if (gi >= M || gj >= N) continue;
+    double sum = 0.0;
+    for (int z = 0; z < S; ++z) sum += part[((size_t)z * N + gj) * M + gi];
+    double out = alpha * sum;
+    if (beta != 0.0) out += beta * C[gi + (size_t)gj * ldc];
+    C[gi + (size_t)gj * ldc] = out;
+  }
 }
 
 template <typename T, int BN2, bool TA, bool TB>
 void launch(Ctx &c, dim3 grid, int M, int N, int K, int kchunk, double alpha, const double *A,
             int lda, const double *B, int ldb, double beta, double *C, int ldc, double *part) {
   hipLaunchKernelGGL((k_gemm_mfma<T, BN2, TA, TB>), grid, dim3(NT), 0, c.stream, M, N, K, kchunk,
-                     alpha, A, lda, B, ldb, beta, C, ldc, part);
+                     alpha, A, lda, B, ldb, beta, C, ldc, part,
+                     part ? c.tile_counters() : nullptr);
 }
 
 template <typename T, int BN2>
@@ -201,9 +216,6 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
   double *part = c.arena.dalloc((size_t)S * M * N);
   dispatch_any(c, bn2, transA, transB, dim3(tm, tn, S), M, N, K, kchunk, alpha, A, lda, B, ldb,
                beta, C, ldc, part);
-  const size_t tot = (size_t)M * N;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                     c.stream, M, N, S, part, alpha, beta, C, ldc);
 }
 
 }  // namespace ttfv

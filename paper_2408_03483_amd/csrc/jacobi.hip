@@ -22,7 +22,8 @@ constexpr int WAVES = NT / 64;
 template <int LP, int RS>
 __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int m,
                                                double *__restrict__ US,
-                                               double *__restrict__ sig, int max_sweeps) {
+                                               double *__restrict__ sig, int max_sweeps,
+                                               int trans) {
   extern __shared__ double sm[];
   const int mm = (m + 1) & ~1;
   double *S = sm;                               // mm columns of m rows
@@ -35,7 +36,8 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   const int nt = blockDim.x, ngroups = nt / LP;
   double part = 0.0;
   for (int idx = threadIdx.x; idx < mm * m; idx += nt) {
-    const double v = (idx < m * m) ? M[idx] : 0.0;
+    double v = 0.0;
+    if (idx < m * m) v = trans ? M[(idx / m) + (size_t)(idx % m) * m] : M[idx];
     S[idx] = v;
     part += v * v;
   }
@@ -204,7 +206,7 @@ void set_lds(K kern, size_t bytes) {
 
 }  // namespace
 
-void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
+void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans) {
   TT_REQUIRE(m >= 1 && m <= 128, "jacobi_svd: m out of range");
   const int mm = (m + 1) & ~1;
   const size_t lds = ((size_t)mm * m + 2 * mm) * sizeof(double);
@@ -213,7 +215,8 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig) {
   auto launch = [&](auto kern, int lp) {
     const int nthreads = std::max(64, ((mm / 2) * lp + 63) / 64 * 64);
     set_lds(kern, lds);
-    hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40,
+                       trans ? 1 : 0);
   };
   if (m <= 32) launch(k_jacobi<16, 2>, 16);
   else if (m <= 64) launch(k_jacobi<16, 4>, 16);

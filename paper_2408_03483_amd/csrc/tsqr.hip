@@ -147,7 +147,8 @@ template <typename T, int RS, int CS>
 __global__ __launch_bounds__(NT) void k_leaf_qr(const double *__restrict__ Y, int n, int m,
                                                 int ldy, int nleaf, int bmax,
                                                 T *__restrict__ V, T *__restrict__ tau,
-                                                T *__restrict__ R) {
+                                                T *__restrict__ R, double *__restrict__ Rfin,
+                                                int ldr) {
   __shared__ T vbuf[2 * 16 * RS];
   __shared__ T taus[128];
   const int L = blockIdx.x;
@@ -173,6 +174,7 @@ __global__ __launch_bounds__(NT) void k_leaf_qr(const double *__restrict__ Y, in
       if (c >= m) continue;
       if (i < rows) VL[i + (size_t)c * bmax] = x[s][r];
       if (i < m) RL[i + (size_t)c * m] = (i <= c) ? x[s][r] : T(0);
+      if (Rfin && i < m) Rfin[i + (size_t)c * ldr] = (i <= c) ? (double)x[s][r] : 0.0;
     }
   for (int c = threadIdx.x; c < m; c += NT) tau[(size_t)L * m + c] = taus[c];
 }
@@ -181,7 +183,8 @@ __global__ __launch_bounds__(NT) void k_leaf_qr(const double *__restrict__ Y, in
 template <typename T, int RS, int CS>
 __global__ __launch_bounds__(NT) void k_node_qr(const T *__restrict__ Rin, int cnt_in, int m,
                                                 int arity, T *__restrict__ V,
-                                                T *__restrict__ tau, T *__restrict__ Rout) {
+                                                T *__restrict__ tau, T *__restrict__ Rout,
+                                                double *__restrict__ Rfin, int ldr) {
   __shared__ T vbuf[2 * 16 * RS];
   __shared__ T taus[128];
   const int k = blockIdx.x;
@@ -190,7 +193,11 @@ __global__ __launch_bounds__(NT) void k_node_qr(const T *__restrict__ Rin, int c
   const int rows = nch * m;
   T *Ro = Rout + (size_t)k * m * m;
   if (nch == 1) {
-    for (int idx = threadIdx.x; idx < m * m; idx += NT) Ro[idx] = Rin[(size_t)c0 * m * m + idx];
+    for (int idx = threadIdx.x; idx < m * m; idx += NT) {
+      const T v = Rin[(size_t)c0 * m * m + idx];
+      Ro[idx] = v;
+      if (Rfin) Rfin[(idx % m) + (size_t)(idx / m) * ldr] = (double)v;
+    }
     return;
   }
   const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
@@ -218,6 +225,7 @@ __global__ __launch_bounds__(NT) void k_node_qr(const T *__restrict__ Rin, int c
       if (c >= m) continue;
       if (i < rows) Vk[i + (size_t)c * ldv] = x[s][r];
       if (i < m) Ro[i + (size_t)c * m] = (i <= c) ? x[s][r] : T(0);
+      if (Rfin && i < m) Rfin[i + (size_t)c * ldr] = (i <= c) ? (double)x[s][r] : 0.0;
     }
   for (int c = threadIdx.x; c < m; c += NT) tau[(size_t)k * m + c] = taus[c];
 }
@@ -338,13 +346,6 @@ struct Plan {
   std::vector<int> cnt;
 };
 
-__global__ void k_to_double(const float *__restrict__ a, double *__restrict__ b, int n, int ldb,
-                            int rows) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n) return;
-  b[(idx % rows) + (size_t)(idx / rows) * ldb] = a[idx];
-}
-
 template <typename T, int RS, int CS>
 void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int ldq, double *R,
               int ldr) {
@@ -359,7 +360,7 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
     TimedLaunch tl(c, "tsqr_leaf_qr", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
                    8.0 * (2.0 * n * m + (double)nleaf * m * m));
     hipLaunchKernelGGL((k_leaf_qr<T, RS, CS>), dim3(nleaf), dim3(NT), 0, c.stream, Y, n, m, ldy,
-                       nleaf, bmax, Vleaf, tleaf, Rleaf);
+                       nleaf, bmax, Vleaf, tleaf, Rleaf, nleaf == 1 ? R : nullptr, ldr);
   }
   const int levels = (int)pl.cnt.size() - 1;
   std::vector<T *> Vl(levels + 1, nullptr), tl(levels + 1, nullptr), Rl(levels + 1, nullptr);
@@ -373,13 +374,8 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
     TimedLaunch tq(c, "tsqr_node_qr", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * cout,
                    8.0 * (2.0 * rows_l * m + (double)cout * m * m));
     hipLaunchKernelGGL((k_node_qr<T, RS, CS>), dim3(cout), dim3(NT), 0, c.stream, Rl[l - 1],
-                       pl.cnt[l - 1], m, arity, Vl[l], tl[l], Rl[l]);
-  }
-  if (sizeof(T) == sizeof(double)) {
-    copy_scale(c, R, ldr, reinterpret_cast<const double *>(Rl[levels]), m, m, m, 1.0);
-  } else {
-    hipLaunchKernelGGL(k_to_double, dim3((m * m + 255) / 256), dim3(256), 0, c.stream,
-                       reinterpret_cast<const float *>(Rl[levels]), R, m * m, ldr, m);
+                       pl.cnt[l - 1], m, arity, Vl[l], tl[l], Rl[l], l == levels ? R : nullptr,
+                       ldr);
   }
   if (!Q) return;                      // R only: no top-down pass
   size_t zmax = 0;

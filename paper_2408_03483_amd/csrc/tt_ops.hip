@@ -70,6 +70,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   const double *Bsrc = nullptr, *Ra_exact = nullptr;
   int bsrc_cols = 0;
   double *M = nullptr;
+  bool Mt = false;           // M holds the transpose of the core to decompose
   double *US = nullptr, *sg = nullptr;   // SVD of M once computed
   int m = 0;
   if (R <= width && R <= mn) {
@@ -138,7 +139,6 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
     double *qa = c.arena.dalloc((size_t)n1 * m), *qz = c.arena.dalloc((size_t)n2 * m);
     double *rb = c.arena.dalloc((size_t)m * m);
     double *rtmp = c.arena.dalloc((size_t)m * m);
-    M = c.arena.dalloc((size_t)m * m);
     gemm(c, true, R, m, n2, 1.0, x.B, n2, Om, n2, 0.0, T, R);          // B^T Omega
     gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);          // Y = X Omega
     int q = 0;
@@ -156,14 +156,15 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       gemm(c, true, R, m, n1, 1.0, x.A, n1, qa, n1, 0.0, T, R);        // A^T Qa
       gemm(c, false, n2, m, R, 1.0, x.B, n2, T, R, 0.0, Z, n2);        // W = X^T Qa
       tsqr(c, Z, n2, m, n2, nullptr, 0, rb, m);                        // W = Qb Rb (R only)
-      transpose(c, M, m, rb, m, m, m);                                 // X ~ Qa Rb^T Qb^T
+      M = rb;                                                          // X ~ Qa Rb^T Qb^T
+      Mt = true;                                                       // (M^T held)
       if (q >= qlim) break;
       // singular values of Rb estimate those of X on the captured subspace
       if (!US) {
         US = c.arena.dalloc((size_t)m * m);
         sg = c.arena.dalloc((size_t)m);
       }
-      jacobi_svd(c, M, m, US, sg);
+      jacobi_svd(c, M, m, US, sg, Mt);
       std::vector<double> s = to_host(c, sg, m);
       if (s[0] == 0.0) break;
       const int k = trunc_rank(s, eps, rmax, nullptr);
@@ -192,7 +193,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   if (!US) {
     US = c.arena.dalloc((size_t)m * m);
     sg = c.arena.dalloc((size_t)m);
-    jacobi_svd(c, M, m, US, sg);
+    jacobi_svd(c, M, m, US, sg, Mt);
   }
   std::vector<double> s = to_host(c, sg, m);
   for (double v : s)
