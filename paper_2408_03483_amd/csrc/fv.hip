@@ -312,9 +312,8 @@ struct Solver {
 
   // ---- nonlinear flux pieces ----------------------------------------------------------
   // one side: 1/h (Algorithm 1), u, w, P1, P2 -> F2 = round(P1 + g/2 P2), F3 = round(m o w)
-  void side_fluxes(Ctx &w, const DTT &h, const DTT &m, const DTT &t, int recip_site, DTT &F2,
-                   DTT &F3) {
-    DTT rh = alloc(w, h.n1, h.n2, p.r_max);
+  // 1/h of one side: cross of the pointwise reciprocal or Algorithm 1, into rh (cap r_max)
+  void reciprocal(Ctx &w, const DTT &h, int recip_site, DTT &rh) {
     if (p.recip == 1) {
       FiberSpec fr;
       fr.fn = TT_FN_RECIP;
@@ -329,12 +328,6 @@ struct Solver {
       last_err = err;
       last_terms = terms;
     }
-    DTT u = rnd(w, had(w, m, rh));
-    DTT wv = rnd(w, had(w, t, rh));
-    DTT P1 = rnd(w, had(w, m, u));
-    DTT P2 = rnd(w, had(w, h, h));
-    round_tt(w, add(w, {{1.0, P1}, {0.5 * p.g, P2}}), p.eps, p.r_max, F2, nullptr);
-    round_tt(w, had(w, m, wv), p.eps, p.r_max, F3, nullptr);
   }
 
   DTT finish(Ctx &w, const DTT &Fh, DTT &o) {
@@ -384,26 +377,34 @@ struct Solver {
       }
       return;
     }
-    // phase A: per direction and side, the reciprocal and the flux products
-    DTT F[2][2][3];
+    // phase A, per direction d and side s (h, m = momentum along d, t = the other one):
+    //   A1: rh = 1/h, P2 = round(h o h), and the two lambda crosses
+    //   A2: u = round(m o rh), w = round(t o rh)
+    //   A3: F2 = round(round(m o u) + g/2 P2), F3 = round(m o w)
+    // Each value is the same rounding of the same operands as in one sequential chain; the
+    // split only lets independent roundings run on different workers.
+    DTT F[2][2][3], rh[2][2], P2[2][2], U[2][2], Wv[2][2];
     for (int d = 0; d < 2; ++d)
       for (int s = 0; s < 2; ++s) {
         F[d][s][0] = s == 0 ? qm[d][1] : qp[d][1];
         F[d][s][1] = alloc(c, nf, n * nq, p.r_max);
         F[d][s][2] = alloc(c, nf, n * nq, p.r_max);
+        rh[d][s] = alloc(c, nf, n * nq, p.r_max);
+        P2[d][s] = alloc(c, nf, n * nq, p.r_max);
+        U[d][s] = alloc(c, nf, n * nq, p.r_max);
+        Wv[d][s] = alloc(c, nf, n * nq, p.r_max);
       }
     DTT lam[2];
     for (int d = 0; d < 2; ++d) lam[d] = alloc(c, nf, n * nq, p.r_max);
     c.sync();
+    auto side = [&](int d, int s) { return s == 0 ? qm[d] : qp[d]; };
     {
       std::vector<Pool::Task> tasks;
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s)
-          tasks.push_back([this, &qm, &qp, &F, &sb, d, s](Ctx &w) {
-            const DTT *q = s == 0 ? qm[d] : qp[d];
-            side_fluxes(w, q[0], q[1], q[2], sb[d] + 8 + s, F[d][s][1], F[d][s][2]);
+          tasks.push_back([this, &side, &rh, &sb, d, s](Ctx &w) {
+            reciprocal(w, side(d, s)[0], sb[d] + 8 + s, rh[d][s]);
           });
-      // phase A also carries the two lambda crosses (independent of the products)
       for (int d = 0; d < 2; ++d)
         tasks.push_back([this, &qm, &qp, &lam, &sb, d](Ctx &w) {
           const DTT &y0 = norm2(w, qm[d][1]) > 0.0 ? qm[d][1] : qm[d][0];
@@ -415,6 +416,40 @@ struct Solver {
           fl.g = p.g;
           cross(w, fl, nf, n * nq, y0, sb[d], lam[d]);
         });
+      for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < 2; ++s)
+          tasks.push_back([this, &side, &P2, d, s](Ctx &w) {
+            const DTT &h = side(d, s)[0];
+            round_tt(w, had(w, h, h), p.eps, p.r_max, P2[d][s], nullptr);
+          });
+      run_tasks(std::move(tasks));
+    }
+    {
+      std::vector<Pool::Task> tasks;
+      for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < 2; ++s) {
+          tasks.push_back([this, &side, &rh, &U, d, s](Ctx &w) {
+            round_tt(w, had(w, side(d, s)[1], rh[d][s]), p.eps, p.r_max, U[d][s], nullptr);
+          });
+          tasks.push_back([this, &side, &rh, &Wv, d, s](Ctx &w) {
+            round_tt(w, had(w, side(d, s)[2], rh[d][s]), p.eps, p.r_max, Wv[d][s], nullptr);
+          });
+        }
+      run_tasks(std::move(tasks));
+    }
+    {
+      std::vector<Pool::Task> tasks;
+      for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < 2; ++s) {
+          tasks.push_back([this, &side, &U, &P2, &F, d, s](Ctx &w) {
+            DTT P1 = rnd(w, had(w, side(d, s)[1], U[d][s]));
+            round_tt(w, add(w, {{1.0, P1}, {0.5 * p.g, P2[d][s]}}), p.eps, p.r_max, F[d][s][1],
+                     nullptr);
+          });
+          tasks.push_back([this, &side, &Wv, &F, d, s](Ctx &w) {
+            round_tt(w, had(w, side(d, s)[1], Wv[d][s]), p.eps, p.r_max, F[d][s][2], nullptr);
+          });
+        }
       run_tasks(std::move(tasks));
     }
     // phase B: dissipation, LLF flux and finish, per direction and variable
