@@ -24,9 +24,9 @@ against the same members stepped one at a time; learned4096 = the dam break on 4
 crosses whose columns come from the learned pivot proposer (trained on pivots logged from
 the same run's warm-up steps), reported against plain maxvol crosses from the same state.
 
-Independent chains of TT operations run on several HIP streams; the runtime maps streams to
-GPU_MAX_HW_QUEUES hardware queues (4 by default), which would serialise them, so this script
-raises it before HIP starts.
+Independent chains of TT operations run on several HIP streams (8 workers, plus helper streams
+for the Taylor partial sums); the runtime maps streams to GPU_MAX_HW_QUEUES hardware queues (4
+by default), which would serialise them, so this script raises it to 16 before HIP starts.
 """
 import argparse
 import json
@@ -37,10 +37,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-if "--workload" in sys.argv and "ensemble" in sys.argv:
-    os.environ["GPU_MAX_HW_QUEUES"] = "16"
-else:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA peak"
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector (the timed kernels run on VALU)

@@ -133,7 +133,7 @@ typedef struct {
   int cross_sweeps;   /* maxvol cross sweeps                                               */
   int cross_kick;     /* fresh columns per non-final sweep                                 */
   int recip;          /* 1/h: 0 = Taylor series (Algorithm 1), 1 = cross of 1/x            */
-  int workers;        /* own worker streams: 0 = default (6), k = k, -1 = none (the solver
+  int workers;        /* own worker streams: 0 = default (8), k = k, -1 = none (the solver
                          then steps only inside an ensemble, tt_ens_step)                 */
   int precision;      /* TT_PREC_F64 or TT_PREC_F32 (contractions; see tt_ctx_set_precision) */
 } tt_fv_params;

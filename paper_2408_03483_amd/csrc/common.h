@@ -198,8 +198,10 @@ void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, d
 // tt_ops.hip (host algorithms)
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
 void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out);
+// aux: optional second context (own stream and arena) on which a helper thread forms the
+// partial sums while this thread forms the next term
 int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, double *err,
-                  int *terms);
+                  int *terms, Ctx *aux = nullptr);
 std::vector<int> maxvol_host(Ctx &c, const double *Q, int n, int r, int ldq, double tau,
                              int maxit);
 int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, double eps,

@@ -55,11 +55,24 @@ struct Solver {
   int *rep_idx = nullptr;      // row j*nq + m -> j
   // learned pivot proposer (TT_PIV_*): model, per-site validation error of the last plain
   // cross, and counters
+  // helper contexts of the Taylor reciprocal's partial sums, one per (direction, side); used
+  // when the solver steps on its own pool
+  std::unique_ptr<Ctx> aux[4];
   PivotModel *pm = nullptr;
   int piv_mode = TT_PIV_MAXVOL;
   std::map<int, double> ref_err;
   long long sweeps_run = 0, learned = 0, fallbacks = 0;
   double max_learned_err = 0.0;
+
+  ~Solver() {
+    for (auto &a : aux) {
+      if (!a) continue;
+      hipStream_t st = a->stream;
+      (void)hipStreamSynchronize(st);
+      a.reset();
+      (void)hipStreamDestroy(st);
+    }
+  }
 
   static DTT alloc(Ctx &w, int n1, int n2, int cap) {
     DTT t;
@@ -313,7 +326,7 @@ struct Solver {
   // ---- nonlinear flux pieces ----------------------------------------------------------
   // one side: 1/h (Algorithm 1), u, w, P1, P2 -> F2 = round(P1 + g/2 P2), F3 = round(m o w)
   // 1/h of one side: cross of the pointwise reciprocal or Algorithm 1, into rh (cap r_max)
-  void reciprocal(Ctx &w, const DTT &h, int recip_site, DTT &rh) {
+  void reciprocal(Ctx &w, const DTT &h, int recip_site, int chain, DTT &rh) {
     if (p.recip == 1) {
       FiberSpec fr;
       fr.fn = TT_FN_RECIP;
@@ -323,7 +336,9 @@ struct Solver {
     } else {
       double err = 0;
       int terms = 0;
-      reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms);
+      Ctx *a = (exec == pool.get() && aux[chain]) ? aux[chain].get() : nullptr;
+      if (a) a->fp32 = w.fp32;
+      reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms, a);
       std::lock_guard<std::mutex> lk(mu);
       last_err = err;
       last_terms = terms;
@@ -403,7 +418,7 @@ struct Solver {
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s)
           tasks.push_back([this, &side, &rh, &sb, d, s](Ctx &w) {
-            reciprocal(w, side(d, s)[0], sb[d] + 8 + s, rh[d][s]);
+            reciprocal(w, side(d, s)[0], sb[d] + 8 + s, d * 2 + s, rh[d][s]);
           });
       for (int d = 0; d < 2; ++d)
         tasks.push_back([this, &qm, &qp, &lam, &sb, d](Ctx &w) {
@@ -557,10 +572,16 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->c.arena.init(ab);
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
-    const int nw = p->workers == 0 ? 6 : p->workers;
+    const int nw = p->workers == 0 ? 8 : p->workers;
     if (nw > 0) {
       s->pool = std::make_unique<Pool>(nw, ab, dev);
       s->exec = s->pool.get();
+      if (p->nonlinear && p->recip == 0)
+        for (auto &a : s->aux) {
+          a = std::make_unique<Ctx>();
+          HIP_CHECK(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));
+          a->arena.init((size_t)512 << 20);
+        }
     }
     s->st = derive_stencils(p->scheme == 3 ? 3 : 5);
     s->wt = derive_weno_tables();
@@ -685,8 +706,12 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   for (int v = 0; v < 3; ++v) o->ranks[v] = s->Q[v].r;
   Counters t = s->c.cnt;
   const int npool = s->pool ? s->pool->size() : 0;
-  for (int i = 0; i < npool; ++i) {
-    const Counters &w = s->pool->ctx(i).cnt;
+  std::vector<const Counters *> cs;
+  for (int i = 0; i < npool; ++i) cs.push_back(&s->pool->ctx(i).cnt);
+  for (auto &a : s->aux)
+    if (a) cs.push_back(&a->cnt);
+  for (const Counters *wc : cs) {
+    const Counters &w = *wc;
     t.roundings += w.roundings;
     t.crosses += w.crosses;
     t.flops += w.flops;

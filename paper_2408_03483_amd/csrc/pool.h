@@ -40,8 +40,11 @@ class Pool {
     }
     cv_.notify_all();
     for (auto &t : threads_) t.join();
-    for (auto &c : ctx_)
-      if (c->stream) (void)hipStreamDestroy(c->stream);
+    for (auto &c : ctx_) {
+      hipStream_t st = c->stream;
+      c.reset();                       // frees the context's buffers while its stream exists
+      if (st) (void)hipStreamDestroy(st);
+    }
   }
 
   int size() const { return (int)ctx_.size(); }

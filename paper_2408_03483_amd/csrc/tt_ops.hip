@@ -15,6 +15,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <unordered_set>
 
 namespace ttfv {
@@ -266,8 +271,97 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
   normalise_cols(c, US, sg, n, k, Q);
 }
 
+namespace {
+
+// Partial sums y_k = round(y_{k-1} + dy_k) of Algorithm 1 on a helper thread with its own
+// stream: dy_k (made on the caller's stream) is handed over with an event recorded after it,
+// so the sums run while the caller forms dy_{k+1}.  The operations and their operands are
+// those of the one-thread loop, so the result is the same.
+struct SumPipe {
+  Ctx &a;
+  int n1, n2, rmax;
+  double eps;
+  DTT ycur, ynext;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::pair<DTT, hipEvent_t>> q;
+  bool done = false;
+  int warn = 0;
+  std::exception_ptr err;
+  std::thread th;
+
+  SumPipe(Ctx &aux, int n1_, int n2_, int rmax_, double eps_, int device)
+      : a(aux), n1(n1_), n2(n2_), rmax(rmax_), eps(eps_) {
+    const int cap = std::max(rmax, 1);
+    ycur = DTT{n1, n2, 1, a.arena.dalloc((size_t)n1 * cap), a.arena.dalloc((size_t)n2 * cap)};
+    ynext = DTT{n1, n2, 0, a.arena.dalloc((size_t)n1 * cap), a.arena.dalloc((size_t)n2 * cap)};
+    fill_value(a, ycur.A, n1, n1, 1, 1.0);
+    fill_value(a, ycur.B, n2, n2, 1, 1.0);
+    th = std::thread([this, device]() {
+      (void)hipSetDevice(device);
+      run();
+    });
+  }
+
+  void push(const DTT &dy, hipStream_t producer) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(e, producer));
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      q.push_back({dy, e});
+    }
+    cv.notify_one();
+  }
+
+  void finish() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      done = true;
+    }
+    cv.notify_one();
+    if (th.joinable()) th.join();
+  }
+
+  ~SumPipe() { finish(); }
+
+  void run() {
+    for (;;) {
+      std::pair<DTT, hipEvent_t> item;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [this] { return done || !q.empty(); });
+        if (q.empty()) break;
+        item = q.front();
+        q.pop_front();
+      }
+      try {
+        if (!err) {
+          HIP_CHECK(hipStreamWaitEvent(a.stream, item.second, 0));
+          Scope sc(a.arena);
+          const DTT &dy = item.first;
+          const int Rs = ycur.r + dy.r;
+          DTT s{n1, n2, Rs, a.arena.dalloc((size_t)n1 * Rs), a.arena.dalloc((size_t)n2 * Rs)};
+          copy_scale(a, s.A, n1, ycur.A, n1, n1, ycur.r, 1.0);
+          copy_scale(a, s.A + (size_t)n1 * ycur.r, n1, dy.A, n1, n1, dy.r, 1.0);
+          copy_scale(a, s.B, n2, ycur.B, n2, n2, ycur.r, 1.0);
+          copy_scale(a, s.B + (size_t)n2 * ycur.r, n2, dy.B, n2, n2, dy.r, 1.0);
+          warn |= round_tt(a, s, eps, rmax, ynext, nullptr);
+          std::swap(ycur, ynext);
+        }
+      } catch (...) {
+        if (!err) err = std::current_exception();
+      }
+      (void)hipEventDestroy(item.second);
+    }
+    (void)hipStreamSynchronize(a.stream);
+  }
+};
+
+}  // namespace
+
 int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, double *err_out,
-                  int *terms_out) {
+                  int *terms_out, Ctx *aux) {
   TT_REQUIRE(K >= 1, "reciprocal: max_terms < 1");
   Scope sc(c.arena);
   const int n1 = x.n1, n2 = x.n2;
@@ -298,6 +392,46 @@ int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, dou
   DTT dy2{n1, n2, 0, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
   fill_value(c, dy.A, n1, n1, 1, 1.0);
   fill_value(c, dy.B, n2, n2, 1, 1.0);
+  if (aux) {
+    // the terms dy_k each keep their own buffers until the helper has added them
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    Scope sa(aux->arena);
+    SumPipe pipe(*aux, n1, n2, rmax, eps, dev);
+    double err = 1.0;
+    int terms = 1, warn = 0;
+    DTT prev = dy;
+    while (err > eps && terms < K) {
+      DTT next{n1, n2, 0, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+      {
+        Scope s3(c.arena);
+        const int R = prev.r * xt.r;
+        DTT p{n1, n2, R, c.arena.dalloc((size_t)n1 * R), c.arena.dalloc((size_t)n2 * R)};
+        khatri_rao(c, p.A, n1, prev.A, prev.r, xt.A, xt.r);
+        khatri_rao(c, p.B, n2, prev.B, prev.r, xt.B, xt.r);
+        std::vector<double> sdy;
+        warn |= round_tt(c, p, eps, rmax, next, &sdy);
+        double nrm2 = 0.0;
+        for (double v : sdy) nrm2 += v * v;
+        err = std::sqrt(nrm2) / std::sqrt(N);
+      }
+      pipe.push(next, c.stream);
+      prev = next;
+      ++terms;
+    }
+    pipe.finish();
+    if (pipe.err) std::rethrow_exception(pipe.err);
+    warn |= pipe.warn;
+    copy_scale(c, y.A, n1, pipe.ycur.A, n1, n1, pipe.ycur.r, 1.0 / xavg);
+    copy_scale(c, y.B, n2, pipe.ycur.B, n2, n2, pipe.ycur.r, 1.0);
+    y.r = pipe.ycur.r;
+    c.sync();
+    if (err > eps) warn |= TT_WNOCONV;
+    if (err_out) *err_out = err;
+    if (terms_out) *terms_out = terms;
+    c.cnt.warnings |= warn;
+    return warn;
+  }
   // y is accumulated in the caller's buffers; start at 1
   fill_value(c, y.A, n1, n1, 1, 1.0);
   fill_value(c, y.B, n2, n2, 1, 1.0);

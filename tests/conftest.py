@@ -2,7 +2,7 @@ import os
 import sys
 
 # independent chains run on several HIP streams; give them hardware queues of their own
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
