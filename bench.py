@@ -9,8 +9,10 @@ fields (seed 0), dt from CFL 0.4.
 One "step" is one full SSP-RK3 step of the TT solver.  value = cells * steps / seconds over
 the timed steps (cell-updates/s).  Before timing, one step from the initial state is
 checked against the CPU oracle (relative L2 error per field), and that oracle step, timed on
-the host, is the cpu_baseline.  The dominant kernel is timed live with HIP events on the
-streams it runs on, which gives the roofline line.
+the host, is the cpu_baseline.  The dominant kernel family (the rounding GEMMs on the matrix
+cores) is timed live with HIP events on the streams it runs on, which gives the roofline line;
+its HBM traffic per launch comes from the committed counter summary in profiles/ while the GEMM
+source is unchanged.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--timed-kernel NAME]
                     [--workload bumps1024 | dambreak2048 | ensemble | learned4096]
@@ -40,7 +42,44 @@ sys.path.insert(0, ROOT)
 os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA peak"
-PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector (the timed kernels run on VALU)
+PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector
+PEAK_FP64_MFMA_TFLOPS = 78.6        # MI355X FP64 matrix (dense)
+PEAK_FP32_MFMA_TFLOPS = 157.3       # MI355X FP32 matrix (dense)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic_nonlinear_bumps_1024.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2408_03483_amd", "csrc", "gemm.hip")
+
+
+def _gemm_traffic():
+    """Calibrated HBM bytes per GEMM launch from the committed counter summary, or None when
+    the GEMM source changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        vals = dict(l.split(": ", 1) for l in txt.splitlines()
+                    if l.startswith(("bytes_per_launch: ", "source_sha256: ")))
+        sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+        if vals.get("source_sha256", "").strip() != sha:
+            return None
+        return float(vals["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _roof(kernel, stats, elapsed, fp32=False, traffic=None):
+    if not stats["timed_launches"] or stats["timed_ms"] <= 0:
+        return None
+    avg_ms = stats["timed_ms"] / stats["timed_launches"]
+    fl = stats["timed_flops"] / stats["timed_launches"]
+    achieved = fl / (avg_ms * 1e-3) / 1e12
+    if kernel == "gemm":
+        bound, peak = "mfma", PEAK_FP32_MFMA_TFLOPS if fp32 else PEAK_FP64_MFMA_TFLOPS
+    else:
+        bound, peak = "alu", PEAK_FP64_VECTOR_TFLOPS
+    return {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "avg_launch_us": avg_ms * 1e3, "launches": stats["timed_launches"],
+            "share_of_step": stats["timed_ms"] / (elapsed * 1e3), "alg_flops_per_launch": fl,
+            "alg_bytes_per_launch": stats["timed_bytes"] / stats["timed_launches"]}
 PEAK_HBM_GBS = 8000.0
 PARITY_GATE = 1e-9
 
@@ -52,7 +91,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle step")
-    ap.add_argument("--timed-kernel", default="tsqr_node_apply",
+    ap.add_argument("--timed-kernel", default="gemm",
                     help="kernel family timed with HIP events ('' = none)")
     ap.add_argument("--workload", default="bumps1024",
                     choices=["bumps1024", "dambreak2048", "ensemble", "learned4096"])
@@ -132,17 +171,8 @@ def main():
         ttfv.tt_fv_time_kernel(s, None)
     value = n * n * args.steps / elapsed
 
-    roof = None
-    if stats["timed_launches"] > 0 and stats["timed_ms"] > 0:
-        avg_ms = stats["timed_ms"] / stats["timed_launches"]
-        fl = stats["timed_flops"] / stats["timed_launches"]
-        achieved = fl / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": args.timed_kernel, "bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-                "avg_launch_us": avg_ms * 1e3, "launches": stats["timed_launches"],
-                "share_of_step": stats["timed_ms"] / (elapsed * 1e3),
-                "alg_flops_per_launch": fl}
+    roof = _roof(args.timed_kernel, stats, elapsed,
+                 traffic=_gemm_traffic() if args.timed_kernel == "gemm" else None)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -156,19 +186,6 @@ def main():
     }
     print(json.dumps(out), flush=True)
     s.close()
-
-
-def _roofline(stats, kernel, elapsed):
-    if not stats["timed_launches"] or stats["timed_ms"] <= 0:
-        return None
-    avg_ms = stats["timed_ms"] / stats["timed_launches"]
-    fl = stats["timed_flops"] / stats["timed_launches"]
-    achieved = fl / (avg_ms * 1e-3) / 1e12
-    return {"kernel": kernel, "bound": "alu", "achieved": achieved,
-            "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-            "avg_launch_us": avg_ms * 1e3, "launches": stats["timed_launches"],
-            "share_of_step": stats["timed_ms"] / (elapsed * 1e3), "alg_flops_per_launch": fl}
 
 
 def _field_rel(Qa, Qb):
@@ -232,8 +249,8 @@ def dambreak(args):
                       "bc": "walls", "r_max": rmax, "eps": eps, "reciprocal": "cross",
                       "cross_sweeps": 3, "seed": 0,
                       "contractions": "fp32 matrix cores" if args.precision == "f32" else "fp64"},
-           "roofline": _roofline(stats, args.timed_kernel, elapsed), "cpu_baseline": None,
-           "ranks": stats["ranks"], "crosses": stats["crosses"]}
+           "roofline": _roof(args.timed_kernel, stats, elapsed, fp32=args.precision == "f32"),
+           "cpu_baseline": None, "ranks": stats["ranks"], "crosses": stats["crosses"]}
     out.update(extra)
     print(json.dumps(out), flush=True)
 
