@@ -97,7 +97,8 @@ def main():
                     choices=["bumps1024", "dambreak2048", "ensemble", "learned4096"])
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
-                    help="contraction arithmetic of the dambreak2048 / learned4096 workloads")
+                    help="contraction arithmetic of the dambreak2048, ensemble and learned4096 "
+                         "workloads")
     ap.add_argument("--learned-n", type=int, default=4096, help="grid of learned4096")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -360,7 +361,7 @@ def ensemble(args):
             dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=r) for f in st.tt]
             out.append(ttfv.tt_fv_init(st.n, "upwind5", True, True, dev, g=st.g, eps=1e-10,
                                        r_max=r, taylor_terms=8, workers=workers,
-                                       arena_bytes=1 << 28))
+                                       arena_bytes=1 << 28, precision=args.precision))
         return out
 
     # members one at a time (each with its own worker streams)
@@ -410,8 +411,8 @@ def ensemble(args):
     ens.close()
     out = {"metric": METRIC, "value": cells / t_ens, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": 0, "ms_per_step": t_ens * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.precision, "data": "synthetic",
            "config": {"workload": f"ensemble_{M}", "members": M, "sizes": sizes,
                       "r_max": ranks, "eps": 1e-10, "scheme": "upwind5",
                       "autotuned": {"workers": workers, "concurrency": conc}},

@@ -161,9 +161,19 @@ def test_training_reduces_loss_and_learned_steps_stay_valid(lib):
          f"sweeps {stats['cross_sweeps_run']} max err {stats['max_learned_err']:.2e}")
     assert stats["learned_crosses"] + stats["learned_fallbacks"] > 0
     sp = _dam_break_solver(lib, st, 24, 1e-8)
-    lib.tt_fv_step(sp, st.dt, 4)
+    lib.tt_fv_step(sp, st.dt, 2)
+    s2 = lib.tt_fv_get_stats(sp)
+    lib.tt_fv_step(sp, st.dt, 2)
+    s4 = lib.tt_fv_get_stats(sp)
     Qp = lib.tt_fv_get_state(sp)
     sp.close()
+    # what the proposer gains: maxvol sweeps per cross over the two learned steps, against
+    # the plain method's three
+    plain = (s4["cross_sweeps_run"] - s2["cross_sweeps_run"]) / (s4["crosses"] - s2["crosses"])
+    learned = (stats["cross_sweeps_run"] - s2["cross_sweeps_run"]) / (
+        stats["crosses"] - s2["crosses"])
+    _say(f"  sweeps per cross: plain {plain:.2f} learned {learned:.2f}")
+    assert plain == 3.0 and learned < plain
     U = [f.full() for f in st.tt]
     gs = fv_grid.GridSolver(st.n, "weno5", True, False, g=st.g)
     for _ in range(4):
