@@ -63,28 +63,56 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
 #pragma unroll
     for (int v = 0; v < TN; ++v) acc[u][v] = V{0, 0, 0, 0};
 
-  for (int kk = k0; kk < k1; kk += BK) {
+  // the next K-slice is fetched into registers while the current one is multiplied from LDS
+  constexpr int QA = BM * BK / NT, QB = BN2 * BK / NT;
+  double ra[QA], rb[QB];
+  auto fetch = [&](int kk) {
 #pragma unroll
-    for (int t = tid; t < BM * BK; t += NT) {
+    for (int q = 0; q < QA; ++q) {
+      const int t = tid + NT * q;
       int i, k;
       if (!TA) { i = t & 63; k = t >> 6; }
       else     { k = t & 15; i = t >> 4; }
       const int gi = bm + i, gk = kk + k;
       double v = 0.0;
       if (gi < M && gk < k1) v = TA ? A[gk + (size_t)gi * lda] : A[gi + (size_t)gk * lda];
-      As[k][i] = (T)v;
+      ra[q] = v;
     }
 #pragma unroll
-    for (int t = tid; t < BN2 * BK; t += NT) {
+    for (int q = 0; q < QB; ++q) {
+      const int t = tid + NT * q;
       int k, j;
       if (!TB) { k = t & 15; j = t >> 4; }
       else     { j = t % BN2; k = t / BN2; }
       const int gj = bn + j, gk = kk + k;
       double v = 0.0;
       if (gj < N && gk < k1) v = TB ? B[gj + (size_t)gk * ldb] : B[gk + (size_t)gj * ldb];
-      Bs[k][j] = (T)v;
+      rb[q] = v;
     }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int t = tid + NT * q;
+      int i, k;
+      if (!TA) { i = t & 63; k = t >> 6; }
+      else     { k = t & 15; i = t >> 4; }
+      As[k][i] = (T)ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      const int t = tid + NT * q;
+      int k, j;
+      if (!TB) { k = t & 15; j = t >> 4; }
+      else     { j = t % BN2; k = t / BN2; }
+      Bs[k][j] = (T)rb[q];
+    }
+  };
+  if (k0 < k1) fetch(k0);
+  for (int kk = k0; kk < k1; kk += BK) {
+    stage();
     __syncthreads();
+    if (kk + BK < k1) fetch(kk + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       T a[2], b[TN];
@@ -196,7 +224,7 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
   const int tiles = tm * tn;
   int S = 1;
   if (tiles < 256 && K >= 512) {
-    S = std::min((512 + tiles - 1) / tiles, K / 256);
+    S = std::min((512 + tiles - 1) / tiles, K / 512);
     S = std::max(S, 1);
   }
   int kchunk = (K + S - 1) / S;
