@@ -13,6 +13,18 @@ namespace ttfv {
 namespace {
 
 constexpr int NT = 1024;
+
+// hardware reciprocal and reciprocal square root refined by one Newton step (a rotation only
+// needs c^2 + s^2 = 1 to round-off, which these give; correctly rounded division and square
+// roots would lengthen the dependent chain of every round)
+__device__ __forceinline__ double rcp_nr(double a) {
+  const double x = __builtin_amdgcn_rcp(a);
+  return fma(x, fma(-a, x, 1.0), x);
+}
+__device__ __forceinline__ double rsq_nr(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  return y * fma(-0.5 * a * y, y, 1.5);
+}
 constexpr int WAVES = NT / 64;
 
 // One group of LP lanes (8 or 16) per column pair: column entries i = lane + LP r.  A round
@@ -91,8 +103,10 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
           // tan of the rotation angle, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
           // zeta = (be - al) / (2 ga), written with one square root and one division
           const double d = be - al, g2 = 2.0 * ga;
-          const double tt = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(d * d + g2 * g2));
-          const double c = rsqrt(1.0 + tt * tt), s = c * tt;
+          const double dd = fma(d, d, g2 * g2);
+          const double r = dd * rsq_nr(dd);
+          const double tt = (d >= 0.0 ? g2 : -g2) * rcp_nr(fabs(d) + r);
+          const double c = rsq_nr(fma(tt, tt, 1.0)), s = c * tt;
 #pragma unroll
           for (int r = 0; r < RS; ++r) {
             const int i = gl + LP * r;
