@@ -70,6 +70,8 @@ def test_recon_core_parity(lib, ctx, scheme, periodic):
     (1000, 3000, 300, 1e-10, 32),   # randomized path (R > sketch width)
     (777, 1531, 1024, 1e-12, 16),   # randomized path, ragged sizes
     (50, 40, 200, 0.0, 64),         # tiny modes: materialised
+    (3001, 2503, 400, 1e-12, 64),   # widest sketch (96 columns: two columns per lane group)
+    (2049, 6144, 90, 1e-12, 64),    # exact path at 90 columns (192-row blocks)
 ])
 def test_round_parity(lib, ctx, n1, n2, r, eps, rmax):
     _say(f"round {n1}x{n2} r={r} eps={eps} rmax={rmax}")
@@ -91,6 +93,7 @@ def test_round_parity(lib, ctx, n1, n2, r, eps, rmax):
     (300, 200, 20, 1e-6, 32),       # exact path
     (1000, 3000, 300, 1e-6, 32),    # randomized path
     (777, 1531, 1024, 1e-5, 16),    # randomized path, ragged sizes
+    (3001, 2503, 400, 1e-6, 64),    # widest sketch (96 columns)
 ])
 def test_round_fp32_contractions(lib, n1, n2, r, eps, rmax):
     """FP32 contractions (GEMMs and QR panels on the matrix cores, SVD in FP64): the result

@@ -164,3 +164,51 @@ def test_dam_break_fp32_contractions(lib):
     r = field_rel(Qg, Qo)
     _say(f"  diff on h scale {d}, per-field rel {r}")
     assert max(d) <= 1e-4
+
+
+@pytest.mark.parametrize("scheme,recip", [("upwind5", "taylor"), ("weno5", "cross")])
+def test_lake_at_rest_is_preserved(lib, scheme, recip):
+    """Degenerate state: h = 1, hu = hv = 0 (rank-1 and zero TTs) between walls stays at rest
+    to round-off after two steps (the flux differences of a constant state vanish)."""
+    _say(f"lake at rest 40^2 {scheme} {recip}")
+    n = 40
+    ones = np.ones((n, 1))
+    tts = [synth.Factored(ones, ones), synth.Factored(np.zeros((n, 1)), np.zeros((n, 1))),
+           synth.Factored(np.zeros((n, 1)), np.zeros((n, 1)))]
+    U = [np.ones((n, n)), np.zeros((n, n)), np.zeros((n, n))]
+    st = synth.State("rest", n, True, False, 9.81, 1.0, U, tts, 1e-3, {})
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=8) for f in st.tt]
+    s = lib.tt_fv_init(n, scheme, True, False, dev, g=st.g, eps=1e-10, r_max=8, recip=recip,
+                       arena_bytes=1 << 28)
+    lib.tt_fv_step(s, st.dt, 2)
+    Qg = lib.tt_fv_get_state(s)
+    s.close()
+    assert np.max(np.abs(Qg[0].full() - 1.0)) <= 1e-13
+    assert np.max(np.abs(Qg[1].full())) <= 1e-13 and np.max(np.abs(Qg[2].full())) <= 1e-13
+
+
+def test_dam_break_2048_mass_and_positivity(lib):
+    """The 2048^2 dam break of the throughput run (WENO5 crosses, 1/h by cross, walls, cap 64,
+    tol 1e-8, FP64), one step in the bench's launch configuration.  The oracle cannot take
+    this step in test time, so properties that hold at any size are checked: the walls
+    conserve mass up to the roundings' relative changes (a few eps per stage, bound 1e-6),
+    h stays within its initial range up to 1e-3 (WENO5 is essentially non-oscillatory),
+    and the ranks respect the cap."""
+    _say("dam break 2048 one step: mass, range, ranks")
+    st = synth.dam_break(seed=0, n=2048, rmax=64, eps=1e-8)
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=64) for f in st.tt]
+    s = lib.tt_fv_init(2048, "weno5", True, False, dev, g=st.g, eps=1e-8, r_max=64,
+                       recip="cross")
+    lib.tt_fv_step(s, st.dt, 1)
+    Qg = lib.tt_fv_get_state(s)
+    s.close()
+    h0 = st.tt[0].A @ st.tt[0].B.T
+    h1 = Qg[0].full()
+    m0, m1 = h0.sum(), h1.sum()
+    dh = np.max(np.abs(h1 - h0))
+    _say(f"  mass drift {abs(m1 - m0) / m0:.2e}, max |dh| {dh:.2e}, "
+         f"h in [{h1.min():.6f}, {h1.max():.6f}], ranks {[q.rank for q in Qg]}")
+    assert dh > 1e-6                       # the step moved the front
+    assert abs(m1 - m0) / m0 <= 1e-6
+    assert h1.min() >= h0.min() - 1e-3 and h1.max() <= h0.max() + 1e-3
+    assert all(1 <= q.rank <= 64 for q in Qg)
