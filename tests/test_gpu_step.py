@@ -212,3 +212,19 @@ def test_dam_break_2048_mass_and_positivity(lib):
     assert abs(m1 - m0) / m0 <= 1e-6
     assert h1.min() >= h0.min() - 1e-3 and h1.max() <= h0.max() + 1e-3
     assert all(1 <= q.rank <= 64 for q in Qg)
+
+
+def test_bumps_1024_restart_parity_full_size(lib):
+    """The throughput workload itself (1024^2 bumps, Upwind5, Taylor 8 terms, cap 32, tol
+    1e-10, FP64) with the default launch configuration (8 worker streams, helper streams for
+    the Taylor sums): one step from the initial state against the oracle's step, rel-L2 per
+    field <= 1e-9, and for h also on its deviation from the mean."""
+    _say("bumps 1024 restart parity (oracle step ~30 s)")
+    st = synth.nonlinear_bumps(seed=0, n=1024, rmax=32, eps=1e-10)
+    Qg, Qo, stats, ts = run_both(lib, st, "upwind5", True, True, 1e-10, 32, 1)
+    r = field_rel(Qg, Qo)
+    hg, ho = Qg[0].full(), Qo[0].full()
+    dh = np.linalg.norm(hg - ho) / np.linalg.norm(ho - ho.mean())
+    _say(f"  rel {r}, h deviation {dh:.2e}, ranks {[q.rank for q in Qg]} vs "
+         f"{[q.rank for q in Qo]}")
+    assert max(r) <= 1e-9 and dh <= 1e-9
