@@ -105,6 +105,7 @@ __global__ __launch_bounds__(GB) void k_greedy_init(const double *__restrict__ R
   for (int c = threadIdx.x; c < r; c += GB) cvec[(size_t)blockIdx.x * r + c] = R[w.i + (size_t)c * ldr];
 }
 
+template <int MAXR>
 __global__ __launch_bounds__(GB) void k_greedy_step(double *__restrict__ R, int n, int r, int ldr,
                                                     int nblk, int t,
                                                     const double *__restrict__ cval_in,
@@ -135,13 +136,20 @@ __global__ __launch_bounds__(GB) void k_greedy_step(double *__restrict__ R, int 
   const int i = blockIdx.x * GB + threadIdx.x;
   Best b{-1.0, n, 0};
   if (i < n) {
+    double x[MAXR];                          // the row stays in registers between the passes
+#pragma unroll
+    for (int c = 0; c < MAXR; ++c) x[c] = c < r ? R[i + (size_t)c * ldr] : 0.0;
     double d = 0.0;
-    for (int c = 0; c < r; ++c) d += R[i + (size_t)c * ldr] * v[c];
+#pragma unroll
+    for (int c = 0; c < MAXR; ++c)
+      if (c < r) d += x[c] * v[c];
     double s = 0.0;
-    for (int c = 0; c < r; ++c) {
-      const double x = R[i + (size_t)c * ldr] - d * v[c];
-      R[i + (size_t)c * ldr] = x;
-      s += x * x;
+#pragma unroll
+    for (int c = 0; c < MAXR; ++c) {
+      if (c >= r) continue;
+      x[c] = x[c] - d * v[c];
+      R[i + (size_t)c * ldr] = x[c];
+      s += x[c] * x[c];
     }
     b = Best{s, i, 0};
   }
@@ -339,9 +347,10 @@ void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int 
     TimedLaunch tl(c, "maxvol_greedy", 4.0 * n * r * r, 8.0 * 3.0 * n * r);
     hipLaunchKernelGGL(k_greedy_init, dim3(nblk), dim3(GB), 0, c.stream, R, n, r, n, cval, cidx,
                        cvec);
+    auto step = r <= 32 ? k_greedy_step<32> : r <= 64 ? k_greedy_step<64> : k_greedy_step<96>;
     for (int t = 0; t < r; ++t) {
       const int pi = t & 1, po = pi ^ 1;
-      hipLaunchKernelGGL(k_greedy_step, dim3(nblk), dim3(GB), 0, c.stream, R, n, r, n, nblk, t,
+      hipLaunchKernelGGL(step, dim3(nblk), dim3(GB), 0, c.stream, R, n, r, n, nblk, t,
                          cval + pi * nblk, cidx + pi * nblk, cvec + (size_t)pi * nblk * r,
                          cval + po * nblk, cidx + po * nblk, cvec + (size_t)po * nblk * r,
                          rows_dev);

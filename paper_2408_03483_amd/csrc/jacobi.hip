@@ -163,14 +163,21 @@ __global__ __launch_bounds__(NT) void k_inverse(const double *__restrict__ M, in
   }
   __syncthreads();
   for (int j = 0; j < m; ++j) {
-    if (threadIdx.x == 0) {
-      int best = j;
-      double bv = fabs(T[(size_t)j * w + j]);
-      for (int i = j + 1; i < m; ++i) {
+    // pivot: largest |T(i, j)| over i >= j, ties to the smallest row (wave 0, m <= 128)
+    if (threadIdx.x < 64) {
+      double bv = -1.0;
+      int bi = m;
+      for (int i = j + (int)threadIdx.x; i < m; i += 64) {
         const double v = fabs(T[(size_t)i * w + j]);
-        if (v > bv) { bv = v; best = i; }
+        if (v > bv) { bv = v; bi = i; }
       }
-      piv = best;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (threadIdx.x == 0) piv = bi;
     }
     __syncthreads();
     const int pr = piv;
