@@ -92,6 +92,8 @@ Ctx::~Ctx() {
 TimedLaunch::TimedLaunch(Ctx &ctx, const char *name, double flops, double bytes)
     : c(ctx), on(!ctx.timer.name.empty() && ctx.timer.name == name) {
   if (!on) return;
+  on = (c.timer.seen++ % c.timer.every) == 0;   // a sample keeps the events' cost small
+  if (!on) return;
   if (c.timer.spare.empty()) {
     hipEvent_t a, b;
     HIP_CHECK(hipEventCreate(&a));

@@ -754,6 +754,7 @@ void solver_time_kernel(Solver *s, const char *name) {
     c->timer.name = name;
     c->timer.ms = c->timer.flops = c->timer.bytes = 0;
     c->timer.launches = 0;
+    c->timer.seen = 0;
   }
 }
 
