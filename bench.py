@@ -210,8 +210,9 @@ def dambreak(args):
     n, rmax, eps = 2048, 64, 1e-8
     st = synth.dam_break(seed=0, n=n, rmax=rmax, eps=eps)
 
-    def run(precision, timed_kernel):
-        dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+    def run(precision, timed_kernel, h_scale=1.0):
+        dev = [ttfv.DeviceTT.from_factors(f.A * (h_scale if v == 0 else 1.0), f.B, cap=rmax)
+               for v, f in enumerate(st.tt)]
         s = ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
                             recip="cross", precision=precision)
         for _ in range(args.warmup):
@@ -234,6 +235,9 @@ def dambreak(args):
     extra = {}
     if args.precision == "f32":
         e64, s64, Q64 = run("f64", "")
+        # the FP64 method's own sensitivity: the same run from h scaled by 1 + 1e-12
+        _, _, Qp = run("f64", "", 1.0 + 1e-12)
+        sens = _field_rel(Qp, Q64)
         rel = _field_rel(Q, Q64)
         import numpy as np
         hn = float(np.linalg.norm(Q64[0].full()))
@@ -241,6 +245,7 @@ def dambreak(args):
         extra = {"fp64_value": n * n * args.steps / e64,
                  "speedup_vs_fp64": e64 / elapsed,
                  "rel_l2_vs_fp64": rel, "diff_vs_fp64_on_h_scale": on_h,
+                 "fp64_rel_l2_after_1e-12_perturbation": sens,
                  "gate": 1e-4, "gate_pass_per_field": max(rel) <= 1e-4,
                  "gate_pass_on_h_scale": max(on_h) <= 1e-4, "ranks_fp64": s64["ranks"]}
     out = {"metric": METRIC, "value": n * n * args.steps / elapsed, "unit": "cell-updates/s",
