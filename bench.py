@@ -101,6 +101,8 @@ def main():
                     help="contraction arithmetic of the dambreak2048, ensemble and learned4096 "
                          "workloads")
     ap.add_argument("--learned-n", type=int, default=4096, help="grid of learned4096")
+    ap.add_argument("--gemm-autotune", action="store_true",
+                    help="ensemble: tune the GEMM tile shapes on a first pass of every member")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
@@ -370,6 +372,18 @@ def ensemble(args):
                                        arena_bytes=1 << 28, precision=args.precision))
         return out
 
+    tune = None
+    if args.gemm_autotune:
+        # one throwaway step of every member alone tunes each GEMM shape class the first
+        # steps meet; the timed runs and the equality check then reuse the same choices
+        ttfv.tt_gemm_autotune(True)
+        t0 = time.perf_counter()
+        for m, s in enumerate(make(range(M), 0)):
+            ttfv.tt_fv_step(s, states[m].dt, 1)
+            s.close()
+        torch.cuda.synchronize()
+        tune = {"classes": ttfv.tt_gemm_autotune(True), "s": time.perf_counter() - t0}
+        print(f"[ensemble] GEMM tiles tuned: {tune}", file=sys.stderr, flush=True)
     # members one at a time (each with its own worker streams)
     alone = make(range(M), 0)
     torch.cuda.synchronize()
@@ -423,7 +437,8 @@ def ensemble(args):
                       "r_max": ranks, "eps": 1e-10, "scheme": "upwind5",
                       "autotuned": {"workers": workers, "concurrency": conc}},
            "sequential": {"value": cells / t_seq, "s_per_step": t_seq},
-           "speedup_vs_sequential": t_seq / t_ens, "members_equal_alone": bool(same)}
+           "speedup_vs_sequential": t_seq / t_ens, "members_equal_alone": bool(same),
+           "gemm_autotune": tune}
     print(json.dumps(out), flush=True)
 
 

@@ -224,6 +224,14 @@ int  tt_ens_step(tt_ens *e, tt_fv *const *members, int count, const double *dts,
                  int concurrency);
 void tt_ens_destroy(tt_ens *e);
 
+/* GEMM tile-shape autotuner (process-wide; off by default): while on, the first rounding GEMM
+ * of each shape class (transposes, precision, M and K rounded up to powers of two, N) times
+ * the candidate tile shapes (output tile width 64 or 128; split-K chunks of at least 256,
+ * 512 or 1024, or no split) on its stream and keeps the fastest for later calls.  With it on,
+ * choices and hence the last bits of results can differ from run to run.  classes_out (may be
+ * NULL) receives the number of tuned shape classes. */
+int  tt_gemm_autotune(int on, int *classes_out);
+
 const char *tt_last_error(void);
 
 #ifdef __cplusplus

@@ -579,3 +579,11 @@ int tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm) {
     return 0;
   });
 }
+
+int tt_gemm_autotune(int on, int *classes_out) {
+  return guarded([&]() {
+    gemm_autotune(on != 0);
+    if (classes_out) *classes_out = gemm_tuned_classes();
+    return 0;
+  });
+}

@@ -151,6 +151,9 @@ void gemm(Ctx &c, bool transA, int M, int N, int K, double alpha, const double *
           const double *B, int ldb, double beta, double *C, int ldc);
 void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, const double *A,
            int lda, const double *B, int ldb, double beta, double *C, int ldc);
+// tile-shape autotuner of the GEMMs (process-wide; off by default)
+void gemm_autotune(bool on);
+int gemm_tuned_classes();
 
 // tsqr.hip: Q (n x m, ldq) and R (m x m, ldr) of Y (n x m, n >= m, m <= 96); Q == nullptr
 // forms R only

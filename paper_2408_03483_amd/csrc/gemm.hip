@@ -9,6 +9,10 @@
 #include "common.h"
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace ttfv {
 namespace {
@@ -211,6 +215,104 @@ void gemm(Ctx &c, bool transA, int M, int N, int K, double alpha, const double *
   gemm2(c, transA, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
+namespace {
+
+// Tile shape of one call: output tile width (64 or 128) and the shortest K chunk a split may
+// cut (0: no split).  Default: 128-wide tiles when N fills them (each row panel of A is then
+// read once) and chunks of at least 512.
+struct TileChoice {
+  int bn2, min_chunk;
+};
+
+TileChoice default_tiles(int N) { return {N > 64 ? 128 : 64, 512}; }
+
+// Autotuner: the first call of a shape class (transposes, precision, M and K rounded up to
+// powers of two, N) times every candidate tile shape on its own stream and keeps the fastest
+// for the process.  Off by default; while on, the choice can differ from run to run, and with
+// it the split-K summation order (results then differ in their last bits between runs).
+std::atomic<bool> g_tune{false};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int>, TileChoice> g_tuned;
+
+int ceil_log2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+void run_tiles(Ctx &c, TileChoice t, bool transA, bool transB, int M, int N, int K,
+               double alpha, const double *A, int lda, const double *B, int ldb, double beta,
+               double *C, int ldc) {
+  const int tm = (M + BM - 1) / BM, tn = (N + t.bn2 - 1) / t.bn2;
+  const int tiles = tm * tn;
+  int S = 1;
+  if (t.min_chunk > 0 && tiles < 256 && K >= t.min_chunk) {
+    S = std::min((512 + tiles - 1) / tiles, K / t.min_chunk);
+    S = std::max(S, 1);
+  }
+  int kchunk = (K + S - 1) / S;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  S = (K + kchunk - 1) / kchunk;
+  if (S == 1) {
+    dispatch_any(c, t.bn2, transA, transB, dim3(tm, tn, 1), M, N, K, kchunk, alpha, A, lda, B,
+                 ldb, beta, C, ldc, nullptr);
+    return;
+  }
+  Scope sc(c.arena);
+  double *part = c.arena.dalloc((size_t)S * M * N);
+  dispatch_any(c, t.bn2, transA, transB, dim3(tm, tn, S), M, N, K, kchunk, alpha, A, lda, B,
+               ldb, beta, C, ldc, part);
+}
+
+TileChoice tuned_tiles(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha,
+                       const double *A, int lda, const double *B, int ldb, double *C,
+                       int ldc) {
+  const auto key = std::make_tuple((int)transA, (int)transB, (int)c.fp32, ceil_log2(M), N,
+                                   ceil_log2(K));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  std::vector<TileChoice> cand;
+  for (int bn2 : {64, 128}) {
+    if (bn2 == 128 && N <= 64) continue;
+    for (int mc : {256, 512, 1024, 0}) cand.push_back({bn2, mc});
+  }
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  TileChoice best = default_tiles(N);
+  float best_ms = 1e30f;
+  for (const TileChoice &t : cand) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {      // the second run is timed (warm caches)
+      HIP_CHECK(hipEventRecord(e0, c.stream));
+      run_tiles(c, t, transA, transB, M, N, K, alpha, A, lda, B, ldb, 0.0, C, ldc);
+      HIP_CHECK(hipEventRecord(e1, c.stream));
+      HIP_CHECK(hipEventSynchronize(e1));
+      HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tuned.emplace(key, best).first->second;   // a concurrent tuner may have won
+}
+
+}  // namespace
+
+void gemm_autotune(bool on) { g_tune = on; }
+
+int gemm_tuned_classes() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int)g_tuned.size();
+}
+
 void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, const double *A,
            int lda, const double *B, int ldb, double beta, double *C, int ldc) {
   if (M <= 0 || N <= 0) return;
@@ -218,32 +320,15 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
     copy_scale(c, C, ldc, C, ldc, M, N, beta);
     return;
   }
-  // 128-wide tiles when N fills them (each row panel of A is then read once)
-  const int bn2 = N > 64 ? 128 : 64;
-  const int tm = (M + BM - 1) / BM, tn = (N + bn2 - 1) / bn2;
-  const int tiles = tm * tn;
-  int S = 1;
-  if (tiles < 256 && K >= 512) {
-    S = std::min((512 + tiles - 1) / tiles, K / 512);
-    S = std::max(S, 1);
-  }
-  int kchunk = (K + S - 1) / S;
-  kchunk = ((kchunk + BK - 1) / BK) * BK;
-  S = (K + kchunk - 1) / kchunk;
   const double fl = 2.0 * M * N * K;
   const double by = 8.0 * ((double)M * K + (double)K * N + (double)M * N);
   c.cnt.flops += fl;
   c.cnt.bytes += by;
+  TileChoice t = default_tiles(N);
+  if (g_tune && beta == 0.0)
+    t = tuned_tiles(c, transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc);
   TimedLaunch tl(c, "gemm", fl, by);
-  if (S == 1) {
-    dispatch_any(c, bn2, transA, transB, dim3(tm, tn, 1), M, N, K, kchunk, alpha, A, lda, B, ldb,
-                 beta, C, ldc, nullptr);
-    return;
-  }
-  Scope sc(c.arena);
-  double *part = c.arena.dalloc((size_t)S * M * N);
-  dispatch_any(c, bn2, transA, transB, dim3(tm, tn, S), M, N, K, kchunk, alpha, A, lda, B, ldb,
-               beta, C, ldc, part);
+  run_tiles(c, t, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 }  // namespace ttfv

@@ -62,7 +62,7 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_fv_time_kernel", "tt_ens_create", "tt_ens_step", "tt_ens_destroy",
            "tt_pm_create", "tt_pm_destroy", "tt_pm_set_weights", "tt_pm_get_weights",
            "tt_pm_forward", "tt_pm_grad", "tt_pm_train", "tt_pm_dataset", "tt_pm_features",
-           "tt_pm_topk", "tt_fv_set_pivots", "tt_last_error"]
+           "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2}
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_pm_features.argtypes = [P, P, I, I, I, P, I, P]
     L.tt_pm_topk.argtypes = [P, P, I, I, P]
     L.tt_fv_set_pivots.argtypes = [P, I, P]
+    L.tt_gemm_autotune.argtypes = [I, ctypes.POINTER(I)]
     for name in EXPORTS:
         if not hasattr(L, name):
             raise RuntimeError(f"libttfv.so lacks {name}")
@@ -489,3 +490,11 @@ def tt_pm_topk(ctx: Ctx, s, k: int):
 def tt_fv_set_pivots(s: Solver, mode: str, model: Optional[PivotModel] = None) -> None:
     _check(_lib.tt_fv_set_pivots(s.h, PIVOTS[mode], model.h if model is not None else None),
            "tt_fv_set_pivots")
+
+
+def tt_gemm_autotune(on: bool) -> int:
+    """Switch the GEMM tile-shape autotuner on or off; returns the number of tuned classes."""
+    load_library()
+    n = ctypes.c_int()
+    _check(_lib.tt_gemm_autotune(1 if on else 0, ctypes.byref(n)), "tt_gemm_autotune")
+    return n.value

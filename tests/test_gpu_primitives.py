@@ -115,6 +115,32 @@ def test_round_fp32_contractions(lib, n1, n2, r, eps, rmax):
     assert e < 1e-5
 
 
+def test_round_with_gemm_autotune(lib, ctx):
+    """With the tile-shape autotuner on, every candidate shape gives the same rounding (to the
+    oracle's tolerance), and a second call of a tuned class reuses the stored choice."""
+    _say("round with GEMM autotune")
+    rng = np.random.default_rng(3)
+    try:
+        n0 = lib.tt_gemm_autotune(True)
+        for n1, n2, r, eps, rmax in ((1000, 3000, 300, 1e-10, 32), (2049, 6144, 90, 1e-12, 64)):
+            A, B = decaying_tt(rng, n1, n2, r, decay=0.8)
+            x = lib.DeviceTT.from_factors(A, B)
+            ref = ott.tt_round(ott.TT(A, B), eps, rmax)
+            outs = []
+            for _ in range(2):
+                y = lib.DeviceTT(n1, n2, rmax)
+                lib.tt_round(ctx, x, eps, rmax, y)
+                assert y.rank == ref.rank
+                assert rel(y.full(), ref.full()) < 1e-10
+                outs.append(y.full())
+            n1c = lib.tt_gemm_autotune(True)
+            assert n1c > n0
+            n0 = n1c
+            assert rel(outs[0], outs[1]) < 1e-13      # the same tiles on the second call
+    finally:
+        lib.tt_gemm_autotune(False)
+
+
 def test_hadamard_round_parity(lib, ctx):
     _say("hadamard")
     rng = np.random.default_rng(2)
