@@ -2,13 +2,13 @@
 //
 // Used by TT rounding (Section 3.2 orthogonalises the cores by QR) and by the cross
 // (orthonormal column/row bases for maxvol).  The n x m panel (m <= 96) is cut into row
-// blocks that fit one workgroup's LDS; each block is factorised by Householder reflections
-// in LDS (LAPACK-style reflectors, R on and above the diagonal, v below it, v_0 = 1).  The
-// m x m triangles are then combined `arity` at a time in a reduction tree, again by
-// Householder in LDS.  The explicit Q is formed top-down: the root starts from the first m
-// columns of the identity, every node applies its reflectors to its slab, and each leaf
-// applies its reflectors to produce its rows of Q.  In the apply kernels each wavefront
-// keeps one column of the slab in registers and runs through all reflectors (no barriers).
+// blocks of at most 256 rows; each block is factorised by Householder reflections held in
+// registers (LAPACK-style reflectors, R on and above the diagonal, v below it, v_0 = 1).
+// The m x m triangles are then combined `arity` at a time in a reduction tree, again by
+// Householder.  The explicit Q is formed top-down: the root starts from the first m columns
+// of the identity, every node applies its reflectors to its slab, and each leaf applies its
+// reflectors to produce its rows of Q; these applications use the compact WY form of the
+// block's reflectors on the matrix cores (k_apply_wy).
 //
 // Row blocks hold between m and 2m..bmax rows (blocks are balanced), so every block has at
 // least m real rows and no padding rows enter the factorisation.
@@ -104,39 +104,6 @@ __device__ void qr_regs(T (&x)[CS][RS], int rows, int m, T *vbuf, T *taus) {
   __syncthreads();
 }
 
-// Apply H_0 ... H_{m-1} (V in LDS, rows x m, ld rows; taus) to the register panel x;
-// reflectors run m-1 .. 0.  No barriers: V is read-only here.
-template <typename T, int RS, int CS>
-__device__ void apply_regs(const T *V, const T *taus, int rows, int m, T (&x)[CS][RS]) {
-  const int gl = threadIdx.x & 15;
-  for (int j = m - 1; j >= 0; --j) {
-    const T t = taus[j];
-    if (t == T(0)) continue;
-    const T *vj = V + (size_t)j * rows;
-    T v[RS];
-#pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int i = gl + 16 * r;
-      v[r] = (i < rows && i >= j) ? (i == j ? T(1) : vj[i]) : T(0);
-    }
-    T d[CS];
-#pragma unroll
-    for (int s = 0; s < CS; ++s) {
-      T acc = T(0);
-#pragma unroll
-      for (int r = 0; r < RS; ++r) acc += v[r] * x[s][r];
-      d[s] = acc;
-    }
-    row16_sum_n<CS>(d);
-#pragma unroll
-    for (int s = 0; s < CS; ++s) {
-      const T du = t * d[s];
-#pragma unroll
-      for (int r = 0; r < RS; ++r) x[s][r] -= du * v[r];
-    }
-  }
-}
-
 __device__ __forceinline__ void leaf_range(int L, int n, int nleaf, int &start, int &rows) {
   start = (int)(((long long)L * n) / nleaf);
   const int end = (int)(((long long)(L + 1) * n) / nleaf);
@@ -230,97 +197,287 @@ __global__ __launch_bounds__(NT) void k_node_qr(const T *__restrict__ Rin, int c
   for (int c = threadIdx.x; c < m; c += NT) tau[(size_t)k * m + c] = taus[c];
 }
 
-// Top-down: slab Zin[k] (m x m) of node k -> slabs Zout[c0 .. c0+nch-1] of its children.
-// Zin == nullptr means the identity slab (root).
-template <typename T, int RS, int CS>
-__global__ __launch_bounds__(NT) void k_node_apply(const T *__restrict__ V,
-                                                   const T *__restrict__ tau, int cnt_in,
-                                                   int m, int arity, const T *__restrict__ Zin,
-                                                   T *__restrict__ Zout) {
+// ---------------------------------------------------------------------------------------
+// Top-down pass in compact WY form.  The reflectors of a block (leaf or node) multiply to
+// H_0 ... H_{m-1} = I - V T V^T with T upper triangular and T^{-1} = diag(1 / tau) +
+// strictly-upper(V^T V) (the unit-diagonal V of the stored reflectors).  The block's slab
+// of Q is then  [Z; 0] - V W2  with  W1 = V_top^T Z  (V_top: its first m rows) and W2 the
+// solution of T^{-1} W2 = W1 by back substitution, where a reflector with tau = 0 (H = I)
+// gives a zero row of W2.  The three products run on the matrix cores (16x16x4 MFMA); the
+// back substitution is m dependent rows, one lane per column of W1.
+
+// exchange with the neighbouring lane of the quad (quad_perm [1,0,3,2]) and with the other
+// pair (quad_perm [2,3,0,1])
+template <typename T>
+__device__ __forceinline__ T quad_swap1(T v) { return dpp_shift<0xB1>(v); }
+template <typename T>
+__device__ __forceinline__ T quad_swap2(T v) { return dpp_shift<0x4E>(v); }
+
+template <typename T>
+struct Mf;
+template <>
+struct Mf<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16); result v is D(row, l % 16)
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mf<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+constexpr int WY_KC = 32;        // rows of V (and Z) staged per step of the S / W1 products
+constexpr int NTW = 512;         // 8 wavefronts: up to 256 VGPRs each
+
+template <typename T, bool LEAF>
+__global__ __launch_bounds__(NTW) void k_apply_wy(const T *__restrict__ V,
+                                                 const T *__restrict__ tau, int cnt_in, int m,
+                                                 int arity, int n, int nleaf, int bmax,
+                                                 const T *__restrict__ Zin,
+                                                 T *__restrict__ Zout, double *__restrict__ Q,
+                                                 int ldq) {
   extern __shared__ __align__(8) unsigned char smraw[];
-  T *sm = reinterpret_cast<T *>(smraw);
-  const int k = blockIdx.x;
-  const int c0 = k * arity;
-  const int nch = min(arity, cnt_in - c0);
-  const int rows = nch * m;
-  if (nch == 1) {
-    for (int idx = threadIdx.x; idx < m * m; idx += NT) {
-      const int i = idx % m, c = idx / m;
-      Zout[(size_t)c0 * m * m + idx] = Zin ? Zin[(size_t)k * m * m + idx] : T(i == c ? 1 : 0);
-    }
-    return;
+  using V4 = typename Mf<T>::v4;
+  constexpr int NBMAX = QR_MAXM / 16;              // 16-column tiles of the widest slab
+  const int mp = (m + 15) & ~15, nb = mp >> 4, ld = mp + 1;
+  T *Ss = reinterpret_cast<T *>(smraw);          // V^T V, row-major (ld)
+  T *W = Ss + (size_t)mp * ld;                   // W1, then W2 in place, row-major (ld)
+  T *ts = W + (size_t)mp * ld;                   // tau (mp, zero padded)
+  T *Vst = ts + mp;                              // staging of WY_KC rows of V and of Z;
+  T *Zst = Vst + (size_t)WY_KC * ld;             // (overlaid on Ss / W when they fit)
+  if ((size_t)2 * WY_KC * ld <= (size_t)2 * mp * ld) {
+    Vst = Ss;
+    Zst = Ss + (size_t)WY_KC * ld;
   }
-  const int ldv = arity * m;
-  T *Vs = sm;
-  T *ts = sm + (size_t)rows * m;
-  const T *Vk = V + (size_t)k * ldv * m;
-  for (int idx = threadIdx.x; idx < rows * m; idx += NT) {
-    const int i = idx % rows, c = idx / rows;
-    Vs[i + (size_t)c * rows] = Vk[i + (size_t)c * ldv];
-  }
-  for (int c = threadIdx.x; c < m; c += NT) ts[c] = tau[(size_t)k * m + c];
-  const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  T x[CS][RS];
-#pragma unroll
-  for (int s = 0; s < CS; ++s)
-#pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int c = gid + NG * s, i = gl + 16 * r;
-      T v = T(0);
-      if (c < m && i < m) v = Zin ? Zin[(size_t)k * m * m + i + (size_t)c * m] : T(i == c ? 1 : 0);
-      x[s][r] = v;
+  int rows, ldv, start = 0, c0 = 0;
+  const T *Vb, *Zb, *tb;
+  if (LEAF) {
+    const int L = blockIdx.x;
+    leaf_range(L, n, nleaf, start, rows);
+    Vb = V + (size_t)L * bmax * m;
+    ldv = bmax;
+    tb = tau + (size_t)L * m;
+    Zb = Zin ? Zin + (size_t)L * m * m : nullptr;
+  } else {
+    const int k = blockIdx.x;
+    c0 = k * arity;
+    const int nch = min(arity, cnt_in - c0);
+    if (nch == 1) {
+      for (int idx = threadIdx.x; idx < m * m; idx += NTW) {
+        const int i = idx % m, c = idx / m;
+        Zout[(size_t)c0 * m * m + idx] =
+            Zin ? Zin[(size_t)k * m * m + idx] : T(i == c ? 1 : 0);
+      }
+      return;
     }
+    rows = nch * m;
+    ldv = arity * m;
+    Vb = V + (size_t)k * ldv * m;
+    tb = tau + (size_t)k * m;
+    Zb = Zin ? Zin + (size_t)k * m * m : nullptr;
+  }
+  // unit lower-trapezoidal V and the slab Z (identity at the root), zero outside; the loads
+  // are unconditional (clamped to a valid address) so that unrolled loops can batch them
+  auto vfull = [&](int i, int c) -> T {
+    const bool in = c < m && i < rows && i > c;
+    const T v = Vb[in ? i + c * ldv : 0];         // 32-bit offsets: a block holds < 2^31
+    return in ? v : T(i == c && c < m ? 1 : 0);
+  };
+  auto zfull = [&](int i, int c) -> T {
+    const bool in = i < m && c < m;
+    if (!Zb) return T(in && i == c ? 1 : 0);
+    const T v = Zb[in ? i + c * m : 0];
+    return in ? v : T(0);
+  };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  for (int i = threadIdx.x; i < mp; i += NTW) ts[i] = i < m ? tb[i] : T(0);
+
+  // S = V^T V on the block-upper tiles (ti <= tj) and W1 = V_top^T Z on all tiles; wave w
+  // owns tiles w, w + 16, ...; V and Z rows are staged through LDS with coalesced loads
+  const int ns = nb * (nb + 1) / 2, ntile = ns + nb * nb;
+  auto decode = [&](int q, int &ti, int &tj) {
+    if (q < ns) {
+      int r = q;
+      ti = 0;
+      while (r >= nb - ti) {
+        r -= nb - ti;
+        ++ti;
+      }
+      tj = ti + r;
+    } else {
+      ti = (q - ns) / nb;
+      tj = (q - ns) - ti * nb;
+    }
+  };
+  constexpr int TPW = 8;                           // tiles per wave (57 at most)
+  V4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = V4{0, 0, 0, 0};
+  // the next chunk is fetched into registers while the current one is multiplied
+  constexpr int PF = WY_KC * QR_MAXM / NTW;          // staged values per thread (6)
+  T pv[PF], pz[PF];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = threadIdx.x + NTW * e;
+      const int kk = idx % WY_KC, cc = idx / WY_KC;
+      pv[e] = vfull(k0 + kk, cc);                    // zero for cc >= m
+      pz[e] = k0 < mp ? zfull(k0 + kk, cc) : T(0);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < rows; k0 += WY_KC) {
+    const bool withZ = k0 < mp;
+#pragma unroll
+    for (int e = 0; e < PF; ++e) {
+      const int idx = threadIdx.x + NTW * e;
+      const int kk = idx % WY_KC, cc = idx / WY_KC;
+      if (cc < mp) {
+        Vst[(size_t)kk * ld + cc] = pv[e];
+        if (withZ) Zst[(size_t)kk * ld + cc] = pz[e];
+      }
+    }
+    __syncthreads();
+    if (k0 + WY_KC < rows) fetch(k0 + WY_KC);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int q = wave + (NTW / 64) * t;
+      if (q >= ntile || (q >= ns && !withZ)) continue;
+      int ti, tj;
+      decode(q, ti, tj);
+      const T *Ap = Vst + (size_t)lk * ld + 16 * ti + li;
+      const T *Bp = (q < ns ? Vst : Zst) + (size_t)lk * ld + 16 * tj + li;
+#pragma unroll
+      for (int u = 0; u < WY_KC / 4; ++u)
+        acc[t] = Mf<T>::op(Ap[(size_t)4 * u * ld], Bp[(size_t)4 * u * ld], acc[t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int q = wave + (NTW / 64) * t;
+    if (q >= ntile) continue;
+    int ti, tj;
+    decode(q, ti, tj);
+    T *D = q < ns ? Ss : W;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      D[(size_t)(16 * ti + Mf<T>::row(lk, v)) * ld + 16 * tj + li] = acc[t][v];
+  }
   __syncthreads();
-  apply_regs<T, RS, CS>(Vs, ts, rows, m, x);
+
+  // back substitution W2(i, c) = tau_i (W1(i, c) - sum_{l > i} S(i, l) W2(l, c)), i from
+  // the bottom, four rows at a time: a quad of lanes per column c, lane p summing the terms
+  // l = p (mod 4) below the block (quad sums are symmetric, so the four lanes agree
+  // bitwise), then the 4 x 4 triangle in every lane of the quad
+  if (threadIdx.x < 4 * mp) {
+    const int c = threadIdx.x >> 2, p = threadIdx.x & 3;
+    for (int i0 = mp - 4; i0 >= 0; i0 -= 4) {
+      const T *S0 = Ss + (size_t)i0 * ld;
+      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+      // rows l = i0 + 4 + p + 4 e below the block, 4 per lane at a time so that the loads of
+      // a pass are in flight together (rows >= mp read row mp - 1 and count zero)
+      for (int l0 = i0 + 4 + p; l0 < mp; l0 += 16) {
+        T w[4], a0[4], a1[4], a2[4], a3[4];
 #pragma unroll
-  for (int s = 0; s < CS; ++s)
+        for (int e = 0; e < 4; ++e) {
+          const int l = l0 + 4 * e, lc = min(l, mp - 1);
+          const T wv = W[(size_t)lc * ld + c];
+          w[e] = l < mp ? wv : T(0);
+          a0[e] = S0[lc];
+          a1[e] = S0[ld + lc];
+          a2[e] = S0[2 * ld + lc];
+          a3[e] = S0[3 * ld + lc];
+        }
 #pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int c = gid + NG * s, i = gl + 16 * r;
-      if (c >= m || i >= rows) continue;
-      const int ch = i / m, ii = i - ch * m;
-      Zout[(size_t)(c0 + ch) * m * m + ii + (size_t)c * m] = x[s][r];
+        for (int e = 0; e < 4; ++e) {
+          s0 += a0[e] * w[e];
+          s1 += a1[e] * w[e];
+          s2 += a2[e] * w[e];
+          s3 += a3[e] * w[e];
+        }
+      }
+      s0 += quad_swap1(s0);
+      s1 += quad_swap1(s1);
+      s2 += quad_swap1(s2);
+      s3 += quad_swap1(s3);
+      s0 += quad_swap2(s0);
+      s1 += quad_swap2(s1);
+      s2 += quad_swap2(s2);
+      s3 += quad_swap2(s3);
+      const T y0 = W[(size_t)i0 * ld + c], y1 = W[(size_t)(i0 + 1) * ld + c];
+      const T y2 = W[(size_t)(i0 + 2) * ld + c], y3 = W[(size_t)(i0 + 3) * ld + c];
+      const T w3 = ts[i0 + 3] * (y3 - s3);
+      const T w2 = ts[i0 + 2] * (y2 - s2 - S0[2 * ld + i0 + 3] * w3);
+      const T w1 = ts[i0 + 1] * (y1 - s1 - S0[ld + i0 + 2] * w2 - S0[ld + i0 + 3] * w3);
+      const T w0 = ts[i0] * (y0 - s0 - S0[i0 + 1] * w1 - S0[i0 + 2] * w2 - S0[i0 + 3] * w3);
+      const T wp = p == 0 ? w0 : p == 1 ? w1 : p == 2 ? w2 : w3;
+      W[(size_t)(i0 + p) * ld + c] = wp;
     }
+  }
+  __syncthreads();
+
+  // output slab [Z; 0] - V W2, formed transposed so that lanes run along rows: tile
+  // (columns 16 tc.., rows 16 st..) = W2^T V^T
+  const int nstrip = (rows + 15) >> 4;
+  constexpr int NH = NBMAX;                          // column tiles per pass
+  for (int job = wave; job < nstrip; job += NTW / 64) {
+    const int st = job, tc0 = 0;
+    V4 o[NH];
+#pragma unroll
+    for (int tc = 0; tc < NH; ++tc) o[tc] = V4{0, 0, 0, 0};
+    const int kend = min(mp, 16 * st + 16);          // V(i, k) = 0 for k > i
+#pragma unroll 1
+    for (int k0 = 0; k0 < kend; k0 += 32) {        // 32 columns of V per group of loads
+      T b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = vfull(16 * st + li, k0 + 4 * u + lk);
+      const int ucnt = min(8, (kend - k0) >> 2);
+      for (int u = 0; u < ucnt; ++u) {
+        const T *Wk = W + (size_t)(k0 + 4 * u + lk) * ld + 16 * tc0 + li;
+        T bu = b[0];
+#pragma unroll
+        for (int uu = 1; uu < 8; ++uu) bu = u == uu ? b[uu] : bu;
+#pragma unroll
+        for (int tc = 0; tc < NH; ++tc)
+          if (tc0 + tc < nb) o[tc] = Mf<T>::op(Wk[16 * tc], bu, o[tc]);
+      }
+    }
+    const int i = 16 * st + li;
+    if (i >= rows) continue;
+    // destination of row i: Q row start + i (leaf) or row ii of child ch (node)
+    const int ch = LEAF ? 0 : i / m, ii = LEAF ? 0 : i - ch * m;
+    double *qrow = LEAF ? Q + (start + i) : nullptr;
+    T *zrow = LEAF ? nullptr : Zout + (size_t)(c0 + ch) * m * m + ii;
+    const int ldo = LEAF ? ldq : m;
+#pragma unroll
+    for (int tc = 0; tc < NH; ++tc) {
+      if (tc0 + tc >= nb) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * (tc0 + tc) + Mf<T>::row(lk, v);
+        if (c >= m) continue;
+        const T val = (i < m ? zfull(i, c) : T(0)) - o[tc][v];
+        if (LEAF)
+          qrow[c * ldo] = double(val);
+        else
+          zrow[c * ldo] = val;
+      }
+    }
+  }
 }
 
-template <typename T, int RS, int CS>
-__global__ __launch_bounds__(NT) void k_leaf_apply(const T *__restrict__ V,
-                                                   const T *__restrict__ tau, int n, int m,
-                                                   int nleaf, int bmax, const T *__restrict__ Z,
-                                                   double *__restrict__ Q, int ldq) {
-  extern __shared__ __align__(8) unsigned char smraw[];
-  T *sm = reinterpret_cast<T *>(smraw);
-  const int L = blockIdx.x;
-  int start, rows;
-  leaf_range(L, n, nleaf, start, rows);
-  T *Vs = sm;
-  T *ts = sm + (size_t)rows * m;
-  const T *VL = V + (size_t)L * bmax * m;
-  for (int idx = threadIdx.x; idx < rows * m; idx += NT) {
-    const int i = idx % rows, c = idx / rows;
-    Vs[i + (size_t)c * rows] = VL[i + (size_t)c * bmax];
-  }
-  for (int c = threadIdx.x; c < m; c += NT) ts[c] = tau[(size_t)L * m + c];
-  const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  T x[CS][RS];
-#pragma unroll
-  for (int s = 0; s < CS; ++s)
-#pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int c = gid + NG * s, i = gl + 16 * r;
-      T v = T(0);
-      if (c < m && i < m) v = Z ? Z[(size_t)L * m * m + i + (size_t)c * m] : T(i == c ? 1 : 0);
-      x[s][r] = v;
-    }
-  __syncthreads();
-  apply_regs<T, RS, CS>(Vs, ts, rows, m, x);
-#pragma unroll
-  for (int s = 0; s < CS; ++s)
-#pragma unroll
-    for (int r = 0; r < RS; ++r) {
-      const int c = gid + NG * s, i = gl + 16 * r;
-      if (c < m && i < rows) Q[(size_t)(start + i) + (size_t)c * ldq] = double(x[s][r]);
-    }
+size_t apply_wy_lds(int m, size_t elem) {
+  const size_t mp = (size_t)((m + 15) & ~15), ld = mp + 1;
+  const size_t stage = 2 * (size_t)WY_KC * ld;
+  return (2 * mp * ld + mp + (stage <= 2 * mp * ld ? 0 : stage)) * elem;
 }
 
 int g_lds_doubles = 0;
@@ -383,23 +540,23 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
   T *Z[2] = {talloc(zmax * m * m), talloc(zmax * m * m)};
   const T *Zin = nullptr;
   int which = 0;
+  const size_t wy_lds = apply_wy_lds(m, sizeof(T));
   for (int l = levels; l >= 1; --l) {
-    const size_t lds = ((size_t)arity * m * m + m) * sizeof(T);
-    set_lds(k_node_apply<T, RS, CS>, lds);
+    set_lds(k_apply_wy<T, false>, wy_lds);
     const double rows_l = (double)pl.cnt[l - 1] * m;
     TimedLaunch ta(c, "tsqr_node_apply", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * pl.cnt[l],
                    8.0 * (2.0 * rows_l * m + (double)pl.cnt[l] * m * m));
-    hipLaunchKernelGGL((k_node_apply<T, RS, CS>), dim3(pl.cnt[l]), dim3(NT), lds, c.stream, Vl[l],
-                       tl[l], pl.cnt[l - 1], m, arity, Zin, Z[which]);
+    hipLaunchKernelGGL((k_apply_wy<T, false>), dim3(pl.cnt[l]), dim3(NTW), wy_lds, c.stream,
+                       Vl[l], tl[l], pl.cnt[l - 1], m, arity, 0, 0, 0, Zin, Z[which],
+                       (double *)nullptr, 0);
     Zin = Z[which];
     which ^= 1;
   }
-  const size_t lds = ((size_t)bmax * m + m) * sizeof(T);
-  set_lds(k_leaf_apply<T, RS, CS>, lds);
+  set_lds(k_apply_wy<T, true>, wy_lds);
   TimedLaunch tl2(c, "tsqr_leaf_apply", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
                   8.0 * (2.0 * n * m + (double)nleaf * m * m));
-  hipLaunchKernelGGL((k_leaf_apply<T, RS, CS>), dim3(nleaf), dim3(NT), lds, c.stream, Vleaf,
-                     tleaf, n, m, nleaf, bmax, Zin, Q, ldq);
+  hipLaunchKernelGGL((k_apply_wy<T, true>), dim3(nleaf), dim3(NTW), wy_lds, c.stream, Vleaf,
+                     tleaf, 0, m, 0, n, nleaf, bmax, Zin, (T *)nullptr, Q, ldq);
 }
 
 template <typename T>
@@ -429,13 +586,13 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
   Plan pl;
   pl.n = n;
   pl.m = m;
-  // rows per leaf: registers hold <= 256 rows; the apply kernel keeps V (rows x m) in LDS
-  pl.bmax = std::min(MAXROWS, (d - 2 * m) / m);
-  // two columns per lane group above 64 columns: 192-row blocks keep the panel in registers
-  if (m > NG) pl.bmax = std::min(pl.bmax, 192);
-  TT_REQUIRE(pl.bmax >= 2 * m || n <= pl.bmax, "tsqr: LDS too small for this width");
+  // rows per leaf: registers hold <= 256 rows; two columns per lane group above 64
+  // columns: 192-row blocks keep the panel in registers
+  pl.bmax = m > NG ? 192 : MAXROWS;
+  TT_REQUIRE(apply_wy_lds(m, sizeof(double)) <= (size_t)d * sizeof(double),
+             "tsqr: LDS too small for this width");
   pl.nleaf = std::max(1, (n + pl.bmax - 1) / pl.bmax);
-  pl.arity = std::max(2, std::min(16, std::min(MAXROWS / m, (d - m) / (m * m))));
+  pl.arity = std::max(2, std::min(16, MAXROWS / m));
   pl.cnt = {pl.nleaf};
   while (pl.cnt.back() > 1) pl.cnt.push_back((pl.cnt.back() + pl.arity - 1) / pl.arity);
   const int rowsmax = std::max(std::min(pl.bmax, n), pl.nleaf > 1 ? pl.arity * m : 0);

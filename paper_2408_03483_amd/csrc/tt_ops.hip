@@ -130,7 +130,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
     }
   } else {
     // randomized range finder with subspace iterations; more iterations are run while the
-    // estimated contraction (s_m / s_k)^(2q+1) of the discarded directions is above 1e-13
+    // estimated leak (s_m / s_k)^(2q+1) s_k of the discarded directions is above 1e-13 s_0
     m = std::min(width, mn);
     double *Om = c.arena.dalloc((size_t)n2 * m);
     // the test matrix depends only on the shape, so a rounding gives the same result on any
@@ -177,11 +177,12 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       // (a) the sketch reached round-off: beyond m - p the captured spectrum is below
       //     1e-14 s_0, so with oversampling p the range error is at that level;
       // (b) otherwise the subspace iteration has contracted the discarded directions by
-      //     (s_m / s_k)^(2q+1) <= 1e-13.
+      //     (s_m / s_k)^(2q+1); what they can still leak into the kept part is at most that
+      //     factor times s_k, which must be below 1e-13 s_0.
       const int pover = std::max(8, m / 4);
       if (m - pover > k && s[m - pover] <= 1e-14 * s[0]) break;
       const double ratio = s[m - 1] / s[k - 1];
-      if (std::pow(ratio, 2 * q + 1) <= 1e-13) break;
+      if (std::pow(ratio, 2 * q + 1) * s[k - 1] <= 1e-13 * s[0]) break;
       US = nullptr;   // basis changes below: the SVD must be recomputed
       // one more subspace iteration from the current basis: Y = X (X^T Qa) = X Z
       tsqr(c, Z, n2, m, n2, qz, n2, rtmp, m);
