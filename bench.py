@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--learned-n", type=int, default=4096, help="grid of learned4096")
     ap.add_argument("--gemm-autotune", action="store_true",
                     help="ensemble: tune the GEMM tile shapes on a first pass of every member")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB on the device first (a kernel of known traffic that "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
@@ -117,6 +120,11 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
     if args.workload == "ensemble":
         return ensemble(args)
     if args.workload == "dambreak2048":
