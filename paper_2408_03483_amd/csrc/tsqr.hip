@@ -204,7 +204,8 @@ __global__ __launch_bounds__(NT) void k_node_qr(const T *__restrict__ Rin, int c
 // of Q is then  [Z; 0] - V W2  with  W1 = V_top^T Z  (V_top: its first m rows) and W2 the
 // solution of T^{-1} W2 = W1 by back substitution, where a reflector with tau = 0 (H = I)
 // gives a zero row of W2.  The three products run on the matrix cores (16x16x4 MFMA); the
-// back substitution is m dependent rows, one lane per column of W1.
+// back substitution takes the rows four at a time from the bottom (m / 4 dependent steps),
+// with a quad of lanes per column of W1.
 
 // exchange with the neighbouring lane of the quad (quad_perm [1,0,3,2]) and with the other
 // pair (quad_perm [2,3,0,1])
