@@ -67,10 +67,11 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
 #pragma unroll
     for (int v = 0; v < TN; ++v) acc[u][v] = V{0, 0, 0, 0};
 
-  // the next K-slice is fetched into registers while the current one is multiplied from LDS
+  // K-slices are fetched into registers two ahead of the one multiplied from LDS (two
+  // register sets, so a slice's global loads have two slices of MFMA work to arrive)
   constexpr int QA = BM * BK / NT, QB = BN2 * BK / NT;
-  double ra[QA], rb[QB];
-  auto fetch = [&](int kk) {
+  double ra0[QA], rb0[QB], ra1[QA], rb1[QB];
+  auto fetch = [&](int kk, double (&ra)[QA], double (&rb)[QB]) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int t = tid + NT * q;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
       rb[q] = v;
     }
   };
-  auto stage = [&]() {
+  auto stage = [&](const double (&ra)[QA], const double (&rb)[QB]) {
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int t = tid + NT * q;
@@ -112,11 +113,7 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
       Bs[k][j] = (T)rb[q];
     }
   };
-  if (k0 < k1) fetch(k0);
-  for (int kk = k0; kk < k1; kk += BK) {
-    stage();
-    __syncthreads();
-    if (kk + BK < k1) fetch(kk + BK);
+  auto mult = [&]() {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       T a[2], b[TN];
@@ -129,6 +126,20 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
 #pragma unroll
         for (int v = 0; v < TN; ++v) acc[u][v] = Mfma<T>::op(a[u], b[v], acc[u][v]);
     }
+  };
+  if (k0 < k1) fetch(k0, ra0, rb0);
+  if (k0 + BK < k1) fetch(k0 + BK, ra1, rb1);
+  for (int kk = k0; kk < k1; kk += 2 * BK) {
+    stage(ra0, rb0);
+    __syncthreads();
+    if (kk + 2 * BK < k1) fetch(kk + 2 * BK, ra0, rb0);
+    mult();
+    __syncthreads();
+    if (kk + BK >= k1) break;
+    stage(ra1, rb1);
+    __syncthreads();
+    if (kk + 3 * BK < k1) fetch(kk + 3 * BK, ra1, rb1);
+    mult();
     __syncthreads();
   }
 #pragma unroll
