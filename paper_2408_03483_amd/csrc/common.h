@@ -165,8 +165,10 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
 // jacobi.hip
 // One-sided Jacobi on M (m x m, ld m, m <= 96): writes U*Sigma columns sorted by norm into
 // US (m x m) and the norms into sig (device, m).
-// trans: M holds the transpose of the matrix to decompose
-void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans = false);
+// trans: M holds the transpose of the matrix to decompose.  Columns with norm below
+// floor_rel ||M||_F take no rotations (a rounding passes eps / 100).
+void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans = false,
+                double floor_rel = 0.0);
 // inverse of a small square matrix (m <= 96) with partial pivoting
 void small_inverse(Ctx &c, const double *M, int m, int ldm, double *Minv);
 // normalise the first k columns of US by sig into U

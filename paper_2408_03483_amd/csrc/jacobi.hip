@@ -30,12 +30,14 @@ constexpr int WAVES = NT / 64;
 // One group of LP lanes (8 or 16) per column pair: column entries i = lane + LP r.  A round
 // is a dependent chain (loads, dot products, group reduction, rotation, stores, barrier),
 // so its latency, not the issue rate, sets the time per round.
-// Columns whose squared norm is below 1e-34 ||M||_F^2 are left alone (numerical zeros).
+// Columns whose norm is below floor ||M||_F (at least 1e-17 ||M||_F) are left alone: for a
+// rounding with tolerance eps the caller sets floor = eps / 100, below which a column can
+// neither change the kept rank nor move the kept part by more than a fraction of eps.
 template <int LP, int RS>
 __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int m,
                                                double *__restrict__ US,
                                                double *__restrict__ sig, int max_sweeps,
-                                               int trans) {
+                                               int trans, double floor2) {
   extern __shared__ double sm[];
   const int mm = (m + 1) & ~1;
   double *S = sm;                               // mm columns of m rows
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   __syncthreads();
   double fro2 = 0.0;
   for (int w = 0; w < nt / 64; ++w) fro2 += fro_part[w];
-  const double tiny = 1e-34 * fro2;
+  const double tiny = fmax(1e-34, floor2) * fro2;
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   const int np = mm - 1;                        // round-robin over mm players, np rounds
@@ -227,7 +229,8 @@ void set_lds(K kern, size_t bytes) {
 
 }  // namespace
 
-void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans) {
+void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans,
+                double floor_rel) {
   TT_REQUIRE(m >= 1 && m <= 128, "jacobi_svd: m out of range");
   const int mm = (m + 1) & ~1;
   const size_t lds = ((size_t)mm * m + 2 * mm) * sizeof(double);
@@ -237,7 +240,7 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool tr
     const int nthreads = std::max(64, ((mm / 2) * lp + 63) / 64 * 64);
     set_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40,
-                       trans ? 1 : 0);
+                       trans ? 1 : 0, floor_rel * floor_rel);
   };
   if (m <= 32) launch(k_jacobi<16, 2>, 16);
   else if (m <= 64) launch(k_jacobi<16, 4>, 16);

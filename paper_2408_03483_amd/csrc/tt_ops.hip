@@ -169,7 +169,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
         US = c.arena.dalloc((size_t)m * m);
         sg = c.arena.dalloc((size_t)m);
       }
-      jacobi_svd(c, M, m, US, sg, Mt);
+      jacobi_svd(c, M, m, US, sg, Mt, 1e-2 * eps);
       std::vector<double> s = to_host(c, sg, m);
       if (s[0] == 0.0) break;
       const int k = trunc_rank(s, eps, rmax, nullptr);
@@ -199,7 +199,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   if (!US) {
     US = c.arena.dalloc((size_t)m * m);
     sg = c.arena.dalloc((size_t)m);
-    jacobi_svd(c, M, m, US, sg, Mt);
+    jacobi_svd(c, M, m, US, sg, Mt, 1e-2 * eps);
   }
   std::vector<double> s = to_host(c, sg, m);
   for (double v : s)
@@ -241,7 +241,7 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
     double *q = c.arena.dalloc((size_t)n * m), *r = c.arena.dalloc((size_t)m * m);
     tsqr(c, C, n, m, ldc, q, n, r, m);
     double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc(m);
-    jacobi_svd(c, r, m, US, sg);
+    jacobi_svd(c, r, m, US, sg, false, 1e-2 * drop);
     std::vector<double> s = to_host(c, sg, m);
     int k = 0;
     if (s[0] > 0.0)
@@ -262,7 +262,7 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
   double *Rt = c.arena.dalloc((size_t)n * n);
   transpose(c, Rt, n, rt, n, n, n);
   double *US = c.arena.dalloc((size_t)n * n), *sg = c.arena.dalloc(n);
-  jacobi_svd(c, Rt, n, US, sg);
+  jacobi_svd(c, Rt, n, US, sg, false, 1e-2 * drop);
   std::vector<double> s = to_host(c, sg, n);
   int k = 0;
   if (s[0] > 0.0)
