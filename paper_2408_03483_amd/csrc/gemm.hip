@@ -238,8 +238,8 @@ struct TileChoice {
 TileChoice default_tiles(int N) { return {N > 64 ? 128 : 64, 512}; }
 
 // Autotuner: the first call of a shape class (transposes, precision, M and K rounded up to
-// powers of two, N) times every candidate tile shape on its own stream and keeps the fastest
-// for the process.  Off by default; while on, the choice can differ from run to run, and with
+// powers of two, N) times every candidate tile shape on the caller's stream (writing C, so
+// only calls with beta = 0 are tuned) and keeps the fastest for the process.  Off by default; while on, the choice can differ from run to run, and with
 // it the split-K summation order (results then differ in their last bits between runs).
 std::atomic<bool> g_tune{false};
 std::mutex g_tune_mu;
@@ -290,9 +290,16 @@ TileChoice tuned_tiles(Ctx &c, bool transA, bool transB, int M, int N, int K, do
     if (bn2 == 128 && N <= 64) continue;
     for (int mc : {256, 512, 1024, 0}) cand.push_back({bn2, mc});
   }
-  hipEvent_t e0, e1;
-  HIP_CHECK(hipEventCreate(&e0));
-  HIP_CHECK(hipEventCreate(&e1));
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIP_CHECK(hipEventCreate(&ev.e0));
+  HIP_CHECK(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   TileChoice best = default_tiles(N);
   float best_ms = 1e30f;
   for (const TileChoice &t : cand) {
@@ -309,8 +316,6 @@ TileChoice tuned_tiles(Ctx &c, bool transA, bool transB, int M, int N, int K, do
       best = t;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   return g_tuned.emplace(key, best).first->second;   // a concurrent tuner may have won
 }
