@@ -115,6 +115,29 @@ def test_round_fp32_contractions(lib, n1, n2, r, eps, rmax):
     assert e < 1e-5
 
 
+@pytest.mark.parametrize("m", [1, 7, 17, 33, 63, 65, 81, 96])
+def test_round_full_rank_orthonormal_factor(lib, ctx, m):
+    """Full-rank rounding (eps = 0, r_max = m) takes the exact path: two TSQRs (leaves of 250
+    or 171 rows, node levels, the compact-WY top-down pass) and the SVD of Ra Rb^T.  The TT is
+    reproduced to round-off, the first output core is orthonormal, and the singular values
+    match LAPACK's."""
+    _say(f"full-rank round m={m}")
+    rng = np.random.default_rng(100 + m)
+    n1, n2 = 1000, 4097
+    Ua, _ = np.linalg.qr(rng.standard_normal((n1, m)))
+    Ub, _ = np.linalg.qr(rng.standard_normal((n2, m)))
+    s = np.logspace(0, -3, m)
+    A, B = Ua * s, Ub
+    x = lib.DeviceTT.from_factors(A, B)
+    y = lib.DeviceTT(n1, n2, m)
+    _, sig = lib.tt_round(ctx, x, 0.0, m, y)
+    assert y.rank == m
+    Ay, By = y.factors()
+    assert np.max(np.abs(Ay.T @ Ay - np.eye(m))) < 1e-12
+    assert rel(Ay @ By.T, A @ B.T) < 1e-12
+    assert np.allclose(sig, s, rtol=1e-12, atol=0)
+
+
 def test_round_with_gemm_autotune(lib, ctx):
     """With the tile-shape autotuner on, every candidate shape gives the same rounding (to the
     oracle's tolerance), and a second call of a tuned class reuses the stored choice."""
