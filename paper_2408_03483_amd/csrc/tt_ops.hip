@@ -77,6 +77,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   double *M = nullptr;
   bool Mt = false;           // M holds the transpose of the core to decompose
   double *US = nullptr, *sg = nullptr;   // SVD of M once computed
+  std::vector<double> s_host;            // its singular values on the host, when fetched
   int m = 0;
   if (R <= width && R <= mn) {
     m = R;
@@ -170,7 +171,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
         sg = c.arena.dalloc((size_t)m);
       }
       jacobi_svd(c, M, m, US, sg, Mt, 1e-2 * eps);
-      std::vector<double> s = to_host(c, sg, m);
+      s_host = to_host(c, sg, m);
+      const std::vector<double> &s = s_host;
       if (s[0] == 0.0) break;
       const int k = trunc_rank(s, eps, rmax, nullptr);
       if (k >= m) break;
@@ -184,6 +186,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       const double ratio = s[m - 1] / s[k - 1];
       if (std::pow(ratio, 2 * q + 1) * s[k - 1] <= 1e-13 * s[0]) break;
       US = nullptr;   // basis changes below: the SVD must be recomputed
+      s_host.clear();
       // one more subspace iteration from the current basis: Y = X (X^T Qa) = X Z
       tsqr(c, Z, n2, m, n2, qz, n2, rtmp, m);
       gemm(c, true, R, m, n2, 1.0, x.B, n2, qz, n2, 0.0, T, R);
@@ -201,7 +204,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
     sg = c.arena.dalloc((size_t)m);
     jacobi_svd(c, M, m, US, sg, Mt, 1e-2 * eps);
   }
-  std::vector<double> s = to_host(c, sg, m);
+  // the range finder's last check already brought these singular values to the host
+  std::vector<double> s = s_host.empty() ? to_host(c, sg, m) : std::move(s_host);
   for (double v : s)
     if (!std::isfinite(v)) throw Error(TT_ENONFINITE, "round: non-finite singular value");
   int warn = 0;
