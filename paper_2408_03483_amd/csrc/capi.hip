@@ -74,11 +74,15 @@ int *Ctx::tile_counters() {
   return tile_cnt;
 }
 
+double *Ctx::pinned_staging() {
+  if (!pinned) HIP_CHECK(hipHostMalloc((void **)&pinned, kPinnedDoubles * sizeof(double)));
+  return pinned;
+}
+
 Ctx::~Ctx() {
-  if (tile_cnt) {
-    (void)hipStreamSynchronize(stream);
-    (void)hipFree(tile_cnt);
-  }
+  if (tile_cnt || pinned) (void)hipStreamSynchronize(stream);
+  if (tile_cnt) (void)hipFree(tile_cnt);
+  if (pinned) (void)hipHostFree(pinned);
   for (auto &e : timer.spare) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);

@@ -99,6 +99,9 @@ struct Ctx {
   KernelTimer timer;
   int *tile_cnt = nullptr;  // zeroed per-tile arrival counters of split-K GEMMs (this stream)
   int *tile_counters();     // allocates them on first use
+  double *pinned = nullptr; // pinned host staging for small device-to-host reads
+  static constexpr size_t kPinnedDoubles = 4096;
+  double *pinned_staging(); // allocates it on first use
   void sync();
   ~Ctx();
 };

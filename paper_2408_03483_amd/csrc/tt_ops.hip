@@ -26,8 +26,17 @@ namespace ttfv {
 
 namespace {
 
+// small reads go through the context's pinned staging buffer: a copy into pageable memory
+// is staged by the runtime and costs a longer round trip on this path of every rounding
 std::vector<double> to_host(Ctx &c, const double *dev, size_t n) {
   std::vector<double> h(n);
+  if (n && n <= Ctx::kPinnedDoubles) {
+    double *st = c.pinned_staging();
+    HIP_CHECK(hipMemcpyAsync(st, dev, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    std::copy(st, st + n, h.begin());
+    return h;
+  }
   if (n) HIP_CHECK(hipMemcpyAsync(h.data(), dev, n * sizeof(double), hipMemcpyDeviceToHost,
                                   c.stream));
   c.sync();
