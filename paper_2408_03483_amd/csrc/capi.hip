@@ -49,7 +49,11 @@ void *Arena::alloc(size_t bytes) {
 }
 
 void Ctx::sync() {
-  HIP_CHECK(hipStreamSynchronize(stream));
+  // an event with default flags is waited for by polling, which wakes the host sooner than a
+  // stream synchronisation that may yield the thread
+  if (!sync_ev) HIP_CHECK(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(sync_ev, stream));
+  HIP_CHECK(hipEventSynchronize(sync_ev));
   for (size_t i = 0; i < timer.pending.size(); ++i) {
     float ms = 0.f;
     HIP_CHECK(hipEventElapsedTime(&ms, timer.pending[i].first, timer.pending[i].second));
@@ -81,6 +85,7 @@ double *Ctx::pinned_staging() {
 
 Ctx::~Ctx() {
   if (tile_cnt || pinned) (void)hipStreamSynchronize(stream);
+  if (sync_ev) (void)hipEventDestroy(sync_ev);
   if (tile_cnt) (void)hipFree(tile_cnt);
   if (pinned) (void)hipHostFree(pinned);
   for (auto &e : timer.spare) {

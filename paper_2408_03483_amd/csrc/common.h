@@ -100,6 +100,7 @@ struct Ctx {
   int *tile_cnt = nullptr;  // zeroed per-tile arrival counters of split-K GEMMs (this stream)
   int *tile_counters();     // allocates them on first use
   double *pinned = nullptr; // pinned host staging for small device-to-host reads
+  hipEvent_t sync_ev = nullptr;   // recorded and waited for by sync()
   static constexpr size_t kPinnedDoubles = 4096;
   double *pinned_staging(); // allocates it on first use
   void sync();
