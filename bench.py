@@ -78,7 +78,7 @@ def _roof(kernel, stats, elapsed, fp32=False, traffic=None):
     return {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
             "avg_launch_us": avg_ms * 1e3, "launches_timed": stats["timed_launches"],
-            "timed_sample": "1 launch in 8 of the family",
+            "timed_sample": "1 launch in 32 of the family",
             "alg_flops_per_launch": fl,
             "alg_bytes_per_launch": stats["timed_bytes"] / stats["timed_launches"]}
 PEAK_HBM_GBS = 8000.0

@@ -167,7 +167,7 @@ int  tt_fv_step(tt_fv *s, double dt, int nsteps);
 /* Copy the state into caller buffers (cap >= rank). */
 int  tt_fv_get_state(tt_fv *s, tt_matrix q[3]);
 int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
-/* Time one launch in eight of one kernel family with HIP events on the stream it runs on (name:
+/* Time one launch in 32 of one kernel family with HIP events on the stream it runs on (name:
  * "jacobi", "tsqr_leaf_qr", "tsqr_node_qr", "tsqr_node_apply", "tsqr_leaf_apply", "gemm",
  * "maxvol_greedy"; NULL or "" switches timing off) and reset the timed_* statistics. */
 int  tt_fv_time_kernel(tt_fv *s, const char *name);

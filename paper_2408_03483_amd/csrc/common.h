@@ -81,7 +81,7 @@ struct Counters {
 // bracketed by HIP events on their own stream; pairs are resolved at the next sync.
 struct KernelTimer {
   std::string name;                         // empty: off
-  int every = 8;                            // one launch in `every` of the family is timed
+  int every = 32;                           // one launch in `every` of the family is timed
   long long seen = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, spare;
   std::vector<double> pending_flops, pending_bytes;
