@@ -3,6 +3,8 @@
 //    truncates the SVD of G1 R): columns are rotated pairwise until mutually orthogonal,
 //    giving U * Sigma column by column; a round-robin schedule makes the m/2 pair rotations
 //    of a round independent, one wavefront per pair;
+//  * Householder QR with column pivoting, which grades a matrix before the Jacobi SVD of its
+//    triangular factor (far fewer sweeps on strongly graded spectra);
 //  * Gauss-Jordan inverse with partial pivoting (skeleton of the cross, maxvol start).
 #include "common.h"
 #include "wave.h"
@@ -37,12 +39,13 @@ template <int LP, int RS>
 __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int m,
                                                double *__restrict__ US,
                                                double *__restrict__ sig, int max_sweeps,
-                                               int trans, double floor2) {
+                                               int trans, double floor2, int accum) {
   extern __shared__ double sm[];
   const int mm = (m + 1) & ~1;
   double *S = sm;                               // mm columns of m rows
   double *nrm = sm + (size_t)mm * m;            // mm norms
   double *cn = nrm + mm;                        // squared column norms during the sweeps
+  double *Jr = cn + mm;                         // accum: product of the rotations, mm x mm
   __shared__ int rotated;
   __shared__ double fro_part[NT / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -55,6 +58,9 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
     S[idx] = v;
     part += v * v;
   }
+  if (accum)
+    for (int idx = threadIdx.x; idx < mm * mm; idx += nt)
+      Jr[idx] = (idx % mm) == (idx / mm) ? 1.0 : 0.0;
   part = wave_sum(part);
   if (lane == 0) fro_part[wave] = part;
   __syncthreads();
@@ -117,6 +123,18 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
               cq[i] = s * xp[r] + c * xq[r];
             }
           }
+          if (accum) {
+            double *jp = Jr + (size_t)p * mm, *jq = Jr + (size_t)q * mm;
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+              const int i = gl + LP * r;
+              if (i < mm) {
+                const double a = jp[i], b = jq[i];
+                jp[i] = c * a - s * b;
+                jq[i] = s * a + c * b;
+              }
+            }
+          }
           if (gl == 0) {
             cn[p] = al - tt * ga;
             cn[q] = be + tt * ga;
@@ -147,8 +165,134 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
       rk += (nj > ni) || (nj == ni && j < i);
     }
     sig[rk] = ni;
-    for (int r = 0; r < m; ++r) US[(size_t)rk * m + r] = S[(size_t)i * m + r];
+    if (accum)   // left singular vectors of the transpose held in S, scaled by the norms
+      for (int r = 0; r < m; ++r) US[(size_t)rk * m + r] = Jr[(size_t)i * mm + r] * ni;
+    else
+      for (int r = 0; r < m; ++r) US[(size_t)rk * m + r] = S[(size_t)i * m + r];
   }
+}
+
+// Householder QR with column pivoting of an m x m matrix (m <= 96) in one workgroup,
+// M P = Q2 R2, with Q2 formed explicitly (backward accumulation of the reflectors).  The
+// pivot is the remaining column of largest norm below the current row (ties to the smallest
+// index); the norms are recomputed exactly after every step instead of downdated.  The
+// permutation is not returned: the left singular vectors of M are Q2 times those of R2.
+// Wave 0 picks the pivot, swaps it in and forms the reflector; then groups of 16 lanes, one
+// column each, apply it to the trailing columns: two barriers per column.
+constexpr int QRCP_NT = 1024;
+__global__ __launch_bounds__(QRCP_NT) void k_qrcp(const double *__restrict__ M, int m,
+                                                  double *__restrict__ R2,
+                                                  double *__restrict__ Q2) {
+  extern __shared__ double sm[];
+  double *A = sm;                               // m x m, column-major: R above, v below
+  double *Qs = A + (size_t)m * m;               // m x m, the explicit Q2
+  double *vn = Qs + (size_t)m * m;              // squared norms below the current row
+  double *tau = vn + m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gid = threadIdx.x >> 4, gl = threadIdx.x & 15, ngroups = QRCP_NT / 16;
+  for (int idx = threadIdx.x; idx < m * m; idx += QRCP_NT) A[idx] = M[idx];
+  __syncthreads();
+  for (int k = gid; k < m; k += ngroups) {
+    double s2[1] = {0.0};
+    for (int i = gl; i < m; i += 16) s2[0] += A[i + (size_t)k * m] * A[i + (size_t)k * m];
+    row16_sum_n<1>(s2);
+    if (gl == 0) vn[k] = s2[0];
+  }
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    double *aj = A + (size_t)j * m;
+    if (wave == 0) {
+      // pivot: largest squared norm, smallest index among equals
+      double bv = -1.0;
+      int bi = j;
+      for (int k = j + lane; k < m; k += 64)
+        if (vn[k] > bv) {
+          bv = vn[k];
+          bi = k;
+        }
+      const double mx = wave_max(bv);
+      const unsigned long long hit = __ballot(bv == mx);
+      if (hit) {
+        // among the lanes that hold the maximum, the smallest index
+        int best = m;
+        unsigned long long h = hit;
+        while (h) {
+          const int l = __builtin_ctzll(h);
+          h &= h - 1;
+          best = min(best, __builtin_amdgcn_readlane(bi, l));
+        }
+        bi = best;
+      } else {
+        bi = j;   // no finite norm: keep the column (the caller sees the non-finite result)
+      }
+      if (bi != j) {
+        double *ap = A + (size_t)bi * m;
+        for (int i = lane; i < m; i += 64) {
+          const double x = aj[i];
+          aj[i] = ap[i];
+          ap[i] = x;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      // reflector of column j over rows j .. m-1 (LAPACK's dlarfg convention)
+      double ss = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) ss += aj[i] * aj[i];
+      ss = wave_sum(ss);
+      const double alpha = aj[j];
+      double beta = alpha, t = 0.0, scal = 0.0;
+      if (ss > 0.0) {
+        const double nrm = sqrt(alpha * alpha + ss);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        t = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int i = j + 1 + lane; i < m; i += 64) aj[i] *= scal;
+      if (lane == 0) {
+        aj[j] = beta;
+        tau[j] = t;
+      }
+    }
+    __syncthreads();
+    const double t = tau[j];
+    // apply the reflector to the columns right of j, then their squared norms below row j
+    for (int k = j + 1 + gid; k < m; k += ngroups) {
+      double *ak = A + (size_t)k * m;
+      if (t != 0.0) {
+        double w[1] = {0.0};
+        for (int i = j + gl; i < m; i += 16) w[0] += (i == j ? 1.0 : aj[i]) * ak[i];
+        row16_sum_n<1>(w);
+        const double tw = t * w[0];
+        for (int i = j + gl; i < m; i += 16) ak[i] -= tw * (i == j ? 1.0 : aj[i]);
+      }
+      double s2[1] = {0.0};
+      for (int i = j + 1 + gl; i < m; i += 16) s2[0] += ak[i] * ak[i];
+      row16_sum_n<1>(s2);
+      if (gl == 0) vn[k] = s2[0];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * m; idx += QRCP_NT) {
+    const int i = idx % m, c = idx / m;
+    R2[idx] = i <= c ? A[idx] : 0.0;
+    Qs[idx] = i == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = m - 1; j >= 0; --j) {   // Q2 = H_0 ... H_{m-1}: apply H_j to Q2(j:, j:)
+    const double t = tau[j];
+    const double *aj = A + (size_t)j * m;
+    if (t != 0.0)
+      for (int k = j + gid; k < m; k += ngroups) {
+        double *qk = Qs + (size_t)k * m;
+        double w[1] = {0.0};
+        for (int i = j + gl; i < m; i += 16) w[0] += (i == j ? 1.0 : aj[i]) * qk[i];
+        row16_sum_n<1>(w);
+        const double tw = t * w[0];
+        for (int i = j + gl; i < m; i += 16) qk[i] -= tw * (i == j ? 1.0 : aj[i]);
+      }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * m; idx += QRCP_NT) Q2[idx] = Qs[idx];
 }
 
 // Gauss-Jordan inverse of an m x m matrix (m <= 96) with partial pivoting
@@ -230,23 +374,39 @@ void set_lds(K kern, size_t bytes) {
 }  // namespace
 
 void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool trans,
-                double floor_rel) {
+                double floor_rel, bool accumulate) {
   TT_REQUIRE(m >= 1 && m <= 128, "jacobi_svd: m out of range");
+  TT_REQUIRE(!accumulate || m <= QR_MAXM, "jacobi_svd: accumulation needs m <= 96");
   const int mm = (m + 1) & ~1;
-  const size_t lds = ((size_t)mm * m + 2 * mm) * sizeof(double);
+  const size_t lds = ((size_t)mm * m + 2 * mm + (accumulate ? (size_t)mm * mm : 0)) *
+                     sizeof(double);
   TimedLaunch tl(c, "jacobi", 22.0 * m * m * m, 8.0 * (2.0 * m * m + m));
   // 16 lanes per pair (measured faster than 8 at m = 64); threads = pairs * lanes per pair
   auto launch = [&](auto kern, int lp) {
     const int nthreads = std::max(64, ((mm / 2) * lp + 63) / 64 * 64);
     set_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40,
-                       trans ? 1 : 0, floor_rel * floor_rel);
+                       trans ? 1 : 0, floor_rel * floor_rel, accumulate ? 1 : 0);
   };
   if (m <= 32) launch(k_jacobi<16, 2>, 16);
   else if (m <= 64) launch(k_jacobi<16, 4>, 16);
   else if (m <= 96) launch(k_jacobi<16, 6>, 16);
   else launch(k_jacobi<16, 8>, 16);
   c.cnt.flops += 22.0 * m * m * m;
+}
+
+void svd_pivoted(Ctx &c, const double *M, int m, double *US, double *sig, double floor_rel) {
+  TT_REQUIRE(m >= 1 && m <= QR_MAXM, "svd_pivoted: m out of range");
+  Scope sc(c.arena);
+  double *R2 = c.arena.dalloc((size_t)m * m), *Q2 = c.arena.dalloc((size_t)m * m);
+  double *UJ = c.arena.dalloc((size_t)m * m);
+  const size_t lds = (2 * (size_t)m * m + 2 * (size_t)m) * sizeof(double);
+  set_lds(k_qrcp, lds);
+  hipLaunchKernelGGL(k_qrcp, dim3(1), dim3(QRCP_NT), lds, c.stream, M, m, R2, Q2);
+  c.cnt.flops += 8.0 * m * m * m / 3.0;
+  // one-sided Jacobi on R2^T with the rotations accumulated: R2 = J Sigma V^T
+  jacobi_svd(c, R2, m, UJ, sig, true, floor_rel, true);
+  gemm2(c, false, false, m, m, m, 1.0, Q2, m, UJ, m, 0.0, US, m);
 }
 
 void small_inverse(Ctx &c, const double *M, int m, int ldm, double *Minv) {

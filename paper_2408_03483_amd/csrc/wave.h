@@ -41,6 +41,18 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
   }
 }
 
+// Maximum over the wavefront with the same DPP pattern (lanes shifted in from outside a row
+// read 0, so the inputs must not all be negative); NaNs are ignored.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_shift<0x111>(v));
+  v = fmax(v, dpp_shift<0x112>(v));
+  v = fmax(v, dpp_shift<0x114>(v));
+  v = fmax(v, dpp_shift<0x118>(v));
+  const double a = lane_value(v, 15), b = lane_value(v, 31);
+  const double c = lane_value(v, 47), d = lane_value(v, 63);
+  return fmax(fmax(a, b), fmax(c, d));
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
   double v[1] = {x};
   wave_sum_n<1>(v);

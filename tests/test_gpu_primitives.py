@@ -211,13 +211,17 @@ def test_maxvol_parity(lib, ctx):
         assert np.max(np.abs(B)) <= 1.05 + 1e-12
 
 
-def test_cross_identity_reproduces_low_rank(lib, ctx):
-    _say("cross identity")
+@pytest.mark.parametrize("r,rmax,ncols", [(6, 16, 3), (50, 64, 52), (40, 64, 64)])
+def test_cross_identity_reproduces_low_rank(lib, ctx, r, rmax, ncols):
+    """With 52 and 64 start columns the orthogonalisations of the cross take the pivoted-QR
+    SVD path (m >= 48); the graded spectrum (0.8^i) is what that path is for."""
+    _say(f"cross identity r={r}")
     rng = np.random.default_rng(5)
-    A, B = decaying_tt(rng, 700, 900, 6, decay=0.9)
+    A, B = decaying_tt(rng, 700, 900, r, decay=0.9 if r < 10 else 0.8)
     X = lib.DeviceTT.from_factors(A, B)
-    Y = lib.DeviceTT(700, 900, 16)
-    w, J = lib.tt_cross(ctx, lib.TT_FN_IDENTITY, [X], [], 700, 900, [0, 1, 2], 1e-13, 16, 3, 4,
+    Y = lib.DeviceTT(700, 900, rmax)
+    J0 = list(range(0, 900, 900 // ncols))[:ncols]
+    w, J = lib.tt_cross(ctx, lib.TT_FN_IDENTITY, [X], [], 700, 900, J0, 1e-13, rmax, 3, 4,
                         7, Y)
     assert rel(Y.full(), A @ B.T) < 1e-11
 
