@@ -173,6 +173,7 @@ def main():
         ttfv.tt_fv_step(s, st.dt, 1)
     if args.timed_kernel:
         ttfv.tt_fv_time_kernel(s, args.timed_kernel)
+    stats0 = ttfv.tt_fv_get_stats(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ttfv.tt_fv_step(s, st.dt, args.steps)
@@ -194,7 +195,9 @@ def main():
                    "bc": "periodic", "r_max": rmax, "eps": eps, "taylor_terms": K, "seed": 0,
                    "cfl": 0.4, "dt": st.dt},
         "roofline": roof, "cpu_baseline": cpu, "parity": parity,
-        "ranks": stats["ranks"], "roundings_per_step": None,
+        "ranks": stats["ranks"],
+        "roundings_per_step": (stats["roundings"] - stats0["roundings"]) / args.steps,
+        "crosses_per_step": (stats["crosses"] - stats0["crosses"]) / args.steps,
     }
     print(json.dumps(out), flush=True)
     s.close()
