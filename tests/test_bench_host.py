@@ -1,0 +1,51 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the roofline arithmetic and the
+counter-traffic lookup that is tied to the GEMM source it was measured on."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def _stats(launches, ms, flops, byts):
+    return {"timed_launches": launches, "timed_ms": ms, "timed_flops": flops,
+            "timed_bytes": byts}
+
+
+def test_roofline_arithmetic():
+    # 100 launches in 10 ms with 1e9 flops in all: 1e7 flops per 100 us = 0.1 TFLOP/s
+    roof = bench._roof("gemm", _stats(100, 10.0, 1e9, 5e8), 1.0)
+    assert roof["bound"] == "mfma" and roof["unit"] == "TFLOP/s"
+    assert roof["avg_launch_us"] == pytest.approx(100.0)
+    assert roof["achieved"] == pytest.approx(0.1)
+    assert roof["peak"] == bench.PEAK_FP64_MFMA_TFLOPS
+    assert roof["frac"] == pytest.approx(0.1 / bench.PEAK_FP64_MFMA_TFLOPS)
+    assert roof["alg_flops_per_launch"] == pytest.approx(1e7)
+    assert roof["alg_bytes_per_launch"] == pytest.approx(5e6)
+    assert roof["traffic"] is None
+    f32 = bench._roof("gemm", _stats(100, 10.0, 1e9, 5e8), 1.0, fp32=True, traffic=123.0)
+    assert f32["peak"] == bench.PEAK_FP32_MFMA_TFLOPS and f32["traffic"] == 123.0
+    assert bench._roof("gemm", _stats(0, 0.0, 0.0, 0.0), 1.0) is None
+
+
+def test_traffic_follows_the_gemm_source(tmp_path, monkeypatch):
+    txt = open(bench.TRAFFIC_FILE).read()
+    recorded = [l for l in txt.splitlines() if l.startswith("bytes_per_launch: ")]
+    assert len(recorded) == 1
+    assert bench._gemm_traffic() == pytest.approx(float(recorded[0].split(": ", 1)[1]))
+    other = tmp_path / "gemm.hip"
+    other.write_text(open(bench.GEMM_SOURCE).read() + "\n// changed\n")
+    monkeypatch.setattr(bench, "GEMM_SOURCE", str(other))
+    assert bench._gemm_traffic() is None
