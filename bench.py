@@ -109,7 +109,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a single TT-FV member "
-              "does not shard across GPUs in this build", file=sys.stderr)
+              "is not sharded across GPUs (independent members would be placed one set per GPU)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
