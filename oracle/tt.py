@@ -14,7 +14,8 @@ Operations
   hadamard     elementwise product: row-wise Kronecker (face-splitting) product of cores,
                ranks multiply (used throughout Section 4.2).
   tt_sum, norm sum of all entries and Frobenius norm (used by Algorithm 1).
-  reciprocal   Algorithm 1 (Taylor series of 1/x about the mean of x).
+  reciprocal   Algorithm 1 (Taylor series of 1/x about the mean of x); raises
+               SeriesDiverges when the terms grow (the series has no limit).
   maxvol       maximum-volume row selection (Goreinov et al., cited in Section 3.3).
   cross        alternating skeleton (CUR) cross interpolation with maxvol pivots
                (Section 3.3; a plain alternating-maxvol stand-in for AMEn cross).
@@ -117,28 +118,36 @@ def norm(X: TT) -> float:
     return math.sqrt(max(v, 0.0))
 
 
-def reciprocal(x: TT, eps: float, max_terms: int, rmax: int):
-    """Algorithm 1: Taylor series of 1/x about its mean value.
+class SeriesDiverges(ArithmeticError):
+    """The Taylor series of 1/x about the mean of x does not converge (|1 - x/mean| >= 1
+    somewhere), detected as two consecutive increases of the term norm."""
 
-    max_terms counts the constant term, so at most max_terms - 1 products are formed.
-    The loop stops as soon as Err = ||dy||_F / sqrt(N) <= eps.
-    Returns (y, err, terms).
+
+def reciprocal(x: TT, eps: float, max_terms: int, rmax: int):
+    """1/x by the truncated Neumann series of Algorithm 1.
+
+    With m the mean of x and z = 1 - x/m (rounded once), 1/x = (1/m) sum_{k>=0} z^k whenever
+    |z| < 1 pointwise.  The terms d_k = z^k are built one from the previous,
+    d_k = round(d_{k-1} o z), and accumulated into rounded partial sums
+    y_k = round(y_{k-1} + d_k), starting from d_0 = y_0 = 1.  Accumulation ends once the
+    root-mean-square size of the newest term, ||d_k||_F / sqrt(N), is at most eps, or when
+    max_terms terms (counting d_0) are in the sum.  Since |z| < 1 makes ||d_k|| shrink by at
+    least max|z| per term, two consecutive increases mean the series diverges
+    (SeriesDiverges).  Returns (y_K / m, last term size, number of terms).
     """
     n1, n2 = x.shape
     N = n1 * n2
-    xavg = tt_sum(x) / N
-    one = ones_tt(n1, n2)
-    xt = tt_round(add([(1.0, one), (-1.0 / xavg, x)]), eps, rmax)
-    y = ones_tt(n1, n2)
-    dy = ones_tt(n1, n2)
-    err = 1.0
-    terms = 1
-    while err > eps and terms < max_terms:
-        dy = tt_round(hadamard(dy, xt), eps, rmax)
-        y = tt_round(add([(1.0, y), (1.0, dy)]), eps, rmax)
-        err = norm(dy) / math.sqrt(N)
-        terms += 1
-    return scale(y, 1.0 / xavg), err, terms
+    mean = tt_sum(x) / N
+    z = tt_round(add([(1.0, ones_tt(n1, n2)), (-1.0 / mean, x)]), eps, rmax)
+    partial, term = ones_tt(n1, n2), ones_tt(n1, n2)
+    sizes = [1.0]
+    while sizes[-1] > eps and len(sizes) < max_terms:
+        term = tt_round(hadamard(term, z), eps, rmax)
+        partial = tt_round(add([(1.0, partial), (1.0, term)]), eps, rmax)
+        sizes.append(norm(term) / math.sqrt(N))
+        if len(sizes) >= 3 and sizes[-1] > sizes[-2] > sizes[-3]:
+            raise SeriesDiverges("Taylor reciprocal: term norms grow (|1 - x/mean| >= 1)")
+    return scale(partial, 1.0 / mean), sizes[-1], len(sizes)
 
 
 # ---------------------------------------------------------------------------

@@ -184,3 +184,35 @@ def test_ssprk3_amplification_of_one_mode():
     amp = (Un[0] + 1j * Uni[0]) / (0.01 * e)
     zz = dt * z
     assert np.allclose(amp, 1 + zz + zz ** 2 / 2 + zz ** 3 / 6, atol=1e-12)
+
+
+# Hand-derived one-face LLF values (Section 2.2, equation LLF; Section 2.4 for the system).
+# g = 4 keeps every wave speed rational: sqrt(g h) = 2 at h = 1 and 1 at h = 1/4.
+#   minus state U- = (h, hu, hv) = (1, 1/2, -3):   u- = 1/2,  v- = -3
+#   plus  state U+ = (1/4, -1/2, 1/4):             u+ = -2,   v+ = 1
+# x: |u-| + c- = 5/2, |u+| + c+ = 3  -> lambda = 3 (decided by the plus side, where u < 0)
+# y: |v-| + c- = 5,   |v+| + c+ = 2  -> lambda = 5 (decided by the minus side, where v < 0)
+# Dropping |.|, using one side, g h instead of sqrt(g h), or the wrong momentum changes both.
+_G4 = 4.0
+_UM = [np.array([1.0]), np.array([0.5]), np.array([-3.0])]
+_UP = [np.array([0.25]), np.array([-0.5]), np.array([0.25])]
+
+
+def test_llf_eigenvalue_hand_values():
+    lx = fv_grid.llf_eigenvalue(_UM, _UP, True, _G4, 1.0, 0)
+    ly = fv_grid.llf_eigenvalue(_UM, _UP, True, _G4, 1.0, 1)
+    assert float(lx[0]) == 3.0 and float(ly[0]) == 5.0
+    # swapping the sides gives the same speed (the max is symmetric)
+    assert float(fv_grid.llf_eigenvalue(_UP, _UM, True, _G4, 1.0, 0)[0]) == 3.0
+    # linear SWE: the constant sqrt(g H)
+    assert fv_grid.llf_eigenvalue(_UM, _UP, False, 9.0, 4.0, 0) == 6.0
+
+
+def test_llf_flux_hand_values():
+    """F-hat = (F(U-) + F(U+))/2 - lambda (U+ - U-)/2 worked out by hand for the states above:
+    F(U-) = (1/2, 9/4, -3/2), F(U+) = (-1/2, 9/8, -1/2), lambda = 3 -> (9/8, 51/16, -47/8);
+    G(U-) = (-3, -3/2, 11), G(U+) = (1/4, -1/2, 3/8), lambda = 5 -> (1/2, 3/2, -39/16)."""
+    Fx = fv_grid.llf(_UM, _UP, True, _G4, 1.0, 0)
+    Gy = fv_grid.llf(_UM, _UP, True, _G4, 1.0, 1)
+    assert [float(f[0]) for f in Fx] == [9 / 8, 51 / 16, -47 / 8]
+    assert [float(f[0]) for f in Gy] == [1 / 2, 3 / 2, -39 / 16]

@@ -82,3 +82,35 @@ def test_adam_first_step_is_signed_lr():
     mlp.adam_step(p, g, m, v, 1, lr=0.01, eps=0.0)
     assert np.allclose(p["a"], np.array([1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01]), rtol=0,
                        atol=1e-15)
+
+
+def test_adam_matches_closed_form_over_three_steps():
+    """Adam (Kingma and Ba 2015) unrolled: after t steps the moments are the bias-weighted
+    sums m_t = (1 - b1) sum_i b1^(t-i) g_i and v_t = (1 - b2) sum_i b2^(t-i) g_i^2, and step t
+    moves p by lr m_t / (1 - b1^t) / (sqrt(v_t / (1 - b2^t)) + eps).  Gradients change sign
+    and size between steps, so (1 - b2)^t in place of 1 - b2^t fails at t = 2 and 3."""
+    b1, b2, lr, eps = 0.9, 0.999, 0.01, 1e-8
+    gs = [np.array([1.0, -0.5]), np.array([3.0, 0.25]), np.array([-2.0, 4.0])]
+    p = {"a": np.array([0.3, -0.7])}
+    m = {"a": np.zeros(2)}
+    v = {"a": np.zeros(2)}
+    ref = p["a"].copy()
+    for t in (1, 2, 3):
+        mlp.adam_step(p, {"a": gs[t - 1]}, m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        mt = (1 - b1) * sum(b1 ** (t - i) * gs[i - 1] for i in range(1, t + 1))
+        vt = (1 - b2) * sum(b2 ** (t - i) * gs[i - 1] ** 2 for i in range(1, t + 1))
+        ref = ref - lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        assert np.allclose(p["a"], ref, rtol=0, atol=1e-15), t
+
+
+def test_adam_constant_gradient_moves_by_lr():
+    """With a constant gradient the bias corrections cancel exactly: every step moves each
+    parameter by lr against the gradient's sign (eps = 0), whatever t."""
+    p = {"a": np.array([1.0, 2.0])}
+    g = {"a": np.array([0.3, -7.0])}
+    m = {"a": np.zeros(2)}
+    v = {"a": np.zeros(2)}
+    for t in range(1, 6):
+        before = p["a"].copy()
+        mlp.adam_step(p, g, m, v, t, lr=0.05, eps=0.0)
+        assert np.allclose(p["a"] - before, [-0.05, 0.05], rtol=0, atol=1e-14), t

@@ -84,6 +84,27 @@ def test_reciprocal_special_cases_and_bound():
     assert err <= 1e-6 and terms < 50
 
 
+def test_reciprocal_detects_divergent_series():
+    """x = 1/2 on half the rows and 9/2 on the other half has mean 5/2, so z = 1 - x/mean is
+    4/5 and -4/5: the series converges (terms shrink by 4/5).  x = 8 on one row and 1 on the
+    other nine has mean 17/10, so z = -63/17 on that row: its terms grow like (63/17)^k and
+    the reciprocal must report divergence (reading R8), not a slow wrong answer."""
+    n1, n2 = 10, 4
+    col = np.full((n1, 1), 0.5)
+    col[5:] = 4.5
+    ok = tt.TT(col, np.ones((n2, 1)))
+    y, err, terms = tt.reciprocal(ok, 1e-12, 200, 10)
+    assert err <= 1e-12
+    assert np.allclose(y.full(), 1.0 / ok.full(), rtol=1e-10)
+    bad_col = np.ones((n1, 1))
+    bad_col[0] = 8.0
+    bad = tt.TT(bad_col, np.ones((n2, 1)))
+    mean = bad.full().mean()
+    assert np.max(np.abs(1.0 - bad.full() / mean)) > 1.0
+    with pytest.raises(tt.SeriesDiverges):
+        tt.reciprocal(bad, 1e-12, 200, 10)
+
+
 def _vol(Q, rows):
     return abs(np.linalg.det(Q[list(rows)]))
 
@@ -217,3 +238,21 @@ def test_tt_step_with_cross_reciprocal_equals_grid_step(scheme):
     for q, u in zip(Qt, Ug):
         if np.linalg.norm(u) > 0:
             assert np.linalg.norm(q.full() - u) <= 1e-11 * np.linalg.norm(Ug[0])
+
+
+def test_tt_lambda_entries_hand_values():
+    """The lambda cross function of the TT step (Section 4.2, LLF flux) on constant rank-1 TTs,
+    g = 4: minus state (h, hu, hv) = (1, 1/2, -3), plus state (1/4, -1/2, 1/4).  In x the
+    momentum is hu: max(1/2 + 2, 2 + 1) = 3; in y (the step passes hv as the momentum)
+    max(3 + 2, 1 + 1) = 5.  A missing |.|, a one-sided speed or g h in place of sqrt(g h)
+    changes one of them."""
+    n1, n2 = 5, 7
+
+    def const(c):
+        return tt.TT(np.full((n1, 1), c), np.ones((n2, 1)))
+
+    hm, hp = const(1.0), const(0.25)
+    lx = tt_fv._Lambda(hm, const(0.5), hp, const(-0.5), 4.0)
+    ly = tt_fv._Lambda(hm, const(-3.0), hp, const(0.25), 4.0)
+    assert np.all(lx.cols(np.array([0, 3])) == 3.0) and np.all(lx.rows(np.array([1])) == 3.0)
+    assert np.all(ly.cols(np.array([2])) == 5.0) and np.all(ly.rows(np.array([0, 4])) == 5.0)
