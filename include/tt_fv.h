@@ -35,9 +35,14 @@ extern "C" {
 #define TT_ENOMEM  (-2)   /* the context arena is too small for this call                  */
 #define TT_EHIP    (-3)   /* a HIP runtime call failed (message in tt_last_error)          */
 #define TT_ENONFINITE (-4)/* NaN or Inf met in a factorisation                             */
+#define TT_EDOMAIN (-5)   /* the Taylor series of 1/x diverges: its term norms grew twice in a
+                             row, i.e. |1 - x / mean(x)| >= 1 somewhere (Algorithm 1)       */
 /* warning bits (positive) */
 #define TT_WRANKCAP  1    /* a rounding hit r_max with a tail above eps                      */
 #define TT_WNOCONV   2    /* the Taylor reciprocal stopped at max_terms with Err > eps       */
+#define TT_WSKETCH   4    /* a randomized rounding of rank > 96 reached its subspace-iteration
+                             limit before its leak bound (rank <= 96 is redone exactly)      */
+#define TT_WJACOBI   8    /* a Jacobi SVD stopped at its sweep cap while still rotating      */
 
 typedef struct {
   int n1, n2;      /* mode sizes (rows of g1, rows of g2)                                  */
@@ -62,6 +67,11 @@ int  tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters);
  * the small SVD, maxvol, the Taylor mean and error estimates and all stored cores stay FP64).
  * Results in FP32 mode are accurate to about 1e-6 relative, so tolerances below that
  * saturate the rank cap. */
+/* Iteration limits: the sweep cap of the Jacobi SVDs (default 40; TT_WJACOBI when reached
+ * while still rotating) and the number of subspace iterations after which a randomized
+ * rounding stops (default 8; an unconverged rounding of rank <= 96 is then redone exactly,
+ * otherwise TT_WSKETCH).  Ranges [1, 100] and [0, 16]. */
+int  tt_ctx_set_limits(tt_ctx *ctx, int jacobi_max_sweeps, int sketch_max_iters);
 #define TT_PREC_F64 0
 #define TT_PREC_F32 1
 int  tt_ctx_set_precision(tt_ctx *ctx, int precision);
@@ -112,6 +122,15 @@ int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const d
              int n1, int n2, const int *J0, int nJ0, double eps, int r_max, int sweeps,
              int kick, uint64_t key, tt_matrix *y, int *J_out, int *nJ_out);
 
+/* The final step of tt_cross for given pivots (Section 3.3, skeleton decomposition): with Qc
+ * the nI leading orthonormal directions of the columns fn(:, J), y = round(Qc Qc[I]^-1
+ * fn(I, :), eps, r_max).  J, I: host index arrays (1 <= nJ <= 96 columns < n2, nI <= nJ rows
+ * < n1; nI = 0 gives the zero TT).  Inputs and fparams as tt_cross.  TT_EINVAL when the
+ * columns have fewer than nI nonzero directions. */
+int tt_cross_skeleton(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs,
+                      const double *fparams, int n1, int n2, const int *J, int nJ, const int *I,
+                      int nI, double eps, int r_max, tt_matrix *y);
+
 /* Linear reconstruction of one core (Section 4.3.1).  core: n x rank cell values (device).
  * scheme: 3 = Upwind3, 5 = Upwind5.  face_m / face_p (n_f x rank, n_f = n periodic or n + 1
  * with walls) get the face values from the left / right; quad (n*nq x rank, row j*nq + m)
@@ -156,6 +175,9 @@ typedef struct {
   long long learned_crosses;  /* crosses accepted from the learned pivot proposer          */
   long long learned_fallbacks;/* proposer results rejected (plain crosses run instead)     */
   double max_learned_err;     /* largest validation error of an accepted proposer cross    */
+  long long sketch_fallbacks; /* randomized roundings redone exactly (limit reached)       */
+  long long sketch_unconverged; /* randomized roundings kept unconverged (TT_WSKETCH)      */
+  long long jacobi_capped;    /* Jacobi SVDs stopped at the sweep cap (TT_WJACOBI)         */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build
@@ -188,6 +210,8 @@ void tt_fv_destroy(tt_fv *s);
 #define TT_PIV_MAXVOL  0    /* plain alternating maxvol sweeps                              */
 #define TT_PIV_LOG     1    /* plain sweeps; log (features, pivots) into the model          */
 #define TT_PIV_LEARNED 2    /* proposer + one sweep, plain sweeps as the fallback           */
+#define TT_PIV_REPLAY  3    /* each cross takes the (J, I) given by tt_fv_replay_pivots for
+                               its (step, site) and forms only the skeleton (no model)       */
 typedef struct tt_pm tt_pm;
 /* max_rows: capacity of the training log (rows of 16 features); seed: weight init. */
 int  tt_pm_create(tt_pm **out, size_t max_rows, unsigned long long seed);
@@ -200,6 +224,10 @@ int  tt_pm_forward(tt_pm *pm, const float *X_dev, int N, float *s_dev);
  * sum_i w_i (log(1 + e^s_i) - y_i s_i) / N, w_i = pos_weight where y_i = 1, else 1. */
 int  tt_pm_grad(tt_pm *pm, const float *X_dev, const float *y_dev, int N, double pos_weight,
                 float *grad_host, size_t n, double *loss_out);
+/* One Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8, FP32) of the weights
+ * with the caller's gradient (host FP32, n = TT_PM_NPARAM), step count continuing from the
+ * model's previous updates. */
+int  tt_pm_adam(tt_pm *pm, const float *grad_host, size_t n, double lr);
 /* Adam (lr) over the logged samples, positive weight = negatives / positives. */
 int  tt_pm_train(tt_pm *pm, int epochs, int batch, double lr, double *loss_out);
 int  tt_pm_dataset(tt_pm *pm, size_t *rows, size_t *positives);
@@ -209,8 +237,28 @@ int  tt_pm_features(tt_ctx *ctx, const double *B0, int n2, int r, int ldb, const
                     int nJ, float *X_dev);
 /* Indices of the k largest scores (ties: smaller index first), ascending, into idx_dev. */
 int  tt_pm_topk(tt_ctx *ctx, const float *s_dev, int n, int k, int *idx_dev);
-/* Pivot mode of a solver's crosses (TT_PIV_*); pm must outlive its use (NULL with mode 0). */
+/* Pivot mode of a solver's crosses (TT_PIV_*); pm must outlive its use (NULL with modes 0
+ * and 3). */
 int  tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm);
+
+/* Pivot replay (Section 3.3: a skeleton is fixed by its column and row sets).  At the rank
+ * cap several pivot sets of a cross are equally valid and maxvol's choice among them can flip
+ * under round-off, so two implementations of the same step are compared by giving both the
+ * same sets.  Store the column set J (host, 1 <= nJ <= 96 distinct indices < n2 of that
+ * cross) and row set I (host, nI = the rank of the columns f(:, J) after dropping directions
+ * below 1e-13 of the largest, 1e-6 with FP32 contractions; the skeleton uses exactly nI
+ * leading directions) for the cross at `site` in step
+ * `step` (0 = the first step after tt_fv_init).  Sites: base = ((direction * 3 + stage) << 6),
+ * direction 0 = x, 1 = y, stage 0..2; lambda cross base + 0; cross 1/h base + 8 + side
+ * (0 = minus, 1 = plus); WENO5 Algorithm 2 base + 16 + 4 variable + side and Algorithm 3 the
+ * same + 2 (variables in normal-first order h, normal momentum, tangential momentum).  In
+ * mode TT_PIV_REPLAY a step fails with TT_EINVAL when a cross finds no entry or its columns
+ * have fewer than nI nonzero directions.  Entries are kept until the solver is destroyed. */
+int  tt_fv_replay_pivots(tt_fv *s, long long step, int site, const int *J, int nJ, const int *I,
+                         int nI);
+/* The last sweep's column and row sets of the latest cross at `site` (host outputs of
+ * capacity capJ / capI).  Returns 1 when the site has run, 0 (and nJ = nI = 0) when not. */
+int  tt_fv_get_pivots(tt_fv *s, int site, int *J, int capJ, int *nJ, int *I, int capI, int *nI);
 
 /* ---------------------------------------------------------------------------------------
  * Batched ensemble: independent solvers advanced together.  Their independent chains of TT

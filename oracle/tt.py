@@ -192,8 +192,9 @@ def maxvol(Q: np.ndarray, tau: float = 1.05, maxit: int = 100):
     return I
 
 
-def orth(C: np.ndarray, drop: float = 1e-13) -> np.ndarray:
-    """Orthonormal basis of range(C): QR, SVD of R, drop directions with s <= drop*s_max.
+def orth(C: np.ndarray, drop: float = 1e-13, k: int = None) -> np.ndarray:
+    """Orthonormal basis of range(C): QR, SVD of R, drop directions with s <= drop*s_max
+    (or keep exactly the k leading directions when k is given).
 
     Each kept column is given a fixed sign (its entry of largest magnitude is positive) so
     the basis is unique up to rounding.
@@ -202,7 +203,10 @@ def orth(C: np.ndarray, drop: float = 1e-13) -> np.ndarray:
     u, s, _ = np.linalg.svd(r)
     if s.size == 0 or s[0] == 0.0:
         return np.zeros((C.shape[0], 0))
-    k = int(np.sum(s > drop * s[0]))
+    if k is None:
+        k = int(np.sum(s > drop * s[0]))
+    elif k > s.size or s[k - 1] == 0.0:
+        raise ValueError(f"orth: the columns have fewer than {k} nonzero directions")
     U = q @ u[:, :k]
     idx = np.argmax(np.abs(U), axis=0)
     sg = np.sign(U[idx, np.arange(k)])
@@ -238,40 +242,62 @@ def kick_indices(existing, n: int, count: int, key: int):
     return out
 
 
+def skeleton(fun, n1: int, n2: int, J, I, eps: float, rmax: int, Qc=None) -> TT:
+    """Skeleton (CUR) approximation of the matrix defined by `fun` from column set J and row
+    set I (Section 3.3): with Qc the |I| leading orthonormal directions of the columns
+    f(:, J), X ~ Qc Qc[I]^{-1} f(I, :), then rounded to (eps, rmax).  An empty I (the
+    columns are zero) gives the zero TT."""
+    I = np.asarray(I, dtype=np.int64)
+    if len(I) == 0:
+        return zero_tt(n1, n2)
+    if Qc is None:
+        Qc = orth(fun.cols(np.asarray(J, dtype=np.int64)), k=len(I))
+    if Qc.shape[1] != len(I):
+        raise ValueError(f"skeleton: {len(I)} rows for a column basis of width {Qc.shape[1]}")
+    G1 = np.linalg.solve(Qc[I].T, Qc.T).T         # Qc Qc[I]^{-1}
+    return tt_round(TT(G1, fun.rows(I).T), eps, rmax)
+
+
 def cross(fun, n1: int, n2: int, J0, eps: float, rmax: int, sweeps: int = 3,
-          kick: int = 4, key: int = 0):
+          kick: int = 4, key: int = 0, rows_out: list = None, drop: float = 1e-13):
     """Alternating maxvol skeleton cross of the n1 x n2 matrix defined by `fun`.
 
     fun.cols(J) -> n1 x |J| array of entries, fun.rows(I) -> |I| x n2 array.
     Each sweep: C = f(:, J); Qc = orth(C); I = maxvol(Qc); R = f(I, :); and, except in the
     last sweep, J = maxvol(orth(R^T)) enlarged by `kick` fresh indices while |J| < rmax.
-    Result: round(Qc Qc[I]^{-1} R, eps, rmax).  Returns (TT, J used by the last sweep).
+    Result: the skeleton of the last sweep's (J, I).  Returns (TT, J of the last sweep); the
+    last sweep's I is appended to `rows_out` when given.  `drop`: relative singular value
+    below which orth discards a direction.
     """
     J = np.array(J0, dtype=np.int64)
-    Qc = I = Rw = None
+    Qc = I = None
     for s in range(sweeps):
         C = fun.cols(J)
-        Qc = orth(C)
+        Qc = orth(C, drop)
         if Qc.shape[1] == 0:
+            if rows_out is not None:
+                rows_out.append(np.zeros(0, dtype=np.int64))
             return zero_tt(n1, n2), J
         I = maxvol(Qc)
-        Rw = fun.rows(I)
         if s == sweeps - 1:
             break
-        Qr = orth(Rw.T)
+        Qr = orth(fun.rows(I).T, drop)
         if Qr.shape[1] == 0:
+            if rows_out is not None:
+                rows_out.append(np.zeros(0, dtype=np.int64))
             return zero_tt(n1, n2), J
         J = maxvol(Qr)
         if len(J) < rmax and kick > 0:
             extra = kick_indices(J, n2, min(kick, rmax - len(J)), key + 1000003 * (s + 1))
             J = np.concatenate([J, np.array(extra, dtype=np.int64)])
-    G1 = np.linalg.solve(Qc[I].T, Qc.T).T         # Qc Qc[I]^{-1}
-    return tt_round(TT(G1, Rw.T), eps, rmax), J
+    if rows_out is not None:
+        rows_out.append(I.copy())
+    return skeleton(fun, n1, n2, J, I, eps, rmax, Qc=Qc), J
 
 
-def initial_columns(Y: TT) -> np.ndarray:
+def initial_columns(Y: TT, drop: float = 1e-13) -> np.ndarray:
     """Starting column set for a cross: maxvol rows of an orthonormal basis of Y's second core."""
-    Q = orth(Y.B)
+    Q = orth(Y.B, drop)
     if Q.shape[1] == 0:
         return np.array([0], dtype=np.int64)
     return maxvol(Q)

@@ -39,8 +39,8 @@ import numpy as np
 
 from . import stencils
 from . import fv_grid
-from .tt import TT, add, cross, hadamard, initial_columns, norm, reciprocal, scale, tt_round, \
-    zero_tt
+from .tt import TT, add, cross, hadamard, initial_columns, norm, reciprocal, scale, skeleton, \
+    tt_round, zero_tt
 
 NG = 3
 
@@ -139,12 +139,14 @@ class TTSolver:
     def __init__(self, n: int, scheme: str, nonlinear: bool, periodic: bool = True,
                  g: float = 9.81, H: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                  rmax: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
-                 cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor"):
+                 cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor",
+                 replay=None, cross_drop: float = 1e-13):
         self.n, self.scheme, self.nonlinear, self.periodic = n, scheme, nonlinear, periodic
         self.g, self.H, self.f = g, H, f
         self.eps, self.rmax, self.K = eps, rmax, taylor_terms
         self.sweeps, self.kick, self.cross_full = cross_sweeps, cross_kick, cross_full
         self.recip = recip
+        self.cross_drop = cross_drop     # orth drop threshold of the crosses (reading R12)
         self.dx = 1.0 / n
         self.tab = stencils.tables(scheme)
         self.nq = self.tab["nq"]
@@ -154,6 +156,12 @@ class TTSolver:
         self.quad_w = [np.asarray(w) for w in self.tab["quad_full"]]
         self.k = k
         self.pivots = {}
+        # (step, site) -> (J, I) of every cross's last sweep; with `replay` given, each cross
+        # takes its (J, I) from there and forms only the skeleton (several pivot sets are
+        # equally valid at the rank cap; replaying one set makes two implementations
+        # comparable)
+        self.cross_log = {}
+        self.replay = replay
         self.step_index = 0
         self.stats = {"taylor_terms": [], "taylor_err": [], "ranks": []}
 
@@ -184,12 +192,20 @@ class TTSolver:
             J0 = np.arange(n2)
             X, J = cross(fun, n1, n2, J0, self.eps, self.rmax, sweeps=1, kick=0)
             return X
+        if self.replay is not None:
+            J, I = self.replay[(self.step_index, site)]
+            self.pivots[site] = np.asarray(J, dtype=np.int64)
+            self.cross_log[(self.step_index, site)] = (np.asarray(J), np.asarray(I))
+            return skeleton(fun, n1, n2, J, I, self.eps, self.rmax)
         J0 = self.pivots.get(site)
         if J0 is None:
-            J0 = initial_columns(y0)
+            J0 = initial_columns(y0, self.cross_drop)
         key = (site << 32) | (self.step_index & 0xFFFFFFFF)
-        X, J = cross(fun, n1, n2, J0, self.eps, self.rmax, self.sweeps, self.kick, key)
+        rows = []
+        X, J = cross(fun, n1, n2, J0, self.eps, self.rmax, self.sweeps, self.kick, key,
+                     rows_out=rows, drop=self.cross_drop)
         self.pivots[site] = J
+        self.cross_log[(self.step_index, site)] = (J.copy(), rows[0])
         return X
 
     # -- one direction -----------------------------------------------------------

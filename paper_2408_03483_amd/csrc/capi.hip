@@ -15,6 +15,10 @@ void solver_stats(Solver *s, tt_fv_stats *o);
 void solver_destroy(Solver *s);
 void solver_time_kernel(Solver *s, const char *name);
 void solver_set_pivots(Solver *s, int mode, PivotModel *pm);
+void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,
+                          const int *I, int nI);
+int solver_get_pivots(Solver *s, int site, int *J, int capJ, int *nJ, int *I, int capI,
+                      int *nI);
 struct Ensemble;
 Ensemble *ensemble_create(int workers, size_t arena_bytes);
 void ensemble_destroy(Ensemble *e);
@@ -31,11 +35,15 @@ Arena::~Arena() {
   if (base_) (void)hipFree(base_);
 }
 
+constexpr size_t kArenaHeader = 256;   // status words (Arena::status)
+
 void Arena::init(size_t bytes) {
   TT_REQUIRE(base_ == nullptr, "arena already initialised");
+  TT_REQUIRE(bytes > kArenaHeader, "arena too small");
   HIP_CHECK(hipMalloc(&base_, bytes));
+  HIP_CHECK(hipMemset(base_, 0, kArenaHeader));
   cap_ = bytes;
-  top_ = hw_ = 0;
+  top_ = hw_ = kArenaHeader;
 }
 
 void *Arena::alloc(size_t bytes) {
@@ -66,6 +74,21 @@ void Ctx::sync() {
   timer.pending.clear();
   timer.pending_flops.clear();
   timer.pending_bytes.clear();
+}
+
+int Ctx::jacobi_capped() {
+  int v = 0;
+  HIP_CHECK(hipMemcpyAsync(&v, arena.status(), sizeof(int), hipMemcpyDeviceToHost, stream));
+  sync();
+  return v;
+}
+
+int jacobi_warning(Ctx &c) {
+  const int n = c.jacobi_capped();
+  const int w = n > c.jacobi_seen ? TT_WJACOBI : 0;
+  c.jacobi_seen = n;
+  c.cnt.warnings |= w;
+  return w;
 }
 
 constexpr int kTileCounters = 16384;
@@ -173,6 +196,67 @@ static int guarded(F &&f) {
   }
 }
 
+// the fiber description of a cross's entry function fn (TT_FN_*) over its inputs; ghost
+// extensions of WENO inputs are allocated on the context's arena (the caller's scope)
+static FiberSpec make_fiber_spec(Ctx &c, int fn, const tt_matrix *inputs, int n_inputs,
+                                 const double *fparams, int n1, int n2) {
+  static WenoTables wt = derive_weno_tables();
+  FiberSpec fs;
+  fs.fn = fn;
+  fs.wt = &wt;
+  switch (fn) {
+    case TT_FN_IDENTITY:
+    case TT_FN_RECIP:
+      TT_REQUIRE(n_inputs == 1, "identity/recip: one input");
+      check_matrix(&inputs[0], "input", true);
+      TT_REQUIRE(inputs[0].n1 == n1 && inputs[0].n2 == n2, "identity: input shape");
+      fs.n_in = 1;
+      fs.in[0] = {inputs[0].g1, inputs[0].g2, n1, n2, inputs[0].rank};
+      break;
+    case TT_FN_LLF_LAMBDA:
+      TT_REQUIRE(n_inputs == 4 && fparams, "lambda: four inputs and g");
+      for (int t = 0; t < 4; ++t) {
+        check_matrix(&inputs[t], "input", true);
+        TT_REQUIRE(inputs[t].n1 == n1 && inputs[t].n2 == n2, "lambda: input shape");
+        fs.in[t] = {inputs[t].g1, inputs[t].g2, n1, n2, inputs[t].rank};
+      }
+      fs.n_in = 4;
+      fs.g = fparams[0];
+      break;
+    case TT_FN_WENO_FACE_M:
+    case TT_FN_WENO_FACE_P: {
+      TT_REQUIRE(n_inputs == 1 && fparams, "weno face: one input and params");
+      const tt_matrix &v = inputs[0];
+      check_matrix(&v, "input", true);
+      const bool per = fparams[0] != 0.0;
+      TT_REQUIRE(v.n2 == n2 && n1 == (per ? v.n1 : v.n1 + 1) && v.n1 >= 3,
+                 "weno face: shapes (n_f x n from an n x n input)");
+      double *Ae = c.arena.dalloc((size_t)(v.n1 + 6) * v.rank);
+      ghost_extend(c, v.g1, v.n1, v.rank, per, fparams[1], Ae);
+      fs.n_in = 1;
+      fs.in[0] = {Ae, v.g2, v.n1 + 6, v.n2, v.rank};
+      fs.eps_w = fparams[2];
+      break;
+  }
+  case TT_FN_WENO_QUAD: {
+    TT_REQUIRE(n_inputs == 1 && fparams, "weno quad: one input and params");
+    const tt_matrix &v = inputs[0];
+    check_matrix(&v, "input", true);
+    TT_REQUIRE(v.n1 == n1 && n2 == 3 * v.n2 && v.n2 >= 3, "weno quad: shapes (n_f x 3n)");
+    double *Be = c.arena.dalloc((size_t)(v.n2 + 6) * v.rank);
+    ghost_extend(c, v.g2, v.n2, v.rank, fparams[0] != 0.0, fparams[1], Be);
+    fs.n_in = 1;
+    fs.in[0] = {v.g1, Be, v.n1, v.n2 + 6, v.rank};
+    fs.eps_w = fparams[2];
+    fs.nq = 3;
+    break;
+  }
+  default:
+    throw Error(TT_EINVAL, "tt_cross: unknown fn id");
+  }
+  return fs;
+}
+
 extern "C" {
 
 const char *tt_last_error(void) { return g_last_error.c_str(); }
@@ -207,6 +291,19 @@ int tt_ctx_set_sketch(tt_ctx *ctx, int width, int power_iters) {
   });
 }
 
+int tt_ctx_set_limits(tt_ctx *ctx, int jacobi_max_sweeps, int sketch_max_iters) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    TT_REQUIRE(jacobi_max_sweeps >= 1 && jacobi_max_sweeps <= 100,
+               "jacobi_max_sweeps out of [1, 100]");
+    TT_REQUIRE(sketch_max_iters >= 0 && sketch_max_iters <= 16,
+               "sketch_max_iters out of [0, 16]");
+    ctx->c.jacobi_max_sweeps = jacobi_max_sweeps;
+    ctx->c.sketch_max_iters = sketch_max_iters;
+    return 0;
+  });
+}
+
 int tt_ctx_set_precision(tt_ctx *ctx, int precision) {
   return guarded([&]() {
     TT_REQUIRE(ctx, "null ctx");
@@ -231,7 +328,7 @@ int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *
     y->rank = yv.r;
     if (sigma_out)
       for (size_t i = 0; i < s.size(); ++i) sigma_out[i] = s[i];
-    return w;
+    return w | jacobi_warning(ctx->c);
   });
 }
 
@@ -254,7 +351,7 @@ int tt_hadamard_round(tt_ctx *ctx, const tt_matrix *x, const tt_matrix *z, doubl
     DTT yv = view(y);
     const int w = round_tt(c, p, eps, r_max, yv, nullptr);
     y->rank = yv.r;
-    return w;
+    return w | jacobi_warning(ctx->c);
   });
 }
 
@@ -270,7 +367,7 @@ int tt_reciprocal(tt_ctx *ctx, const tt_matrix *x, double eps, int max_terms, in
     DTT xv = view(x), yv = view(y);
     const int w = reciprocal_tt(ctx->c, xv, eps, max_terms, r_max, yv, err_out, terms_out);
     y->rank = yv.r;
-    return w;
+    return w | jacobi_warning(ctx->c);
   });
 }
 
@@ -300,60 +397,7 @@ int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const d
     for (int j : J) TT_REQUIRE(j >= 0 && j < n2, "tt_cross: J0 index out of range");
     Ctx &c = ctx->c;
     Scope sc(c.arena);
-    static WenoTables wt = derive_weno_tables();
-    FiberSpec fs;
-    fs.fn = fn;
-    fs.wt = &wt;
-    switch (fn) {
-      case TT_FN_IDENTITY:
-      case TT_FN_RECIP:
-        TT_REQUIRE(n_inputs == 1, "identity/recip: one input");
-        check_matrix(&inputs[0], "input", true);
-        TT_REQUIRE(inputs[0].n1 == n1 && inputs[0].n2 == n2, "identity: input shape");
-        fs.n_in = 1;
-        fs.in[0] = {inputs[0].g1, inputs[0].g2, n1, n2, inputs[0].rank};
-        break;
-      case TT_FN_LLF_LAMBDA:
-        TT_REQUIRE(n_inputs == 4 && fparams, "lambda: four inputs and g");
-        for (int t = 0; t < 4; ++t) {
-          check_matrix(&inputs[t], "input", true);
-          TT_REQUIRE(inputs[t].n1 == n1 && inputs[t].n2 == n2, "lambda: input shape");
-          fs.in[t] = {inputs[t].g1, inputs[t].g2, n1, n2, inputs[t].rank};
-        }
-        fs.n_in = 4;
-        fs.g = fparams[0];
-        break;
-      case TT_FN_WENO_FACE_M:
-      case TT_FN_WENO_FACE_P: {
-        TT_REQUIRE(n_inputs == 1 && fparams, "weno face: one input and params");
-        const tt_matrix &v = inputs[0];
-        check_matrix(&v, "input", true);
-        const bool per = fparams[0] != 0.0;
-        TT_REQUIRE(v.n2 == n2 && n1 == (per ? v.n1 : v.n1 + 1) && v.n1 >= 3,
-                   "weno face: shapes (n_f x n from an n x n input)");
-        double *Ae = c.arena.dalloc((size_t)(v.n1 + 6) * v.rank);
-        ghost_extend(c, v.g1, v.n1, v.rank, per, fparams[1], Ae);
-        fs.n_in = 1;
-        fs.in[0] = {Ae, v.g2, v.n1 + 6, v.n2, v.rank};
-        fs.eps_w = fparams[2];
-        break;
-      }
-      case TT_FN_WENO_QUAD: {
-        TT_REQUIRE(n_inputs == 1 && fparams, "weno quad: one input and params");
-        const tt_matrix &v = inputs[0];
-        check_matrix(&v, "input", true);
-        TT_REQUIRE(v.n1 == n1 && n2 == 3 * v.n2 && v.n2 >= 3, "weno quad: shapes (n_f x 3n)");
-        double *Be = c.arena.dalloc((size_t)(v.n2 + 6) * v.rank);
-        ghost_extend(c, v.g2, v.n2, v.rank, fparams[0] != 0.0, fparams[1], Be);
-        fs.n_in = 1;
-        fs.in[0] = {v.g1, Be, v.n1, v.n2 + 6, v.rank};
-        fs.eps_w = fparams[2];
-        fs.nq = 3;
-        break;
-      }
-      default:
-        throw Error(TT_EINVAL, "tt_cross: unknown fn id");
-    }
+    FiberSpec fs = make_fiber_spec(c, fn, inputs, n_inputs, fparams, n1, n2);
     DTT yv = view(y);
     std::vector<int> Jo;
     const int w = cross_tt(c, fs, n1, n2, J, eps, r_max, sweeps, kick, key, yv, &Jo);
@@ -361,7 +405,7 @@ int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const d
     if (J_out)
       for (size_t i = 0; i < Jo.size(); ++i) J_out[i] = Jo[i];
     if (nJ_out) *nJ_out = (int)Jo.size();
-    return w;
+    return w | jacobi_warning(ctx->c);
   });
 }
 
@@ -538,6 +582,20 @@ int tt_pm_grad(tt_pm *pm, const float *X_dev, const float *y_dev, int N, double 
   });
 }
 
+int tt_pm_adam(tt_pm *pm, const float *grad_host, size_t n, double lr) {
+  return guarded([&]() {
+    TT_REQUIRE(pm && grad_host && n == PM_NPARAM && lr > 0.0, "tt_pm_adam: bad argument");
+    PivotModel &m = *pm->m;
+    std::lock_guard<std::mutex> lk(m.mu);
+    HIP_CHECK(hipMemcpyAsync(m.g, grad_host, PM_NPARAM * sizeof(float), hipMemcpyHostToDevice,
+                             m.c.stream));
+    m.adam(m.c, lr);
+    m.refresh_bf16();
+    m.c.sync();
+    return 0;
+  });
+}
+
 int tt_pm_train(tt_pm *pm, int epochs, int batch, double lr, double *loss_out) {
   return guarded([&]() {
     TT_REQUIRE(pm && lr > 0.0, "tt_pm_train: bad argument");
@@ -581,11 +639,48 @@ int tt_pm_topk(tt_ctx *ctx, const float *s_dev, int n, int k, int *idx_dev) {
 int tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm) {
   return guarded([&]() {
     TT_REQUIRE(s, "null solver");
-    TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_LOG || mode == TT_PIV_LEARNED,
+    TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_LOG || mode == TT_PIV_LEARNED ||
+                   mode == TT_PIV_REPLAY,
                "tt_fv_set_pivots: unknown mode");
-    TT_REQUIRE(mode == TT_PIV_MAXVOL || pm, "tt_fv_set_pivots: mode needs a model");
+    TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_REPLAY || pm,
+               "tt_fv_set_pivots: mode needs a model");
     solver_set_pivots(s->s, mode, pm ? pm->m.get() : nullptr);
     return 0;
+  });
+}
+
+int tt_fv_replay_pivots(tt_fv *s, long long step, int site, const int *J, int nJ, const int *I,
+                        int nI) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null solver");
+    solver_replay_pivots(s->s, step, site, J, nJ, I, nI);
+    return 0;
+  });
+}
+
+int tt_fv_get_pivots(tt_fv *s, int site, int *J, int capJ, int *nJ, int *I, int capI, int *nI) {
+  return guarded([&]() {
+    TT_REQUIRE(s && J && nJ && I && nI, "tt_fv_get_pivots: null argument");
+    return solver_get_pivots(s->s, site, J, capJ, nJ, I, capI, nI);
+  });
+}
+
+int tt_cross_skeleton(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs,
+                      const double *fparams, int n1, int n2, const int *J, int nJ, const int *I,
+                      int nI, double eps, int r_max, tt_matrix *y) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && inputs && J && y && (I || nI == 0), "tt_cross_skeleton: null argument");
+    check_matrix(y, "tt_cross_skeleton y", false);
+    TT_REQUIRE(y->n1 == n1 && y->n2 == n2 && y->cap >= r_max, "tt_cross_skeleton: bad output");
+    TT_REQUIRE(r_max >= 1 && eps >= 0.0, "tt_cross_skeleton: bad r_max / eps");
+    TT_REQUIRE(nJ >= 1 && nI >= 0 && nI <= nJ, "tt_cross_skeleton: bad pivot counts");
+    Scope sc(ctx->c.arena);
+    FiberSpec fs = make_fiber_spec(ctx->c, fn, inputs, n_inputs, fparams, n1, n2);
+    DTT out = view(y);
+    const int w = skeleton_tt(ctx->c, fs, n1, n2, std::vector<int>(J, J + nJ),
+                              std::vector<int>(I, I + nI), eps, r_max, out);
+    y->rank = out.r;
+    return w | jacobi_warning(ctx->c);
   });
 }
 

@@ -46,6 +46,9 @@ class Arena {
   void *alloc(size_t bytes);                 // 256-byte aligned
   double *dalloc(size_t n) { return static_cast<double *>(alloc(n * sizeof(double))); }
   int *ialloc(size_t n) { return static_cast<int *>(alloc(n * sizeof(int))); }
+  // status words at the arena's base (zeroed at init, never sub-allocated): [0] counts the
+  // Jacobi SVDs on this arena's stream that stopped at their sweep cap
+  int *status() const { return reinterpret_cast<int *>(base_); }
   size_t mark() const { return top_; }
   void release(size_t m) { top_ = m; }
   size_t capacity() const { return cap_; }
@@ -73,6 +76,8 @@ struct DTT {
 
 struct Counters {
   long long roundings = 0, crosses = 0, extra_power_iters = 0;
+  long long sketch_fallbacks = 0;    // range finders unconverged at the limit, redone exactly
+  long long sketch_unconverged = 0;  // range finders unconverged at the limit, kept (warning)
   double flops = 0, bytes = 0;
   int warnings = 0;
 };
@@ -95,6 +100,8 @@ struct Ctx {
   int sketch_width = 0;     // 0: automatic
   int power_iters = 1;      // subspace iterations always run; more are added on demand
   bool fp32 = false;        // core contractions (GEMM, face-splitting products, TSQR) in FP32
+  int jacobi_max_sweeps = 40;     // sweep cap of the one-sided Jacobi SVD
+  int sketch_max_iters = 8;       // subspace iterations after which a range finder stops
   Counters cnt;
   KernelTimer timer;
   int *tile_cnt = nullptr;  // zeroed per-tile arrival counters of split-K GEMMs (this stream)
@@ -104,6 +111,8 @@ struct Ctx {
   static constexpr size_t kPinnedDoubles = 4096;
   double *pinned_staging(); // allocates it on first use
   void sync();
+  int jacobi_capped();      // syncs; Jacobi SVDs of this context stopped at the sweep cap
+  int jacobi_seen = 0;      // the count at the last check (jacobi_warning)
   ~Ctx();
 };
 
@@ -117,6 +126,9 @@ struct TimedLaunch {
 };
 
 struct Solver;
+
+// TT_WJACOBI when Jacobi SVDs of this context stopped at their sweep cap since the last check
+int jacobi_warning(Ctx &c);
 
 // ---------------------------------------------------------------------------------------
 // launchers (kernels.hip)
@@ -214,7 +226,10 @@ void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, d
 
 // tt_ops.hip (host algorithms)
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
-void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out);
+// orthonormal basis of range(C) (n x m): QR, SVD of R, keep directions above drop * s_0, or
+// exactly `want` leading directions when want >= 0
+void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out,
+          int want = -1);
 // aux: optional second context (own stream and arena) on which a helper thread forms the
 // partial sums while this thread forms the next term
 int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, double *err,
@@ -222,7 +237,12 @@ int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, dou
 std::vector<int> maxvol_host(Ctx &c, const double *Q, int n, int r, int ldq, double tau,
                              int maxit);
 int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, double eps,
-             int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out);
+             int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out,
+             std::vector<int> *I_out = nullptr);
+// the final step of a cross for given pivots: Qc = the |I| leading orthonormal directions of
+// f(:, J), y = round(Qc Qc[I]^-1 f(I, :), eps, rmax)
+int skeleton_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, const std::vector<int> &J,
+                const std::vector<int> &I, double eps, int rmax, DTT &y);
 uint64_t splitmix64_next(uint64_t &state);
 std::vector<int> kick_indices(const std::vector<int> &have, int n, int count, uint64_t key);
 

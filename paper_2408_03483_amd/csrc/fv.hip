@@ -61,6 +61,10 @@ struct Solver {
   PivotModel *pm = nullptr;
   int piv_mode = TT_PIV_MAXVOL;
   std::map<int, double> ref_err;
+  // pivot replay (TT_PIV_REPLAY): (step, site) -> (J, I) given by the caller; and the last
+  // sweep's (J, I) of every site's latest cross, for the caller to read back
+  std::map<std::pair<long long, int>, std::pair<std::vector<int>, std::vector<int>>> replay;
+  std::map<int, std::pair<std::vector<int>, std::vector<int>>> last_piv;
   long long sweeps_run = 0, learned = 0, fallbacks = 0;
   double max_learned_err = 0.0;
 
@@ -211,6 +215,22 @@ struct Solver {
   void cross(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y0, int site, DTT &out) {
     std::vector<int> J0;
     double ref = -1.0;
+    if (piv_mode == TT_PIV_REPLAY) {
+      std::pair<std::vector<int>, std::vector<int>> ji;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = replay.find({step_index, site});
+        if (it == replay.end())
+          throw Error(TT_EINVAL, "replay: no pivots for step " + std::to_string(step_index) +
+                                     ", site " + std::to_string(site));
+        ji = it->second;
+      }
+      skeleton_tt(w, fs, n1, n2, ji.first, ji.second, p.eps, p.r_max, out);
+      std::lock_guard<std::mutex> lk(mu);
+      piv[site] = ji.first;
+      last_piv[site] = ji;
+      return;
+    }
     {
       std::lock_guard<std::mutex> lk(mu);
       auto it = piv.find(site);
@@ -251,7 +271,8 @@ struct Solver {
           if (std::find(J0.begin(), J0.end(), j) == J0.end()) Jp.push_back(j);
         }
       }
-      cross_tt(w, fs, n1, n2, Jp, p.eps, p.r_max, 1, 0, key, out, &J);
+      std::vector<int> Il;
+      cross_tt(w, fs, n1, n2, Jp, p.eps, p.r_max, 1, 0, key, out, &J, &Il);
       const double err = validate(w, fs, n1, n2, out, J, key);
       std::lock_guard<std::mutex> lk(mu);
       sweeps_run += 1;
@@ -259,11 +280,13 @@ struct Solver {
         learned++;
         max_learned_err = std::max(max_learned_err, err);
         piv[site] = J;
+        last_piv[site] = {J, Il};
         return;
       }
       fallbacks++;
     }
-    cross_tt(w, fs, n1, n2, J0, p.eps, p.r_max, p.cross_sweeps, p.cross_kick, key, out, &J);
+    std::vector<int> I;
+    cross_tt(w, fs, n1, n2, J0, p.eps, p.r_max, p.cross_sweeps, p.cross_kick, key, out, &J, &I);
     double err = -1.0;
     if (piv_mode != TT_PIV_MAXVOL) err = validate(w, fs, n1, n2, out, J, key);
     if (piv_mode == TT_PIV_LOG && Xb) {
@@ -276,6 +299,7 @@ struct Solver {
     sweeps_run += p.cross_sweeps;
     if (err >= 0.0) ref_err[site] = err;
     piv[site] = J;
+    last_piv[site] = {J, I};
   }
 
   // ---- reconstruction -------------------------------------------------------------
@@ -710,8 +734,14 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   for (int i = 0; i < npool; ++i) cs.push_back(&s->pool->ctx(i).cnt);
   for (auto &a : s->aux)
     if (a) cs.push_back(&a->cnt);
+  long long jcap = s->c.jacobi_capped();
+  for (int i = 0; i < npool; ++i) jcap += s->pool->ctx(i).jacobi_capped();
+  for (auto &a : s->aux)
+    if (a) jcap += a->jacobi_capped();
   for (const Counters *wc : cs) {
     const Counters &w = *wc;
+    t.sketch_fallbacks += w.sketch_fallbacks;
+    t.sketch_unconverged += w.sketch_unconverged;
     t.roundings += w.roundings;
     t.crosses += w.crosses;
     t.flops += w.flops;
@@ -727,7 +757,10 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->crosses = t.crosses;
   o->last_taylor_terms = s->last_terms;
   o->last_taylor_err = s->last_err;
-  o->warnings = t.warnings;
+  o->warnings = t.warnings | (jcap > 0 ? TT_WJACOBI : 0);
+  o->sketch_fallbacks = t.sketch_fallbacks;
+  o->sketch_unconverged = t.sketch_unconverged;
+  o->jacobi_capped = jcap;
   o->flops = t.flops;
   o->bytes = t.bytes;
   KernelTimer *tm[8];
@@ -762,6 +795,34 @@ void solver_set_pivots(Solver *s, int mode, PivotModel *pm) {
   std::lock_guard<std::mutex> lk(s->mu);
   s->piv_mode = mode;
   s->pm = pm;
+}
+
+void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,
+                          const int *I, int nI) {
+  TT_REQUIRE(step >= 0 && site >= 0, "tt_fv_replay_pivots: negative step or site");
+  TT_REQUIRE(nJ >= 1 && nJ <= qr_max_cols() && nI >= 0 && nI <= nJ && J && (I || nI == 0),
+             "tt_fv_replay_pivots: need 1 <= nJ <= 96 and 0 <= nI <= nJ");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->replay[{step, site}] = {std::vector<int>(J, J + nJ), std::vector<int>(I, I + nI)};
+}
+
+int solver_get_pivots(Solver *s, int site, int *J, int capJ, int *nJ, int *I, int capI,
+                      int *nI) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->last_piv.find(site);
+  if (it == s->last_piv.end()) {
+    *nJ = 0;
+    *nI = 0;
+    return 0;
+  }
+  const auto &ji = it->second;
+  TT_REQUIRE((int)ji.first.size() <= capJ && (int)ji.second.size() <= capI,
+             "tt_fv_get_pivots: output capacity too small");
+  std::copy(ji.first.begin(), ji.first.end(), J);
+  std::copy(ji.second.begin(), ji.second.end(), I);
+  *nJ = (int)ji.first.size();
+  *nI = (int)ji.second.size();
+  return 1;
 }
 
 void solver_destroy(Solver *s) { delete s; }

@@ -39,7 +39,8 @@ template <int LP, int RS>
 __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int m,
                                                double *__restrict__ US,
                                                double *__restrict__ sig, int max_sweeps,
-                                               int trans, double floor2, int accum) {
+                                               int trans, double floor2, int accum,
+                                               int *__restrict__ status) {
   extern __shared__ double sm[];
   const int mm = (m + 1) & ~1;
   double *S = sm;                               // mm columns of m rows
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
   const double tol2 = tol * tol;
   const int np = mm - 1;                        // round-robin over mm players, np rounds
+  bool converged = false;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     // exact squared norms at the start of each sweep; within a sweep they follow the
@@ -146,8 +148,14 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double *__restrict__ M, int
     }
     const int any = rotated;
     __syncthreads();
-    if (!any) break;
+    if (!any) {
+      converged = true;
+      break;
+    }
   }
+  // stopped at the sweep cap while still rotating: count it (one lane; launches on a
+  // stream run in order, so the count needs no atomic)
+  if (!converged && threadIdx.x == 0) status[0] = status[0] + 1;
   // norms
   for (int cidx = wave; cidx < mm; cidx += nt / 64) {
     const double *cc = S + (size_t)cidx * m;
@@ -385,8 +393,9 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool tr
   auto launch = [&](auto kern, int lp) {
     const int nthreads = std::max(64, ((mm / 2) * lp + 63) / 64 * 64);
     set_lds(kern, lds);
-    hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig, 40,
-                       trans ? 1 : 0, floor_rel * floor_rel, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig,
+                       c.jacobi_max_sweeps, trans ? 1 : 0, floor_rel * floor_rel,
+                       accumulate ? 1 : 0, c.arena.status());
   };
   if (m <= 32) launch(k_jacobi<16, 2>, 16);
   else if (m <= 64) launch(k_jacobi<16, 4>, 16);

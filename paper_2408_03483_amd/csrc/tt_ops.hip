@@ -72,6 +72,21 @@ void zero_tt(Ctx &c, DTT &y) {
 
 uint64_t g_sketch_seed = 0x5EED5EED12345ull;
 
+// number of orthonormal directions orth keeps: those above drop * s_0, or exactly `want`
+// (a replayed skeleton fixes its width), which must all be nonzero
+int kept_directions(const std::vector<double> &s, double drop, int want) {
+  const int m = (int)s.size();
+  if (want >= 0) {
+    TT_REQUIRE(want <= m && (want == 0 || s[want - 1] > 0.0),
+               "orth: the columns have fewer nonzero directions than requested");
+    return want;
+  }
+  int k = 0;
+  if (s[0] > 0.0)
+    while (k < m && s[k] > drop * s[0]) ++k;
+  return k;
+}
+
 }  // namespace
 
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig_out) {
@@ -95,6 +110,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   bool Mt = false;           // M holds the transpose of the core to decompose
   double *US = nullptr, *sg = nullptr;   // SVD of M once computed
   std::vector<double> s_host;            // its singular values on the host, when fetched
+  int sketch_warn = 0;                   // TT_WSKETCH when the range finder did not converge
   int m = 0;
   if (R <= width && R <= mn) {
     m = R;
@@ -165,7 +181,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
     gemm(c, true, R, m, n2, 1.0, x.B, n2, Om, n2, 0.0, T, R);          // B^T Omega
     gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);          // Y = X Omega
     int q = 0;
-    const int qlim = std::max(c.power_iters, 8);
+    const int qlim = std::max(c.power_iters, c.sketch_max_iters);
+    bool unconverged = false;
     for (;;) {
       for (; q < c.power_iters; ++q) {
         tsqr(c, Y, n1, m, n1, qa, n1, rtmp, m);
@@ -181,7 +198,6 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       tsqr(c, Z, n2, m, n2, nullptr, 0, rb, m);                        // W = Qb Rb (R only)
       M = rb;                                                          // X ~ Qa Rb^T Qb^T
       Mt = true;                                                       // (M^T held)
-      if (q >= qlim) break;
       // singular values of Rb estimate those of X on the captured subspace
       if (!US) {
         US = c.arena.dalloc((size_t)m * m);
@@ -202,6 +218,10 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       if (m - pover > k && s[m - pover] <= 1e-14 * s[0]) break;
       const double ratio = s[m - 1] / s[k - 1];
       if (std::pow(ratio, 2 * q + 1) * s[k - 1] <= 1e-13 * s[0]) break;
+      if (q >= qlim) {
+        unconverged = true;
+        break;
+      }
       US = nullptr;   // basis changes below: the SVD must be recomputed
       s_host.clear();
       // one more subspace iteration from the current basis: Y = X (X^T Qa) = X Z
@@ -210,6 +230,28 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
       gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);
       ++q;
       c.cnt.extra_power_iters++;
+    }
+    if (unconverged) {
+      // the discarded directions may still leak more than 1e-13 s_0 into the kept part:
+      // redo the rounding exactly (QR of both cores and SVD of Ra Rb^T) when the input rank
+      // fits the factorization width, else keep the sketch's answer and say so
+      if (R <= qmax && R <= mn) {
+        c.cnt.sketch_fallbacks++;
+        c.cnt.roundings--;
+        const int saved = c.sketch_width;
+        c.sketch_width = R;
+        int w = 0;
+        try {
+          w = round_tt(c, x, eps, rmax, y, sig_out);
+        } catch (...) {
+          c.sketch_width = saved;
+          throw;
+        }
+        c.sketch_width = saved;
+        return w;
+      }
+      c.cnt.sketch_unconverged++;
+      sketch_warn = TT_WSKETCH;
     }
     Qa = qa;
     Bsrc = Z;
@@ -226,11 +268,12 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   std::vector<double> s = s_host.empty() ? to_host(c, sg, m) : std::move(s_host);
   for (double v : s)
     if (!std::isfinite(v)) throw Error(TT_ENONFINITE, "round: non-finite singular value");
-  int warn = 0;
+  int warn = sketch_warn;
   if (s[0] == 0.0) {
     zero_tt(c, y);
     if (sig_out) sig_out->assign(1, 0.0);
-    return 0;
+    c.cnt.warnings |= warn;
+    return warn;
   }
   bool capped = false;
   const int k = trunc_rank(s, eps, rmax, &capped);
@@ -255,7 +298,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   return warn;
 }
 
-void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out) {
+void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out,
+          int want) {
   Scope sc(c.arena);
   TT_REQUIRE(m >= 1, "orth: no columns");
   if (m <= n) {
@@ -265,9 +309,7 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
     double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc(m);
     small_svd(c, r, m, US, sg, 1e-2 * drop);
     std::vector<double> s = to_host(c, sg, m);
-    int k = 0;
-    if (s[0] > 0.0)
-      while (k < m && s[k] > drop * s[0]) ++k;
+    const int k = kept_directions(s, drop, want);
     *k_out = k;
     if (k == 0) return;
     double *U = c.arena.dalloc((size_t)m * k);
@@ -286,9 +328,7 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
   double *US = c.arena.dalloc((size_t)n * n), *sg = c.arena.dalloc(n);
   small_svd(c, Rt, n, US, sg, 1e-2 * drop);
   std::vector<double> s = to_host(c, sg, n);
-  int k = 0;
-  if (s[0] > 0.0)
-    while (k < n && s[k] > drop * s[0]) ++k;
+  const int k = kept_directions(s, drop, want);
   *k_out = k;
   if (k == 0) return;
   normalise_cols(c, US, sg, n, k, Q);
@@ -421,7 +461,7 @@ int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, dou
     HIP_CHECK(hipGetDevice(&dev));
     Scope sa(aux->arena);
     SumPipe pipe(*aux, n1, n2, rmax, eps, dev);
-    double err = 1.0;
+    double err = 1.0, err1 = 1.0, err2 = 1.0;   // the last three term sizes
     int terms = 1, warn = 0;
     DTT prev = dy;
     while (err > eps && terms < K) {
@@ -436,11 +476,17 @@ int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, dou
         warn |= round_tt(c, p, eps, rmax, next, &sdy);
         double nrm2 = 0.0;
         for (double v : sdy) nrm2 += v * v;
+        err2 = err1;
+        err1 = err;
         err = std::sqrt(nrm2) / std::sqrt(N);
       }
       pipe.push(next, c.stream);
       prev = next;
       ++terms;
+      if (terms >= 3 && err > err1 && err1 > err2) {
+        pipe.finish();
+        throw Error(TT_EDOMAIN, "reciprocal: the Taylor terms grow, |1 - x/mean| >= 1");
+      }
     }
     pipe.finish();
     if (pipe.err) std::rethrow_exception(pipe.err);
@@ -459,7 +505,7 @@ int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, dou
   fill_value(c, y.A, n1, n1, 1, 1.0);
   fill_value(c, y.B, n2, n2, 1, 1.0);
   y.r = 1;
-  double err = 1.0;
+  double err = 1.0, err1 = 1.0, err2 = 1.0;   // the last three term sizes
   int terms = 1, warn = 0;
   while (err > eps && terms < K) {
     Scope s3(c.arena);
@@ -479,8 +525,12 @@ int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, dou
     warn |= round_tt(c, s, eps, rmax, y, nullptr);
     double nrm2 = 0.0;
     for (double v : sdy) nrm2 += v * v;
+    err2 = err1;
+    err1 = err;
     err = std::sqrt(nrm2) / std::sqrt(N);
     ++terms;
+    if (terms >= 3 && err > err1 && err1 > err2)
+      throw Error(TT_EDOMAIN, "reciprocal: the Taylor terms grow, |1 - x/mean| >= 1");
   }
   copy_scale(c, y.A, n1, y.A, n1, n1, y.r, 1.0 / xavg);
   if (err > eps) warn |= TT_WNOCONV;
@@ -526,8 +576,26 @@ std::vector<int> kick_indices(const std::vector<int> &have_v, int n, int count, 
   return out;
 }
 
+namespace {
+
+// G1 = Qc Qc[I]^-1 (Qc: n1 x rc orthonormal columns, I: rc rows), G2^T = RwT, then rounding
+int skeleton_round(Ctx &c, const double *Qc, int n1, int n2, int rc, const int *Id,
+                   double *RwT, double eps, int rmax, DTT &y) {
+  Scope sc(c.arena);
+  double *QI = c.arena.dalloc((size_t)rc * rc), *QIi = c.arena.dalloc((size_t)rc * rc);
+  gather_rows(c, QI, rc, Qc, n1, Id, rc, rc);
+  small_inverse(c, QI, rc, rc, QIi);
+  double *G1 = c.arena.dalloc((size_t)n1 * rc);
+  gemm(c, false, n1, rc, rc, 1.0, Qc, n1, QIi, rc, 0.0, G1, n1);
+  DTT sk{n1, n2, rc, G1, RwT};
+  return round_tt(c, sk, eps, rmax, y, nullptr);
+}
+
+}  // namespace
+
 int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, double eps,
-             int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out) {
+             int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out,
+             std::vector<int> *I_out) {
   TT_REQUIRE(!J.empty(), "cross: empty starting column set");
   TT_REQUIRE(sweeps >= 1, "cross: sweeps < 1");
   c.cnt.crosses++;
@@ -546,17 +614,19 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
   // fiber directions below this fraction of the largest are dropped: round-off level of
   // the QR's arithmetic
   const double drop = c.fp32 ? 1e-6 : 1e-13;
+  auto zero_result = [&]() {
+    zero_tt(c, y);
+    if (J_out) *J_out = J;
+    if (I_out) I_out->clear();
+    return 0;
+  };
   for (int s = 0; s < sweeps; ++s) {
     TT_REQUIRE((int)J.size() <= qmax, "cross: column set exceeds the factorization width");
     HIP_CHECK(hipMemcpyAsync(Jd, J.data(), J.size() * sizeof(int), hipMemcpyHostToDevice,
                              c.stream));
     fiber_cols(c, fs, n1, Jd, (int)J.size(), C);
     orth(c, C, n1, (int)J.size(), n1, drop, Qc, &rc);
-    if (rc == 0) {
-      zero_tt(c, y);
-      if (J_out) *J_out = J;
-      return 0;
-    }
+    if (rc == 0) return zero_result();
     I = maxvol_host(c, Qc, n1, rc, n1, 1.05, 100);
     HIP_CHECK(hipMemcpyAsync(Id, I.data(), I.size() * sizeof(int), hipMemcpyHostToDevice,
                              c.stream));
@@ -564,11 +634,7 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
     if (s == sweeps - 1) break;
     int rr = 0;
     orth(c, RwT, n2, rc, n2, drop, Qr, &rr);
-    if (rr == 0) {
-      zero_tt(c, y);
-      if (J_out) *J_out = J;
-      return 0;
-    }
+    if (rr == 0) return zero_result();
     J = maxvol_host(c, Qr, n2, rr, n2, 1.05, 100);
     if ((int)J.size() < rmax && kick > 0) {
       std::vector<int> extra = kick_indices(J, n2, std::min(kick, rmax - (int)J.size()),
@@ -576,16 +642,36 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
       J.insert(J.end(), extra.begin(), extra.end());
     }
   }
-  // skeleton: G1 = Qc Qc[I]^-1, G2^T = RwT
-  double *QI = c.arena.dalloc((size_t)rc * rc), *QIi = c.arena.dalloc((size_t)rc * rc);
-  gather_rows(c, QI, rc, Qc, n1, Id, rc, rc);
-  small_inverse(c, QI, rc, rc, QIi);
-  double *G1 = c.arena.dalloc((size_t)n1 * rc);
-  gemm(c, false, n1, rc, rc, 1.0, Qc, n1, QIi, rc, 0.0, G1, n1);
-  DTT sk{n1, n2, rc, G1, RwT};
-  const int w = round_tt(c, sk, eps, rmax, y, nullptr);
+  const int w = skeleton_round(c, Qc, n1, n2, rc, Id, RwT, eps, rmax, y);
   if (J_out) *J_out = J;
+  if (I_out) *I_out = I;
   return w;
+}
+
+int skeleton_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, const std::vector<int> &J,
+                const std::vector<int> &I, double eps, int rmax, DTT &y) {
+  TT_REQUIRE(!J.empty() && (int)J.size() <= qr_max_cols(), "skeleton: |J| must be in [1, 96]");
+  for (int j : J) TT_REQUIRE(j >= 0 && j < n2, "skeleton: column index out of range");
+  for (int i : I) TT_REQUIRE(i >= 0 && i < n1, "skeleton: row index out of range");
+  c.cnt.crosses++;
+  Scope sc(c.arena);
+  const int nj = (int)J.size();
+  int *Jd = c.arena.ialloc(nj);
+  double *C = c.arena.dalloc((size_t)n1 * nj);
+  double *Qc = c.arena.dalloc((size_t)n1 * nj);
+  HIP_CHECK(hipMemcpyAsync(Jd, J.data(), nj * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  fiber_cols(c, fs, n1, Jd, nj, C);
+  if (I.empty()) {
+    zero_tt(c, y);
+    return 0;
+  }
+  int rc = 0;
+  orth(c, C, n1, nj, n1, 0.0, Qc, &rc, (int)I.size());
+  int *Id = c.arena.ialloc(rc);
+  HIP_CHECK(hipMemcpyAsync(Id, I.data(), rc * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  double *RwT = c.arena.dalloc((size_t)n2 * rc);
+  fiber_rows(c, fs, n2, Id, rc, RwT);
+  return skeleton_round(c, Qc, n1, n2, rc, Id, RwT, eps, rmax, y);
 }
 
 }  // namespace ttfv

@@ -25,6 +25,10 @@ TT_FN_RECIP = 5
 
 TT_WRANKCAP = 1
 TT_WNOCONV = 2
+TT_WSKETCH = 4
+TT_WJACOBI = 8
+TT_EDOMAIN = -5
+TT_ENONFINITE = -4
 
 
 class TTMatrixC(ctypes.Structure):
@@ -50,7 +54,8 @@ class StatsC(ctypes.Structure):
                 ("timed_launches", ctypes.c_longlong), ("timed_flops", ctypes.c_double),
                 ("timed_bytes", ctypes.c_double), ("cross_sweeps_run", ctypes.c_longlong),
                 ("learned_crosses", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_longlong),
-                ("max_learned_err", ctypes.c_double)]
+                ("max_learned_err", ctypes.c_double), ("sketch_fallbacks", ctypes.c_longlong),
+                ("sketch_unconverged", ctypes.c_longlong), ("jacobi_capped", ctypes.c_longlong)]
 
 
 PRECISIONS = {"f64": 0, "f32": 1}
@@ -62,10 +67,12 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_fv_time_kernel", "tt_ens_create", "tt_ens_step", "tt_ens_destroy",
            "tt_pm_create", "tt_pm_destroy", "tt_pm_set_weights", "tt_pm_get_weights",
            "tt_pm_forward", "tt_pm_grad", "tt_pm_train", "tt_pm_dataset", "tt_pm_features",
-           "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error"]
+           "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error",
+           "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
+           "tt_ctx_set_limits"]
 
 PM_NPARAM = 70401
-PIVOTS = {"maxvol": 0, "log": 1, "learned": 2}
+PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3}
 
 _lib = None
 
@@ -86,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_destroy.restype = None
     L.tt_ctx_set_sketch.argtypes = [P, I, I]
     L.tt_ctx_set_precision.argtypes = [P, I]
+    L.tt_ctx_set_limits.argtypes = [P, I, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
     L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
@@ -113,11 +121,16 @@ def load_library(path: str = LIB_PATH):
     L.tt_pm_forward.argtypes = [P, P, I, P]
     L.tt_pm_grad.argtypes = [P, P, P, I, D, pF, S, ctypes.POINTER(D)]
     L.tt_pm_train.argtypes = [P, I, I, D, ctypes.POINTER(D)]
+    L.tt_pm_adam.argtypes = [P, pF, S, D]
     L.tt_pm_dataset.argtypes = [P, ctypes.POINTER(S), ctypes.POINTER(S)]
     L.tt_pm_features.argtypes = [P, P, I, I, I, P, I, P]
     L.tt_pm_topk.argtypes = [P, P, I, I, P]
     L.tt_fv_set_pivots.argtypes = [P, I, P]
     L.tt_gemm_autotune.argtypes = [I, ctypes.POINTER(I)]
+    pI = ctypes.POINTER(I)
+    L.tt_fv_replay_pivots.argtypes = [P, ctypes.c_longlong, I, pI, I, pI, I]
+    L.tt_fv_get_pivots.argtypes = [P, I, pI, I, pI, pI, I, pI]
+    L.tt_cross_skeleton.argtypes = [P, I, pM, I, ctypes.POINTER(D), I, I, pI, I, pI, I, D, I, pM]
     for name in EXPORTS:
         if not hasattr(L, name):
             raise RuntimeError(f"libttfv.so lacks {name}")
@@ -208,6 +221,11 @@ def tt_ctx_set_sketch(ctx: Ctx, width: int, power_iters: int) -> None:
     _check(_lib.tt_ctx_set_sketch(ctx.h, width, power_iters), "tt_ctx_set_sketch")
 
 
+def tt_ctx_set_limits(ctx: Ctx, jacobi_max_sweeps: int, sketch_max_iters: int) -> None:
+    _check(_lib.tt_ctx_set_limits(ctx.h, jacobi_max_sweeps, sketch_max_iters),
+           "tt_ctx_set_limits")
+
+
 def tt_ctx_set_precision(ctx: Ctx, precision: str) -> None:
     _check(_lib.tt_ctx_set_precision(ctx.h, PRECISIONS[precision]), "tt_ctx_set_precision")
 
@@ -265,6 +283,20 @@ def tt_cross(ctx: Ctx, fn: int, inputs: Sequence[DeviceTT], fparams: Sequence[fl
                              ctypes.byref(yc), Jo, ctypes.byref(nJ)), "tt_cross")
     y.rank = yc.rank
     return w, np.array(Jo[:nJ.value], dtype=np.int64)
+
+
+def tt_cross_skeleton(ctx: Ctx, fn: int, inputs: Sequence[DeviceTT], fparams: Sequence[float],
+                      n1: int, n2: int, J: Sequence[int], I: Sequence[int], eps: float,
+                      r_max: int, y: DeviceTT) -> int:
+    arr = (TTMatrixC * len(inputs))(*[t.c() for t in inputs])
+    fp = (ctypes.c_double * max(1, len(fparams)))(*fparams)
+    Jc = (ctypes.c_int * max(1, len(J)))(*[int(j) for j in J])
+    Ic = (ctypes.c_int * max(1, len(I)))(*[int(i) for i in I])
+    yc = y.c()
+    w = _check(_lib.tt_cross_skeleton(ctx.h, fn, arr, len(inputs), fp, n1, n2, Jc, len(J), Ic,
+                                      len(I), eps, r_max, ctypes.byref(yc)), "tt_cross_skeleton")
+    y.rank = yc.rank
+    return w
 
 
 def tt_recon_core(ctx: Ctx, core, scheme: int, periodic: bool, sign: float = 1.0):
@@ -343,7 +375,8 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "timed_launches": st.timed_launches, "timed_flops": st.timed_flops,
             "timed_bytes": st.timed_bytes, "cross_sweeps_run": st.cross_sweeps_run,
             "learned_crosses": st.learned_crosses, "learned_fallbacks": st.learned_fallbacks,
-            "max_learned_err": st.max_learned_err}
+            "max_learned_err": st.max_learned_err, "sketch_fallbacks": st.sketch_fallbacks,
+            "sketch_unconverged": st.sketch_unconverged, "jacobi_capped": st.jacobi_capped}
 
 
 def tt_fv_time_kernel(s: Solver, name: Optional[str]) -> None:
@@ -440,6 +473,12 @@ class PivotModel:
                                ctypes.byref(loss)), "tt_pm_grad")
         return loss.value, g
 
+    def adam(self, grad: np.ndarray, lr: float) -> None:
+        """One Adam step of the weights with a given (host) gradient."""
+        a = np.ascontiguousarray(grad, dtype=np.float32)
+        _check(_lib.tt_pm_adam(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size,
+                               lr), "tt_pm_adam")
+
     def train(self, epochs: int = 4, batch: int = 8192, lr: float = 1e-3) -> float:
         loss = ctypes.c_double()
         _check(_lib.tt_pm_train(self.h, epochs, batch, lr, ctypes.byref(loss)), "tt_pm_train")
@@ -490,6 +529,25 @@ def tt_pm_topk(ctx: Ctx, s, k: int):
 def tt_fv_set_pivots(s: Solver, mode: str, model: Optional[PivotModel] = None) -> None:
     _check(_lib.tt_fv_set_pivots(s.h, PIVOTS[mode], model.h if model is not None else None),
            "tt_fv_set_pivots")
+
+
+def tt_fv_replay_pivots(s: Solver, step: int, site: int, J: Sequence[int],
+                        I: Sequence[int]) -> None:
+    Jc = (ctypes.c_int * max(1, len(J)))(*[int(j) for j in J])
+    Ic = (ctypes.c_int * max(1, len(I)))(*[int(i) for i in I])
+    _check(_lib.tt_fv_replay_pivots(s.h, step, site, Jc, len(J), Ic, len(I)),
+           "tt_fv_replay_pivots")
+
+
+def tt_fv_get_pivots(s: Solver, site: int, cap: int = 256):
+    """(J, I) of the latest cross at `site`, or None when the site has not run."""
+    Jc, Ic = (ctypes.c_int * cap)(), (ctypes.c_int * cap)()
+    nJ, nI = ctypes.c_int(), ctypes.c_int()
+    had = _check(_lib.tt_fv_get_pivots(s.h, site, Jc, cap, ctypes.byref(nJ), Ic, cap,
+                                       ctypes.byref(nI)), "tt_fv_get_pivots")
+    if not had:
+        return None
+    return (np.array(Jc[:nJ.value], dtype=np.int64), np.array(Ic[:nI.value], dtype=np.int64))
 
 
 def tt_gemm_autotune(on: bool) -> int:

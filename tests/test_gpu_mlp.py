@@ -94,7 +94,7 @@ def test_forward_matches_oracle(lib):
     ref, _ = omlp.forward(_rounded(p), bf16_round(X))
     e = np.linalg.norm(s - ref) / np.linalg.norm(ref)
     _say(f"  rel {e:.2e}")
-    assert e < 2e-2
+    assert e < 5e-3           # measured 1.5e-3 (BF16 activations, FP32 accumulation)
 
 
 def test_gradients_match_oracle(lib):
@@ -120,7 +120,31 @@ def test_gradients_match_oracle(lib):
     for k in ref:
         e = np.linalg.norm(gg[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-30)
         _say(f"  {k}: rel {e:.2e}")
-        assert e < 5e-2, k
+        assert e < 2e-2, k    # measured at most 9.4e-3
+
+
+def test_adam_steps_match_oracle(lib):
+    """Three device Adam steps (FP32) with seeded gradients of mixed magnitudes against the
+    oracle's Adam in FP64 from the same FP32 weights: the updates agree to FP32 accuracy."""
+    _say("adam, 3 steps")
+    rng = np.random.default_rng(13)
+    flat0 = lib.pm_flat(_weights(14)).astype(np.float32)
+    m = lib.PivotModel(0, 1)
+    m.set_weights(flat0)
+    ref = {"w": flat0.astype(np.float64)}
+    mo = {"w": np.zeros(flat0.size)}
+    vo = {"w": np.zeros(flat0.size)}
+    for t in (1, 2, 3):
+        g = (rng.standard_normal(flat0.size) * 10.0 ** rng.uniform(-4, 1, flat0.size))
+        g = g.astype(np.float32)
+        m.adam(g, 1e-2)
+        omlp.adam_step(ref, {"w": g.astype(np.float64)}, mo, vo, t, lr=1e-2)
+    got = m.get_weights().astype(np.float64)
+    m.close()
+    d_gpu, d_ref = got - flat0, ref["w"] - flat0
+    e = np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)
+    _say(f"  update rel {e:.2e}")
+    assert e < 1e-4
 
 
 def _dam_break_solver(lib, st, rmax, eps, precision="f64"):

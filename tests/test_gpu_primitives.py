@@ -249,6 +249,50 @@ def test_cross_lambda_parity(lib, ctx):
     assert rel(Y.full(), ref.full()) < 1e-9
 
 
+def test_cross_lambda_hand_values(lib, ctx):
+    """The device lambda function (Section 4.2, LLF) on constant rank-1 TTs, g = 4: minus state
+    (h, m) = (1, 1/2), plus (1/4, -1/2) gives max(1/2 + 2, 2 + 1) = 3; with the momenta
+    -3 and 1/4 it gives max(3 + 2, 1 + 1) = 5 (the values derived by hand for the oracle)."""
+    _say("cross lambda hand values")
+    n1, n2 = 40, 30
+
+    def const(c):
+        return lib.DeviceTT.from_factors(np.full((n1, 1), c), np.ones((n2, 1)))
+
+    hm, hp = const(1.0), const(0.25)
+    for mm, mp, want in ((0.5, -0.5, 3.0), (-3.0, 0.25, 5.0)):
+        Y = lib.DeviceTT(n1, n2, 4)
+        lib.tt_cross(ctx, lib.TT_FN_LLF_LAMBDA, [hm, const(mm), hp, const(mp)], [4.0], n1, n2,
+                     [0], 1e-12, 4, 1, 0, 1, Y)
+        assert Y.rank == 1
+        assert np.max(np.abs(Y.full() - want)) <= 1e-13 * want
+
+
+def test_cross_skeleton_replays_oracle_pivots(lib, ctx):
+    """Given the oracle's final column and row sets of a capped lambda cross (Section 3.3), the
+    device skeleton equals the oracle's: the skeleton is fixed by its pivots."""
+    _say("cross skeleton from oracle pivots")
+    import synth
+    rng = np.random.default_rng(16)
+    n1, n2 = 300, 900
+    fs = [synth.smooth_factored(rng, n1, n2, 9, base=b) for b in (1.0, 0.0, 1.0, 0.0)]
+    T = [ott.TT(f.A, f.B) for f in fs]
+    D = [lib.DeviceTT.from_factors(f.A, f.B) for f in fs]
+    fun = otf._Lambda(T[0], T[1], T[2], T[3], 9.81)
+    rows = []
+    ref, J = ott.cross(fun, n1, n2, ott.initial_columns(T[1]), 1e-10, 12, 3, 4, key=3,
+                       rows_out=rows)
+    I = rows[0]
+    assert len(I) >= 8                       # the cap binds: many valid pivot sets exist
+    Y = lib.DeviceTT(n1, n2, 12)
+    lib.tt_cross_skeleton(ctx, lib.TT_FN_LLF_LAMBDA, D, [9.81], n1, n2, J.tolist(), I.tolist(),
+                          1e-10, 12, Y)
+    assert Y.rank == ref.rank
+    e = rel(Y.full(), ref.full())
+    _say(f"  rank {Y.rank}, rel {e:.2e}")
+    assert e < 1e-10
+
+
 @pytest.mark.parametrize("periodic", [True, False])
 def test_cross_weno_parity(lib, ctx, periodic):
     _say(f"cross weno periodic={periodic}")
@@ -297,3 +341,105 @@ def test_error_paths(lib, ctx):
     X.rank = 1
     with pytest.raises(RuntimeError, match="cap"):
         lib.tt_round(ctx, X, 1e-10, 8, Y)
+
+
+# ---- failure detection, each condition forced from the host ---------------------------
+
+def _spectrum_tt(rng, n1, n2, R, decay):
+    """A TT of rank R with singular values decay^i (orthonormal factors)."""
+    qa, _ = np.linalg.qr(rng.standard_normal((n1, R)))
+    qb, _ = np.linalg.qr(rng.standard_normal((n2, R)))
+    return qa * decay ** np.arange(R), qb
+
+
+def test_round_sketch_limit_redone_exactly(lib):
+    """A slowly decaying spectrum (0.97^i, rank 80 > the 32-column sketch of r_max 16) keeps
+    the discarded directions leaking past the subspace-iteration limit; at rank <= 96 the
+    rounding is then redone exactly, so it must equal the oracle's truncated SVD."""
+    _say("round: unconverged sketch redone exactly")
+    rng = np.random.default_rng(21)
+    A, B = _spectrum_tt(rng, 700, 500, 80, 0.97)
+    c = lib.tt_ctx_create(1 << 28)
+    for limit in (8, 0):
+        lib.tt_ctx_set_limits(c, 40, limit)
+        X = lib.DeviceTT.from_factors(A, B)
+        Y = lib.DeviceTT(700, 500, 16)
+        w, _ = lib.tt_round(c, X, 1e-10, 16, Y)
+        ref = ott.tt_round(ott.TT(A, B), 1e-10, 16)
+        assert w & lib.TT_WRANKCAP and not (w & lib.TT_WSKETCH)
+        assert rel(Y.full(), ref.full()) < 1e-10
+    c.close()
+
+
+def test_round_sketch_unconverged_warns(lib):
+    """The same spectrum at rank 200 (beyond the exact path's 96 columns): the rounding keeps
+    the sketch's answer and returns TT_WSKETCH; its error stays within a few times the optimal
+    truncation error."""
+    _say("round: unconverged sketch warning")
+    rng = np.random.default_rng(22)
+    A, B = _spectrum_tt(rng, 700, 500, 200, 0.97)
+    c = lib.tt_ctx_create(1 << 28)
+    X = lib.DeviceTT.from_factors(A, B)
+    Y = lib.DeviceTT(700, 500, 16)
+    w, _ = lib.tt_round(c, X, 1e-10, 16, Y)
+    F = A @ B.T
+    best = np.linalg.norm(F - ott.tt_round(ott.TT(A, B), 1e-10, 16).full())
+    got = np.linalg.norm(F - Y.full())
+    _say(f"  warnings {w}, error {got:.4e} vs optimal {best:.4e}")
+    assert w & lib.TT_WSKETCH
+    assert got <= 1.5 * best
+    c.close()
+
+
+def test_jacobi_sweep_cap_warns(lib):
+    """With the sweep cap forced to 1, the Jacobi SVD of a rounding stops while still
+    rotating and the rounding returns TT_WJACOBI; with the default cap it does not."""
+    _say("jacobi sweep cap warning")
+    rng = np.random.default_rng(23)
+    A, B = rng.standard_normal((90, 24)), rng.standard_normal((70, 24))
+    c = lib.tt_ctx_create(1 << 28)
+    X = lib.DeviceTT.from_factors(A, B)
+    Y = lib.DeviceTT(90, 70, 24)
+    w, _ = lib.tt_round(c, X, 0.0, 24, Y)
+    assert not (w & lib.TT_WJACOBI)
+    lib.tt_ctx_set_limits(c, 1, 8)
+    w, _ = lib.tt_round(c, X, 0.0, 24, Y)
+    assert w & lib.TT_WJACOBI
+    c.close()
+
+
+def test_reciprocal_divergent_series_is_an_error(lib):
+    """x = 8 on one row and 1 elsewhere: |1 - x/mean| = 63/17 there, the Taylor terms grow
+    and Algorithm 1 must fail with TT_EDOMAIN (the oracle raises SeriesDiverges on the same
+    input); a convergent input still works on the same context."""
+    _say("reciprocal divergence")
+    n1, n2 = 10, 4
+    col = np.ones((n1, 1))
+    col[0] = 8.0
+    with pytest.raises(ott.SeriesDiverges):
+        ott.reciprocal(ott.TT(col, np.ones((n2, 1))), 1e-12, 200, 10)
+    c = lib.tt_ctx_create(1 << 28)
+    X = lib.DeviceTT.from_factors(col, np.ones((n2, 1)))
+    Y = lib.DeviceTT(n1, n2, 10)
+    with pytest.raises(RuntimeError, match=r"\(-5\)"):
+        lib.tt_reciprocal(c, X, 1e-12, 200, 10, Y)
+    ok = np.full((n1, 1), 0.5)
+    ok[5:] = 4.5
+    X = lib.DeviceTT.from_factors(ok, np.ones((n2, 1)))
+    w, err, terms = lib.tt_reciprocal(c, X, 1e-12, 200, 10, Y)
+    assert err <= 1e-12 and np.allclose(Y.full(), 1.0 / (ok @ np.ones((1, n2))), rtol=1e-10)
+    c.close()
+
+
+def test_nonfinite_core_is_an_error(lib):
+    """A NaN in a core reaches the singular values: rounding fails with TT_ENONFINITE."""
+    _say("non-finite input")
+    rng = np.random.default_rng(24)
+    A, B = rng.standard_normal((50, 6)), rng.standard_normal((40, 6))
+    A[7, 2] = np.nan
+    c = lib.tt_ctx_create(1 << 28)
+    X = lib.DeviceTT.from_factors(A, B)
+    Y = lib.DeviceTT(50, 40, 6)
+    with pytest.raises(RuntimeError, match=r"\(-4\)"):
+        lib.tt_round(c, X, 1e-10, 6, Y)
+    c.close()

@@ -49,10 +49,11 @@ def run_both(lib, st, scheme, nonlinear, periodic, eps, rmax, nsteps, taylor=8, 
 
 
 def test_linear_gaussian_64_parity(lib):
-    """64^2 linear Gaussian, Upwind3, rank cap 8, tol 1e-12, 10 steps: rel-L2 <= 1e-9 per field."""
-    _say("linear 64 upwind3")
+    """64^2 linear Gaussian, Upwind3, rank cap 8, tol 1e-12, the whole run of 100 steps
+    (trajectory parity): rel-L2 <= 1e-9 per field."""
+    _say("linear 64 upwind3, 100 steps")
     st = synth.linear_gaussian(seed=0)
-    Qg, Qo, stats, ts = run_both(lib, st, "upwind3", False, True, 1e-12, 8, 10)
+    Qg, Qo, stats, ts = run_both(lib, st, "upwind3", False, True, 1e-12, 8, 100)
     assert [q.rank for q in Qg] == [q.rank for q in Qo]
     r = field_rel(Qg, Qo)
     _say(f"  rel {r}")
@@ -97,45 +98,105 @@ def test_weno5_unique_parity(lib, periodic, recip):
     assert max(r) <= 1e-9
 
 
+def run_replayed(lib, st, scheme, periodic, eps, rmax, nsteps, recip="taylor",
+                 precision="f64", cross_drop=1e-13, taylor=8):
+    """The oracle's steps, then the GPU's from the same state with every cross given the
+    oracle's final column and row sets (Section 3.3: a skeleton is fixed by its pivots).  At
+    the rank cap several pivot sets are equally valid and maxvol's choice among them flips
+    under round-off, so replaying one set is what makes the two steps comparable."""
+    Q0 = [ott.TT(f.A, f.B) for f in st.tt]
+    ts = otf.TTSolver(st.n, scheme, True, periodic, g=st.g, H=st.H0, eps=eps, rmax=rmax,
+                      taylor_terms=taylor, recip=recip, cross_drop=cross_drop)
+    Qo = ts.run(Q0, st.dt, nsteps)
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+    s = lib.tt_fv_init(st.n, scheme, True, periodic, dev, g=st.g, H0=st.H0, eps=eps,
+                       r_max=rmax, taylor_terms=taylor, recip=recip, arena_bytes=1 << 30,
+                       precision=precision)
+    for (step, site), (J, I) in ts.cross_log.items():
+        lib.tt_fv_replay_pivots(s, step, site, J, I)
+    lib.tt_fv_set_pivots(s, "replay")
+    lib.tt_fv_step(s, st.dt, nsteps)
+    Qg = lib.tt_fv_get_state(s)
+    s.close()
+    return Qg, Qo, ts
+
+
+def pivot_agreement(lib, st, scheme, periodic, eps, rmax, ts, recip="taylor"):
+    """One plain GPU step (its own maxvol pivots): the fraction of cross sites whose final
+    column sets and row sets equal the oracle's, and the GPU state."""
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
+    s = lib.tt_fv_init(st.n, scheme, True, periodic, dev, g=st.g, H0=st.H0, eps=eps,
+                       r_max=rmax, recip=recip, arena_bytes=1 << 30)
+    lib.tt_fv_step(s, st.dt, 1)
+    same_j = same_i = total = 0
+    for (step, site), (J, I) in ts.cross_log.items():
+        if step != 0:
+            continue
+        g = lib.tt_fv_get_pivots(s, site)
+        total += 1
+        same_j += set(g[0].tolist()) == set(J.tolist())
+        same_i += set(g[1].tolist()) == set(I.tolist())
+    Qg = lib.tt_fv_get_state(s)
+    s.close()
+    return same_j / total, same_i / total, total, Qg
+
+
 @pytest.mark.parametrize("periodic", [True, False])
-def test_weno5_capped_equally_valid(lib, periodic):
-    """Nonlinear bumps on 64^2, WENO5 crosses with the rank cap (24) binding.  Truncating a
-    near-degenerate spectrum at the cap has several valid answers, so GPU and oracle are each
-    compared with the full-grid scheme: the GPU must be as close to it as the oracle is."""
+def test_weno5_capped_replay_parity(lib, periodic):
+    """Nonlinear bumps on 64^2, WENO5 by crosses with the rank cap (24) binding, tol 1e-8,
+    two steps.  With the oracle's pivots replayed the GPU must match it to 1e-9 per field.
+    Without replay (the GPU's own maxvol pivots) the result must be as close to the
+    full-grid scheme as the oracle's: within twice its distance plus 20 eps."""
     from oracle import fv_grid
-    _say(f"weno5 64 capped periodic={periodic}")
+    _say(f"weno5 64 capped, replayed pivots, periodic={periodic}")
     st = synth.nonlinear_bumps(seed=2, n=64, rmax=24, eps=1e-8)
-    Qg, Qo, stats, ts = run_both(lib, st, "weno5", True, periodic, 1e-8, 24, 1)
-    U0 = [f.full() for f in st.tt]
-    gs = fv_grid.GridSolver(st.n, "weno5", True, periodic, g=st.g)
-    Ug = gs.step(U0, st.dt)
+    Qg, Qo, ts = run_replayed(lib, st, "weno5", periodic, 1e-8, 24, 2)
+    r = field_rel(Qg, Qo)
+    _say(f"  replayed rel {r} ranks {[q.rank for q in Qg]} vs {[q.rank for q in Qo]}")
+    assert max(r) <= 1e-9
+    # the GPU's own pivots: agreement with the oracle's, and accuracy against the grid
+    ts1 = otf.TTSolver(st.n, "weno5", True, periodic, g=st.g, eps=1e-8, rmax=24)
+    Qo1 = ts1.run([ott.TT(f.A, f.B) for f in st.tt], st.dt, 1)
+    aj, ai, nsite, Qp = pivot_agreement(lib, st, "weno5", periodic, 1e-8, 24, ts1)
+    Ug = fv_grid.GridSolver(st.n, "weno5", True, periodic, g=st.g).step(
+        [f.full() for f in st.tt], st.dt)
+    _say(f"  own pivots: {nsite} sites, equal column sets {aj:.2f}, equal row sets {ai:.2f}")
     for c in range(3):
         ref = np.linalg.norm(Ug[c])
-        e_o = np.linalg.norm(Qo[c].full() - Ug[c]) / ref
-        e_g = np.linalg.norm(Qg[c].full() - Ug[c]) / ref
-        d = np.linalg.norm(Qg[c].full() - Qo[c].full()) / ref
-        _say(f"  var {c}: oracle-vs-grid {e_o:.3e} gpu-vs-grid {e_g:.3e} gpu-vs-oracle {d:.3e}")
+        e_o = np.linalg.norm(Qo1[c].full() - Ug[c]) / ref
+        e_g = np.linalg.norm(Qp[c].full() - Ug[c]) / ref
+        _say(f"  var {c}: oracle-vs-grid {e_o:.3e} gpu-vs-grid {e_g:.3e}")
         assert e_g <= 2.0 * e_o + 20 * 1e-8
 
 
-def test_dam_break_weno5_cross_reciprocal_equally_valid(lib):
-    """Dam break (h from 0.5 to 1.5, walls) on 48^2: WENO5 crosses and 1/h by cross, cap 24,
-    tol 1e-8.  Both results are compared with the full-grid scheme; a step makes a few hundred
-    roundings, each allowed a relative change of eps, so the GPU must be within twice the
-    oracle's distance plus 20 eps."""
-    from oracle import fv_grid
-    _say("dam break 48 weno5 cross reciprocal")
+def test_dam_break_cross_reciprocal_replay_parity(lib):
+    """Dam break (h from 0.5 to 1.5, walls) on 48^2: WENO5 crosses and 1/h by cross (reading
+    R7), cap 24, tol 1e-8, two steps, the oracle's pivots replayed: rel-L2 <= 1e-9 per
+    field, and for h also on its deviation from the mean."""
+    _say("dam break 48 weno5 cross reciprocal, replayed pivots")
     st = synth.dam_break(seed=0, n=48, rmax=24, eps=1e-8, width=0.05)
-    Qg, Qo, stats, ts = run_both(lib, st, "weno5", True, False, 1e-8, 24, 1, recip="cross")
-    U0 = [f.full() for f in st.tt]
-    Ug = fv_grid.GridSolver(st.n, "weno5", True, False, g=st.g).step(U0, st.dt)
-    scale = np.linalg.norm(Ug[0])
-    for c in range(3):
-        e_o = np.linalg.norm(Qo[c].full() - Ug[c]) / scale
-        e_g = np.linalg.norm(Qg[c].full() - Ug[c]) / scale
-        d = np.linalg.norm(Qg[c].full() - Qo[c].full()) / scale
-        _say(f"  var {c}: oracle-vs-grid {e_o:.3e} gpu-vs-grid {e_g:.3e} gpu-vs-oracle {d:.3e}")
-        assert e_g <= 2.0 * e_o + 20 * 1e-8
+    Qg, Qo, ts = run_replayed(lib, st, "weno5", False, 1e-8, 24, 2, recip="cross")
+    r = field_rel(Qg, Qo)
+    hg, ho = Qg[0].full(), Qo[0].full()
+    dh = np.linalg.norm(hg - ho) / np.linalg.norm(ho - ho.mean())
+    _say(f"  rel {r}, h deviation {dh:.2e}, ranks {[q.rank for q in Qg]}")
+    assert max(r) <= 1e-9 and dh <= 1e-9
+
+
+def test_dam_break_fp32_contractions_replay(lib):
+    """Mixed precision on the 48^2 dam break (WENO5 crosses, 1/h by cross, walls, cap 24, tol
+    1e-8, two steps): FP32 contractions against the FP64 oracle with the same cross drop
+    rule (1e-6, reading R12) and its pivots replayed.  Gate: rel-L2 <= 1e-4 per field, and
+    for h also on its deviation from the mean."""
+    _say("dam break 48 weno5 cross reciprocal fp32, replayed pivots")
+    st = synth.dam_break(seed=0, n=48, rmax=24, eps=1e-8, width=0.05)
+    Qg, Qo, ts = run_replayed(lib, st, "weno5", False, 1e-8, 24, 2, recip="cross",
+                              precision="f32", cross_drop=1e-6)
+    r = field_rel(Qg, Qo)
+    hg, ho = Qg[0].full(), Qo[0].full()
+    dh = np.linalg.norm(hg - ho) / np.linalg.norm(ho - ho.mean())
+    _say(f"  per-field rel {r}, h deviation {dh:.2e}")
+    assert max(r) <= 1e-4 and dh <= 1e-4
 
 
 def test_nonlinear_upwind5_fp32_contractions(lib):
@@ -150,20 +211,6 @@ def test_nonlinear_upwind5_fp32_contractions(lib):
     dev = np.linalg.norm(hg - ho) / np.linalg.norm(ho - ho.mean())
     _say(f"  rel {r}, h deviation {dev:.2e}, ranks {[q.rank for q in Qg]}")
     assert max(r) <= 1e-4 and dev <= 1e-4
-
-
-def test_dam_break_fp32_contractions(lib):
-    """Mixed precision on the 48^2 dam break (WENO5 crosses, 1/h by cross, walls, cap 24,
-    tol 1e-8): rel-L2 <= 1e-4 per field against the FP64 oracle, measured on the scale of h."""
-    _say("dam break 48 weno5 cross reciprocal fp32")
-    st = synth.dam_break(seed=0, n=48, rmax=24, eps=1e-8, width=0.05)
-    Qg, Qo, stats, ts = run_both(lib, st, "weno5", True, False, 1e-8, 24, 1, recip="cross",
-                                 precision="f32")
-    scale = np.linalg.norm(Qo[0].full())
-    d = [np.linalg.norm(g.full() - o.full()) / scale for g, o in zip(Qg, Qo)]
-    r = field_rel(Qg, Qo)
-    _say(f"  diff on h scale {d}, per-field rel {r}")
-    assert max(d) <= 1e-4
 
 
 @pytest.mark.parametrize("scheme,recip", [("upwind5", "taylor"), ("weno5", "cross")])
@@ -228,3 +275,46 @@ def test_bumps_1024_restart_parity_full_size(lib):
     _say(f"  rel {r}, h deviation {dh:.2e}, ranks {[q.rank for q in Qg]} vs "
          f"{[q.rank for q in Qo]}")
     assert max(r) <= 1e-9 and dh <= 1e-9
+
+
+def test_bumps_trajectory_and_restart_parity(lib):
+    """The throughput workload's scheme on 64^2 bumps (Upwind5, Taylor 8 terms, cap 24
+    binding, tol 1e-10, periodic).  Trajectory parity: the GPU's 12 steps against the
+    oracle's at steps 4, 8 and 12.  Restart parity: the oracle's states at steps 4 and 8
+    fed to a fresh GPU solver and a fresh oracle solver for one step.  Gate 1e-9 per field
+    throughout, and for h also on its deviation from the mean."""
+    _say("bumps 64 trajectory (12 steps) and restarts at steps 4 and 8")
+    n, rmax, eps = 64, 24, 1e-10
+    st = synth.nonlinear_bumps(seed=5, n=n, rmax=rmax, eps=eps)
+    kw = dict(g=st.g, H=st.H0, eps=eps, rmax=rmax, taylor_terms=8)
+    ts = otf.TTSolver(n, "upwind5", True, True, **kw)
+    Q = [ott.TT(f.A, f.B) for f in st.tt]
+    snaps = {}
+    for k in range(1, 13):
+        Q = ts.step(Q, st.dt)
+        if k % 4 == 0:
+            snaps[k] = Q
+
+    def gpu_solver(tts):
+        dev = [lib.DeviceTT.from_factors(t.A, t.B, cap=rmax) for t in tts]
+        return lib.tt_fv_init(n, "upwind5", True, True, dev, g=st.g, H0=st.H0, eps=eps,
+                              r_max=rmax, taylor_terms=8, arena_bytes=1 << 30)
+
+    def check(Qg, Qo, what):
+        r = field_rel(Qg, Qo)
+        hg, ho = Qg[0].full(), Qo[0].full()
+        dh = np.linalg.norm(hg - ho) / np.linalg.norm(ho - ho.mean())
+        _say(f"  {what}: rel {r}, h deviation {dh:.2e}")
+        assert max(r) <= 1e-9 and dh <= 1e-9, what
+
+    s = gpu_solver([ott.TT(f.A, f.B) for f in st.tt])
+    for k in (4, 8, 12):
+        lib.tt_fv_step(s, st.dt, 4)
+        check(lib.tt_fv_get_state(s), snaps[k], f"trajectory step {k}")
+    s.close()
+    for k in (4, 8):
+        ref = otf.TTSolver(n, "upwind5", True, True, **kw).step(snaps[k], st.dt)
+        s = gpu_solver(snaps[k])
+        lib.tt_fv_step(s, st.dt, 1)
+        check(lib.tt_fv_get_state(s), ref, f"restart from step {k}")
+        s.close()
