@@ -83,6 +83,23 @@ int  tt_ctx_set_precision(tt_ctx *ctx, int precision);
 int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
              double *sigma_out);
 
+/* TT rounding that allocates nothing, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same result
+ * and arguments as tt_round with a default context (FP64 contractions, automatic sketch), but
+ * without a tt_ctx: work runs on hip_stream (a hipStream_t, NULL = default stream) and every
+ * temporary lives in one fixed device array of TT_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each GPU it runs on until the process ends; the call allocates no device or pinned host
+ * memory and creates no events.  The call returns after synchronising hip_stream.
+ * Errors: TT_EINVAL for bad arguments (as tt_round); TT_ENOMEM, before any work is enqueued,
+ * when an n1 x n2 input of this rank could need more scratch than the maximum (the message
+ * gives both sizes; e.g. 1024 x 3072 at rank 1024 with r_max 32 fits, 20000 x 20000 at rank
+ * 2000 does not).  All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents: calls that overlap in time on the same GPU (several threads, or several streams)
+ * race and must be serialised by the caller. */
+#define TT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tt_round_noalloc(const tt_matrix *x, double eps, int r_max, tt_matrix *y,
+                     double *sigma_out, void *hip_stream);
+
 /* Elementwise (Hadamard) product of two TTs on the same index space followed by rounding:
  * y = round(x o z, eps, r_max).  The product has rank x.rank * z.rank (Section 4.2). */
 int tt_hadamard_round(tt_ctx *ctx, const tt_matrix *x, const tt_matrix *z, double eps,

@@ -3,6 +3,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <map>
 #include <memory>
 
 namespace ttfv {
@@ -32,7 +33,7 @@ thread_local std::string g_last_error;
 void set_last_error(const std::string &m) { g_last_error = m; }
 
 Arena::~Arena() {
-  if (base_) (void)hipFree(base_);
+  if (base_ && owned_) (void)hipFree(base_);
 }
 
 constexpr size_t kArenaHeader = 256;   // status words (Arena::status)
@@ -41,7 +42,18 @@ void Arena::init(size_t bytes) {
   TT_REQUIRE(base_ == nullptr, "arena already initialised");
   TT_REQUIRE(bytes > kArenaHeader, "arena too small");
   HIP_CHECK(hipMalloc(&base_, bytes));
+  owned_ = true;
   HIP_CHECK(hipMemset(base_, 0, kArenaHeader));
+  cap_ = bytes;
+  top_ = hw_ = kArenaHeader;
+}
+
+void Arena::adopt(void *base, size_t bytes) {
+  TT_REQUIRE(base_ == nullptr, "arena already initialised");
+  TT_REQUIRE(base && bytes > kArenaHeader && ((uintptr_t)base & 255) == 0,
+             "arena: bad caller memory");
+  base_ = static_cast<char *>(base);
+  owned_ = false;
   cap_ = bytes;
   top_ = hw_ = kArenaHeader;
 }
@@ -57,6 +69,10 @@ void *Arena::alloc(size_t bytes) {
 }
 
 void Ctx::sync() {
+  if (no_alloc) {          // creates no event
+    HIP_CHECK(hipStreamSynchronize(stream));
+    return;
+  }
   // an event with default flags is waited for by polling, which wakes the host sooner than a
   // stream synchronisation that may yield the thread
   if (!sync_ev) HIP_CHECK(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
@@ -95,6 +111,7 @@ constexpr int kTileCounters = 16384;
 
 int *Ctx::tile_counters() {
   if (!tile_cnt) {
+    if (no_alloc) throw Error(TT_EINVAL, "no_alloc context without tile counters");
     HIP_CHECK(hipMalloc(&tile_cnt, kTileCounters * sizeof(int)));
     HIP_CHECK(hipMemsetAsync(tile_cnt, 0, kTileCounters * sizeof(int), stream));
   }
@@ -102,6 +119,7 @@ int *Ctx::tile_counters() {
 }
 
 double *Ctx::pinned_staging() {
+  if (no_alloc) return nullptr;
   if (!pinned) HIP_CHECK(hipHostMalloc((void **)&pinned, kPinnedDoubles * sizeof(double)));
   return pinned;
 }
@@ -109,7 +127,7 @@ double *Ctx::pinned_staging() {
 Ctx::~Ctx() {
   if (tile_cnt || pinned) (void)hipStreamSynchronize(stream);
   if (sync_ev) (void)hipEventDestroy(sync_ev);
-  if (tile_cnt) (void)hipFree(tile_cnt);
+  if (tile_cnt && !no_alloc) (void)hipFree(tile_cnt);
   if (pinned) (void)hipHostFree(pinned);
   for (auto &e : timer.spare) {
     (void)hipEventDestroy(e.first);
@@ -163,6 +181,39 @@ void check_matrix(const tt_matrix *m, const char *what, bool need_rank) {
     throw Error(TT_EINVAL, std::string(what) + ": rank out of [1, cap]");
 }
 
+}  // namespace ttfv
+
+// ---------------------------------------------------------------------------------------
+// Scratch of tt_round_noalloc: one fixed device array, held on every GPU the library runs on
+// until the process ends.  Layout: split-K arrival counters (kScratchCounterBytes), then an
+// arena (its first 256 bytes are status words).  Host code never uses the array's name as an
+// address: each GPU's copy is reached through the pointer hipGetSymbolAddress returns with
+// that GPU current, fetched once per device.
+namespace ttfv {
+namespace {
+
+constexpr size_t kScratchCounterBytes = (size_t)kTileCounters * sizeof(int);
+static_assert(kScratchCounterBytes % 256 == 0, "arena part must stay 256-byte aligned");
+
+__device__ __align__(256) unsigned char scratch[TT_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;   // device -> its copy of `scratch`
+
+unsigned char *scratch_address(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  unsigned char *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr)
+    throw Error(TT_EHIP, std::string("tt_round_noalloc: hipGetSymbolAddress(scratch): ") +
+                             hipGetErrorString(e));
+  g_scratch_addr[dev] = ptr;
+  return ptr;
+}
+
+}  // namespace
 }  // namespace ttfv
 
 struct tt_ctx {
@@ -329,6 +380,43 @@ int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *
     if (sigma_out)
       for (size_t i = 0; i < s.size(); ++i) sigma_out[i] = s[i];
     return w | jacobi_warning(ctx->c);
+  });
+}
+
+int tt_round_noalloc(const tt_matrix *x, double eps, int r_max, tt_matrix *y,
+                     double *sigma_out, void *hip_stream) {
+  return guarded([&]() {
+    check_matrix(x, "tt_round_noalloc x", true);
+    check_matrix(y, "tt_round_noalloc y", false);
+    TT_REQUIRE(eps >= 0.0 && r_max >= 1, "tt_round_noalloc: eps < 0 or r_max < 1");
+    TT_REQUIRE(y->cap >= r_max, "tt_round_noalloc: y->cap < r_max");
+    TT_REQUIRE(x->n1 == y->n1 && x->n2 == y->n2, "tt_round_noalloc: shape mismatch");
+    const size_t need = round_arena_bound(x->n1, x->n2, x->rank, r_max) + kScratchCounterBytes;
+    if (need > TT_NOALLOC_SCRATCH_BYTES)
+      throw Error(TT_ENOMEM, "tt_round_noalloc: a " + std::to_string(x->n1) + " x " +
+                                 std::to_string(x->n2) + " TT of rank " +
+                                 std::to_string(x->rank) + " may need " + std::to_string(need) +
+                                 " bytes of scratch; the fixed maximum is " +
+                                 std::to_string((size_t)TT_NOALLOC_SCRATCH_BYTES));
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    unsigned char *base = scratch_address(dev);
+    Ctx c;
+    c.no_alloc = true;
+    c.stream = (hipStream_t)hip_stream;
+    c.tile_cnt = reinterpret_cast<int *>(base);
+    c.arena.adopt(base + kScratchCounterBytes, TT_NOALLOC_SCRATCH_BYTES - kScratchCounterBytes);
+    // the split-K arrival counters and the arena's status words start at zero (a fill
+    // kernel, not a memset node, so the call may also be captured)
+    const int nz = (int)((kScratchCounterBytes + 256) / sizeof(double));
+    fill_value(c, reinterpret_cast<double *>(base), nz, nz, 1, 0.0);
+    DTT xv = view(x), yv = view(y);
+    std::vector<double> s;
+    const int w = round_tt(c, xv, eps, r_max, yv, &s);
+    y->rank = yv.r;
+    if (sigma_out)
+      for (size_t i = 0; i < s.size(); ++i) sigma_out[i] = s[i];
+    return w | jacobi_warning(c);
   });
 }
 

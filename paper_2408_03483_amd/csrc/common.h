@@ -43,6 +43,9 @@ class Arena {
   Arena() = default;
   ~Arena();
   void init(size_t bytes);
+  // use caller-owned device memory (not freed here); its first 256 bytes become the status
+  // words, which the caller must have zeroed
+  void adopt(void *base, size_t bytes);
   void *alloc(size_t bytes);                 // 256-byte aligned
   double *dalloc(size_t n) { return static_cast<double *>(alloc(n * sizeof(double))); }
   int *ialloc(size_t n) { return static_cast<int *>(alloc(n * sizeof(int))); }
@@ -57,6 +60,7 @@ class Arena {
  private:
   char *base_ = nullptr;
   size_t cap_ = 0, top_ = 0, hw_ = 0;
+  bool owned_ = false;
 };
 
 struct Scope {  // releases everything allocated after construction
@@ -106,10 +110,13 @@ struct Ctx {
   KernelTimer timer;
   int *tile_cnt = nullptr;  // zeroed per-tile arrival counters of split-K GEMMs (this stream)
   int *tile_counters();     // allocates them on first use
+  // the context allocates nothing: arena and tile counters are preset on caller memory,
+  // small reads go to pageable host memory, sync() waits on the stream, no GEMM autotuning
+  bool no_alloc = false;
   double *pinned = nullptr; // pinned host staging for small device-to-host reads
   hipEvent_t sync_ev = nullptr;   // recorded and waited for by sync()
   static constexpr size_t kPinnedDoubles = 4096;
-  double *pinned_staging(); // allocates it on first use
+  double *pinned_staging(); // allocates it on first use (nullptr in a no_alloc context)
   void sync();
   int jacobi_capped();      // syncs; Jacobi SVDs of this context stopped at the sweep cap
   int jacobi_seen = 0;      // the count at the last check (jacobi_warning)
@@ -167,6 +174,9 @@ void gemm(Ctx &c, bool transA, int M, int N, int K, double alpha, const double *
           const double *B, int ldb, double beta, double *C, int ldc);
 void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, const double *A,
            int lda, const double *B, int ldb, double beta, double *C, int ldc);
+// arena bytes of the split-K partial tiles one gemm/gemm2 call of these sizes draws (default
+// tile rule; alignment included)
+size_t gemm_arena_bytes(int M, int N, int K);
 // tile-shape autotuner of the GEMMs (process-wide; off by default)
 void gemm_autotune(bool on);
 int gemm_tuned_classes();
@@ -177,6 +187,8 @@ constexpr int QR_MAXM = 96;
 int qr_max_cols();   // largest m the device's LDS allows (<= QR_MAXM)
 void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, double *R,
           int ldr);
+// arena bytes one FP64 tsqr call of these sizes draws (upper bound, alignment included)
+size_t tsqr_arena_bytes(int n, int m);
 
 // jacobi.hip
 // One-sided Jacobi on M (m x m, ld m, m <= 96): writes U*Sigma columns sorted by norm into
@@ -226,6 +238,9 @@ void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, d
 
 // tt_ops.hip (host algorithms)
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
+// upper bound of the arena bytes round_tt draws for an n1 x n2 input of rank R with the
+// context's default sketch settings (FP64), every branch included
+size_t round_arena_bound(int n1, int n2, int R, int rmax);
 // orthonormal basis of range(C) (n x m): QR, SVD of R, keep directions above drop * s_0, or
 // exactly `want` leading directions when want >= 0
 void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out,

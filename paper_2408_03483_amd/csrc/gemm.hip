@@ -322,6 +322,18 @@ TileChoice tuned_tiles(Ctx &c, bool transA, bool transB, int M, int N, int K, do
 
 }  // namespace
 
+size_t gemm_arena_bytes(int M, int N, int K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0;
+  const TileChoice t = default_tiles(N);
+  const int tiles = ((M + BM - 1) / BM) * ((N + t.bn2 - 1) / t.bn2);
+  if (tiles >= 256 || K < t.min_chunk) return 0;
+  int S = std::max(1, std::min((512 + tiles - 1) / tiles, K / t.min_chunk));
+  int kchunk = (K + S - 1) / S;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  S = (K + kchunk - 1) / kchunk;
+  return S == 1 ? 0 : (size_t)S * M * N * sizeof(double) + 256;
+}
+
 void gemm_autotune(bool on) { g_tune = on; }
 
 int gemm_tuned_classes() {
@@ -341,7 +353,7 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
   c.cnt.flops += fl;
   c.cnt.bytes += by;
   TileChoice t = default_tiles(N);
-  if (g_tune && beta == 0.0)
+  if (g_tune && beta == 0.0 && !c.no_alloc)
     t = tuned_tiles(c, transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc);
   TimedLaunch tl(c, "gemm", fl, by);
   run_tiles(c, t, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);

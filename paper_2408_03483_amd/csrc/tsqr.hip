@@ -577,6 +577,26 @@ void dispatch_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, int rs, int
 
 }  // namespace
 
+// the arena draws of run_tsqr<double> for the plan tsqr() makes (each rounded up to the
+// arena's 256-byte alignment)
+size_t tsqr_arena_bytes(int n, int m) {
+  if (m < 1 || n < m) return 0;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t e = sizeof(double);
+  const int bmax = m > NG ? 192 : MAXROWS;
+  const int nleaf = std::max(1, (n + bmax - 1) / bmax);
+  const int arity = std::max(2, std::min(16, MAXROWS / m));
+  std::vector<int> cnt{nleaf};
+  while (cnt.back() > 1) cnt.push_back((cnt.back() + arity - 1) / arity);
+  const size_t mm = (size_t)m * m;
+  size_t b = al((size_t)nleaf * bmax * m * e) + al((size_t)nleaf * m * e) + al(nleaf * mm * e);
+  size_t zmax = 0;
+  for (size_t l = 1; l < cnt.size(); ++l)
+    b += al((size_t)cnt[l] * arity * mm * e) + al((size_t)cnt[l] * m * e) + al(cnt[l] * mm * e);
+  for (int v : cnt) zmax = std::max(zmax, (size_t)v);
+  return b + 2 * al(zmax * mm * e);
+}
+
 int qr_max_cols() { return QR_MAXM; }
 
 void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, double *R,

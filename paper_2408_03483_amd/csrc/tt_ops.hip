@@ -30,8 +30,8 @@ namespace {
 // is staged by the runtime and costs a longer round trip on this path of every rounding
 std::vector<double> to_host(Ctx &c, const double *dev, size_t n) {
   std::vector<double> h(n);
-  if (n && n <= Ctx::kPinnedDoubles) {
-    double *st = c.pinned_staging();
+  double *st = n && n <= Ctx::kPinnedDoubles ? c.pinned_staging() : nullptr;
+  if (st) {
     HIP_CHECK(hipMemcpyAsync(st, dev, n * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     c.sync();
     std::copy(st, st + n, h.begin());
@@ -296,6 +296,56 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   if (sig_out) sig_out->assign(s.begin(), s.begin() + k);
   c.cnt.warnings |= warn;
   return warn;
+}
+
+size_t round_arena_bound(int n1, int n2, int R, int rmax) {
+  auto al = [](size_t d) { return ((d * sizeof(double)) + 255) & ~(size_t)255; };
+  const int qmax = qr_max_cols();
+  const int width = std::min(std::min(QR_MAXM, std::max(2 * rmax, 16)), qmax);
+  const int mn = std::min(n1, n2), nmax = std::max(n1, n2);
+  const size_t N1 = n1, N2 = n2, RR = R;
+  size_t persist = 0, transient = 0;
+  auto tr = [&](size_t b) { transient = std::max(transient, b); };
+  // the last part of every path: U_k, and W of the exact path, plus an SVD's pivoted-QR scratch
+  auto tail = [&](int m) {
+    const size_t mm = (size_t)m * m;
+    persist += 4 * al(mm) + al(m);                 // US, sg, U, W
+    tr(3 * al(mm) + gemm_arena_bytes(m, m, m));
+    tr(gemm_arena_bytes(n1, m, m));
+    tr(gemm_arena_bytes(n2, m, m));
+    tr(gemm_arena_bytes(m, m, m));
+  };
+  // exact path (also the redo of an unconverged range finder)
+  if (R <= qmax && R <= mn) {
+    const size_t m = R;
+    persist += al(N1 * m) + 3 * al(m * m);
+    tr(tsqr_arena_bytes(n1, R));
+    tr(tsqr_arena_bytes(n2, R));
+    tail(R);
+  }
+  if (R <= width && R <= mn) return persist + transient + 64 * 256;
+  if (mn <= width && mn <= qmax) {
+    const size_t m = mn;
+    persist += al(N1 * N2) + 2 * al((N1 + N2) * m) + 2 * al(m * m);
+    tr(gemm_arena_bytes(nmax, mn, R));
+    tr(tsqr_arena_bytes(nmax, mn));
+    tail(mn);
+    return persist + transient + 64 * 256;
+  }
+  const int m = std::min(width, mn);
+  const size_t M = m;
+  // Omega, T, Y, Z, Qa, Qz, Rb, Rtmp; and a fresh (US, sg) per convergence check, at most
+  // one per subspace iteration up to the default limit of 8
+  persist += al(N2 * M) + al(RR * M) + al(N1 * M) + al(N2 * M) + al(N1 * M) + al(N2 * M) +
+             2 * al(M * M) + 10 * (al(M * M) + al(M));
+  tr(gemm_arena_bytes(R, m, n2));
+  tr(gemm_arena_bytes(n1, m, R));
+  tr(gemm_arena_bytes(R, m, n1));
+  tr(gemm_arena_bytes(n2, m, R));
+  tr(tsqr_arena_bytes(n1, m));
+  tr(tsqr_arena_bytes(n2, m));
+  tail(m);
+  return persist + transient + 64 * 256;
 }
 
 void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out,

@@ -61,7 +61,7 @@ class StatsC(ctypes.Structure):
 PRECISIONS = {"f64": 0, "f32": 1}
 
 EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_precision",
-           "tt_round",
+           "tt_round", "tt_round_noalloc",
            "tt_hadamard_round", "tt_reciprocal", "tt_maxvol", "tt_cross", "tt_recon_core",
            "tt_fv_init", "tt_fv_step", "tt_fv_get_state", "tt_fv_get_stats", "tt_fv_destroy",
            "tt_fv_time_kernel", "tt_ens_create", "tt_ens_step", "tt_ens_destroy",
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_set_precision.argtypes = [P, I]
     L.tt_ctx_set_limits.argtypes = [P, I, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
+    L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
     L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
     L.tt_maxvol.argtypes = [P, P, I, I, I, D, I, ctypes.POINTER(I)]
@@ -235,6 +236,17 @@ def tt_round(ctx: Ctx, x: DeviceTT, eps: float, r_max: int, y: DeviceTT):
     sig = (ctypes.c_double * max(r_max, 1))()
     w = _check(_lib.tt_round(ctx.h, ctypes.byref(xc), eps, r_max, ctypes.byref(yc), sig),
                "tt_round")
+    y.rank = yc.rank
+    return w, np.array(sig[:y.rank])
+
+
+def tt_round_noalloc(x: DeviceTT, eps: float, r_max: int, y: DeviceTT, stream=None):
+    """tt_round without a context: temporaries in the library's fixed per-GPU scratch array."""
+    L = load_library()
+    xc, yc = x.c(), y.c()
+    sig = (ctypes.c_double * max(r_max, 1))()
+    w = _check(L.tt_round_noalloc(ctypes.byref(xc), eps, r_max, ctypes.byref(yc), sig,
+                                  _stream_ptr(stream)), "tt_round_noalloc")
     y.rank = yc.rank
     return w, np.array(sig[:y.rank])
 
