@@ -64,6 +64,14 @@ void small_svd(Ctx &c, const double *M, int m, double *US, double *sg, double fl
   else jacobi_svd(c, M, m, US, sg, false, floor_rel);
 }
 
+// Norm floor of a rounding's Jacobi SVD, relative to ||M||_F: columns below it take no
+// rotations, so the kept part can differ from the exact truncated SVD by about the floor.
+// eps / 100 keeps a rounding within its tolerance; the cap at 1e-13 keeps it at round-off
+// level as well, which the rank-capped dam break needs (it amplifies a 5e-10 change of one
+// step's state into 1e-7 over the next step, so an eps / 100 floor at eps = 1e-8 moves its
+// result by 1e-7 from the exact rounding's).
+double jacobi_floor(double eps) { return std::min(1e-2 * eps, 1e-13); }
+
 void zero_tt(Ctx &c, DTT &y) {
   fill_value(c, y.A, y.n1, y.n1, 1, 0.0);
   fill_value(c, y.B, y.n2, y.n2, 1, 0.0);
@@ -203,7 +211,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
         US = c.arena.dalloc((size_t)m * m);
         sg = c.arena.dalloc((size_t)m);
       }
-      jacobi_svd(c, M, m, US, sg, Mt, 1e-2 * eps);
+      jacobi_svd(c, M, m, US, sg, Mt, jacobi_floor(eps));
       s_host = to_host(c, sg, m);
       const std::vector<double> &s = s_host;
       if (s[0] == 0.0) break;
@@ -261,8 +269,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   if (!US) {
     US = c.arena.dalloc((size_t)m * m);
     sg = c.arena.dalloc((size_t)m);
-    if (Mt) jacobi_svd(c, M, m, US, sg, true, 1e-2 * eps);
-    else small_svd(c, M, m, US, sg, 1e-2 * eps);
+    if (Mt) jacobi_svd(c, M, m, US, sg, true, jacobi_floor(eps));
+    else small_svd(c, M, m, US, sg, jacobi_floor(eps));
   }
   // the range finder's last check already brought these singular values to the host
   std::vector<double> s = s_host.empty() ? to_host(c, sg, m) : std::move(s_host);
