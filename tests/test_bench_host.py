@@ -41,11 +41,18 @@ def test_roofline_arithmetic():
 
 
 def test_traffic_follows_the_gemm_source(tmp_path, monkeypatch):
-    txt = open(bench.TRAFFIC_FILE).read()
-    recorded = [l for l in txt.splitlines() if l.startswith("bytes_per_launch: ")]
-    assert len(recorded) == 1
-    assert bench._gemm_traffic() == pytest.approx(float(recorded[0].split(": ", 1)[1]))
+    """The counter traffic is reported only while the GEMM source hashes to the value recorded
+    with the counters (a summary written for the current source is read back; any change of
+    the source makes it null)."""
+    import hashlib
+    sha = hashlib.sha256(open(bench.GEMM_SOURCE, "rb").read()).hexdigest()
+    summary = tmp_path / "traffic.txt"
+    summary.write_text(f"# counters\nbytes_per_launch: 12345678\nsource_sha256: {sha}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(summary))
+    assert bench._gemm_traffic() == pytest.approx(12345678.0)
     other = tmp_path / "gemm.hip"
     other.write_text(open(bench.GEMM_SOURCE).read() + "\n// changed\n")
     monkeypatch.setattr(bench, "GEMM_SOURCE", str(other))
+    assert bench._gemm_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
     assert bench._gemm_traffic() is None
