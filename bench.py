@@ -101,6 +101,9 @@ def main():
                     help="contraction arithmetic of the dambreak2048, ensemble and learned4096 "
                          "workloads")
     ap.add_argument("--learned-n", type=int, default=4096, help="grid of learned4096")
+    ap.add_argument("--qr", default="auto", choices=["auto", "cholesky", "householder"],
+                    help="QR of the rounding factors: Cholesky QR on the matrix cores above 64 "
+                         "columns and Householder TSQR otherwise (auto), or one of the two")
     ap.add_argument("--gemm-autotune", action="store_true",
                     help="ensemble: tune the GEMM tile shapes on a first pass of every member")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -136,7 +139,7 @@ def main():
     st = synth.nonlinear_bumps(seed=0, n=n, rmax=rmax, eps=eps)
     dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
     s = ttfv.tt_fv_init(n, "upwind5", True, True, dev, g=st.g, eps=eps, r_max=rmax,
-                        taylor_terms=K)
+                        taylor_terms=K, qr=args.qr)
 
     # step 1 from the initial state: parity against the oracle (and the CPU baseline)
     torch.cuda.synchronize()
@@ -228,7 +231,7 @@ def dambreak(args):
         dev = [ttfv.DeviceTT.from_factors(f.A * (h_scale if v == 0 else 1.0), f.B, cap=rmax)
                for v, f in enumerate(st.tt)]
         s = ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
-                            recip="cross", precision=precision)
+                            recip="cross", precision=precision, qr=args.qr)
         for _ in range(args.warmup):
             ttfv.tt_fv_step(s, st.dt, 1)
         if timed_kernel:
@@ -293,7 +296,7 @@ def learned(args):
     def make():
         dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
         return ttfv.tt_fv_init(n, "weno5", True, False, dev, g=st.g, eps=eps, r_max=rmax,
-                               recip="cross", precision=args.precision)
+                               recip="cross", precision=args.precision, qr=args.qr)
 
     def timed(s):
         s0 = ttfv.tt_fv_get_stats(s)
@@ -381,7 +384,8 @@ def ensemble(args):
             dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=r) for f in st.tt]
             out.append(ttfv.tt_fv_init(st.n, "upwind5", True, True, dev, g=st.g, eps=1e-10,
                                        r_max=r, taylor_terms=8, workers=workers,
-                                       arena_bytes=1 << 28, precision=args.precision))
+                                       arena_bytes=1 << 28, precision=args.precision,
+                                       qr=args.qr))
         return out
 
     tune = None

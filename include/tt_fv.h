@@ -75,6 +75,17 @@ int  tt_ctx_set_limits(tt_ctx *ctx, int jacobi_max_sweeps, int sketch_max_iters)
 #define TT_PREC_F64 0
 #define TT_PREC_F32 1
 int  tt_ctx_set_precision(tt_ctx *ctx, int precision);
+/* QR of the tall-skinny factors inside roundings and cross orthogonalisations (Section 3.2's
+ * orthogonalisation step).  TT_QR_CHOLESKY: repeated shifted Cholesky QR on the FP64 matrix
+ * cores, at most max_passes passes (default 6, range [2, 8]); a call whose columns are not
+ * orthonormal after them is redone with Householder QR (tt_fv_stats.qr_redos).
+ * TT_QR_HOUSEHOLDER: Householder TSQR always.  TT_QR_AUTO (default): Cholesky QR for more
+ * than 64 columns, Householder QR otherwise (the faster of the two at each width when eight
+ * chains share the GPU).  All give the same factors up to round-off. */
+#define TT_QR_AUTO        0
+#define TT_QR_CHOLESKY    1
+#define TT_QR_HOUSEHOLDER 2
+int  tt_ctx_set_qr(tt_ctx *ctx, int method, int max_passes);
 
 /* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
  * eps and rank <= r_max.  x may have any rank <= x->cap; y->cap must be >= r_max.
@@ -172,6 +183,7 @@ typedef struct {
   int workers;        /* own worker streams: 0 = default (8), k = k, -1 = none (the solver
                          then steps only inside an ensemble, tt_ens_step)                 */
   int precision;      /* TT_PREC_F64 or TT_PREC_F32 (contractions; see tt_ctx_set_precision) */
+  int qr;             /* TT_QR_AUTO, TT_QR_CHOLESKY or TT_QR_HOUSEHOLDER (tt_ctx_set_qr)    */
 } tt_fv_params;
 
 typedef struct {
@@ -195,6 +207,8 @@ typedef struct {
   long long sketch_fallbacks; /* randomized roundings redone exactly (limit reached)       */
   long long sketch_unconverged; /* randomized roundings kept unconverged (TT_WSKETCH)      */
   long long jacobi_capped;    /* Jacobi SVDs stopped at the sweep cap (TT_WJACOBI)         */
+  long long qr_redos;         /* roundings or orthogonalisations redone with Householder QR
+                                 because a Cholesky QR ended without orthonormal columns   */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build

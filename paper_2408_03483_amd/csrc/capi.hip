@@ -364,6 +364,18 @@ int tt_ctx_set_precision(tt_ctx *ctx, int precision) {
   });
 }
 
+int tt_ctx_set_qr(tt_ctx *ctx, int method, int max_passes) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    TT_REQUIRE(method == TT_QR_AUTO || method == TT_QR_CHOLESKY || method == TT_QR_HOUSEHOLDER,
+               "unknown QR method");
+    TT_REQUIRE(max_passes >= 2 && max_passes <= 8, "max_passes out of [2, 8]");
+    ctx->c.qr = method;
+    ctx->c.cqr_passes = max_passes;
+    return 0;
+  });
+}
+
 int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
              double *sigma_out) {
   return guarded([&]() {

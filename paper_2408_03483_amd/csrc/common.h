@@ -82,6 +82,8 @@ struct Counters {
   long long roundings = 0, crosses = 0, extra_power_iters = 0;
   long long sketch_fallbacks = 0;    // range finders unconverged at the limit, redone exactly
   long long sketch_unconverged = 0;  // range finders unconverged at the limit, kept (warning)
+  long long qr_redos = 0;            // roundings and orthogonalisations redone with Householder
+                                     // QR after a Cholesky QR ended without orthonormal columns
   double flops = 0, bytes = 0;
   int warnings = 0;
 };
@@ -104,6 +106,9 @@ struct Ctx {
   int sketch_width = 0;     // 0: automatic
   int power_iters = 1;      // subspace iterations always run; more are added on demand
   bool fp32 = false;        // core contractions (GEMM, face-splitting products, TSQR) in FP32
+  int qr = TT_QR_AUTO;      // QR method of tsqr() (TT_QR_*)
+  int cqr_passes = 6;       // pass limit of the Cholesky QR
+  bool householder = false; // force Householder TSQR (the redo after a failed Cholesky QR)
   int jacobi_max_sweeps = 40;     // sweep cap of the one-sided Jacobi SVD
   int sketch_max_iters = 8;       // subspace iterations after which a range finder stops
   Counters cnt;
@@ -189,6 +194,12 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
           int ldr);
 // arena bytes one FP64 tsqr call of these sizes draws (upper bound, alignment included)
 size_t tsqr_arena_bytes(int n, int m);
+// cholqr.hip: the same outputs by repeated Cholesky QR on the matrix cores (FP64); tsqr()
+// uses it unless the context asks for Householder.  When it ends without orthonormal
+// columns, Q and R are NaN.
+void cholqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, double *R,
+            int ldr);
+size_t cholqr_arena_bytes(int n, int m, bool with_q);
 
 // jacobi.hip
 // One-sided Jacobi on M (m x m, ld m, m <= 96): writes U*Sigma columns sorted by norm into

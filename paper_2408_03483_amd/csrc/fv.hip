@@ -91,9 +91,11 @@ struct Solver {
   // every task sets its worker's arithmetic to this solver's (an ensemble shares workers)
   void run_tasks(std::vector<Pool::Task> tasks) {
     const bool f32 = p.precision == TT_PREC_F32;
+    const int qr = p.qr;
     for (auto &t : tasks)
-      t = [f32, f = std::move(t)](Ctx &w) {
+      t = [f32, qr, f = std::move(t)](Ctx &w) {
         w.fp32 = f32;
+        w.qr = qr;
         f(w);
       };
     exec->run(std::move(tasks));
@@ -361,7 +363,10 @@ struct Solver {
       double err = 0;
       int terms = 0;
       Ctx *a = (exec == pool.get() && aux[chain]) ? aux[chain].get() : nullptr;
-      if (a) a->fp32 = w.fp32;
+      if (a) {
+        a->fp32 = w.fp32;
+        a->qr = w.qr;
+      }
       reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms, a);
       std::lock_guard<std::mutex> lk(mu);
       last_err = err;
@@ -578,6 +583,8 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   TT_REQUIRE(p->workers >= -1 && p->workers <= 16, "tt_fv_init: workers must be in [-1, 16]");
   TT_REQUIRE(p->precision == TT_PREC_F64 || p->precision == TT_PREC_F32,
              "tt_fv_init: unknown precision");
+  TT_REQUIRE(p->qr == TT_QR_AUTO || p->qr == TT_QR_CHOLESKY || p->qr == TT_QR_HOUSEHOLDER,
+             "tt_fv_init: unknown QR method");
   TT_REQUIRE(p->recip == 0 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
@@ -592,6 +599,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->p = *p;
     s->c.stream = (hipStream_t)stream;
     s->c.fp32 = p->precision == TT_PREC_F32;
+    s->c.qr = p->qr;
     const size_t ab = arena_bytes ? arena_bytes : ((size_t)4 << 30);
     s->c.arena.init(ab);
     int dev = 0;
@@ -741,6 +749,7 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   for (const Counters *wc : cs) {
     const Counters &w = *wc;
     t.sketch_fallbacks += w.sketch_fallbacks;
+    t.qr_redos += w.qr_redos;
     t.sketch_unconverged += w.sketch_unconverged;
     t.roundings += w.roundings;
     t.crosses += w.crosses;
@@ -761,6 +770,7 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->sketch_fallbacks = t.sketch_fallbacks;
   o->sketch_unconverged = t.sketch_unconverged;
   o->jacobi_capped = jcap;
+  o->qr_redos = t.qr_redos;
   o->flops = t.flops;
   o->bytes = t.bytes;
   KernelTimer *tm[8];

@@ -594,7 +594,7 @@ size_t tsqr_arena_bytes(int n, int m) {
   for (size_t l = 1; l < cnt.size(); ++l)
     b += al((size_t)cnt[l] * arity * mm * e) + al((size_t)cnt[l] * m * e) + al(cnt[l] * mm * e);
   for (int v : cnt) zmax = std::max(zmax, (size_t)v);
-  return b + 2 * al(zmax * mm * e);
+  return std::max(b + 2 * al(zmax * mm * e), cholqr_arena_bytes(n, m, false));
 }
 
 int qr_max_cols() { return QR_MAXM; }
@@ -603,6 +603,11 @@ void tsqr(Ctx &c, const double *Y, int n, int m, int ldy, double *Q, int ldq, do
           int ldr) {
   TT_REQUIRE(m >= 1 && n >= m, "tsqr: need n >= m >= 1");
   TT_REQUIRE(m <= QR_MAXM, "tsqr: more than 96 columns");
+  const bool chol = c.qr == TT_QR_CHOLESKY || (c.qr == TT_QR_AUTO && m > 64);
+  if (chol && !c.householder) {
+    cholqr(c, Y, n, m, ldy, Q, ldq, R, ldr);
+    return;
+  }
   const int d = lds_doubles();
   Plan pl;
   pl.n = n;

@@ -72,6 +72,12 @@ void small_svd(Ctx &c, const double *M, int m, double *US, double *sg, double fl
 // result by 1e-7 from the exact rounding's).
 double jacobi_floor(double eps) { return std::min(1e-2 * eps, 1e-13); }
 
+void require_finite(const std::vector<double> &s, const char *what) {
+  for (double v : s)
+    if (!std::isfinite(v))
+      throw Error(TT_ENONFINITE, std::string(what) + ": non-finite singular value");
+}
+
 void zero_tt(Ctx &c, DTT &y) {
   fill_value(c, y.A, y.n1, y.n1, 1, 0.0);
   fill_value(c, y.B, y.n2, y.n2, 1, 0.0);
@@ -97,7 +103,48 @@ int kept_directions(const std::vector<double> &s, double drop, int want) {
 
 }  // namespace
 
+namespace {
+
+// Runs f with Cholesky QR; when that leaves non-finite singular values (a Cholesky QR that
+// ended without orthonormal columns sets its Q and R to NaN), runs f again with Householder
+// QR, which reports a truly non-finite input as before.
+template <typename F>
+auto with_qr_fallback(Ctx &c, F &&f) -> decltype(f()) {
+  if (c.householder) return f();
+  try {
+    return f();
+  } catch (const Error &e) {
+    if (e.code != TT_ENONFINITE) throw;
+  }
+  c.cnt.qr_redos++;
+  c.householder = true;
+  try {
+    auto r = f();
+    c.householder = false;
+    return r;
+  } catch (...) {
+    c.householder = false;
+    throw;
+  }
+}
+
+int round_impl(Ctx &c, const DTT &x, double eps, int rmax, DTT &y,
+               std::vector<double> *sig_out);
+
+}  // namespace
+
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig_out) {
+  const long long r0 = c.cnt.roundings;
+  return with_qr_fallback(c, [&]() {
+    c.cnt.roundings = r0;     // a redone rounding counts once
+    return round_impl(c, x, eps, rmax, y, sig_out);
+  });
+}
+
+namespace {
+
+int round_impl(Ctx &c, const DTT &x, double eps, int rmax, DTT &y,
+               std::vector<double> *sig_out) {
   TT_REQUIRE(x.r >= 1 && rmax >= 1, "round: empty input or rmax < 1");
   TT_REQUIRE(x.n1 == y.n1 && x.n2 == y.n2, "round: shape mismatch");
   c.cnt.roundings++;
@@ -274,8 +321,7 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   }
   // the range finder's last check already brought these singular values to the host
   std::vector<double> s = s_host.empty() ? to_host(c, sg, m) : std::move(s_host);
-  for (double v : s)
-    if (!std::isfinite(v)) throw Error(TT_ENONFINITE, "round: non-finite singular value");
+  require_finite(s, "round");
   int warn = sketch_warn;
   if (s[0] == 0.0) {
     zero_tt(c, y);
@@ -305,6 +351,8 @@ int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<dou
   c.cnt.warnings |= warn;
   return warn;
 }
+
+}  // namespace
 
 size_t round_arena_bound(int n1, int n2, int R, int rmax) {
   auto al = [](size_t d) { return ((d * sizeof(double)) + 255) & ~(size_t)255; };
@@ -356,8 +404,23 @@ size_t round_arena_bound(int n1, int n2, int R, int rmax) {
   return persist + transient + 64 * 256;
 }
 
+namespace {
+void orth_impl(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q,
+               int *k_out, int want);
+}
+
 void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q, int *k_out,
           int want) {
+  with_qr_fallback(c, [&]() {
+    orth_impl(c, C, n, m, ldc, drop, Q, k_out, want);
+    return 0;
+  });
+}
+
+namespace {
+
+void orth_impl(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q,
+               int *k_out, int want) {
   Scope sc(c.arena);
   TT_REQUIRE(m >= 1, "orth: no columns");
   if (m <= n) {
@@ -367,6 +430,7 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
     double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc(m);
     small_svd(c, r, m, US, sg, 1e-2 * drop);
     std::vector<double> s = to_host(c, sg, m);
+    require_finite(s, "orth");
     const int k = kept_directions(s, drop, want);
     *k_out = k;
     if (k == 0) return;
@@ -386,11 +450,14 @@ void orth(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q
   double *US = c.arena.dalloc((size_t)n * n), *sg = c.arena.dalloc(n);
   small_svd(c, Rt, n, US, sg, 1e-2 * drop);
   std::vector<double> s = to_host(c, sg, n);
+  require_finite(s, "orth");
   const int k = kept_directions(s, drop, want);
   *k_out = k;
   if (k == 0) return;
   normalise_cols(c, US, sg, n, k, Q);
 }
+
+}  // namespace
 
 namespace {
 

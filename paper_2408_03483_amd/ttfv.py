@@ -42,7 +42,7 @@ class ParamsC(ctypes.Structure):
                 ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
                 ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("qr", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):
@@ -55,10 +55,12 @@ class StatsC(ctypes.Structure):
                 ("timed_bytes", ctypes.c_double), ("cross_sweeps_run", ctypes.c_longlong),
                 ("learned_crosses", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_longlong),
                 ("max_learned_err", ctypes.c_double), ("sketch_fallbacks", ctypes.c_longlong),
-                ("sketch_unconverged", ctypes.c_longlong), ("jacobi_capped", ctypes.c_longlong)]
+                ("sketch_unconverged", ctypes.c_longlong), ("jacobi_capped", ctypes.c_longlong),
+                ("qr_redos", ctypes.c_longlong)]
 
 
 PRECISIONS = {"f64": 0, "f32": 1}
+QR_METHODS = {"auto": 0, "cholesky": 1, "householder": 2}
 
 EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_precision",
            "tt_round", "tt_round_noalloc",
@@ -69,7 +71,7 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_pm_forward", "tt_pm_grad", "tt_pm_train", "tt_pm_dataset", "tt_pm_features",
            "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error",
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
-           "tt_ctx_set_limits"]
+           "tt_ctx_set_limits", "tt_ctx_set_qr"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3}
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_set_sketch.argtypes = [P, I, I]
     L.tt_ctx_set_precision.argtypes = [P, I]
     L.tt_ctx_set_limits.argtypes = [P, I, I]
+    L.tt_ctx_set_qr.argtypes = [P, I, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
@@ -220,6 +223,10 @@ def tt_ctx_create(arena_bytes: int = 1 << 30, stream=None) -> Ctx:
 
 def tt_ctx_set_sketch(ctx: Ctx, width: int, power_iters: int) -> None:
     _check(_lib.tt_ctx_set_sketch(ctx.h, width, power_iters), "tt_ctx_set_sketch")
+
+
+def tt_ctx_set_qr(ctx: Ctx, method: str, max_passes: int = 6) -> None:
+    _check(_lib.tt_ctx_set_qr(ctx.h, QR_METHODS[method], max_passes), "tt_ctx_set_qr")
 
 
 def tt_ctx_set_limits(ctx: Ctx, jacobi_max_sweeps: int, sketch_max_iters: int) -> None:
@@ -350,12 +357,13 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                g: float = 9.81, H0: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
-               arena_bytes: int = 4 << 30, precision: str = "f64") -> Solver:
+               arena_bytes: int = 4 << 30, precision: str = "f64",
+               qr: str = "auto") -> Solver:
     L = load_library()
     _torch()
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
-                workers, PRECISIONS[precision])
+                workers, PRECISIONS[precision], QR_METHODS[qr])
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -388,7 +396,8 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "timed_bytes": st.timed_bytes, "cross_sweeps_run": st.cross_sweeps_run,
             "learned_crosses": st.learned_crosses, "learned_fallbacks": st.learned_fallbacks,
             "max_learned_err": st.max_learned_err, "sketch_fallbacks": st.sketch_fallbacks,
-            "sketch_unconverged": st.sketch_unconverged, "jacobi_capped": st.jacobi_capped}
+            "sketch_unconverged": st.sketch_unconverged, "jacobi_capped": st.jacobi_capped,
+            "qr_redos": st.qr_redos}
 
 
 def tt_fv_time_kernel(s: Solver, name: Optional[str]) -> None:
