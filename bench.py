@@ -45,19 +45,25 @@ METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA 
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector
 PEAK_FP64_MFMA_TFLOPS = 78.6        # MI355X FP64 matrix (dense)
 PEAK_FP32_MFMA_TFLOPS = 157.3       # MI355X FP32 matrix (dense)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic_nonlinear_bumps_1024.txt")
+PEAK_HBM_GBS = 8000.0
+# counter traffic summaries per timed family, each tied to the source of its kernels
+TRAFFIC = {
+    "gemm": ("gemm_traffic_nonlinear_bumps_1024.txt", "gemm.hip"),
+    "tsqr_qr": ("householder_qr_traffic_nonlinear_bumps_1024.txt", "tsqr.hip"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", TRAFFIC["gemm"][0])
 GEMM_SOURCE = os.path.join(ROOT, "paper_2408_03483_amd", "csrc", "gemm.hip")
 
 
-def _gemm_traffic():
-    """Calibrated HBM bytes per GEMM launch from the committed counter summary, or None when
-    the GEMM source changed since the counters were taken."""
+def _traffic(summary, source):
+    """Calibrated HBM bytes per launch from a committed counter summary, or None when the
+    kernel source changed since the counters were taken (or there is no summary)."""
     import hashlib
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(summary).read()
         vals = dict(l.split(": ", 1) for l in txt.splitlines()
                     if l.startswith(("bytes_per_launch: ", "source_sha256: ")))
-        sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+        sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
         if vals.get("source_sha256", "").strip() != sha:
             return None
         return float(vals["bytes_per_launch"])
@@ -65,23 +71,41 @@ def _gemm_traffic():
         return None
 
 
-def _roof(kernel, stats, elapsed, fp32=False, traffic=None):
+def _gemm_traffic():
+    return _traffic(TRAFFIC_FILE, GEMM_SOURCE)
+
+
+def _family_traffic(kernel):
+    if kernel == "gemm":
+        return _gemm_traffic()
+    if kernel not in TRAFFIC:
+        return None
+    name, src = TRAFFIC[kernel]
+    return _traffic(os.path.join(ROOT, "profiles", name),
+                    os.path.join(ROOT, "paper_2408_03483_amd", "csrc", src))
+
+
+def _roof(kernel, stats, elapsed, fp32=False, traffic=None, every=128):
     if not stats["timed_launches"] or stats["timed_ms"] <= 0:
         return None
     avg_ms = stats["timed_ms"] / stats["timed_launches"]
     fl = stats["timed_flops"] / stats["timed_launches"]
+    by = stats["timed_bytes"] / stats["timed_launches"]
     achieved = fl / (avg_ms * 1e-3) / 1e12
-    if kernel == "gemm":
+    if kernel in ("gemm", "cholqr", "cholqr_slab"):
         bound, peak = "mfma", PEAK_FP32_MFMA_TFLOPS if fp32 else PEAK_FP64_MFMA_TFLOPS
     else:
         bound, peak = "alu", PEAK_FP64_VECTOR_TFLOPS
+    gbs = by / (avg_ms * 1e-3) / 1e9
     return {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "hbm_achieved_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
             "avg_launch_us": avg_ms * 1e3, "launches_timed": stats["timed_launches"],
-            "timed_sample": "1 launch in 32 of the family",
-            "alg_flops_per_launch": fl,
-            "alg_bytes_per_launch": stats["timed_bytes"] / stats["timed_launches"]}
-PEAK_HBM_GBS = 8000.0
+            "timed_sample": f"1 launch in {every} of the family, kernel start to end (launch "
+                             "events)",
+            "alg_flops_per_launch": fl, "alg_bytes_per_launch": by}
+
+
 PARITY_GATE = 1e-9
 
 
@@ -92,8 +116,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle step")
-    ap.add_argument("--timed-kernel", default="gemm",
-                    help="kernel family timed with HIP events ('' = none)")
+    ap.add_argument("--timed-kernel", default="tsqr_qr",
+                    help="kernel family timed with HIP launch events ('' = none); default: "
+                         "the Householder factorisations, the largest share of kernel time")
+    ap.add_argument("--gemm-steps", type=int, default=2,
+                    help="steps after the timed region on which the GEMM family is timed")
+    ap.add_argument("--time-every", type=int, default=128,
+                    help="one launch in this many of the timed family carries launch events")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="worker streams of the solver (0: 8; 1: every kernel on one stream)")
     ap.add_argument("--workload", default="bumps1024",
                     choices=["bumps1024", "dambreak2048", "ensemble", "learned4096"])
     ap.add_argument("--members", type=int, default=64)
@@ -139,7 +170,7 @@ def main():
     st = synth.nonlinear_bumps(seed=0, n=n, rmax=rmax, eps=eps)
     dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
     s = ttfv.tt_fv_init(n, "upwind5", True, True, dev, g=st.g, eps=eps, r_max=rmax,
-                        taylor_terms=K, qr=args.qr)
+                        taylor_terms=K, qr=args.qr, workers=args.workers)
 
     # step 1 from the initial state: parity against the oracle (and the CPU baseline)
     torch.cuda.synchronize()
@@ -176,7 +207,7 @@ def main():
     for _ in range(max(args.warmup - 1, 0)):
         ttfv.tt_fv_step(s, st.dt, 1)
     if args.timed_kernel:
-        ttfv.tt_fv_time_kernel(s, args.timed_kernel)
+        ttfv.tt_fv_time_kernel(s, args.timed_kernel, args.time_every)
     stats0 = ttfv.tt_fv_get_stats(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -184,12 +215,23 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stats = ttfv.tt_fv_get_stats(s)
+    value = n * n * args.steps / elapsed
+    # the rounding GEMMs, the next family by kernel time: timed over two more steps after the
+    # timed region (same workload, not part of `value`)
+    roof_gemm = None
+    if args.timed_kernel and args.timed_kernel != "gemm" and args.gemm_steps > 0:
+        ttfv.tt_fv_time_kernel(s, "gemm", args.time_every)
+        ttfv.tt_fv_step(s, st.dt, args.gemm_steps)
+        torch.cuda.synchronize()
+        roof_gemm = _roof("gemm", ttfv.tt_fv_get_stats(s), 0.0, traffic=_family_traffic("gemm"),
+                          every=args.time_every)
+        if roof_gemm:
+            roof_gemm["measured_on"] = f"{args.gemm_steps} steps after the timed region"
     if args.timed_kernel:
         ttfv.tt_fv_time_kernel(s, None)
-    value = n * n * args.steps / elapsed
 
-    roof = _roof(args.timed_kernel, stats, elapsed,
-                 traffic=_gemm_traffic() if args.timed_kernel == "gemm" else None)
+    roof = _roof(args.timed_kernel, stats, elapsed, traffic=_family_traffic(args.timed_kernel),
+                 every=args.time_every)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -197,8 +239,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"nonlinear_bumps_{n}", "grid": f"{n}x{n}", "scheme": "upwind5",
                    "bc": "periodic", "r_max": rmax, "eps": eps, "taylor_terms": K, "seed": 0,
-                   "cfl": 0.4, "dt": st.dt},
-        "roofline": roof, "cpu_baseline": cpu, "parity": parity,
+                   "cfl": 0.4, "dt": st.dt, "qr": args.qr,
+                   "worker_streams": args.workers if args.workers > 0 else 8},
+        "roofline": roof, "roofline_gemm": roof_gemm, "cpu_baseline": cpu, "parity": parity,
         "ranks": stats["ranks"],
         "roundings_per_step": (stats["roundings"] - stats0["roundings"]) / args.steps,
         "crosses_per_step": (stats["crosses"] - stats0["crosses"]) / args.steps,
@@ -235,7 +278,7 @@ def dambreak(args):
         for _ in range(args.warmup):
             ttfv.tt_fv_step(s, st.dt, 1)
         if timed_kernel:
-            ttfv.tt_fv_time_kernel(s, timed_kernel)
+            ttfv.tt_fv_time_kernel(s, timed_kernel, args.time_every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ttfv.tt_fv_step(s, st.dt, args.steps)
@@ -273,7 +316,8 @@ def dambreak(args):
                       "bc": "walls", "r_max": rmax, "eps": eps, "reciprocal": "cross",
                       "cross_sweeps": 3, "seed": 0,
                       "contractions": "fp32 matrix cores" if args.precision == "f32" else "fp64"},
-           "roofline": _roof(args.timed_kernel, stats, elapsed, fp32=args.precision == "f32"),
+           "roofline": _roof(args.timed_kernel, stats, elapsed, fp32=args.precision == "f32",
+                             every=args.time_every),
            "cpu_baseline": None, "ranks": stats["ranks"], "crosses": stats["crosses"]}
     out.update(extra)
     print(json.dumps(out), flush=True)

@@ -180,8 +180,9 @@ typedef struct {
   int cross_sweeps;   /* maxvol cross sweeps                                               */
   int cross_kick;     /* fresh columns per non-final sweep                                 */
   int recip;          /* 1/h: 0 = Taylor series (Algorithm 1), 1 = cross of 1/x            */
-  int workers;        /* own worker streams: 0 = default (8), k = k, -1 = none (the solver
-                         then steps only inside an ensemble, tt_ens_step)                 */
+  int workers;        /* own worker streams: 0 = default (8), k = k (1: every kernel of the
+                         step on one stream), -1 = none (the solver then steps only inside
+                         an ensemble, tt_ens_step)                                         */
   int precision;      /* TT_PREC_F64 or TT_PREC_F32 (contractions; see tt_ctx_set_precision) */
   int qr;             /* TT_QR_AUTO, TT_QR_CHOLESKY or TT_QR_HOUSEHOLDER (tt_ctx_set_qr)    */
 } tt_fv_params;
@@ -220,10 +221,14 @@ int  tt_fv_step(tt_fv *s, double dt, int nsteps);
 /* Copy the state into caller buffers (cap >= rank). */
 int  tt_fv_get_state(tt_fv *s, tt_matrix q[3]);
 int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
-/* Time one launch in 32 of one kernel family with HIP events on the stream it runs on (name:
- * "jacobi", "tsqr_leaf_qr", "tsqr_node_qr", "tsqr_node_apply", "tsqr_leaf_apply", "gemm",
- * "maxvol_greedy"; NULL or "" switches timing off) and reset the timed_* statistics. */
-int  tt_fv_time_kernel(tt_fv *s, const char *name);
+/* Time one launch in `every` of a kernel family: the sampled launches carry a start and a stop
+ * event on the stream they run on, which HIP sets to the kernel's own start and end.  The
+ * family is every kernel whose timing name starts with `name`: "jacobi", "gemm", the
+ * Householder factorisations "tsqr_qr_leaf" and "tsqr_qr_node" ("tsqr_qr" for both), their
+ * Q formation "tsqr_wy_node" and "tsqr_wy_leaf" ("tsqr" for all four), "cholqr_slab" and
+ * "cholqr_factor" ("cholqr" for both); NULL or "" switches timing off.  The timed_*
+ * statistics are reset. */
+int  tt_fv_time_kernel(tt_fv *s, const char *name, int every);
 void tt_fv_destroy(tt_fv *s);
 
 /* ---------------------------------------------------------------------------------------

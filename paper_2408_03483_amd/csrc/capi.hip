@@ -3,6 +3,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <memory>
 
@@ -14,7 +15,7 @@ void solver_step(Solver *s, double dt, int nsteps);
 void solver_get_state(Solver *s, tt_matrix q[3]);
 void solver_stats(Solver *s, tt_fv_stats *o);
 void solver_destroy(Solver *s);
-void solver_time_kernel(Solver *s, const char *name);
+void solver_time_kernel(Solver *s, const char *name, int every);
 void solver_set_pivots(Solver *s, int mode, PivotModel *pm);
 void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,
                           const int *I, int nI);
@@ -78,18 +79,20 @@ void Ctx::sync() {
   if (!sync_ev) HIP_CHECK(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
   HIP_CHECK(hipEventRecord(sync_ev, stream));
   HIP_CHECK(hipEventSynchronize(sync_ev));
-  for (size_t i = 0; i < timer.pending.size(); ++i) {
+  // every sampled launch on this stream has ended: resolve its event pair (a pair HIP cannot
+  // time is dropped from the sample) and recycle the events
+  std::vector<KernelTimer::Rec> done;
+  done.swap(timer.pending);
+  for (const auto &r : done) {
     float ms = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&ms, timer.pending[i].first, timer.pending[i].second));
-    timer.ms += ms;
-    timer.flops += timer.pending_flops[i];
-    timer.bytes += timer.pending_bytes[i];
-    timer.launches++;
-    timer.spare.push_back(timer.pending[i]);
+    if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      timer.ms += ms;
+      timer.flops += r.flops;
+      timer.bytes += r.bytes;
+      timer.launches++;
+    }
+    timer.spare.push_back({r.start, r.stop});
   }
-  timer.pending.clear();
-  timer.pending_flops.clear();
-  timer.pending_bytes.clear();
 }
 
 int Ctx::jacobi_capped() {
@@ -134,33 +137,37 @@ Ctx::~Ctx() {
     (void)hipEventDestroy(e.second);
   }
   for (auto &e : timer.pending) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.start);
+    (void)hipEventDestroy(e.stop);
   }
 }
 
 TimedLaunch::TimedLaunch(Ctx &ctx, const char *name, double flops, double bytes)
-    : c(ctx), on(!ctx.timer.name.empty() && ctx.timer.name == name) {
-  if (!on) return;
-  on = (c.timer.seen++ % c.timer.every) == 0;   // a sample keeps the events' cost small
-  if (!on) return;
+    : c(ctx), on(false) {
+  const std::string &fam = c.timer.name;
+  if (fam.empty() || std::strncmp(name, fam.c_str(), fam.size()) != 0) return;
+  if ((c.timer.seen++ % c.timer.every) != 0) return;   // a sample keeps the cost small
   if (c.timer.spare.empty()) {
-    hipEvent_t a, b;
+    hipEvent_t a = nullptr, b = nullptr;
     HIP_CHECK(hipEventCreate(&a));
-    HIP_CHECK(hipEventCreate(&b));
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      throw Error(TT_EHIP, "hipEventCreate failed");
+    }
     c.timer.spare.push_back({a, b});
   }
-  ev = c.timer.spare.back();
+  const auto ev = c.timer.spare.back();
   c.timer.spare.pop_back();
-  HIP_CHECK(hipEventRecord(ev.first, c.stream));
-  c.timer.pending_flops.push_back(flops);
-  c.timer.pending_bytes.push_back(bytes);
+  c.timer.pending.push_back({ev.first, ev.second, flops, bytes});
+  c.ev_start = ev.first;
+  c.ev_stop = ev.second;
+  on = true;
 }
 
 TimedLaunch::~TimedLaunch() {
   if (!on) return;
-  (void)hipEventRecord(ev.second, c.stream);
-  c.timer.pending.push_back(ev);
+  c.ev_start = nullptr;
+  c.ev_stop = nullptr;
 }
 
 DTT view(const tt_matrix *m) {
@@ -554,10 +561,11 @@ int tt_fv_get_state(tt_fv *s, tt_matrix q[3]) {
   });
 }
 
-int tt_fv_time_kernel(tt_fv *s, const char *name) {
+int tt_fv_time_kernel(tt_fv *s, const char *name, int every) {
   return guarded([&]() {
     TT_REQUIRE(s, "null solver");
-    solver_time_kernel(s->s, name ? name : "");
+    TT_REQUIRE(every >= 1, "tt_fv_time_kernel: every < 1");
+    solver_time_kernel(s->s, name ? name : "", every);
     return 0;
   });
 }

@@ -436,15 +436,14 @@ void launch_passes(Ctx &c, const double *Y, int n, int m, int ldy, double *Qb, i
       TimedLaunch tl(c, "cholqr_slab",
                      (p > 0 ? 2.0 : 0.0) * n * (double)MP * MP + (double)n * MP * (MP + 16),
                      8.0 * ((p > 0 ? 2.0 : 1.0) * n * (double)m + (double)nb * NTILE * 256));
-      hipLaunchKernelGGL(k_cqr_slab<MP>, dim3(nb), dim3(CQ_NT), lds_s, c.stream, n, m, p, rpb,
-                         src, lsrc, Qb, ldq, W, part, flags);
+      TT_LAUNCH(c, k_cqr_slab<MP>, dim3(nb), dim3(CQ_NT), lds_s, n, m, p, rpb, src, lsrc, Qb,
+                ldq, (const double *)W, part, (const int *)flags);
     }
     {
       TimedLaunch tl(c, "cholqr_factor", (double)MP * MP * MP,
                      8.0 * ((double)nb * NTILE * 256 + 3.0 * MP * MP));
-      hipLaunchKernelGGL(k_cqr_factor<MP>, dim3(1), dim3(CQ_NT), lds_f, c.stream, n, m, p,
-                         passes - 1, nb,
-                         W, Racc, part, flags, fails, Qb, ldq, R, ldr);
+      TT_LAUNCH(c, k_cqr_factor<MP>, dim3(1), dim3(CQ_NT), lds_f, n, m, p, passes - 1, nb, W,
+                Racc, (const double *)part, flags, fails, Qb, ldq, R, ldr);
     }
   }
 }

@@ -1,5 +1,6 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -88,14 +89,19 @@ struct Counters {
   int warnings = 0;
 };
 
-// Optional event timing of one kernel family: launches of the family named in `name` are
-// bracketed by HIP events on their own stream; pairs are resolved at the next sync.
+// Optional event timing of one kernel family: one launch in `every` of the kernels whose
+// timing name starts with `name` is launched with a start and a stop event, which HIP sets to
+// that kernel's own start and end on its stream; pairs are resolved at the next sync.
 struct KernelTimer {
   std::string name;                         // empty: off
   int every = 32;                           // one launch in `every` of the family is timed
   long long seen = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, spare;
-  std::vector<double> pending_flops, pending_bytes;
+  struct Rec {
+    hipEvent_t start, stop;
+    double flops, bytes;
+  };
+  std::vector<Rec> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;
   double ms = 0, flops = 0, bytes = 0;
   long long launches = 0;
 };
@@ -120,6 +126,8 @@ struct Ctx {
   bool no_alloc = false;
   double *pinned = nullptr; // pinned host staging for small device-to-host reads
   hipEvent_t sync_ev = nullptr;   // recorded and waited for by sync()
+  // events of the sampled launch in progress (set by TimedLaunch, used by TT_LAUNCH)
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   static constexpr size_t kPinnedDoubles = 4096;
   double *pinned_staging(); // allocates it on first use (nullptr in a no_alloc context)
   void sync();
@@ -128,14 +136,20 @@ struct Ctx {
   ~Ctx();
 };
 
-// RAII bracket around one launch: records events when `name` is the timed family
+// RAII bracket around one launch (made with TT_LAUNCH): when the launch is a sampled one of
+// the timed family, the context's launch events are set for it
 struct TimedLaunch {
   Ctx &c;
   bool on;
-  std::pair<hipEvent_t, hipEvent_t> ev;
   TimedLaunch(Ctx &ctx, const char *name, double flops, double bytes);
   ~TimedLaunch();
 };
+
+// kernel launch on the context's stream carrying the events of a sampled TimedLaunch (none
+// otherwise): HIP records the kernel's own start and end in them
+#define TT_LAUNCH(c, kernel, grid, block, shmem, ...)                                        \
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, (c).stream, (c).ev_start, (c).ev_stop, 0, \
+                        __VA_ARGS__)
 
 struct Solver;
 

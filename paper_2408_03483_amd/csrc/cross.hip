@@ -344,7 +344,6 @@ void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int 
     double *cval = c.arena.dalloc(2 * (size_t)nblk);
     int *cidx = c.arena.ialloc(2 * (size_t)nblk);
     double *cvec = c.arena.dalloc(2 * (size_t)nblk * r);
-    TimedLaunch tl(c, "maxvol_greedy", 4.0 * n * r * r, 8.0 * 3.0 * n * r);
     hipLaunchKernelGGL(k_greedy_init, dim3(nblk), dim3(GB), 0, c.stream, R, n, r, n, cval, cidx,
                        cvec);
     auto step = r <= 32 ? k_greedy_step<32> : r <= 64 ? k_greedy_step<64> : k_greedy_step<96>;

@@ -608,7 +608,9 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     if (nw > 0) {
       s->pool = std::make_unique<Pool>(nw, ab, dev);
       s->exec = s->pool.get();
-      if (p->nonlinear && p->recip == 0)
+      // helper streams for the Taylor partial sums; a single worker keeps every kernel of
+      // the step on one stream
+      if (nw > 1 && p->nonlinear && p->recip == 0)
         for (auto &a : s->aux) {
           a = std::make_unique<Ctx>();
           HIP_CHECK(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));
@@ -773,10 +775,11 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->qr_redos = t.qr_redos;
   o->flops = t.flops;
   o->bytes = t.bytes;
-  KernelTimer *tm[8];
-  int nt = 0;
-  tm[nt++] = &s->c.timer;
-  for (int i = 0; i < npool && nt < 8; ++i) tm[nt++] = &s->pool->ctx(i).timer;
+  std::vector<KernelTimer *> tm{&s->c.timer};
+  for (int i = 0; i < npool; ++i) tm.push_back(&s->pool->ctx(i).timer);
+  for (auto &a : s->aux)
+    if (a) tm.push_back(&a->timer);
+  const int nt = (int)tm.size();
   o->timed_ms = 0;
   o->timed_launches = 0;
   o->timed_flops = 0;
@@ -789,12 +792,15 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   }
 }
 
-void solver_time_kernel(Solver *s, const char *name) {
+void solver_time_kernel(Solver *s, const char *name, int every) {
   std::vector<Ctx *> cs{&s->c};
   for (int i = 0; s->pool && i < s->pool->size(); ++i) cs.push_back(&s->pool->ctx(i));
+  for (auto &a : s->aux)
+    if (a) cs.push_back(a.get());
   for (Ctx *c : cs) {
     c->sync();
     c->timer.name = name;
+    c->timer.every = every;
     c->timer.ms = c->timer.flops = c->timer.bytes = 0;
     c->timer.launches = 0;
     c->timer.seen = 0;

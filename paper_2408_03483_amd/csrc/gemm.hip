@@ -192,9 +192,8 @@ __global__ __launch_bounds__(NT) void k_gemm_mfma(int M, int N, int K, int kchun
 template <typename T, int BN2, bool TA, bool TB>
 void launch(Ctx &c, dim3 grid, int M, int N, int K, int kchunk, double alpha, const double *A,
             int lda, const double *B, int ldb, double beta, double *C, int ldc, double *part) {
-  hipLaunchKernelGGL((k_gemm_mfma<T, BN2, TA, TB>), grid, dim3(NT), 0, c.stream, M, N, K, kchunk,
-                     alpha, A, lda, B, ldb, beta, C, ldc, part,
-                     part ? c.tile_counters() : nullptr);
+  TT_LAUNCH(c, (k_gemm_mfma<T, BN2, TA, TB>), grid, dim3(NT), 0, M, N, K, kchunk, alpha, A,
+            lda, B, ldb, beta, C, ldc, part, part ? c.tile_counters() : (int *)nullptr);
 }
 
 template <typename T, int BN2>

@@ -393,9 +393,8 @@ void jacobi_svd(Ctx &c, const double *M, int m, double *US, double *sig, bool tr
   auto launch = [&](auto kern, int lp) {
     const int nthreads = std::max(64, ((mm / 2) * lp + 63) / 64 * 64);
     set_lds(kern, lds);
-    hipLaunchKernelGGL(kern, dim3(1), dim3(nthreads), lds, c.stream, M, m, US, sig,
-                       c.jacobi_max_sweeps, trans ? 1 : 0, floor_rel * floor_rel,
-                       accumulate ? 1 : 0, c.arena.status());
+    TT_LAUNCH(c, kern, dim3(1), dim3(nthreads), lds, M, m, US, sig, c.jacobi_max_sweeps,
+              trans ? 1 : 0, floor_rel * floor_rel, accumulate ? 1 : 0, c.arena.status());
   };
   if (m <= 32) launch(k_jacobi<16, 2>, 16);
   else if (m <= 64) launch(k_jacobi<16, 4>, 16);

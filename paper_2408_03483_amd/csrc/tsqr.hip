@@ -515,10 +515,10 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
   T *Rleaf = talloc((size_t)nleaf * m * m);
   const double mm3 = (double)m * m * m;
   {
-    TimedLaunch tl(c, "tsqr_leaf_qr", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
+    TimedLaunch tl(c, "tsqr_qr_leaf", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
                    8.0 * (2.0 * n * m + (double)nleaf * m * m));
-    hipLaunchKernelGGL((k_leaf_qr<T, RS, CS>), dim3(nleaf), dim3(NT), 0, c.stream, Y, n, m, ldy,
-                       nleaf, bmax, Vleaf, tleaf, Rleaf, nleaf == 1 ? R : nullptr, ldr);
+    TT_LAUNCH(c, (k_leaf_qr<T, RS, CS>), dim3(nleaf), dim3(NT), 0, Y, n, m, ldy, nleaf, bmax,
+              Vleaf, tleaf, Rleaf, nleaf == 1 ? R : (double *)nullptr, ldr);
   }
   const int levels = (int)pl.cnt.size() - 1;
   std::vector<T *> Vl(levels + 1, nullptr), tl(levels + 1, nullptr), Rl(levels + 1, nullptr);
@@ -529,11 +529,11 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
     tl[l] = talloc((size_t)cout * m);
     Rl[l] = talloc((size_t)cout * m * m);
     const double rows_l = (double)pl.cnt[l - 1] * m;
-    TimedLaunch tq(c, "tsqr_node_qr", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * cout,
+    TimedLaunch tq(c, "tsqr_qr_node", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * cout,
                    8.0 * (2.0 * rows_l * m + (double)cout * m * m));
-    hipLaunchKernelGGL((k_node_qr<T, RS, CS>), dim3(cout), dim3(NT), 0, c.stream, Rl[l - 1],
-                       pl.cnt[l - 1], m, arity, Vl[l], tl[l], Rl[l], l == levels ? R : nullptr,
-                       ldr);
+    TT_LAUNCH(c, (k_node_qr<T, RS, CS>), dim3(cout), dim3(NT), 0, (const T *)Rl[l - 1],
+              pl.cnt[l - 1], m, arity, Vl[l], tl[l], Rl[l], l == levels ? R : (double *)nullptr,
+              ldr);
   }
   if (!Q) return;                      // R only: no top-down pass
   size_t zmax = 0;
@@ -545,19 +545,19 @@ void run_tsqr(Ctx &c, const double *Y, int ldy, const Plan &pl, double *Q, int l
   for (int l = levels; l >= 1; --l) {
     set_lds(k_apply_wy<T, false>, wy_lds);
     const double rows_l = (double)pl.cnt[l - 1] * m;
-    TimedLaunch ta(c, "tsqr_node_apply", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * pl.cnt[l],
+    TimedLaunch ta(c, "tsqr_wy_node", 2.0 * rows_l * m * m - 2.0 / 3.0 * mm3 * pl.cnt[l],
                    8.0 * (2.0 * rows_l * m + (double)pl.cnt[l] * m * m));
-    hipLaunchKernelGGL((k_apply_wy<T, false>), dim3(pl.cnt[l]), dim3(NTW), wy_lds, c.stream,
-                       Vl[l], tl[l], pl.cnt[l - 1], m, arity, 0, 0, 0, Zin, Z[which],
-                       (double *)nullptr, 0);
+    TT_LAUNCH(c, (k_apply_wy<T, false>), dim3(pl.cnt[l]), dim3(NTW), wy_lds,
+              (const T *)Vl[l], (const T *)tl[l], pl.cnt[l - 1], m, arity, 0, 0, 0, Zin, Z[which],
+              (double *)nullptr, 0);
     Zin = Z[which];
     which ^= 1;
   }
   set_lds(k_apply_wy<T, true>, wy_lds);
-  TimedLaunch tl2(c, "tsqr_leaf_apply", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
+  TimedLaunch tl2(c, "tsqr_wy_leaf", 2.0 * n * m * m - 2.0 / 3.0 * mm3 * nleaf,
                   8.0 * (2.0 * n * m + (double)nleaf * m * m));
-  hipLaunchKernelGGL((k_apply_wy<T, true>), dim3(nleaf), dim3(NTW), wy_lds, c.stream, Vleaf,
-                     tleaf, 0, m, 0, n, nleaf, bmax, Zin, (T *)nullptr, Q, ldq);
+  TT_LAUNCH(c, (k_apply_wy<T, true>), dim3(nleaf), dim3(NTW), wy_lds, (const T *)Vleaf,
+            (const T *)tleaf, 0, m, 0, n, nleaf, bmax, Zin, (T *)nullptr, Q, ldq);
 }
 
 template <typename T>

@@ -109,7 +109,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_fv_step.argtypes = [P, D, I]
     L.tt_fv_get_state.argtypes = [P, pM]
     L.tt_fv_get_stats.argtypes = [P, ctypes.POINTER(StatsC)]
-    L.tt_fv_time_kernel.argtypes = [P, ctypes.c_char_p]
+    L.tt_fv_time_kernel.argtypes = [P, ctypes.c_char_p, I]
     L.tt_fv_destroy.argtypes = [P]
     L.tt_fv_destroy.restype = None
     L.tt_ens_create.argtypes = [ctypes.POINTER(P), I, S]
@@ -400,8 +400,8 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "qr_redos": st.qr_redos}
 
 
-def tt_fv_time_kernel(s: Solver, name: Optional[str]) -> None:
-    _check(_lib.tt_fv_time_kernel(s.h, (name or "").encode()), "tt_fv_time_kernel")
+def tt_fv_time_kernel(s: Solver, name: Optional[str], every: int = 32) -> None:
+    _check(_lib.tt_fv_time_kernel(s.h, (name or "").encode(), every), "tt_fv_time_kernel")
 
 
 def tt_fv_destroy(s: Solver) -> None:
