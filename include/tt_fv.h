@@ -237,17 +237,19 @@ void tt_fv_destroy(tt_fv *s);
  * (ReLU; BF16 weights and activations, FP32 accumulation) scores every column index of a
  * cross from 16 features of the cross's starting TT (second core B0) and the call site's
  * previous pivots; the previous pivots together with the top K = min(r_max, |J_prev| + kick)
- * indices (at most 96 columns) are the columns of one refinement sweep.  The result is checked on 16 seeded validation columns outside J: if
- * |f - Y|_F / |Y|_F exceeds max(1e-6, the same error of the site's last plain cross), the
- * plain maxvol cross runs instead.  The model is trained with Adam on (features, final
- * maxvol pivots) pairs logged from plain crosses.  Weights: flat FP32 vector of
- * TT_PM_NPARAM entries, W1 (16 x 256, row-major) | b1 | W2 (256 x 256) | b2 | w3 | b3. */
+ * indices (at most 96 columns) are the columns of one refinement sweep, accepted or replaced
+ * by the plain maxvol cross by the rule of tt_fv_set_pivot_acceptance.  The model is trained
+ * with Adam on (features, final maxvol pivots) pairs logged from plain crosses.  Weights:
+ * flat FP32 vector of TT_PM_NPARAM entries, W1 (16 x 256, row-major) | b1 | W2 (256 x 256) |
+ * b2 | w3 | b3. */
 #define TT_PM_NPARAM 70401
 #define TT_PIV_MAXVOL  0    /* plain alternating maxvol sweeps                              */
 #define TT_PIV_LOG     1    /* plain sweeps; log (features, pivots) into the model          */
 #define TT_PIV_LEARNED 2    /* proposer + one sweep, plain sweeps as the fallback           */
 #define TT_PIV_REPLAY  3    /* each cross takes the (J, I) given by tt_fv_replay_pivots for
                                its (step, site) and forms only the skeleton (no model)       */
+#define TT_PIV_KICKS   4    /* ablation of TT_PIV_LEARNED without a model: the one sweep starts
+                               from the previous pivots and fresh SplitMix64 columns          */
 typedef struct tt_pm tt_pm;
 /* max_rows: capacity of the training log (rows of 16 features); seed: weight init. */
 int  tt_pm_create(tt_pm **out, size_t max_rows, unsigned long long seed);
@@ -273,9 +275,16 @@ int  tt_pm_features(tt_ctx *ctx, const double *B0, int n2, int r, int ldb, const
                     int nJ, float *X_dev);
 /* Indices of the k largest scores (ties: smaller index first), ascending, into idx_dev. */
 int  tt_pm_topk(tt_ctx *ctx, const float *s_dev, int n, int k, int *idx_dev);
-/* Pivot mode of a solver's crosses (TT_PIV_*); pm must outlive its use (NULL with modes 0
- * and 3). */
+/* Pivot mode of a solver's crosses (TT_PIV_*); pm must outlive its use (NULL with modes 0,
+ * 3 and 4). */
 int  tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm);
+/* Acceptance of a one-sweep cross from proposed columns (TT_PIV_LEARNED, TT_PIV_KICKS): its
+ * error on 16 seeded validation columns outside J, |f - Y|_F / |Y|_F, must be <= abs_tol;
+ * with rel_slack >= 0 a cross is also accepted when that error is <= (1 + rel_slack) times
+ * the same error of the site's last plain cross (equal accuracy), and proposals are tried
+ * only at sites that have one.  Otherwise the plain maxvol cross runs.  Default: abs_tol
+ * 1e-6, rel_slack -1 (the absolute rule alone). */
+int  tt_fv_set_pivot_acceptance(tt_fv *s, double abs_tol, double rel_slack);
 
 /* Pivot replay (Section 3.3: a skeleton is fixed by its column and row sets).  At the rank
  * cap several pivot sets of a cross are equally valid and maxvol's choice among them can flip

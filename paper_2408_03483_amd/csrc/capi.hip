@@ -17,6 +17,7 @@ void solver_stats(Solver *s, tt_fv_stats *o);
 void solver_destroy(Solver *s);
 void solver_time_kernel(Solver *s, const char *name, int every);
 void solver_set_pivots(Solver *s, int mode, PivotModel *pm);
+void solver_set_acceptance(Solver *s, double abs_tol, double rel_slack);
 void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,
                           const int *I, int nI);
 int solver_get_pivots(Solver *s, int site, int *J, int capJ, int *nJ, int *I, int capI,
@@ -748,11 +749,21 @@ int tt_fv_set_pivots(tt_fv *s, int mode, tt_pm *pm) {
   return guarded([&]() {
     TT_REQUIRE(s, "null solver");
     TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_LOG || mode == TT_PIV_LEARNED ||
-                   mode == TT_PIV_REPLAY,
+                   mode == TT_PIV_REPLAY || mode == TT_PIV_KICKS,
                "tt_fv_set_pivots: unknown mode");
-    TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_REPLAY || pm,
+    TT_REQUIRE(mode == TT_PIV_MAXVOL || mode == TT_PIV_REPLAY || mode == TT_PIV_KICKS || pm,
                "tt_fv_set_pivots: mode needs a model");
     solver_set_pivots(s->s, mode, pm ? pm->m.get() : nullptr);
+    return 0;
+  });
+}
+
+int tt_fv_set_pivot_acceptance(tt_fv *s, double abs_tol, double rel_slack) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null solver");
+    TT_REQUIRE(abs_tol >= 0.0 && std::isfinite(abs_tol) && std::isfinite(rel_slack),
+               "tt_fv_set_pivot_acceptance: bad tolerance");
+    solver_set_acceptance(s->s, abs_tol, rel_slack);
     return 0;
   });
 }

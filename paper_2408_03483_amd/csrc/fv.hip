@@ -60,6 +60,10 @@ struct Solver {
   std::unique_ptr<Ctx> aux[4];
   PivotModel *pm = nullptr;
   int piv_mode = TT_PIV_MAXVOL;
+  // acceptance of a one-sweep cross from proposed columns (TT_PIV_LEARNED, TT_PIV_KICKS):
+  // validation error <= acc_abs, or with acc_rel >= 0 also <= (1 + acc_rel) times the error of
+  // the site's last plain cross
+  double acc_abs = 1e-6, acc_rel = -1.0;
   std::map<int, double> ref_err;
   // pivot replay (TT_PIV_REPLAY): (step, site) -> (J, I) given by the caller; and the last
   // sweep's (J, I) of every site's latest cross, for the caller to read back
@@ -246,39 +250,47 @@ struct Solver {
     std::vector<int> J;
     Scope sc(w.arena);
     bf16_t *Xb = nullptr;
-    if (pm && piv_mode != TT_PIV_MAXVOL && have_prev && (int)J0.size() <= 128) {
+    if (pm && (piv_mode == TT_PIV_LOG || piv_mode == TT_PIV_LEARNED) && have_prev &&
+        (int)J0.size() <= 128) {
       int *Jd = w.arena.ialloc(J0.size());
       HIP_CHECK(hipMemcpyAsync(Jd, J0.data(), J0.size() * sizeof(int), hipMemcpyHostToDevice,
                                w.stream));
       Xb = static_cast<bf16_t *>(w.arena.alloc((size_t)n2 * PM_F * sizeof(bf16_t)));
       pivot_features(w, y0.B, n2, y0.r, y0.n2, Jd, (int)J0.size(), nullptr, Xb);
     }
-    if (piv_mode == TT_PIV_LEARNED && Xb && ref >= 0.0) {
-      std::vector<int> Jp;
-      {
+    const bool propose = (piv_mode == TT_PIV_LEARNED && Xb) ||
+                         (piv_mode == TT_PIV_KICKS && have_prev && (int)J0.size() <= 128);
+    if (propose && (acc_rel < 0.0 || ref >= 0.0)) {
+      // the previous pivots, then up to K = min(r_max, |J_prev| + kick) columns they miss,
+      // within the factorization width: the proposer's best scores, or (ablation) fresh
+      // SplitMix64 columns
+      const int K = std::min(std::min(p.r_max, (int)J0.size() + p.cross_kick), n2);
+      std::vector<int> top;
+      if (piv_mode == TT_PIV_LEARNED) {
         Scope s2(w.arena);
         float *sc_dev = static_cast<float *>(w.arena.alloc((size_t)n2 * sizeof(float)));
         pm->forward(w, Xb, n2, sc_dev, nullptr, nullptr);
-        const int K = std::min(std::min(p.r_max, (int)J0.size() + p.cross_kick), n2);
         int *Kd = w.arena.ialloc(K);
         topk_indices(w, sc_dev, n2, K, Kd);
-        std::vector<int> top(K);
+        top.resize(K);
         HIP_CHECK(hipMemcpyAsync(top.data(), Kd, K * sizeof(int), hipMemcpyDeviceToHost,
                                  w.stream));
         w.sync();
-        // the previous pivots, then the proposals they miss, up to the factorization width
-        Jp = J0;
-        for (int j : top) {
-          if ((int)Jp.size() >= qr_max_cols()) break;
-          if (std::find(J0.begin(), J0.end(), j) == J0.end()) Jp.push_back(j);
-        }
+      } else {
+        top = kick_indices(J0, n2, std::max(0, K - (int)J0.size()), key ^ 0x4B1C5ull);
+      }
+      std::vector<int> Jp = J0;
+      for (int j : top) {
+        if ((int)Jp.size() >= qr_max_cols()) break;
+        if (std::find(Jp.begin(), Jp.end(), j) == Jp.end()) Jp.push_back(j);
       }
       std::vector<int> Il;
       cross_tt(w, fs, n1, n2, Jp, p.eps, p.r_max, 1, 0, key, out, &J, &Il);
       const double err = validate(w, fs, n1, n2, out, J, key);
+      const double bar = acc_rel >= 0.0 ? std::max(acc_abs, (1.0 + acc_rel) * ref) : acc_abs;
       std::lock_guard<std::mutex> lk(mu);
       sweeps_run += 1;
-      if (err <= std::max(1e-6, ref)) {
+      if (err <= bar) {
         learned++;
         max_learned_err = std::max(max_learned_err, err);
         piv[site] = J;
@@ -811,6 +823,12 @@ void solver_set_pivots(Solver *s, int mode, PivotModel *pm) {
   std::lock_guard<std::mutex> lk(s->mu);
   s->piv_mode = mode;
   s->pm = pm;
+}
+
+void solver_set_acceptance(Solver *s, double abs_tol, double rel_slack) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->acc_abs = abs_tol;
+  s->acc_rel = rel_slack;
 }
 
 void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,

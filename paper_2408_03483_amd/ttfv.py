@@ -71,10 +71,10 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_pm_forward", "tt_pm_grad", "tt_pm_train", "tt_pm_dataset", "tt_pm_features",
            "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error",
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
-           "tt_ctx_set_limits", "tt_ctx_set_qr"]
+           "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance"]
 
 PM_NPARAM = 70401
-PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3}
+PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
 
 _lib = None
 
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_pm_features.argtypes = [P, P, I, I, I, P, I, P]
     L.tt_pm_topk.argtypes = [P, P, I, I, P]
     L.tt_fv_set_pivots.argtypes = [P, I, P]
+    L.tt_fv_set_pivot_acceptance.argtypes = [P, D, D]
     L.tt_gemm_autotune.argtypes = [I, ctypes.POINTER(I)]
     pI = ctypes.POINTER(I)
     L.tt_fv_replay_pivots.argtypes = [P, ctypes.c_longlong, I, pI, I, pI, I]
@@ -550,6 +551,11 @@ def tt_pm_topk(ctx: Ctx, s, k: int):
 def tt_fv_set_pivots(s: Solver, mode: str, model: Optional[PivotModel] = None) -> None:
     _check(_lib.tt_fv_set_pivots(s.h, PIVOTS[mode], model.h if model is not None else None),
            "tt_fv_set_pivots")
+
+
+def tt_fv_set_pivot_acceptance(s: Solver, abs_tol: float = 1e-6, rel_slack: float = -1.0) -> None:
+    _check(_lib.tt_fv_set_pivot_acceptance(s.h, abs_tol, rel_slack),
+           "tt_fv_set_pivot_acceptance")
 
 
 def tt_fv_replay_pivots(s: Solver, step: int, site: int, J: Sequence[int],

@@ -153,65 +153,84 @@ def _dam_break_solver(lib, st, rmax, eps, precision="f64"):
                           recip="cross", arena_bytes=1 << 30, precision=precision)
 
 
-def test_training_reduces_loss_and_learned_steps_stay_valid(lib):
-    """Log (features, maxvol pivots) from plain steps of a 48^2 dam break (pivots are logged
-    from the second step on), train, then take two steps with proposed pivots.  The proposer
-    must be used (accepted or rejected by the validation check), and after the four steps
-    the result must stay within three times the distance of four plain GPU steps (or of the
-    oracle's, whichever is larger) to the full-grid scheme, plus 20 eps: one refinement
-    sweep from proposed columns is a coarser cross than three maxvol sweeps (measured 1.5x
-    to 2.1x here).  The plain steps must be as close as the oracle's (within twice its
-    distance plus 20 eps)."""
-    from oracle import fv_grid
-    _say("learned pivots on the 48^2 dam break")
+def _log_training_pivots(lib, m):
+    """Plain maxvol pivots of two stand-ins for the configurations the proposer learns from: a
+    48^2 dam break (WENO5 crosses, walls, cap 24, tol 1e-8) and a 64^2 bumps step (Upwind5,
+    its LLF wave-speed crosses); pivots are logged from each run's second step on."""
     st = synth.dam_break(seed=0, n=48, rmax=24, eps=1e-8, width=0.05)
-    m = lib.PivotModel(1 << 20, 3)
     s = _dam_break_solver(lib, st, 24, 1e-8)
     lib.tt_fv_set_pivots(s, "log", m)
-    lib.tt_fv_step(s, st.dt, 2)
+    lib.tt_fv_step(s, st.dt, 3)
+    s.close()
+    sb = synth.nonlinear_bumps(seed=7, n=64, rmax=16, eps=1e-10)
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=16) for f in sb.tt]
+    s = lib.tt_fv_init(64, "upwind5", True, True, dev, g=sb.g, eps=1e-10, r_max=16,
+                       taylor_terms=8, arena_bytes=1 << 28)
+    lib.tt_fv_set_pivots(s, "log", m)
+    lib.tt_fv_step(s, sb.dt, 3)
+    s.close()
+
+
+def _proposal_run(lib, st, mode, model, nsteps=3):
+    s = _dam_break_solver(lib, st, 24, 1e-8)
+    lib.tt_fv_set_pivots(s, mode, model)
+    lib.tt_fv_set_pivot_acceptance(s, 1e-6, 0.1)
+    lib.tt_fv_step(s, st.dt, nsteps)
+    stats = lib.tt_fv_get_stats(s)
+    Q = lib.tt_fv_get_state(s)
+    s.close()
+    tried = stats["learned_crosses"] + stats["learned_fallbacks"]
+    return Q, stats, stats["learned_crosses"] / max(tried, 1)
+
+
+def test_proposer_trained_elsewhere_against_its_ablations(lib):
+    """Train on pivots logged from other runs (a dam break and a bumps step), then take three
+    steps of a different dam break (56^2, another centre) with one-sweep crosses from
+    (a) the trained proposer, (b) the same network untrained, (c) previous pivots plus random
+    columns; a proposed cross is kept only at equal accuracy: validation error within 1.1
+    times that of the site's last plain cross (or below 1e-6).  Reports acceptance and
+    sweeps per cross for each; every run stays as close to the full-grid scheme as three plain
+    steps (within twice their distance plus 20 eps: the kept crosses are as accurate as the
+    plain ones they replace)."""
+    from oracle import fv_grid
+    m = lib.PivotModel(1 << 21, 3)
+    _log_training_pivots(lib, m)
     rows, pos = m.dataset()
     assert rows > 0 and 0 < pos < rows
     l0 = m.train(epochs=1, batch=4096, lr=1e-3)
     l1 = m.train(epochs=40, batch=4096, lr=1e-3)
-    _say(f"  {rows} rows, {pos} pivots, loss {l0:.4f} -> {l1:.4f}")
+    _say(f"  trained on {rows} rows ({pos} pivots) from other runs: loss {l0:.4f} -> {l1:.4f}")
     assert l1 < l0
-    lib.tt_fv_set_pivots(s, "learned", m)
-    lib.tt_fv_step(s, st.dt, 2)
-    stats = lib.tt_fv_get_stats(s)
-    Qg = lib.tt_fv_get_state(s)
-    s.close()
+    st = synth.dam_break(seed=1, n=56, rmax=24, eps=1e-8, width=0.05)
+    untrained = lib.PivotModel(1 << 10, 11)
+    runs = {"trained": _proposal_run(lib, st, "learned", m),
+            "untrained": _proposal_run(lib, st, "learned", untrained),
+            "kicks": _proposal_run(lib, st, "kicks", None)}
     m.close()
-    _say(f"  learned {stats['learned_crosses']} fallbacks {stats['learned_fallbacks']} "
-         f"sweeps {stats['cross_sweeps_run']} max err {stats['max_learned_err']:.2e}")
-    assert stats["learned_crosses"] + stats["learned_fallbacks"] > 0
+    untrained.close()
     sp = _dam_break_solver(lib, st, 24, 1e-8)
-    lib.tt_fv_step(sp, st.dt, 2)
-    s2 = lib.tt_fv_get_stats(sp)
-    lib.tt_fv_step(sp, st.dt, 2)
-    s4 = lib.tt_fv_get_stats(sp)
+    lib.tt_fv_step(sp, st.dt, 3)
     Qp = lib.tt_fv_get_state(sp)
+    splain = lib.tt_fv_get_stats(sp)
     sp.close()
-    # what the proposer gains: maxvol sweeps per cross over the two learned steps, against
-    # the plain method's three
-    plain = (s4["cross_sweeps_run"] - s2["cross_sweeps_run"]) / (s4["crosses"] - s2["crosses"])
-    learned = (stats["cross_sweeps_run"] - s2["cross_sweeps_run"]) / (
-        stats["crosses"] - s2["crosses"])
-    _say(f"  sweeps per cross: plain {plain:.2f} learned {learned:.2f}")
-    assert plain == 3.0 and learned < plain
     U = [f.full() for f in st.tt]
     gs = fv_grid.GridSolver(st.n, "weno5", True, False, g=st.g)
-    for _ in range(4):
+    for _ in range(3):
         U = gs.step(U, st.dt)
-    ts = otf.TTSolver(st.n, "weno5", True, False, g=st.g, eps=1e-8, rmax=24, recip="cross")
-    Qo = ts.run([ott.TT(f.A, f.B) for f in st.tt], st.dt, 4)
     scale = np.linalg.norm(U[0])
-    for c in range(3):
-        e_o = np.linalg.norm(Qo[c].full() - U[c]) / scale
-        e_p = np.linalg.norm(Qp[c].full() - U[c]) / scale
-        e_g = np.linalg.norm(Qg[c].full() - U[c]) / scale
-        _say(f"  var {c}: oracle {e_o:.3e} plain gpu {e_p:.3e} learned {e_g:.3e} (vs grid)")
-        assert e_p <= 2.0 * e_o + 20 * 1e-8
-        assert e_g <= 3.0 * max(e_p, e_o) + 20 * 1e-8
+    e_p = [np.linalg.norm(Qp[c].full() - U[c]) / scale for c in range(3)]
+    _say(f"  plain: sweeps per cross {splain['cross_sweeps_run'] / splain['crosses']:.2f}, "
+         f"distance to the grid {e_p}")
+    for name, (Q, stt, acc) in runs.items():
+        e = [np.linalg.norm(Q[c].full() - U[c]) / scale for c in range(3)]
+        spc = stt["cross_sweeps_run"] / stt["crosses"]
+        _say(f"  {name}: accepted {stt['learned_crosses']} of "
+             f"{stt['learned_crosses'] + stt['learned_fallbacks']} ({100 * acc:.0f}%), sweeps per "
+             f"cross {spc:.2f}, largest accepted validation error {stt['max_learned_err']:.2e}, "
+             f"distance to the grid {e}")
+        assert stt["learned_crosses"] + stt["learned_fallbacks"] > 0
+        for c in range(3):
+            assert e[c] <= 2.0 * e_p[c] + 20 * 1e-8
 
 
 def test_learned_pivots_full_rank_unique(lib):
