@@ -185,6 +185,8 @@ typedef struct {
                          an ensemble, tt_ens_step)                                         */
   int precision;      /* TT_PREC_F64 or TT_PREC_F32 (contractions; see tt_ctx_set_precision) */
   int qr;             /* TT_QR_AUTO, TT_QR_CHOLESKY or TT_QR_HOUSEHOLDER (tt_ctx_set_qr)    */
+  double cross_drop;  /* a cross drops fiber directions below this fraction of the largest
+                         singular value; 0 = 1e-13, or 1e-6 with FP32 contractions          */
 } tt_fv_params;
 
 typedef struct {

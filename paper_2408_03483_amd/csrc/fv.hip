@@ -96,10 +96,12 @@ struct Solver {
   void run_tasks(std::vector<Pool::Task> tasks) {
     const bool f32 = p.precision == TT_PREC_F32;
     const int qr = p.qr;
+    const double drop = p.cross_drop;
     for (auto &t : tasks)
-      t = [f32, qr, f = std::move(t)](Ctx &w) {
+      t = [f32, qr, drop, f = std::move(t)](Ctx &w) {
         w.fp32 = f32;
         w.qr = qr;
+        w.cross_drop = drop;
         f(w);
       };
     exec->run(std::move(tasks));
@@ -184,7 +186,7 @@ struct Solver {
     const int m = std::min(y0.r, y0.n2);
     double *Qb = w.arena.dalloc((size_t)y0.n2 * std::max(m, 1));
     int k = 0;
-    orth(w, y0.B, y0.n2, y0.r, y0.n2, w.fp32 ? 1e-6 : 1e-13, Qb, &k);
+    orth(w, y0.B, y0.n2, y0.r, y0.n2, w.drop(), Qb, &k);
     if (k == 0) return {0};
     return maxvol_host(w, Qb, y0.n2, k, y0.n2, 1.05, 100);
   }
@@ -597,6 +599,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
              "tt_fv_init: unknown precision");
   TT_REQUIRE(p->qr == TT_QR_AUTO || p->qr == TT_QR_CHOLESKY || p->qr == TT_QR_HOUSEHOLDER,
              "tt_fv_init: unknown QR method");
+  TT_REQUIRE(p->cross_drop >= 0.0 && p->cross_drop < 1.0, "tt_fv_init: cross_drop out of [0, 1)");
   TT_REQUIRE(p->recip == 0 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
@@ -612,6 +615,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->c.stream = (hipStream_t)stream;
     s->c.fp32 = p->precision == TT_PREC_F32;
     s->c.qr = p->qr;
+    s->c.cross_drop = p->cross_drop;
     const size_t ab = arena_bytes ? arena_bytes : ((size_t)4 << 30);
     s->c.arena.init(ab);
     int dev = 0;

@@ -737,8 +737,8 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
   std::vector<int> I;
   int rc = 0;
   // fiber directions below this fraction of the largest are dropped: round-off level of
-  // the QR's arithmetic
-  const double drop = c.fp32 ? 1e-6 : 1e-13;
+  // the QR's arithmetic unless the caller sets another
+  const double drop = c.drop();
   auto zero_result = [&]() {
     zero_tt(c, y);
     if (J_out) *J_out = J;

@@ -42,7 +42,7 @@ class ParamsC(ctypes.Structure):
                 ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
                 ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int),
-                ("precision", ctypes.c_int), ("qr", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double)]
 
 
 class StatsC(ctypes.Structure):
@@ -359,12 +359,12 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
                arena_bytes: int = 4 << 30, precision: str = "f64",
-               qr: str = "auto") -> Solver:
+               qr: str = "auto", cross_drop: float = 0.0) -> Solver:
     L = load_library()
     _torch()
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
-                workers, PRECISIONS[precision], QR_METHODS[qr])
+                workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
