@@ -28,8 +28,11 @@ One evaluation of L(Q) (Sections 4.1-4.3):
   L_c = -dF_c/dx - dG_c/dy (+ Coriolis source), a concatenation of cores.
 
 SSP-RK3 (Section 4.4): Q1 = F(Qn), Q2 = round(3/4 Qn + 1/4 F(Q1)),
-Qn+1 = round(1/3 Qn + 2/3 F(Q2)), with F(q) = round(q + dt L(q)).  One tolerance eps and
-one rank cap rmax serve every rounding.
+Qn+1 = round(1/3 Qn + 2/3 F(Q2)), with F(q) = round(q + dt L(q)).  One rank cap rmax serves
+every rounding.  Tolerances: either one fixed eps for every rounding, or the rule of Section 4.4
+(eps_rule="paper"): at the start of each step, eq. eps-tt-formula gives the tolerance of every
+rounding inside L and of the crosses, and eq. modified-eps-tt-formula one tolerance per variable
+for that variable's forward-Euler and SSP-RK3 combination roundings (see paper_tolerances).
 """
 from __future__ import annotations
 
@@ -43,6 +46,31 @@ from .tt import TT, add, cross, hadamard, initial_columns, norm, reciprocal, sca
     tt_round, zero_tt
 
 NG = 3
+
+
+def paper_tolerances(norms, n: int, order: int, c_eps: float, volume: float = 1.0):
+    """Rounding tolerances of one time step (Section 4.4), from the state's Frobenius norms.
+
+    base = C_eps * V^(1/2) * dx^(p - 1/2), with p the order of the scheme and V the volume of
+    the domain (the unit square here, dx = 1/n).
+      eq. eps-tt-formula:          eps = base / max_q ||q||, for every rounding except the
+                                   time-stepping ones;
+      eq. modified-eps-tt-formula: eps_q = min(1e-3, base / ||q||), for the forward-Euler
+                                   rounding F(q) and the two SSP-RK3 combinations of q.
+    ||q|| is read as the L2 norm of the cell-average field on the domain, the Frobenius norm of
+    the n x n array times the cell side dx (cells are square); a state whose norms are all zero
+    takes eps = 1e-3, the clip of the modified formula (readings in the design notes).
+
+    Returns (eps, [eps_q for the three variables]).
+    """
+    dx = 1.0 / n
+    base = c_eps * math.sqrt(volume) * dx ** (order - 0.5)
+    l2 = [dx * float(v) for v in norms]
+    top = max(l2)
+    eps = base / top if top > 0.0 else 1e-3
+    eps_q = [min(1e-3, base / v) if v > 0.0 else 1e-3 for v in l2]
+    return eps, eps_q
+
 
 # reflection signs in "normal-first" variable order (q0, q_normal, q_tangential)
 SIGN_NORMAL = (1.0, -1.0, 1.0)
@@ -140,10 +168,16 @@ class TTSolver:
                  g: float = 9.81, H: float = 1.0, f: float = 0.0, eps: float = 1e-10,
                  rmax: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                  cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor",
-                 replay=None, cross_drop: float = 1e-13):
+                 replay=None, cross_drop: float = 1e-13, eps_rule: str = "fixed",
+                 c_eps: float = 1.0):
         self.n, self.scheme, self.nonlinear, self.periodic = n, scheme, nonlinear, periodic
         self.g, self.H, self.f = g, H, f
         self.eps, self.rmax, self.K = eps, rmax, taylor_terms
+        if eps_rule not in ("fixed", "paper"):
+            raise ValueError("eps_rule must be 'fixed' or 'paper'")
+        self.eps_rule, self.c_eps = eps_rule, c_eps
+        self.order = 3 if scheme == "upwind3" else 5
+        self.eps_q = [eps, eps, eps]       # tolerances of the time-stepping roundings
         self.sweeps, self.kick, self.cross_full = cross_sweeps, cross_kick, cross_full
         self.recip = recip
         self.cross_drop = cross_drop     # orth drop threshold of the crosses (reading R12)
@@ -163,7 +197,7 @@ class TTSolver:
         self.cross_log = {}
         self.replay = replay
         self.step_index = 0
-        self.stats = {"taylor_terms": [], "taylor_err": [], "ranks": []}
+        self.stats = {"taylor_terms": [], "taylor_err": [], "ranks": [], "eps": []}
 
     # -- helpers ---------------------------------------------------------------
     def rnd(self, X: TT) -> TT:
@@ -303,14 +337,22 @@ class TTSolver:
     def euler(self, Q, dt: float, stage: int):
         """F(q) = round(q + dt L(q))."""
         Lq = self.L(Q, stage)
-        return [self.rnd(add([(1.0, q), (dt, l)])) for q, l in zip(Q, Lq)]
+        return [tt_round(add([(1.0, q), (dt, l)]), e, self.rmax)
+                for q, l, e in zip(Q, Lq, self.eps_q)]
 
     def step(self, Q, dt: float):
+        if self.eps_rule == "paper":
+            self.eps, self.eps_q = paper_tolerances([norm(q) for q in Q], self.n, self.order,
+                                                    self.c_eps)
+            self.stats["eps"].append((self.eps, list(self.eps_q)))
+        e = self.eps_q
         Q1 = self.euler(Q, dt, 0)
         F1 = self.euler(Q1, dt, 1)
-        Q2 = [self.rnd(add([(0.75, q), (0.25, f)])) for q, f in zip(Q, F1)]
+        Q2 = [tt_round(add([(0.75, q), (0.25, f)]), e[c], self.rmax)
+              for c, (q, f) in enumerate(zip(Q, F1))]
         F2 = self.euler(Q2, dt, 2)
-        Qn = [self.rnd(add([(1.0 / 3.0, q), (2.0 / 3.0, f)])) for q, f in zip(Q, F2)]
+        Qn = [tt_round(add([(1.0 / 3.0, q), (2.0 / 3.0, f)]), e[c], self.rmax)
+              for c, (q, f) in enumerate(zip(Q, F2))]
         self.step_index += 1
         self.stats["ranks"].append([q.rank for q in Qn])
         return Qn

@@ -290,3 +290,95 @@ def smooth_factored(rng, n1: int, n2: int, r: int, base: float = 1.0) -> Factore
         A.append(a * np.cos(2 * math.pi * k * x + rng.uniform(0, 2 * math.pi)))
         B.append(np.cos(2 * math.pi * k * y + rng.uniform(0, 2 * math.pi)))
     return Factored(np.stack(A, 1), np.stack(B, 1))
+
+
+# ---------------------------------------------------------------------------
+# Section 5 analytic cases, in the nondimensional variables of the appendix
+#
+# Dimensional constants of Section 5: g* = 10 m/s^2, f* = 1e-4 1/s.  Table 2's reference
+# scales (L_ref, U_ref, H_ref) give t_ref = L_ref/U_ref, g_ref = U_ref^2/H_ref and
+# f_ref = U_ref/L_ref; lengths are divided by L_ref (the domain becomes the unit square),
+# eta and h by H_ref, velocities by U_ref.
+
+G_STAR, F_STAR = 10.0, 1e-4
+SCALES = {"coastal_kelvin": (5e6, 5e-3, 0.1), "inertia_gravity": (1e7, 1.622e-3, 0.2),
+          "barotropic_tide": (25e4, 3.163e-3, 0.2), "manufactured": (1e7, 1e-2, 500.0)}
+# Table 1: time-step ratio (dt/dx for Upwind3, dt/dx^(5/3) for Upwind5 and WENO5) and C_eps
+TABLE1 = {
+    "coastal_kelvin": {"upwind3": (5e-5, 1.0), "upwind5": (2.5e-4, 1.0), "weno5": (2.5e-4, 1000.0)},
+    "inertia_gravity": {"upwind3": (1e-4, 1.0), "upwind5": (1e-3, 1.0), "weno5": (1e-3, 500.0)},
+    "barotropic_tide": {"upwind3": (2.5e-4, 1.0), "upwind5": (5e-4, 1.0), "weno5": (5e-4, 1.0)},
+    "manufactured": {"upwind3": (5e-5, 1e-4), "upwind5": (5e-3, 1.0), "weno5": (5e-3, 1.0)},
+}
+
+
+def nondim(case: str, H_star: float):
+    """(g, H, f, t_ref) of a Section 5 case in nondimensional form."""
+    L, U, Hr = SCALES[case]
+    return G_STAR * Hr / (U * U), H_star / Hr, F_STAR * L / U, L / U
+
+
+def table1_dt(case: str, scheme: str, n: int) -> float:
+    ratio, _ = TABLE1[case][scheme]
+    dx = 1.0 / n
+    return ratio * (dx if scheme == "upwind3" else dx ** (5.0 / 3.0))
+
+
+def _sinc(z: float) -> float:
+    return math.sin(z) / z if z != 0.0 else 1.0
+
+
+def plane_factors(n: int, kx: float, ky: float, phase: float, a: float, b: float):
+    """Exact cell averages of a cos(th) + b sin(th), th = kx x + ky y - phase, on the n x n grid
+    of the unit square, as two factor columns each: field = X @ Y.T.
+
+    cos(th) = cx cy - sx sy and sin(th) = sx cy + cx sy with cx = cos(kx x - phase),
+    sx = sin(kx x - phase), cy = cos(ky y), sy = sin(ky y); the average of cos or sin of
+    k t + c over a cell of side h is sinc(k h/2) times its value at the centre."""
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    fx, fy = _sinc(kx * h / 2.0), _sinc(ky * h / 2.0)
+    cx, sx = fx * np.cos(kx * xc - phase), fx * np.sin(kx * xc - phase)
+    cy, sy = fy * np.cos(ky * xc), fy * np.sin(ky * xc)
+    X = np.stack([cx, sx], axis=1)
+    Y = np.stack([a * cy + b * sy, b * cy - a * sy], axis=1)
+    return X, Y
+
+
+def inertia_gravity_exact(n: int, t: float, f: float, g: float, H: float,
+                          modes=((0.5, 1.0), (1.0, 2.0))):
+    """Section 5.2's inertia-gravity wave at nondimensional time t: for every mode
+    (amplitude, wavenumber multiple m), k = (2 pi m, 2 pi m) and w = sqrt(g H |k|^2 + f^2),
+      eta = a cos(th),
+      u = g a / (w^2 - f^2) (w kx cos(th) - f ky sin(th)),
+      v = g a / (w^2 - f^2) (w ky cos(th) + f kx sin(th)),   th = kx x + ky y - w t.
+    Returns three lists of (X, Y) factor pairs (one per variable) of the exact cell averages."""
+    out = [([], []), ([], []), ([], [])]
+    for amp, m in modes:
+        kx = ky = 2.0 * math.pi * m
+        w = math.sqrt(g * H * (kx * kx + ky * ky) + f * f)
+        s = g * amp / (w * w - f * f)
+        for var, (a, b) in enumerate(((amp, 0.0), (s * w * kx, -s * f * ky),
+                                      (s * w * ky, s * f * kx))):
+            X, Y = plane_factors(n, kx, ky, w * t, a, b)
+            out[var][0].append(X)
+            out[var][1].append(Y)
+    return [(np.concatenate(X, axis=1), np.concatenate(Y, axis=1)) for X, Y in out]
+
+
+def inertia_gravity(n: int = 1280, scheme: str = "upwind5", rmax: int = 16,
+                    t0: float = 0.0) -> State:
+    """Section 5.2: linear SWE, doubly periodic, f != 0; two modes with eta amplitudes 0.1 m and
+    0.2 m and wavenumbers (2 pi/L)(1, 1) and (2 pi/L)(2, 2), L = 1e7 m, H = 1000 m, to T = 3 h.
+    The time step follows Table 1 for the scheme, meta carries f, C_eps and the final time."""
+    g, H, f, t_ref = nondim("inertia_gravity", 1000.0)
+    Lr, Ur, Hr = SCALES["inertia_gravity"]
+    modes = ((0.1 / Hr, 1.0), (0.2 / Hr, 2.0))
+    fac = inertia_gravity_exact(n, t0, f, g, H, modes)
+    tt = [compress(X, Y, 1e-15, rmax) for X, Y in fac]
+    fields = [X @ Y.T for X, Y in fac]
+    meta = {"f": f, "c_eps": TABLE1["inertia_gravity"][scheme][1], "scheme": scheme,
+            "T": 3.0 * 3600.0 / t_ref, "t0": t0, "modes": modes, "t_ref": t_ref,
+            "ranks": [t.rank for t in tt]}
+    return State("inertia_gravity", n, False, True, g, H, fields, tt,
+                 table1_dt("inertia_gravity", scheme, n), meta)
