@@ -187,7 +187,20 @@ typedef struct {
   int qr;             /* TT_QR_AUTO, TT_QR_CHOLESKY or TT_QR_HOUSEHOLDER (tt_ctx_set_qr)    */
   double cross_drop;  /* a cross drops fiber directions below this fraction of the largest
                          singular value; 0 = 1e-13, or 1e-6 with FP32 contractions          */
+  int eps_rule;       /* TT_EPS_FIXED: `eps` for every rounding.  TT_EPS_PAPER: Section 4.4's
+                         rule, set at the start of each step from the state's norms with
+                         base = c_eps V^(1/2) dx^(p - 1/2) (V = 1, dx = 1/n, p = 3 for
+                         Upwind3, 5 for Upwind5 and WENO5): eq. eps-tt-formula,
+                         base / max_q ||q||, for the roundings inside L(Q), the Taylor
+                         reciprocal and the crosses; eq. modified-eps-tt-formula,
+                         min(1e-3, base / ||q||), for the forward-Euler and SSP-RK3
+                         combination roundings of each variable q.  ||q|| is the L2 norm of
+                         the cell averages on the unit square (dx times the Frobenius norm of
+                         the n x n array); a zero state takes 1e-3.  `eps` is then unused.  */
+  double c_eps;       /* C_eps of the paper's rule (> 0; Table 1 lists it per case/scheme)  */
 } tt_fv_params;
+#define TT_EPS_FIXED 0
+#define TT_EPS_PAPER 1
 
 typedef struct {
   long long steps;            /* steps taken                                              */
@@ -212,6 +225,8 @@ typedef struct {
   long long jacobi_capped;    /* Jacobi SVDs stopped at the sweep cap (TT_WJACOBI)         */
   long long qr_redos;         /* roundings or orthogonalisations redone with Householder QR
                                  because a Cholesky QR ended without orthonormal columns   */
+  double eps_inner;           /* tolerance of the last step's roundings inside L(Q)        */
+  double eps_var[3];          /* tolerances of its time-stepping roundings, per variable   */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build
@@ -232,6 +247,22 @@ int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
  * statistics are reset. */
 int  tt_fv_time_kernel(tt_fv *s, const char *name, int every);
 void tt_fv_destroy(tt_fv *s);
+
+/* ---------------------------------------------------------------------------------------
+ * Full-grid comparator: the same finite-volume scheme (Sections 2.2-2.4: reconstruction,
+ * LLF flux, Gauss-Legendre face sums, Coriolis source; SSP-RK3 of Section 4.4 without
+ * rounding) on n x n arrays of cell averages, the full-tensor form of Section 4.1 that the
+ * paper's speed-ups are measured against.  One fused kernel per RK stage. */
+typedef struct tt_grid tt_grid;
+/* Uses n, nonlinear, scheme, periodic, g, H0 and f of `p` (the other fields are ignored).
+ * Allocates two stage buffers of 3 n^2 doubles once here; work runs on hip_stream. */
+int  tt_grid_init(tt_grid **out, const tt_fv_params *p, void *hip_stream);
+/* Advance U nsteps SSP-RK3 steps of size dt in place.  U: device, 3 x n x n doubles, variable
+ * major, then the x cell, then the y cell (y contiguous), the variables of tt_fv_params'
+ * equation set.  Enqueues the stage kernels on the solver's stream and returns; the caller
+ * synchronises that stream before reading U. */
+int  tt_grid_step(tt_grid *s, double *U, double dt, int nsteps);
+void tt_grid_destroy(tt_grid *s);
 
 /* ---------------------------------------------------------------------------------------
  * Learned pivot proposer for the crosses (an addition to the paper, whose crosses choose

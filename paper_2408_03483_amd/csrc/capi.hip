@@ -22,6 +22,10 @@ void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int
                           const int *I, int nI);
 int solver_get_pivots(Solver *s, int site, int *J, int capJ, int *nJ, int *I, int capI,
                       int *nI);
+struct Grid;
+Grid *grid_create(const tt_fv_params *p, void *stream);
+void grid_step(Grid *s, double *U, double dt, int nsteps);
+void grid_destroy(Grid *s);
 struct Ensemble;
 Ensemble *ensemble_create(int workers, size_t arena_bytes);
 void ensemble_destroy(Ensemble *e);
@@ -531,6 +535,32 @@ int tt_recon_core(tt_ctx *ctx, const double *core, int n, int rank, int scheme, 
     ctx->c.sync();
     return 0;
   });
+}
+
+struct tt_grid {
+  ttfv::Grid *g;
+};
+
+int tt_grid_init(tt_grid **out, const tt_fv_params *p, void *hip_stream) {
+  return guarded([&]() {
+    TT_REQUIRE(out, "tt_grid_init: null out");
+    *out = new tt_grid{grid_create(p, hip_stream)};
+    return 0;
+  });
+}
+
+int tt_grid_step(tt_grid *s, double *U, double dt, int nsteps) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null grid solver");
+    grid_step(s->g, U, dt, nsteps);
+    return 0;
+  });
+}
+
+void tt_grid_destroy(tt_grid *s) {
+  if (!s) return;
+  grid_destroy(s->g);
+  delete s;
 }
 
 int tt_fv_init(tt_fv **out, const tt_fv_params *p, const tt_matrix q0[3], void *hip_stream,

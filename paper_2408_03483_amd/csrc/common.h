@@ -266,6 +266,8 @@ void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, d
 
 // tt_ops.hip (host algorithms)
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
+// Frobenius norm of x (sqrt of sum((A^T A) o (B^T B)), the Gram matrices on the matrix cores)
+double norm_tt(Ctx &c, const DTT &x);
 // upper bound of the arena bytes round_tt draws for an n1 x n2 input of rank R with the
 // context's default sketch settings (FP64), every branch included
 size_t round_arena_bound(int n1, int n2, int R, int rmax);

@@ -18,6 +18,10 @@
 //   finish          Gauss-Legendre sum on the second core, (T - 1) on the first (Section 4.1).
 // SSP-RK3 (Section 4.4): Q1 = F(Qn), Q2 = round(3/4 Qn + 1/4 F(Q1)),
 // Qn+1 = round(1/3 Qn + 2/3 F(Q2)), F(q) = round(q + dt L(q)).
+// Tolerances: eps for every rounding, or Section 4.4's rule (TT_EPS_PAPER), set at the start
+// of each step: eq. eps-tt-formula for the roundings inside L, the reciprocal and the
+// crosses (eps_in), eq. modified-eps-tt-formula per variable for its time-stepping roundings
+// (eps_q).
 //
 // Every TT of the step lives in the solver's arena; ranks are known on the host after each
 // rounding (one stream synchronisation per rounding), so every launch has its exact shape.
@@ -53,6 +57,10 @@ struct Solver {
   int last_terms = 0;
   double last_err = 0.0;
   int *rep_idx = nullptr;      // row j*nq + m -> j
+  // tolerances of the current step: roundings inside L, reciprocal and crosses; and each
+  // variable's forward-Euler and SSP-RK3 combination roundings
+  double eps_in = 0.0;
+  double eps_q[3] = {0.0, 0.0, 0.0};
   // learned pivot proposer (TT_PIV_*): model, per-site validation error of the last plain
   // cross, and counters
   // helper contexts of the Taylor reciprocal's partial sums, one per (direction, side); used
@@ -109,7 +117,7 @@ struct Solver {
 
   DTT rnd(Ctx &w, const DTT &x) {
     DTT y = alloc(w, x.n1, x.n2, p.r_max);
-    round_tt(w, x, p.eps, p.r_max, y, nullptr);
+    round_tt(w, x, eps_in, p.r_max, y, nullptr);
     return y;
   }
 
@@ -233,7 +241,7 @@ struct Solver {
                                      ", site " + std::to_string(site));
         ji = it->second;
       }
-      skeleton_tt(w, fs, n1, n2, ji.first, ji.second, p.eps, p.r_max, out);
+      skeleton_tt(w, fs, n1, n2, ji.first, ji.second, eps_in, p.r_max, out);
       std::lock_guard<std::mutex> lk(mu);
       piv[site] = ji.first;
       last_piv[site] = ji;
@@ -287,7 +295,7 @@ struct Solver {
         if (std::find(Jp.begin(), Jp.end(), j) == Jp.end()) Jp.push_back(j);
       }
       std::vector<int> Il;
-      cross_tt(w, fs, n1, n2, Jp, p.eps, p.r_max, 1, 0, key, out, &J, &Il);
+      cross_tt(w, fs, n1, n2, Jp, eps_in, p.r_max, 1, 0, key, out, &J, &Il);
       const double err = validate(w, fs, n1, n2, out, J, key);
       const double bar = acc_rel >= 0.0 ? std::max(acc_abs, (1.0 + acc_rel) * ref) : acc_abs;
       std::lock_guard<std::mutex> lk(mu);
@@ -302,7 +310,8 @@ struct Solver {
       fallbacks++;
     }
     std::vector<int> I;
-    cross_tt(w, fs, n1, n2, J0, p.eps, p.r_max, p.cross_sweeps, p.cross_kick, key, out, &J, &I);
+    cross_tt(w, fs, n1, n2, J0, eps_in, p.r_max, p.cross_sweeps, p.cross_kick, key, out, &J,
+             &I);
     double err = -1.0;
     if (piv_mode != TT_PIV_MAXVOL) err = validate(w, fs, n1, n2, out, J, key);
     if (piv_mode == TT_PIV_LOG && Xb) {
@@ -381,7 +390,7 @@ struct Solver {
         a->fp32 = w.fp32;
         a->qr = w.qr;
       }
-      reciprocal_tt(w, h, p.eps, p.taylor_terms, p.r_max, rh, &err, &terms, a);
+      reciprocal_tt(w, h, eps_in, p.taylor_terms, p.r_max, rh, &err, &terms, a);
       std::lock_guard<std::mutex> lk(mu);
       last_err = err;
       last_terms = terms;
@@ -478,7 +487,7 @@ struct Solver {
         for (int s = 0; s < 2; ++s)
           tasks.push_back([this, &side, &P2, d, s](Ctx &w) {
             const DTT &h = side(d, s)[0];
-            round_tt(w, had(w, h, h), p.eps, p.r_max, P2[d][s], nullptr);
+            round_tt(w, had(w, h, h), eps_in, p.r_max, P2[d][s], nullptr);
           });
       run_tasks(std::move(tasks));
     }
@@ -487,10 +496,10 @@ struct Solver {
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s) {
           tasks.push_back([this, &side, &rh, &U, d, s](Ctx &w) {
-            round_tt(w, had(w, side(d, s)[1], rh[d][s]), p.eps, p.r_max, U[d][s], nullptr);
+            round_tt(w, had(w, side(d, s)[1], rh[d][s]), eps_in, p.r_max, U[d][s], nullptr);
           });
           tasks.push_back([this, &side, &rh, &Wv, d, s](Ctx &w) {
-            round_tt(w, had(w, side(d, s)[2], rh[d][s]), p.eps, p.r_max, Wv[d][s], nullptr);
+            round_tt(w, had(w, side(d, s)[2], rh[d][s]), eps_in, p.r_max, Wv[d][s], nullptr);
           });
         }
       run_tasks(std::move(tasks));
@@ -501,11 +510,11 @@ struct Solver {
         for (int s = 0; s < 2; ++s) {
           tasks.push_back([this, &side, &U, &P2, &F, d, s](Ctx &w) {
             DTT P1 = rnd(w, had(w, side(d, s)[1], U[d][s]));
-            round_tt(w, add(w, {{1.0, P1}, {0.5 * p.g, P2[d][s]}}), p.eps, p.r_max, F[d][s][1],
+            round_tt(w, add(w, {{1.0, P1}, {0.5 * p.g, P2[d][s]}}), eps_in, p.r_max, F[d][s][1],
                      nullptr);
           });
           tasks.push_back([this, &side, &Wv, &F, d, s](Ctx &w) {
-            round_tt(w, had(w, side(d, s)[1], Wv[d][s]), p.eps, p.r_max, F[d][s][2], nullptr);
+            round_tt(w, had(w, side(d, s)[1], Wv[d][s]), eps_in, p.r_max, F[d][s][2], nullptr);
           });
         }
       run_tasks(std::move(tasks));
@@ -543,7 +552,7 @@ struct Solver {
                                                   {-dt / dx, G[v]}};
         if (p.f != 0.0 && v == 1) terms.push_back({dt * p.f, Qv[2]});
         if (p.f != 0.0 && v == 2) terms.push_back({-dt * p.f, Qv[1]});
-        round_tt(w, add(w, terms), p.eps, p.r_max, out[v], nullptr);
+        round_tt(w, add(w, terms), eps_q[v], p.r_max, out[v], nullptr);
       });
     c.sync();
     run_tasks(std::move(tasks));
@@ -553,14 +562,33 @@ struct Solver {
     std::vector<Pool::Task> tasks;
     for (int v = 0; v < 3; ++v)
       tasks.push_back([this, A, B, a, b, out, v](Ctx &w) {
-        round_tt(w, add(w, {{a, A[v]}, {b, B[v]}}), p.eps, p.r_max, out[v], nullptr);
+        round_tt(w, add(w, {{a, A[v]}, {b, B[v]}}), eps_q[v], p.r_max, out[v], nullptr);
       });
     c.sync();
     run_tasks(std::move(tasks));
   }
 
+  // Section 4.4's tolerances from the state at the start of the step (TT_EPS_PAPER)
+  void set_tolerances() {
+    if (p.eps_rule != TT_EPS_PAPER) {
+      eps_in = eps_q[0] = eps_q[1] = eps_q[2] = p.eps;
+      return;
+    }
+    const double dx = 1.0 / n;
+    const int order = p.scheme == 3 ? 3 : 5;
+    const double base = p.c_eps * std::pow(dx, order - 0.5);   // V = 1
+    double l2[3], top = 0.0;
+    for (int v = 0; v < 3; ++v) {
+      l2[v] = dx * norm_tt(c, Q[v]);
+      top = std::max(top, l2[v]);
+    }
+    eps_in = top > 0.0 ? base / top : 1e-3;
+    for (int v = 0; v < 3; ++v) eps_q[v] = l2[v] > 0.0 ? std::min(1e-3, base / l2[v]) : 1e-3;
+  }
+
   void step(double dt) {
     Scope sc(c.arena);
+    set_tolerances();
     DTT Q1[3], F1[3], Q2[3], F2[3], Qn[3];
     for (int v = 0; v < 3; ++v) {
       Q1[v] = alloc(c, n, n, p.r_max);
@@ -591,6 +619,10 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   TT_REQUIRE(p->scheme == 3 || p->scheme == 5 || p->scheme == 55, "tt_fv_init: bad scheme");
   TT_REQUIRE(p->r_max >= 1 && p->r_max <= 64, "tt_fv_init: r_max must be in [1, 64]");
   TT_REQUIRE(p->eps >= 0.0, "tt_fv_init: eps < 0");
+  TT_REQUIRE(p->eps_rule == TT_EPS_FIXED || p->eps_rule == TT_EPS_PAPER,
+             "tt_fv_init: unknown eps_rule");
+  TT_REQUIRE(p->eps_rule != TT_EPS_PAPER || (p->c_eps > 0.0 && std::isfinite(p->c_eps)),
+             "tt_fv_init: c_eps must be positive with TT_EPS_PAPER");
   TT_REQUIRE(!p->nonlinear || p->taylor_terms >= 1 || p->recip == 1,
              "tt_fv_init: taylor_terms < 1");
   TT_REQUIRE(p->recip == 0 || p->recip == 1, "tt_fv_init: recip must be 0 or 1");
@@ -654,6 +686,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     HIP_CHECK(hipMemcpyAsync(s->rep_idx, rep.data(), rep.size() * sizeof(int),
                              hipMemcpyHostToDevice, s->c.stream));
     s->c.sync();
+    s->set_tolerances();
   } catch (...) {
     delete s;
     throw;
@@ -789,6 +822,8 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->sketch_unconverged = t.sketch_unconverged;
   o->jacobi_capped = jcap;
   o->qr_redos = t.qr_redos;
+  o->eps_inner = s->eps_in;
+  for (int v = 0; v < 3; ++v) o->eps_var[v] = s->eps_q[v];
   o->flops = t.flops;
   o->bytes = t.bytes;
   std::vector<KernelTimer *> tm{&s->c.timer};

@@ -43,7 +43,14 @@ std::vector<double> to_host(Ctx &c, const double *dev, size_t n) {
   return h;
 }
 
-int trunc_rank(const std::vector<double> &s, double eps, int rmax, bool *capped) {
+// Kept rank of a truncation: the fewest leading singular values whose discarded tail is within
+// eps of the total, at most rmax, and never a direction at or below the SVD's norm floor
+// max(1e-17, floor_rel) ||s||: the Jacobi SVD does not rotate such columns, so they are not
+// orthogonal to the others and keeping one would turn the projection Q U_k U_k^T into a
+// non-projection.  A tolerance below that floor (below round-off) therefore keeps every
+// direction above it.  capped: the rank cap, not eps or the floor, set k.
+int trunc_rank(const std::vector<double> &s, double eps, int rmax, double floor_rel,
+               bool *capped) {
   const int m = (int)s.size();
   std::vector<double> tail(m + 1, 0.0);
   for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
@@ -51,8 +58,13 @@ int trunc_rank(const std::vector<double> &s, double eps, int rmax, bool *capped)
   int k = m;
   for (int kk = 1; kk <= m; ++kk)
     if (tail[kk] <= thr) { k = kk; break; }
+  const double fl = std::max(1e-17, floor_rel) * std::sqrt(tail[0]);
+  int kf = 0;
+  while (kf < m && s[kf] > fl) ++kf;
+  k = std::min(k, std::max(kf, 1));
+  const bool cap = k > rmax;
   k = std::max(1, std::min(k, rmax));
-  if (capped) *capped = (k < m) && (tail[k] > thr);
+  if (capped) *capped = cap && (tail[k] > thr);
   return k;
 }
 
@@ -262,7 +274,7 @@ int round_impl(Ctx &c, const DTT &x, double eps, int rmax, DTT &y,
       s_host = to_host(c, sg, m);
       const std::vector<double> &s = s_host;
       if (s[0] == 0.0) break;
-      const int k = trunc_rank(s, eps, rmax, nullptr);
+      const int k = trunc_rank(s, eps, rmax, jacobi_floor(eps), nullptr);
       if (k >= m) break;
       // (a) the sketch reached round-off: beyond m - p the captured spectrum is below
       //     1e-14 s_0, so with oversampling p the range error is at that level;
@@ -330,7 +342,7 @@ int round_impl(Ctx &c, const DTT &x, double eps, int rmax, DTT &y,
     return warn;
   }
   bool capped = false;
-  const int k = trunc_rank(s, eps, rmax, &capped);
+  const int k = trunc_rank(s, eps, rmax, jacobi_floor(eps), &capped);
   if (capped) warn |= TT_WRANKCAP;
   double *U = c.arena.dalloc((size_t)m * k);
   normalise_cols(c, US, sg, m, k, U);
@@ -547,6 +559,19 @@ struct SumPipe {
 };
 
 }  // namespace
+
+double norm_tt(Ctx &c, const DTT &x) {
+  if (x.r == 0) return 0.0;
+  Scope sc(c.arena);
+  const int r = x.r;
+  double *G = c.arena.dalloc(2 * (size_t)r * r);
+  gemm(c, true, r, r, x.n1, 1.0, x.A, x.n1, x.A, x.n1, 0.0, G, r);
+  gemm(c, true, r, r, x.n2, 1.0, x.B, x.n2, x.B, x.n2, 0.0, G + (size_t)r * r, r);
+  std::vector<double> h = to_host(c, G, 2 * (size_t)r * r);
+  double s = 0.0;
+  for (size_t i = 0; i < (size_t)r * r; ++i) s += h[i] * h[(size_t)r * r + i];
+  return std::sqrt(std::max(s, 0.0));
+}
 
 int reciprocal_tt(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y, double *err_out,
                   int *terms_out, Ctx *aux) {

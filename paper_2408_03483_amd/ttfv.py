@@ -42,7 +42,8 @@ class ParamsC(ctypes.Structure):
                 ("f", ctypes.c_double), ("eps", ctypes.c_double), ("r_max", ctypes.c_int),
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
                 ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int),
-                ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double),
+                ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double)]
 
 
 class StatsC(ctypes.Structure):
@@ -56,11 +57,13 @@ class StatsC(ctypes.Structure):
                 ("learned_crosses", ctypes.c_longlong), ("learned_fallbacks", ctypes.c_longlong),
                 ("max_learned_err", ctypes.c_double), ("sketch_fallbacks", ctypes.c_longlong),
                 ("sketch_unconverged", ctypes.c_longlong), ("jacobi_capped", ctypes.c_longlong),
-                ("qr_redos", ctypes.c_longlong)]
+                ("qr_redos", ctypes.c_longlong), ("eps_inner", ctypes.c_double),
+                ("eps_var", ctypes.c_double * 3)]
 
 
 PRECISIONS = {"f64": 0, "f32": 1}
 QR_METHODS = {"auto": 0, "cholesky": 1, "householder": 2}
+EPS_RULES = {"fixed": 0, "paper": 1}
 
 EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_precision",
            "tt_round", "tt_round_noalloc",
@@ -71,7 +74,8 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_pm_forward", "tt_pm_grad", "tt_pm_train", "tt_pm_dataset", "tt_pm_features",
            "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error",
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
-           "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance"]
+           "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
+           "tt_grid_init", "tt_grid_step", "tt_grid_destroy"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -112,6 +116,10 @@ def load_library(path: str = LIB_PATH):
     L.tt_fv_time_kernel.argtypes = [P, ctypes.c_char_p, I]
     L.tt_fv_destroy.argtypes = [P]
     L.tt_fv_destroy.restype = None
+    L.tt_grid_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(ParamsC), P]
+    L.tt_grid_step.argtypes = [P, P, D, I]
+    L.tt_grid_destroy.argtypes = [P]
+    L.tt_grid_destroy.restype = None
     L.tt_ens_create.argtypes = [ctypes.POINTER(P), I, S]
     L.tt_ens_step.argtypes = [P, ctypes.POINTER(P), I, ctypes.POINTER(D), I, I]
     L.tt_ens_destroy.argtypes = [P]
@@ -359,12 +367,14 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                r_max: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
                arena_bytes: int = 4 << 30, precision: str = "f64",
-               qr: str = "auto", cross_drop: float = 0.0) -> Solver:
+               qr: str = "auto", cross_drop: float = 0.0, eps_rule: str = "fixed",
+               c_eps: float = 1.0) -> Solver:
     L = load_library()
     _torch()
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
-                workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop)
+                workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop,
+                EPS_RULES[eps_rule], c_eps)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -398,7 +408,8 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "learned_crosses": st.learned_crosses, "learned_fallbacks": st.learned_fallbacks,
             "max_learned_err": st.max_learned_err, "sketch_fallbacks": st.sketch_fallbacks,
             "sketch_unconverged": st.sketch_unconverged, "jacobi_capped": st.jacobi_capped,
-            "qr_redos": st.qr_redos}
+            "qr_redos": st.qr_redos, "eps_inner": st.eps_inner,
+            "eps_var": list(st.eps_var)}
 
 
 def tt_fv_time_kernel(s: Solver, name: Optional[str], every: int = 32) -> None:
@@ -407,6 +418,55 @@ def tt_fv_time_kernel(s: Solver, name: Optional[str], every: int = 32) -> None:
 
 def tt_fv_destroy(s: Solver) -> None:
     s.close()
+
+
+class Grid:
+    """Full-grid comparator (tt_grid_*): the same scheme on n x n cell-average arrays."""
+
+    def __init__(self, n: int, scheme: str, nonlinear: bool, periodic: bool, g: float = 9.81,
+                 H0: float = 1.0, f: float = 0.0, stream=None):
+        L = load_library()
+        _torch()
+        self.params = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0,
+                              g, H0, f, 0.0, 1, 1, 1, 0, 0, 0, 0, 0, 0.0, 0, 1.0)
+        self.h = ctypes.c_void_p()
+        self._stream = stream
+        _check(L.tt_grid_init(ctypes.byref(self.h), ctypes.byref(self.params),
+                              _stream_ptr(stream)), "tt_grid_init")
+
+    def step(self, U, dt: float, nsteps: int = 1) -> None:
+        """Advance U (torch float64 CUDA tensor, 3 x n x n, contiguous) in place; asynchronous
+        on the grid's stream."""
+        n = self.params.n
+        if (tuple(U.shape) != (3, n, n) or not U.is_contiguous() or not U.is_cuda or
+                str(U.dtype) != "torch.float64"):
+            raise ValueError("tt_grid_step: U must be a contiguous float64 CUDA tensor 3 x n x n")
+        _check(_lib.tt_grid_step(self.h, ctypes.c_void_p(U.data_ptr()), dt, nsteps),
+               "tt_grid_step")
+
+    def close(self):
+        if self.h:
+            _lib.tt_grid_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tt_grid_init(n: int, scheme: str, nonlinear: bool, periodic: bool, g: float = 9.81,
+                 H0: float = 1.0, f: float = 0.0, stream=None) -> Grid:
+    return Grid(n, scheme, nonlinear, periodic, g, H0, f, stream)
+
+
+def tt_grid_step(grid: Grid, U, dt: float, nsteps: int = 1) -> None:
+    grid.step(U, dt, nsteps)
+
+
+def tt_grid_destroy(grid: Grid) -> None:
+    grid.close()
 
 
 class Ensemble:

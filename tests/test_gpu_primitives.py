@@ -115,6 +115,31 @@ def test_round_fp32_contractions(lib, n1, n2, r, eps, rmax):
     assert e < 1e-5
 
 
+@pytest.mark.parametrize("eps", [0.0, 1e-20, 1e-17])
+@pytest.mark.parametrize("r", [4, 12, 30])
+def test_round_below_round_off_of_a_rank_deficient_sum(lib, ctx, eps, r):
+    """A tolerance below round-off on a sum whose concatenated cores are rank deficient (the
+    state of a linear step at a fine grid under Section 4.4's rule, where the formula asks for
+    1e-18 or less): the rounding keeps every direction the SVD resolved and none of the
+    unresolved noise, so the result is X to round-off, not a garbled projection."""
+    _say(f"round below round-off r={r} eps={eps}")
+    rng = np.random.default_rng(7 + r)
+    n1, n2 = 700, 900
+    A = rng.standard_normal((n1, r)) * (0.7 ** np.arange(r))[None, :]
+    B = rng.standard_normal((n2, r))
+    # x = A B^T + 0.5 A (2B)^T - 1.5 A B^T + A B^T = 1.5 A B^T: exact rank r from 4 r columns
+    Ac = np.concatenate([A, 0.5 * A, -1.5 * A, A], axis=1)
+    Bc = np.concatenate([B, 2.0 * B, B, B], axis=1)
+    x = lib.DeviceTT.from_factors(Ac, Bc)
+    rmax = min(4 * r, 64)
+    y = lib.DeviceTT(n1, n2, rmax)
+    lib.tt_round(ctx, x, eps, rmax, y)
+    F = 1.5 * (A @ B.T)
+    e = rel(y.full(), F)
+    _say(f"  rank {y.rank}, rel error {e:.2e}")
+    assert e < 1e-13
+
+
 @pytest.mark.parametrize("m", [1, 7, 17, 33, 63, 65, 81, 96])
 def test_round_full_rank_orthonormal_factor(lib, ctx, m):
     """Full-rank rounding (eps = 0, r_max = m) takes the exact path: two TSQRs (leaves of 250
