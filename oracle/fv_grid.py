@@ -16,9 +16,16 @@ with no tensor-train compression:
   * flux differences (T - 1)F/dx (Section 4.1) and the SSP-RK3 step (Section 4.4 with
     rounding replaced by the identity).
 
+Boundaries, per axis: periodic; reflective walls; or "exact", where the ghost cells hold
+given values (the exact solution's cell averages, Section 5's Kelvin wave and barotropic
+tide).  Boundary values and forcing come as separable terms with a harmonic time factor,
+amp cos(omega t + phase) X(.) Y(.) (see ghost_values and forcing_values); at most one axis is
+"exact".  The field is first extended by NG ghost cells along the exact axis (or along x),
+then along the other axis, so corner cells follow the second axis's rule.
+
 Array layout: index [i, j] = (x cell, y cell).  Faces along an axis are numbered by the
 cell on their right: face f is the left face of cell f.  Periodic axes have N faces,
-reflective axes N + 1.  Readings where the paper is silent (ghost cells at walls, the
+other axes N + 1.  Readings where the paper is silent (ghost cells at walls, the
 LLF eigenvalue, the quadrature ordering) are those listed in the design notes: reflective
 walls mirror three ghost cells with the sign of the normal momentum flipped; the LLF
 eigenvalue is max(|u-| + sqrt(g h-), |u+| + sqrt(g h+)) pointwise; quadrature points are
@@ -35,16 +42,52 @@ from . import stencils
 NG = 3  # ghost cells per side
 
 
-def pad(v: np.ndarray, axis: int, periodic: bool, sign: float) -> np.ndarray:
-    """Extend v by NG ghost cells on both ends of `axis`."""
+def pad(v: np.ndarray, axis: int, periodic, sign: float, lo=None, hi=None) -> np.ndarray:
+    """Extend v by NG ghost cells on both ends of `axis`: periodic wrap (periodic True or
+    "periodic"), mirror times sign (False or "wall"), or the given ghost blocks lo, hi
+    ("exact"; NG cells each, ascending cell index, the axis first)."""
+    kind = periodic if isinstance(periodic, str) else ("periodic" if periodic else "wall")
     v = np.moveaxis(v, axis, 0)
-    if periodic:
+    if kind == "periodic":
         out = np.concatenate([v[-NG:], v, v[:NG]], axis=0)
-    else:
+    elif kind == "wall":
         left = sign * v[:NG][::-1]
         right = sign * v[-NG:][::-1]
         out = np.concatenate([left, v, right], axis=0)
+    elif kind == "exact":
+        out = np.concatenate([lo, v, hi], axis=0)
+    else:
+        raise ValueError(f"unknown boundary kind {kind!r}")
     return np.moveaxis(out, 0, axis)
+
+
+def time_factor(term, t: float) -> float:
+    return term.amp * math.cos(term.omega * t + term.phase)
+
+
+def ghost_values(terms, var: int, where: str, t: float) -> np.ndarray:
+    """Sum of the separable ghost terms of one variable and side at time t, with the
+    boundary's normal axis first: (NG, n).  x sides: X holds the NG ghost cells (ascending),
+    Y the n cells along y; y sides: Y holds the ghost cells, X the n cells along x."""
+    out = None
+    for tm in terms:
+        if tm.var != var or tm.where != where:
+            continue
+        if where.startswith("x"):
+            blk = time_factor(tm, t) * np.outer(tm.X, tm.Y)
+        else:
+            blk = time_factor(tm, t) * np.outer(tm.Y, tm.X)
+        out = blk if out is None else out + blk
+    return out
+
+
+def forcing_values(terms, var: int, t: float, n: int) -> np.ndarray:
+    """Sum of the separable forcing terms of one variable at time t: (n, n)."""
+    out = np.zeros((n, n))
+    for tm in terms:
+        if tm.var == var and tm.where == "forcing":
+            out = out + time_factor(tm, t) * np.outer(tm.X, tm.Y)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -167,32 +210,57 @@ class GridSolver:
 
     def __init__(self, n: int, scheme: str, nonlinear: bool, periodic: bool = True,
                  g: float = 9.81, H: float = 1.0, f: float = 0.0, length: float = 1.0,
-                 source=None):
-        self.n, self.scheme, self.nonlinear, self.periodic = n, scheme, nonlinear, periodic
+                 source=None, bc=None, terms=()):
+        self.n, self.scheme, self.nonlinear = n, scheme, nonlinear
         self.g, self.H, self.f = g, H, f
         self.dx = length / n
         self.tab = stencils.tables(scheme)
-        self.n_faces = n if periodic else n + 1
+        # boundary kind per axis (x, y): "periodic", "wall" or "exact"
+        self.bc = tuple(bc) if bc is not None else \
+            (("periodic", "periodic") if periodic else ("wall", "wall"))
+        if any(b not in ("periodic", "wall", "exact") for b in self.bc) or \
+                self.bc.count("exact") > 1:
+            raise ValueError(f"bad boundary kinds {self.bc}")
+        self.n_faces_axis = [n if b == "periodic" else n + 1 for b in self.bc]
         self.source = source  # optional callable t -> list of 3 arrays (manufactured forcing)
+        self.terms = list(terms)  # separable ghost and forcing terms
 
     # reflection signs (normal momentum flips)
     @staticmethod
     def signs(direction: int):
         return (1.0, -1.0, 1.0) if direction == 0 else (1.0, 1.0, -1.0)
 
-    def face_states(self, U, direction: int):
+    def padded(self, v, c: int, t: float):
+        """Variable c extended by NG ghost cells along both axes, (n + 6) x (n + 6): the exact
+        axis first (x when none is exact), then the other; walls negate the momentum normal
+        to them."""
+        first = 1 if self.bc[1] == "exact" else 0
+        P = v
+        for axis in (first, 1 - first):
+            kind = self.bc[axis]
+            lo = hi = None
+            if kind == "exact":
+                side = "x" if axis == 0 else "y"
+                lo = ghost_values(self.terms, c, side + "_lo", t)
+                hi = ghost_values(self.terms, c, side + "_hi", t)
+                if lo is None or hi is None:
+                    lo = np.zeros((NG, self.n)) if lo is None else lo
+                    hi = np.zeros((NG, self.n)) if hi is None else hi
+            P = pad(P, axis, kind, self.signs(axis)[c], lo, hi)
+        return P
+
+    def face_states(self, U, direction: int, t: float = 0.0):
         """(U_minus, U_plus), each a list of 3 arrays of shape (n_faces, n, nq) for x,
         (n, n_faces, nq) for y; the trailing axis is the quadrature point along the face."""
         tab, eps = self.tab, self.dx * self.dx
-        sn = self.signs(direction)
-        st = self.signs(1 - direction)
+        nf = self.n_faces_axis[direction]
         Um, Up = [], []
         for c, v in enumerate(U):
-            vv = v if direction == 0 else v.T                     # normal axis first
-            P = pad(vv, 0, self.periodic, sn[c])
-            fm, fp = faces_1d(P, self.n_faces, tab, self.scheme, eps)
-            qm = quad_1d(pad(fm.T, 0, self.periodic, st[c]), self.n, tab, self.scheme, eps)
-            qp = quad_1d(pad(fp.T, 0, self.periodic, st[c]), self.n, tab, self.scheme, eps)
+            P = self.padded(v, c, t)
+            PP = P if direction == 0 else P.T                     # normal axis first
+            fm, fp = faces_1d(PP, nf, tab, self.scheme, eps)      # (nf, n + 6)
+            qm = quad_1d(fm.T, self.n, tab, self.scheme, eps)
+            qp = quad_1d(fp.T, self.n, tab, self.scheme, eps)
             # q*: (n tangent, n_faces, nq) -> (n_faces, n, nq)
             qm, qp = qm.transpose(1, 0, 2), qp.transpose(1, 0, 2)
             if direction == 1:
@@ -201,9 +269,9 @@ class GridSolver:
             Up.append(qp)
         return Um, Up
 
-    def face_flux(self, U, direction: int):
+    def face_flux(self, U, direction: int, t: float = 0.0):
         """Gauss-Legendre sum of the LLF flux over each face: list of 3 arrays."""
-        Um, Up = self.face_states(U, direction)
+        Um, Up = self.face_states(U, direction, t)
         Fp = llf(Um, Up, self.nonlinear, self.g, self.H, direction)
         w = np.asarray(self.tab["gl_weights"])
         return [np.tensordot(F, w, axes=([2], [0])) for F in Fp]
@@ -211,15 +279,15 @@ class GridSolver:
     def diff(self, Fhat, direction: int):
         """(T - 1) F: value at the right face minus value at the left face of each cell."""
         Fn = Fhat if direction == 0 else Fhat.T
-        if self.periodic:
+        if self.bc[direction] == "periodic":
             d = np.roll(Fn, -1, axis=0) - Fn
         else:
             d = Fn[1:] - Fn[:-1]
         return d if direction == 0 else d.T
 
     def rhs(self, U, t: float = 0.0):
-        Fx = self.face_flux(U, 0)
-        Fy = self.face_flux(U, 1)
+        Fx = self.face_flux(U, 0, t)
+        Fy = self.face_flux(U, 1, t)
         L = [-(self.diff(fx, 0) + self.diff(fy, 1)) / self.dx for fx, fy in zip(Fx, Fy)]
         if self.f != 0.0:
             L[1] = L[1] + self.f * U[2]
@@ -227,6 +295,8 @@ class GridSolver:
         if self.source is not None:
             S = self.source(t)
             L = [l + s for l, s in zip(L, S)]
+        if any(tm.where == "forcing" for tm in self.terms):
+            L = [l + forcing_values(self.terms, c, t, self.n) for c, l in enumerate(L)]
         return L
 
     def step(self, U, dt: float, t: float = 0.0):

@@ -5,6 +5,14 @@ Oracle (test infrastructure only).
 State: three 2-core TTs (x index on the first core, y index on the second), the conserved
 variables (eta, u, v) of the linear SWE or (h, hu, hv) of the nonlinear SWE.
 
+Boundaries per axis: periodic, reflective walls, or "exact" (ghost cells from given
+separable terms amp cos(omega t + phase) X Y, Section 5's exact-solution boundaries).  On an
+exact axis the state's cores are extended by zeros and every ghost term becomes extra rank
+columns of the reconstructed TTs: its factor along the exact axis is an explicit (n + 6)
+column that is zero inside the domain, its other factor is extended by the other axis's rule,
+and both pass through the same stencils (the reconstruction is linear).  Forcing terms add
+rank-1 TTs to L.  Exact boundaries are built for the Upwind schemes.
+
 One evaluation of L(Q) (Sections 4.1-4.3):
 
   x direction (the y direction is the same sequence applied to the transposed TTs with the
@@ -77,11 +85,21 @@ SIGN_NORMAL = (1.0, -1.0, 1.0)
 SIGN_TANGENT = (1.0, 1.0, -1.0)
 
 
-def extend(core: np.ndarray, periodic: bool, sign: float) -> np.ndarray:
-    """Ghost-extend a core along its rows by NG rows per side (wrap, or mirror times sign)."""
-    if periodic:
+def extend(core: np.ndarray, periodic, sign: float) -> np.ndarray:
+    """Ghost-extend a core along its rows by NG rows per side: wrap (periodic True or
+    "periodic"), mirror times sign (False or "wall"), or zeros ("exact": the ghost values then
+    come from separate boundary terms)."""
+    kind = periodic if isinstance(periodic, str) else ("periodic" if periodic else "wall")
+    if kind == "periodic":
         return np.concatenate([core[-NG:], core, core[:NG]], axis=0)
-    return np.concatenate([sign * core[:NG][::-1], core, sign * core[-NG:][::-1]], axis=0)
+    if kind == "wall":
+        return np.concatenate([sign * core[:NG][::-1], core, sign * core[-NG:][::-1]], axis=0)
+    z = np.zeros((NG,) + core.shape[1:])
+    return np.concatenate([z, core, z], axis=0)
+
+
+def _time_factor(term, t: float) -> float:
+    return term.amp * math.cos(term.omega * t + term.phase)
 
 
 class _Lambda:
@@ -169,8 +187,17 @@ class TTSolver:
                  rmax: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                  cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor",
                  replay=None, cross_drop: float = 1e-13, eps_rule: str = "fixed",
-                 c_eps: float = 1.0):
-        self.n, self.scheme, self.nonlinear, self.periodic = n, scheme, nonlinear, periodic
+                 c_eps: float = 1.0, bc=None, terms=(), t0: float = 0.0):
+        self.n, self.scheme, self.nonlinear = n, scheme, nonlinear
+        self.bc = tuple(bc) if bc is not None else \
+            (("periodic", "periodic") if periodic else ("wall", "wall"))
+        if any(b not in ("periodic", "wall", "exact") for b in self.bc) or \
+                self.bc.count("exact") > 1:
+            raise ValueError(f"bad boundary kinds {self.bc}")
+        if "exact" in self.bc and scheme == "weno5":
+            raise NotImplementedError("exact-solution boundaries are built for Upwind3/5")
+        self.terms = list(terms)
+        self.t = t0                        # time at the start of the next step
         self.g, self.H, self.f = g, H, f
         self.eps, self.rmax, self.K = eps, rmax, taylor_terms
         if eps_rule not in ("fixed", "paper"):
@@ -184,7 +211,7 @@ class TTSolver:
         self.dx = 1.0 / n
         self.tab = stencils.tables(scheme)
         self.nq = self.tab["nq"]
-        self.nf = n if periodic else n + 1
+        self.nf_axis = [n if b == "periodic" else n + 1 for b in self.bc]
         k = self.tab["k"]
         self.face_w = np.asarray(self.tab["face_full"])       # offsets -k..k, at +1/2
         self.quad_w = [np.asarray(w) for w in self.tab["quad_full"]]
@@ -203,18 +230,24 @@ class TTSolver:
     def rnd(self, X: TT) -> TT:
         return tt_round(X, self.eps, self.rmax)
 
-    def face_cores(self, A: np.ndarray, sign: float):
-        """(Rf- A, Rf+ A): face values of every column of the core, n_f x r each."""
-        E = extend(A, self.periodic, sign)
-        f = np.arange(self.nf)
+    def face_cores(self, A: np.ndarray, sign: float, axis: int = 0, explicit=None):
+        """(Rf- A, Rf+ A): face values of every column of the core along `axis`, n_f x r each;
+        `explicit` (n + 6 rows, already extended) is appended as further columns."""
+        E = extend(A, self.bc[axis], sign)
+        if explicit is not None:
+            E = np.concatenate([E, explicit], axis=1)
+        f = np.arange(self.nf_axis[axis])
         k = self.k
         m = sum(self.face_w[o + k] * E[NG + f - 1 + o] for o in range(-k, k + 1))
         p = sum(self.face_w[o + k] * E[NG + f - o] for o in range(-k, k + 1))
         return m, p
 
-    def quad_core(self, B: np.ndarray, sign: float) -> np.ndarray:
-        """Gauss-point values of every column, rows j*nq + m, (n*nq) x r."""
-        E = extend(B, self.periodic, sign)
+    def quad_core(self, B: np.ndarray, sign: float, axis: int = 1, explicit=None) -> np.ndarray:
+        """Gauss-point values of every column along `axis`, rows j*nq + m, (n*nq) x r;
+        `explicit` (n + 6 rows, already extended) is appended as further columns."""
+        E = extend(B, self.bc[axis], sign)
+        if explicit is not None:
+            E = np.concatenate([E, explicit], axis=1)
         j = np.arange(self.n)
         k = self.k
         out = np.stack([sum(w[o + k] * E[NG + j + o] for o in range(-k, k + 1))
@@ -243,13 +276,40 @@ class TTSolver:
         return X
 
     # -- one direction -----------------------------------------------------------
-    def states(self, Q, site_base: int):
-        """Face-quadrature states (minus, plus) of the three variables."""
+    def ghost_columns(self, var: int, d: int, t: float):
+        """The ghost terms of natural variable `var` at time t in direction-d orientation:
+        (normal-axis columns, tangent-axis columns), each (n + 6) x J and already extended."""
+        n = self.n
+        sgn = ((1.0, -1.0, 1.0), (1.0, 1.0, -1.0))    # momentum normal to each axis flips
+        cols = ([], [])
+        for tm in self.terms:
+            if tm.var != var or tm.where == "forcing":
+                continue
+            ax = 0 if tm.where.startswith("x") else 1
+            ghost = np.zeros(n + 2 * NG)
+            vals = _time_factor(tm, t) * np.asarray(tm.X if ax == 0 else tm.Y, dtype=float)
+            if tm.where.endswith("lo"):
+                ghost[:NG] = vals
+            else:
+                ghost[n + NG:] = vals
+            other = np.asarray(tm.Y if ax == 0 else tm.X, dtype=float)[:, None]
+            other = extend(other, self.bc[1 - ax], sgn[1 - ax][var])[:, 0]
+            by_axis = {ax: ghost, 1 - ax: other}
+            cols[0].append(by_axis[d])
+            cols[1].append(by_axis[1 - d])
+        if not cols[0]:
+            return None, None
+        return np.stack(cols[0], axis=1), np.stack(cols[1], axis=1)
+
+    def states(self, Q, site_base: int, d: int = 0, t: float = 0.0):
+        """Face-quadrature states (minus, plus) of the three variables, direction d."""
         qm, qp = [], []
         if self.scheme != "weno5":
+            natural = (0, 1, 2) if d == 0 else (0, 2, 1)
             for c, q in enumerate(Q):
-                Am, Ap = self.face_cores(q.A, SIGN_NORMAL[c])
-                Bq = self.quad_core(q.B, SIGN_TANGENT[c])
+                gn, gt = self.ghost_columns(natural[c], d, t)
+                Am, Ap = self.face_cores(q.A, SIGN_NORMAL[c], d, gn)
+                Bq = self.quad_core(q.B, SIGN_TANGENT[c], 1 - d, gt)
                 qm.append(TT(Am, Bq))
                 qp.append(TT(Ap, Bq))
             return qm, qp
@@ -259,20 +319,22 @@ class TTSolver:
             out = []
             for side_i, side in enumerate((-1, 1)):
                 site = site_base + 16 + c * 4 + side_i
-                v = self._cross(_WenoFace(q, self.periodic, SIGN_NORMAL[c], side, self.nf,
-                                          self.tab, eps_w), self.nf, self.n, q, site)
+                nf = self.nf_axis[d]
+                v = self._cross(_WenoFace(q, self.bc[d], SIGN_NORMAL[c], side, nf,
+                                          self.tab, eps_w), nf, self.n, q, site)
                 # initial columns for Step 2: v's second core repeated for every Gauss point
                 y0 = TT(v.A, np.repeat(v.B, self.nq, axis=0))
-                w = self._cross(_WenoQuad(v, self.periodic, SIGN_TANGENT[c], self.n, self.tab,
-                                          eps_w), self.nf, nn, y0, site + 2)
+                w = self._cross(_WenoQuad(v, self.bc[1 - d], SIGN_TANGENT[c], self.n, self.tab,
+                                          eps_w), nf, nn, y0, site + 2)
                 out.append(w)
             qm.append(out[0])
             qp.append(out[1])
         return qm, qp
 
-    def face_flux(self, Q, site_base: int):
+    def face_flux(self, Q, site_base: int, d: int = 0, t: float = 0.0):
         """Fhat for the direction whose normal core is the first core: 3 TTs n_f x (n*nq)."""
-        qm, qp = self.states(Q, site_base)
+        qm, qp = self.states(Q, site_base, d, t)
+        nf = self.nf_axis[d]
         if not self.nonlinear:
             g, H = self.g, self.H
             c = math.sqrt(g * H)
@@ -286,7 +348,7 @@ class TTSolver:
         F = {}
         for si, (s, (h, m, t)) in enumerate((("m", qm), ("p", qp))):
             if self.recip == "cross":
-                rh = self._cross(_Recip(h), self.nf, self.n * self.nq, h, site_base + 8 + si)
+                rh = self._cross(_Recip(h), nf, self.n * self.nq, h, site_base + 8 + si)
             else:
                 rh, err, terms = reciprocal(h, self.eps, self.K, self.rmax)
                 self.stats["taylor_terms"].append(terms)
@@ -301,7 +363,7 @@ class TTSolver:
         hm, mm = qm[0], qm[1]
         hp, mp = qp[0], qp[1]
         y0 = mm if norm(mm) > 0.0 else hm
-        lam = self._cross(_Lambda(hm, mm, hp, mp, g), self.nf, self.n * self.nq, y0, site_base)
+        lam = self._cross(_Lambda(hm, mm, hp, mp, g), nf, self.n * self.nq, y0, site_base)
         out = []
         for c in range(3):
             dq = add([(1.0, qp[c]), (-1.0, qm[c])])
@@ -309,19 +371,19 @@ class TTSolver:
             out.append(self.rnd(add([(0.5, F["m"][c]), (0.5, F["p"][c]), (-0.5, D)])))
         return out
 
-    def finish(self, Fh: TT) -> TT:
+    def finish(self, Fh: TT, d: int = 0) -> TT:
         """Gauss-Legendre sum on the second core, (T - 1) on the first core."""
         w = np.asarray(self.tab["gl_weights"])
         B = np.tensordot(Fh.B.reshape(self.n, self.nq, -1), w, axes=([1], [0]))
         A = Fh.A
-        dA = (np.roll(A, -1, axis=0) - A) if self.periodic else (A[1:] - A[:-1])
+        dA = (np.roll(A, -1, axis=0) - A) if self.bc[d] == "periodic" else (A[1:] - A[:-1])
         return TT(dA, B)
 
-    def L(self, Q, stage: int):
-        """Right-hand side as three TTs (concatenations, not rounded)."""
-        Fx = [self.finish(F) for F in self.face_flux(Q, site_base=(0 * 3 + stage) << 6)]
+    def L(self, Q, stage: int, t: float = 0.0):
+        """Right-hand side as three TTs (concatenations, not rounded) at stage time t."""
+        Fx = [self.finish(F, 0) for F in self.face_flux(Q, (0 * 3 + stage) << 6, 0, t)]
         Qy = [Q[0].T(), Q[2].T(), Q[1].T()]
-        Gy = [self.finish(F) for F in self.face_flux(Qy, site_base=(1 * 3 + stage) << 6)]
+        Gy = [self.finish(F, 1) for F in self.face_flux(Qy, (1 * 3 + stage) << 6, 1, t)]
         G = [Gy[0].T(), Gy[2].T(), Gy[1].T()]
         dx = self.dx
         out = []
@@ -331,12 +393,17 @@ class TTSolver:
                 terms.append((self.f, Q[2]))
             if self.f != 0.0 and c == 2:
                 terms.append((-self.f, Q[1]))
+            for tm in self.terms:
+                if tm.var == c and tm.where == "forcing":
+                    terms.append((_time_factor(tm, t),
+                                  TT(np.asarray(tm.X, dtype=float)[:, None],
+                                     np.asarray(tm.Y, dtype=float)[:, None])))
             out.append(add(terms))
         return out
 
-    def euler(self, Q, dt: float, stage: int):
-        """F(q) = round(q + dt L(q))."""
-        Lq = self.L(Q, stage)
+    def euler(self, Q, dt: float, stage: int, t: float = 0.0):
+        """F(q) = round(q + dt L(q)), L at stage time t."""
+        Lq = self.L(Q, stage, t)
         return [tt_round(add([(1.0, q), (dt, l)]), e, self.rmax)
                 for q, l, e in zip(Q, Lq, self.eps_q)]
 
@@ -346,14 +413,17 @@ class TTSolver:
                                                     self.c_eps)
             self.stats["eps"].append((self.eps, list(self.eps_q)))
         e = self.eps_q
-        Q1 = self.euler(Q, dt, 0)
-        F1 = self.euler(Q1, dt, 1)
+        t = self.t
+        # stage times of SSP-RK3: t, t + dt, t + dt/2
+        Q1 = self.euler(Q, dt, 0, t)
+        F1 = self.euler(Q1, dt, 1, t + dt)
         Q2 = [tt_round(add([(0.75, q), (0.25, f)]), e[c], self.rmax)
               for c, (q, f) in enumerate(zip(Q, F1))]
-        F2 = self.euler(Q2, dt, 2)
+        F2 = self.euler(Q2, dt, 2, t + 0.5 * dt)
         Qn = [tt_round(add([(1.0 / 3.0, q), (2.0 / 3.0, f)]), e[c], self.rmax)
               for c, (q, f) in enumerate(zip(Q, F2))]
         self.step_index += 1
+        self.t = t + dt
         self.stats["ranks"].append([q.rank for q in Qn])
         return Qn
 

@@ -382,3 +382,251 @@ def inertia_gravity(n: int = 1280, scheme: str = "upwind5", rmax: int = 16,
             "ranks": [t.rank for t in tt]}
     return State("inertia_gravity", n, False, True, g, H, fields, tt,
                  table1_dt("inertia_gravity", scheme, n), meta)
+
+
+# ---------------------------------------------------------------------------
+# boundary data and forcing as separable terms with a harmonic time factor
+
+
+@dataclasses.dataclass
+class Term:
+    """amp cos(omega t + phase) X (x) Y (y) added to variable `var`.
+
+    where = "forcing": X (n cells along x), Y (n cells along y), added to L.
+    where = "x_lo" / "x_hi": ghost cells -3, -2, -1 / n, n+1, n+2 along x (X, 3 values,
+    ascending) times Y (n cells along y).  "y_lo" / "y_hi": X (n cells along x) times the
+    ghost cells along y (Y, 3 values)."""
+    var: int
+    where: str
+    amp: float
+    omega: float
+    phase: float
+    X: np.ndarray
+    Y: np.ndarray
+
+
+def _cells(n: int, lo: int, hi: int):
+    """Left and right edges of cells lo .. hi-1 of an n-cell unit interval."""
+    h = 1.0 / n
+    i = np.arange(lo, hi)
+    return i * h, (i + 1) * h
+
+
+def _avg_trig(n: int, k: float, lo: int, hi: int):
+    """Exact cell averages of (cos(k x), sin(k x)) over cells lo .. hi-1."""
+    a, b = _cells(n, lo, hi)
+    if k == 0.0:
+        return np.ones(hi - lo), np.zeros(hi - lo)
+    h = 1.0 / n
+    return (np.sin(k * b) - np.sin(k * a)) / (k * h), (np.cos(k * a) - np.cos(k * b)) / (k * h)
+
+
+def _avg_exp(n: int, R: float, lo: int, hi: int):
+    """Exact cell averages of exp(-x / R) over cells lo .. hi-1."""
+    a, b = _cells(n, lo, hi)
+    return R * (np.exp(-a / R) - np.exp(-b / R)) * n
+
+
+@dataclasses.dataclass
+class Case:
+    """A Section 5 case: initial state, boundary kinds per axis, separable ghost/forcing terms
+    and the exact cell averages at time t (for the accuracy checks)."""
+    state: State
+    bc: tuple
+    terms: list
+    exact: object          # t -> list of three (n, n) arrays
+    T: float               # final time (nondimensional)
+
+
+def _factored_state(name, n, nonlinear, bc, g, H, factors, dt, meta, rmax):
+    tt = [compress(X, Y, 1e-15, rmax) if X is not None else _zero(n) for X, Y in factors]
+    fields = [X @ Y.T if X is not None else np.zeros((n, n)) for X, Y in factors]
+    return State(name, n, nonlinear, bc == ("periodic", "periodic"), g, H, fields, tt, dt, meta)
+
+
+def coastal_kelvin(n: int = 1280, scheme: str = "upwind5", rmax: int = 16) -> Case:
+    """Section 5.1: linear SWE, L = 5e6 m, H = 1000 m, R = c/f; two modes
+    eta = -H eta_m sin(k_m (y + c t)) exp(-x/R), u = 0, v = sqrt(g H) eta_m sin(...) exp(-x/R)
+    with eta_1 = eta_2/2 = 1e-4 and k_1 = k_2/2 = 2 pi/L (the second mode takes k_2, the paper's
+    formula repeats k_1); x boundaries from the exact solution, y periodic; T = 3 hours."""
+    g, H, f, t_ref = nondim("coastal_kelvin", 1000.0)
+    Lr, Ur, Hr = SCALES["coastal_kelvin"]
+    c = math.sqrt(g * H)
+    R = c / f
+    modes = [(1e-4, 2.0 * math.pi), (2e-4, 4.0 * math.pi)]
+    # nondimensional amplitudes of eta and v per mode
+    amps = [(-1000.0 * e / Hr, 100.0 * e / Ur, k) for e, k in modes]
+
+    def factors(t, lo=0, hi=None):
+        hi = n if hi is None else hi
+        ex = _avg_exp(n, R, lo, hi)
+        out = {0: ([], []), 2: ([], [])}
+        for ae, av, k in amps:
+            cy, sy = _avg_trig(n, k, 0, n)
+            # sin(k (y + c t)) = sin(k y) cos(k c t) + cos(k y) sin(k c t)
+            prof = sy * math.cos(k * c * t) + cy * math.sin(k * c * t)
+            for var, a in ((0, ae), (2, av)):
+                out[var][0].append(a * ex)
+                out[var][1].append(prof)
+        return out
+
+    def exact(t):
+        fac = factors(t)
+        return [np.stack(fac[0][0], 1) @ np.stack(fac[0][1], 1).T, np.zeros((n, n)),
+                np.stack(fac[2][0], 1) @ np.stack(fac[2][1], 1).T]
+
+    terms = []
+    for side, (lo, hi) in (("x_lo", (-NG_CELLS, 0)), ("x_hi", (n, n + NG_CELLS))):
+        ex = _avg_exp(n, R, lo, hi)
+        for ae, av, k in amps:
+            cy, sy = _avg_trig(n, k, 0, n)
+            for var, a in ((0, ae), (2, av)):
+                terms.append(Term(var, side, a, k * c, 0.0, ex, sy))              # sin ky cos wt
+                terms.append(Term(var, side, a, k * c, -0.5 * math.pi, ex, cy))   # cos ky sin wt
+    fac0 = factors(0.0)
+    fx = [(np.stack(fac0[0][0], 1), np.stack(fac0[0][1], 1)), (None, None),
+          (np.stack(fac0[2][0], 1), np.stack(fac0[2][1], 1))]
+    ratio, c_eps = TABLE1["coastal_kelvin"][scheme]
+    st = _factored_state("coastal_kelvin", n, False, ("exact", "periodic"), g, H, fx,
+                         table1_dt("coastal_kelvin", scheme, n),
+                         {"f": f, "c_eps": c_eps, "scheme": scheme, "t_ref": t_ref}, rmax)
+    return Case(st, ("exact", "periodic"), terms, exact, 3.0 * 3600.0 / t_ref)
+
+
+def barotropic_tide(n: int = 1280, scheme: str = "upwind5", rmax: int = 16) -> Case:
+    """Section 5.3: linear SWE, L = 25e4 m, H = 200 m; two modes
+    eta = eta_m cos(k_m x) cos(w_m t), u = g eta_m w_m k_m / (w_m^2 - f^2) sin(k_m x) sin(w_m t),
+    v = g eta_m f k_m / (w_m^2 - f^2) sin(k_m x) cos(w_m t), w_m = sqrt(g H k_m^2 + f^2) (the
+    paper's w-hat read as w), eta_1 = eta_2/2 = 0.2 m, k_m = 2 pi / lambda_m with
+    lambda_1 = 4L/5, lambda_2 = 4L/9; x boundaries from the exact solution, y periodic;
+    T = 30 minutes."""
+    g, H, f, t_ref = nondim("barotropic_tide", 200.0)
+    Lr, Ur, Hr = SCALES["barotropic_tide"]
+    modes = [(0.2 / Hr, 2.0 * math.pi * 5.0 / 4.0), (0.4 / Hr, 2.0 * math.pi * 9.0 / 4.0)]
+    ones = np.ones(n)
+    spec = []     # (var, amplitude, k, x function "cos"/"sin", omega, phase)
+    for a, k in modes:
+        w = math.sqrt(g * H * k * k + f * f)
+        s = g * a / (w * w - f * f)
+        spec.append((0, a, k, 0, w, 0.0))
+        spec.append((1, s * w * k, k, 1, w, -0.5 * math.pi))
+        spec.append((2, s * f * k, k, 1, w, 0.0))
+
+    def exact(t):
+        out = [np.zeros((n, n)) for _ in range(3)]
+        for var, a, k, fx, w, ph in spec:
+            out[var] += a * math.cos(w * t + ph) * np.outer(_avg_trig(n, k, 0, n)[fx], ones)
+        return out
+
+    terms = []
+    for side, (lo, hi) in (("x_lo", (-NG_CELLS, 0)), ("x_hi", (n, n + NG_CELLS))):
+        for var, a, k, fx, w, ph in spec:
+            terms.append(Term(var, side, a, w, ph, _avg_trig(n, k, lo, hi)[fx], ones))
+    fac = []
+    for var in range(3):
+        cols = [(a if ph == 0.0 else 0.0) * _avg_trig(n, k, 0, n)[fx]
+                for v, a, k, fx, w, ph in spec if v == var]
+        X = np.stack(cols, 1)
+        fac.append((X, np.ones((n, X.shape[1]))) if np.any(X) else (None, None))
+    ratio, c_eps = TABLE1["barotropic_tide"][scheme]
+    st = _factored_state("barotropic_tide", n, False, ("exact", "periodic"), g, H, fac,
+                         table1_dt("barotropic_tide", scheme, n),
+                         {"f": f, "c_eps": c_eps, "scheme": scheme, "t_ref": t_ref}, rmax)
+    return Case(st, ("exact", "periodic"), terms, exact, 30.0 * 60.0 / t_ref)
+
+
+def _theta_series(fun, mmax: int = 4, samples: int = 32):
+    """Fourier coefficients (a_m, b_m), m = 0..mmax, of a trigonometric polynomial of theta:
+    fun(th) = sum a_m cos(m th) + b_m sin(m th), from equispaced samples (numpy FFT)."""
+    th = 2.0 * math.pi * np.arange(samples) / samples
+    F = np.fft.rfft(fun(th)) / samples
+    a = [float(F[0].real)] + [float(2.0 * F[m].real) for m in range(1, mmax + 1)]
+    b = [0.0] + [float(-2.0 * F[m].imag) for m in range(1, mmax + 1)]
+    return a, b
+
+
+def manufactured(n: int = 1280, scheme: str = "upwind5", rmax: int = 32) -> Case:
+    """Section 5.4: nonlinear SWE, periodic, L = 1e7 m; h = H + eta with
+    eta = eta_hat sin(th), u = u_hat cos(th), v = 0, th = kx x + ky y - w t, kx = ky = 2 pi/L,
+    w = c |k| (c = sqrt(g H), H = 1000 m), eta_hat = 1e-2 m, u_hat = 1e-2 m/s; T = 3 hours.
+    The forcing dQ/dt + dF/dx + dG/dy - S (S the Coriolis source) depends on th only; it is a
+    trigonometric polynomial of degree 3, expanded by FFT of its complex-step values, and each
+    harmonic becomes separable terms with exact cell averages."""
+    g, H, f, t_ref = nondim("manufactured", 1000.0)
+    Lr, Ur, Hr = SCALES["manufactured"]
+    a, b = 1e-2 / Hr, 1e-2 / Ur
+    kx = ky = 2.0 * math.pi
+    w = math.sqrt(g * H * (kx * kx + ky * ky))
+
+    def Q(th):
+        h = H + a * np.sin(th)
+        return [h, h * b * np.cos(th), 0.0 * th]
+
+    def FG(th):
+        h, hu, hv = Q(th)
+        F = [hu, hu * hu / h + 0.5 * g * h * h, hu * hv / h]
+        G = [hv, hu * hv / h, hv * hv / h + 0.5 * g * h * h]
+        return F, G
+
+    def forcing(var):
+        def fun(th):
+            d = 1e-30
+            z = th + 1j * d
+            dq = np.imag(Q(z)[var]) / d
+            F, G = FG(z)
+            dF, dG = np.imag(F[var]) / d, np.imag(G[var]) / d
+            h, hu, hv = Q(th)
+            S = [0.0 * th, f * hv, -f * hu][var]
+            return -w * dq + kx * dF + ky * dG - S
+        return fun
+
+    def plane(m, t, c_cos, c_sin):
+        """Separable factors of c_cos cos(m th) + c_sin sin(m th) at time t (cell averages)."""
+        X, Y = plane_factors(n, m * kx, m * ky, m * w * t, c_cos, c_sin)
+        return X, Y
+
+    terms = []
+    for var in range(3):
+        ac, bs = _theta_series(forcing(var))
+        for m in range(len(ac)):
+            if abs(ac[m]) + abs(bs[m]) < 1e-300:
+                continue
+            if m == 0:
+                terms.append(Term(var, "forcing", ac[0], 0.0, 0.0, np.ones(n), np.ones(n)))
+                continue
+            # cos(m th) = cos(m phi) cos(m w t) + sin(m phi) sin(m w t), phi = kx x + ky y;
+            # sin(m th) = sin(m phi) cos(m w t) - cos(m phi) sin(m w t)
+            cxs, sxs = _avg_trig(n, m * kx, 0, n)
+            cys, sys_ = _avg_trig(n, m * ky, 0, n)
+            cosphi = [(cxs, cys, 1.0), (sxs, sys_, -1.0)]      # cos(mphi) = cx cy - sx sy
+            sinphi = [(sxs, cys, 1.0), (cxs, sys_, 1.0)]       # sin(mphi) = sx cy + cx sy
+            om = m * w
+            for (X, Y, sg) in cosphi:
+                terms.append(Term(var, "forcing", sg * ac[m], om, 0.0, X, Y))
+                terms.append(Term(var, "forcing", -sg * bs[m], om, -0.5 * math.pi, X, Y))
+            for (X, Y, sg) in sinphi:
+                terms.append(Term(var, "forcing", sg * ac[m], om, -0.5 * math.pi, X, Y))
+                terms.append(Term(var, "forcing", sg * bs[m], om, 0.0, X, Y))
+
+    def exact(t):
+        Xh, Yh = plane(1, t, 0.0, a)
+        Xu, Yu = plane(1, t, 1.0, 0.0)
+        hfield = H + Xh @ Yh.T
+        # h u = H u_hat cos(th) + a u_hat sin(th) cos(th) = H u_hat cos(th) + a u_hat/2 sin(2 th)
+        X1, Y1 = plane(1, t, H * b, 0.0)
+        X2, Y2 = plane(2, t, 0.0, 0.5 * a * b)
+        return [hfield, X1 @ Y1.T + X2 @ Y2.T, np.zeros((n, n))]
+
+    Xh, Yh = plane(1, 0.0, 0.0, a)
+    X1, Y1 = plane(1, 0.0, H * b, 0.0)
+    X2, Y2 = plane(2, 0.0, 0.0, 0.5 * a * b)
+    fac = [(np.concatenate([np.full((n, 1), H), Xh], 1), np.concatenate([np.ones((n, 1)), Yh], 1)),
+           (np.concatenate([X1, X2], 1), np.concatenate([Y1, Y2], 1)), (None, None)]
+    ratio, c_eps = TABLE1["manufactured"][scheme]
+    st = _factored_state("manufactured", n, True, ("periodic", "periodic"), g, H, fac,
+                         table1_dt("manufactured", scheme, n),
+                         {"f": f, "c_eps": c_eps, "scheme": scheme, "t_ref": t_ref}, rmax)
+    return Case(st, ("periodic", "periodic"), terms, exact, 3.0 * 3600.0 / t_ref)
+
+
+NG_CELLS = 3

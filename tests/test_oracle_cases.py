@@ -1,0 +1,101 @@
+"""Pins for Section 5's analytic cases as inputs (Table 2 scales, Table 1 steps) and for the
+oracle's exact-solution boundaries and forcing terms.
+
+The full-grid oracle with the cases' ghost terms (Kelvin wave, barotropic tide; x boundaries
+from the exact solution) or forcing terms (manufactured solution) must converge to the closed
+forms at the scheme's formal order: a wrong closed form, ghost value, sign or forcing harmonic
+leaves an O(1) error or an order-one boundary error.  The TT oracle with the same terms must
+then equal the full-grid oracle at round-off tolerances, which pins its ghost columns and
+forcing TTs against the plain padded-array definition."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fv_grid
+from oracle.tt import TT
+from oracle.tt_fv import TTSolver
+
+
+def _rel(U, V):
+    return math.sqrt(sum(float(np.sum((a - b) ** 2)) for a, b in zip(U, V)) /
+                     sum(float(np.sum(b * b)) for b in V))
+
+
+def _run_grid(case, scheme, n_steps, dt):
+    st = case.state
+    s = fv_grid.GridSolver(st.n, scheme, nonlinear=st.nonlinear, g=st.g, H=st.H0,
+                           f=st.meta["f"], bc=case.bc, terms=case.terms)
+    return s.run([x.copy() for x in st.fields], dt, n_steps)
+
+
+def _speed(case):
+    st = case.state
+    c = math.sqrt(st.g * (st.H0 if not st.nonlinear else float(np.max(st.fields[0]))))
+    u = max(float(np.max(np.abs(st.fields[1]))), float(np.max(np.abs(st.fields[2]))))
+    if st.nonlinear:
+        u = u / float(np.min(st.fields[0]))
+    return c + u
+
+
+@pytest.mark.parametrize("name,scheme,order", [
+    ("coastal_kelvin", "upwind3", 3), ("coastal_kelvin", "upwind5", 5),
+    ("barotropic_tide", "upwind3", 3), ("barotropic_tide", "upwind5", 5),
+    ("manufactured", "upwind3", 3), ("manufactured", "upwind5", 5),
+])
+def test_full_grid_converges_to_the_closed_form(name, scheme, order):
+    """Errors at n = 24 and 48 over a fixed time with dt ~ dx (Upwind3) or dx^(5/3): the
+    observed order is within 0.5 of the formal one."""
+    make = getattr(synth, name)
+    errs = []
+    for n in (24, 48):
+        case = make(n, scheme)
+        T = 0.1 * case.T if name != "barotropic_tide" else 0.05 * case.T
+        v = _speed(case)
+        dt0 = 0.3 / n / v if scheme == "upwind3" else 0.3 * (1.0 / 24) ** (-2.0 / 3.0) * \
+            (1.0 / n) ** (5.0 / 3.0) / v
+        nsteps = int(math.ceil(T / dt0))
+        U = _run_grid(case, scheme, nsteps, T / nsteps)
+        errs.append(_rel(U, case.exact(T)))
+    rate = math.log2(errs[0] / errs[1])
+    assert rate > order - 0.5, (errs, rate)
+    assert errs[1] < 1e-3, errs
+
+
+def test_kelvin_boundary_terms_matter():
+    """Replacing the exact x boundaries by walls or dropping the ghost terms breaks the Kelvin
+    wave, so the convergence above is carried by the ghost terms."""
+    case = synth.coastal_kelvin(32, "upwind5")
+    st = case.state
+    T = 0.1 * case.T
+    dt = 0.3 / 32 / _speed(case)
+    nsteps = int(math.ceil(T / dt))
+    ref = case.exact(T)
+    good = _rel(_run_grid(case, "upwind5", nsteps, T / nsteps), ref)
+    walls = fv_grid.GridSolver(32, "upwind5", False, g=st.g, H=st.H0, f=st.meta["f"],
+                               bc=("wall", "periodic"))
+    bad1 = _rel(walls.run([x.copy() for x in st.fields], T / nsteps, nsteps), ref)
+    zero = fv_grid.GridSolver(32, "upwind5", False, g=st.g, H=st.H0, f=st.meta["f"],
+                              bc=("exact", "periodic"), terms=[])
+    bad2 = _rel(zero.run([x.copy() for x in st.fields], T / nsteps, nsteps), ref)
+    assert bad1 > 20 * good and bad2 > 20 * good, (good, bad1, bad2)
+
+
+@pytest.mark.parametrize("name,scheme", [
+    ("coastal_kelvin", "upwind3"), ("coastal_kelvin", "upwind5"),
+    ("barotropic_tide", "upwind5"), ("manufactured", "upwind3"), ("manufactured", "upwind5"),
+])
+def test_tt_oracle_equals_full_grid_with_terms(name, scheme):
+    """TT oracle (tolerance 0, no effective cap, Taylor to round-off, full-rank crosses)
+    against the full-grid oracle over 3 steps: ghost columns and forcing TTs reproduce the
+    padded-array scheme."""
+    n = 20
+    case = getattr(synth, name)(n, scheme, rmax=48)
+    st = case.state
+    dt = 0.3 / n / _speed(case)
+    U = _run_grid(case, scheme, 3, dt)
+    s = TTSolver(n, scheme, st.nonlinear, g=st.g, H=st.H0, f=st.meta["f"], eps=0.0, rmax=48,
+                 taylor_terms=60, cross_full=True, bc=case.bc, terms=case.terms)
+    Q = s.run([TT(x.A, x.B) for x in st.tt], dt, 3)
+    assert _rel([q.A @ q.B.T for q in Q], U) < 1e-10
