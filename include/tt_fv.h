@@ -198,7 +198,36 @@ typedef struct {
                          the cell averages on the unit square (dx times the Frobenius norm of
                          the n x n array); a zero state takes 1e-3.  `eps` is then unused.  */
   double c_eps;       /* C_eps of the paper's rule (> 0; Table 1 lists it per case/scheme)  */
+  int bc_x, bc_y;     /* boundary of each axis: 0 = as `periodic` says, TT_BC_PERIODIC,
+                         TT_BC_WALL, or TT_BC_EXACT (ghost cells from the TT_TERM_X_* /
+                         TT_TERM_Y_* terms of tt_fv_set_terms, Section 5's exact-solution
+                         boundaries; at most one axis, Upwind3/5 only)                      */
+  double t0;          /* time at the start of the first step (for the terms' time factors) */
 } tt_fv_params;
+#define TT_BC_PERIODIC 1
+#define TT_BC_WALL     2
+#define TT_BC_EXACT    3
+
+/* A separable term amp cos(omega t + phase) X (x) Y (y) of variable `var` (0..2), t the stage
+ * time of SSP-RK3 (t, t + dt, t + dt/2 from the step's start).  `where`:
+ *   TT_TERM_FORCING: added to L(Q) (a manufactured solution's forcing, Section 5.4); X has n
+ *                    values along x, Y n values along y (cell averages);
+ *   TT_TERM_X_LO / TT_TERM_X_HI: ghost cells -3, -2, -1 / n, n+1, n+2 along x on an exact x
+ *                    boundary (X, 3 values, ascending) times Y (n cells along y);
+ *   TT_TERM_Y_LO / TT_TERM_Y_HI: X (n cells along x) times the ghost cells along y (Y, 3).
+ * Ghost cells sum the terms of their side; corners follow the other axis's rule. */
+typedef struct {
+  int var;
+  int where;
+  double amp, omega, phase;
+  const double *X;    /* host */
+  const double *Y;    /* host */
+} tt_fv_term;
+#define TT_TERM_FORCING 0
+#define TT_TERM_X_LO    1
+#define TT_TERM_X_HI    2
+#define TT_TERM_Y_LO    3
+#define TT_TERM_Y_HI    4
 #define TT_EPS_FIXED 0
 #define TT_EPS_PAPER 1
 
@@ -227,6 +256,7 @@ typedef struct {
                                  because a Cholesky QR ended without orthonormal columns   */
   double eps_inner;           /* tolerance of the last step's roundings inside L(Q)        */
   double eps_var[3];          /* tolerances of its time-stepping roundings, per variable   */
+  double time;                /* time reached (t0 + dt of every step taken)                */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build
@@ -235,6 +265,10 @@ int  tt_fv_init(tt_fv **out, const tt_fv_params *p, const tt_matrix q0[3], void 
                 size_t arena_bytes);
 /* Advance nsteps SSP-RK3 steps of size dt. */
 int  tt_fv_step(tt_fv *s, double dt, int nsteps);
+/* Replace the solver's separable forcing and boundary terms (copied; count 0 clears them).
+ * Errors: TT_EINVAL for a bad var or where, a null factor, or ghost terms on a non-exact
+ * axis. */
+int  tt_fv_set_terms(tt_fv *s, const tt_fv_term *terms, int count);
 /* Copy the state into caller buffers (cap >= rank). */
 int  tt_fv_get_state(tt_fv *s, tt_matrix q[3]);
 int  tt_fv_get_stats(tt_fv *s, tt_fv_stats *out);
@@ -254,9 +288,12 @@ void tt_fv_destroy(tt_fv *s);
  * rounding) on n x n arrays of cell averages, the full-tensor form of Section 4.1 that the
  * paper's speed-ups are measured against.  One fused kernel per RK stage. */
 typedef struct tt_grid tt_grid;
-/* Uses n, nonlinear, scheme, periodic, g, H0 and f of `p` (the other fields are ignored).
- * Allocates two stage buffers of 3 n^2 doubles once here; work runs on hip_stream. */
+/* Uses n, nonlinear, scheme, periodic, bc_x, bc_y, t0, g, H0 and f of `p` (the other fields
+ * are ignored; exact boundaries work with every scheme here).  Allocates two stage buffers of
+ * 3 n^2 doubles once here; work runs on hip_stream. */
 int  tt_grid_init(tt_grid **out, const tt_fv_params *p, void *hip_stream);
+/* Replace the comparator's separable forcing and boundary terms (as tt_fv_set_terms). */
+int  tt_grid_set_terms(tt_grid *s, const tt_fv_term *terms, int count);
 /* Advance U nsteps SSP-RK3 steps of size dt in place.  U: device, 3 x n x n doubles, variable
  * major, then the x cell, then the y cell (y contiguous), the variables of tt_fv_params'
  * equation set.  Enqueues the stage kernels on the solver's stream and returns; the caller

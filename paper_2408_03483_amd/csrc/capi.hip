@@ -18,6 +18,7 @@ void solver_destroy(Solver *s);
 void solver_time_kernel(Solver *s, const char *name, int every);
 void solver_set_pivots(Solver *s, int mode, PivotModel *pm);
 void solver_set_acceptance(Solver *s, double abs_tol, double rel_slack);
+void solver_set_terms(Solver *s, const tt_fv_term *terms, int count);
 void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,
                           const int *I, int nI);
 int solver_get_pivots(Solver *s, int site, int *J, int capJ, int *nJ, int *I, int capI,
@@ -26,6 +27,7 @@ struct Grid;
 Grid *grid_create(const tt_fv_params *p, void *stream);
 void grid_step(Grid *s, double *U, double dt, int nsteps);
 void grid_destroy(Grid *s);
+void grid_set_terms(Grid *s, const tt_fv_term *terms, int count);
 struct Ensemble;
 Ensemble *ensemble_create(int workers, size_t arena_bytes);
 void ensemble_destroy(Ensemble *e);
@@ -295,7 +297,7 @@ static FiberSpec make_fiber_spec(Ctx &c, int fn, const tt_matrix *inputs, int n_
       TT_REQUIRE(v.n2 == n2 && n1 == (per ? v.n1 : v.n1 + 1) && v.n1 >= 3,
                  "weno face: shapes (n_f x n from an n x n input)");
       double *Ae = c.arena.dalloc((size_t)(v.n1 + 6) * v.rank);
-      ghost_extend(c, v.g1, v.n1, v.rank, per, fparams[1], Ae);
+      ghost_extend(c, v.g1, v.n1, v.rank, per ? Ghost::Periodic : Ghost::Wall, fparams[1], Ae);
       fs.n_in = 1;
       fs.in[0] = {Ae, v.g2, v.n1 + 6, v.n2, v.rank};
       fs.eps_w = fparams[2];
@@ -307,7 +309,8 @@ static FiberSpec make_fiber_spec(Ctx &c, int fn, const tt_matrix *inputs, int n_
     check_matrix(&v, "input", true);
     TT_REQUIRE(v.n1 == n1 && n2 == 3 * v.n2 && v.n2 >= 3, "weno quad: shapes (n_f x 3n)");
     double *Be = c.arena.dalloc((size_t)(v.n2 + 6) * v.rank);
-    ghost_extend(c, v.g2, v.n2, v.rank, fparams[0] != 0.0, fparams[1], Be);
+    ghost_extend(c, v.g2, v.n2, v.rank, fparams[0] != 0.0 ? Ghost::Periodic : Ghost::Wall,
+                 fparams[1], Be);
     fs.n_in = 1;
     fs.in[0] = {v.g1, Be, v.n1, v.n2 + 6, v.rank};
     fs.eps_w = fparams[2];
@@ -530,8 +533,11 @@ int tt_recon_core(tt_ctx *ctx, const double *core, int n, int rank, int scheme, 
     StencilSet st = derive_stencils(scheme);
     const int nf = periodic ? n : n + 1;
     if (face_m && face_p)
-      recon_face(ctx->c, core, n, rank, periodic != 0, sign, st, face_m, face_p, nf);
-    if (quad) recon_quad(ctx->c, core, n, rank, periodic != 0, sign, st, quad);
+      recon_face(ctx->c, core, n, rank, periodic ? Ghost::Periodic : Ghost::Wall, sign, st,
+                 face_m, face_p, nf);
+    if (quad)
+      recon_quad(ctx->c, core, n, rank, periodic ? Ghost::Periodic : Ghost::Wall, sign, st,
+                 quad);
     ctx->c.sync();
     return 0;
   });
@@ -553,6 +559,14 @@ int tt_grid_step(tt_grid *s, double *U, double dt, int nsteps) {
   return guarded([&]() {
     TT_REQUIRE(s, "null grid solver");
     grid_step(s->g, U, dt, nsteps);
+    return 0;
+  });
+}
+
+int tt_grid_set_terms(tt_grid *s, const tt_fv_term *terms, int count) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null grid solver");
+    grid_set_terms(s->g, terms, count);
     return 0;
   });
 }
@@ -581,6 +595,14 @@ int tt_fv_step(tt_fv *s, double dt, int nsteps) {
     tt_fv_stats st{};
     solver_stats(s->s, &st);
     return st.warnings & (TT_WRANKCAP | TT_WNOCONV);
+  });
+}
+
+int tt_fv_set_terms(tt_fv *s, const tt_fv_term *terms, int count) {
+  return guarded([&]() {
+    TT_REQUIRE(s, "null solver");
+    solver_set_terms(s->s, terms, count);
+    return 0;
   });
 }
 

@@ -181,15 +181,18 @@ struct StencilSet {          // weights of the combined linear stencils, offsets
   double quad[3][5] = {{0}}; // value at Gauss point m
   double gw[3] = {0};        // Gauss-Legendre weights (sum 1)
 };
-void recon_face(Ctx &c, const double *A, int n, int r, bool periodic, double sign,
+// ghost cells of a core column along its mode: periodic wrap; mirror times sign (walls);
+// zero (an exact boundary, whose values come as separate columns); or an explicitly extended
+// column of n + 6 rows (cells -3 .. n + 2), which the kernels read as is
+enum class Ghost : int { Periodic = 0, Wall = 1, Zero = 2, Explicit = 3 };
+void recon_face(Ctx &c, const double *A, int n, int r, Ghost rule, double sign,
                 const StencilSet &st, double *Am, double *Ap, int nf);
-void recon_quad(Ctx &c, const double *B, int n, int r, bool periodic, double sign,
+void recon_quad(Ctx &c, const double *B, int n, int r, Ghost rule, double sign,
                 const StencilSet &st, double *Bq);
 void quad_sum(Ctx &c, const double *Bq, int n, int nq, int r, const StencilSet &st, double *Bo);
 void face_diff(Ctx &c, const double *A, int nf, int n, int r, bool periodic, double scale,
                double *Ao, int ldo);
-void ghost_extend(Ctx &c, const double *A, int n, int r, bool periodic, double sign,
-                  double *E);
+void ghost_extend(Ctx &c, const double *A, int n, int r, Ghost rule, double sign, double *E);
 
 // gemm.hip: C = alpha * op(A) * B + beta * C, op = identity or transpose
 void gemm(Ctx &c, bool transA, int M, int N, int K, double alpha, const double *A, int lda,

@@ -23,6 +23,14 @@
 // crosses (eps_in), eq. modified-eps-tt-formula per variable for its time-stepping roundings
 // (eps_q).
 //
+// Boundaries per axis: periodic, walls, or exact (Section 5's exact-solution boundaries): on an
+// exact axis the state's cores are extended by zeros and each separable ghost term
+// amp cos(omega t + phase) X Y becomes further rank columns of the reconstructed TTs (its
+// factor along the exact axis an explicit column of n + 6 rows, zero inside the domain, its
+// other factor extended by the other axis's rule), since the reconstruction is linear.
+// Separable forcing terms add rank-1 TTs to L.  Terms are evaluated at the SSP-RK3 stage
+// times t, t + dt, t + dt/2.
+//
 // Every TT of the step lives in the solver's arena; ranks are known on the host after each
 // rounding (one stream synchronisation per rounding), so every launch has its exact shape.
 #include "common.h"
@@ -48,8 +56,22 @@ struct Solver {
   Pool *exec = nullptr;        // pool the phases run on: the own pool or an ensemble's
   StencilSet st;
   WenoTables wt{};
-  int n = 0, nf = 0, nq = 0;
-  bool periodic = true;
+  int n = 0, nq = 0;
+  // per axis (0 = x, 1 = y): ghost rule of the state's cores, periodic or not, face count
+  Ghost rule_ax[2] = {Ghost::Periodic, Ghost::Periodic};
+  bool periodic_ax[2] = {true, true};
+  int nf_ax[2] = {0, 0};
+  double t = 0.0;              // time at the start of the next step
+  // separable terms on the device: ghost terms keep their exact-axis column (n + 6 rows,
+  // zero inside the domain) in e and their other factor extended by the other axis's rule
+  // (n + 6 rows) in o; forcing terms keep X and Y (n rows each) in e and o
+  struct DevTerm {
+    int var, where;
+    double amp, omega, phase;
+    double *e, *o;
+  };
+  std::vector<DevTerm> terms;
+  double *term_mem = nullptr;
   DTT Q[3];
   std::map<int, std::vector<int>> piv;
   std::mutex mu;               // guards piv and the Taylor statistics
@@ -81,6 +103,10 @@ struct Solver {
   double max_learned_err = 0.0;
 
   ~Solver() {
+    if (term_mem) {
+      (void)hipStreamSynchronize(c.stream);
+      (void)hipFree(term_mem);
+    }
     for (auto &a : aux) {
       if (!a) continue;
       hipStream_t st = a->stream;
@@ -327,27 +353,54 @@ struct Solver {
     last_piv[site] = {J, I};
   }
 
+  static double time_factor(const DevTerm &tm, double tt) {
+    return tm.amp * std::cos(tm.omega * tt + tm.phase);
+  }
+
   // ---- reconstruction -------------------------------------------------------------
-  void states_upwind(Ctx &w, const DTT *Qv, DTT *qm, DTT *qp) {
+  // direction d (the first core of Qv runs along axis d); ghost terms of exact axes become
+  // extra columns after the state's r
+  void states_upwind(Ctx &w, const DTT *Qv, int d, double tt, DTT *qm, DTT *qp) {
+    const int nf = nf_ax[d];
     for (int v = 0; v < 3; ++v) {
+      const int nat = d == 0 ? v : (v == 0 ? 0 : 3 - v);   // natural variable index
+      std::vector<const DevTerm *> gh;
+      for (const DevTerm &tm : terms)
+        if (tm.var == nat && tm.where != TT_TERM_FORCING) gh.push_back(&tm);
       const DTT &q = Qv[v];
-      DTT m = alloc(w, nf, n * nq, q.r);
+      const int J = (int)gh.size(), R = q.r + J;
+      DTT m = alloc(w, nf, n * nq, R);
       DTT pl = m;
-      pl.A = w.arena.dalloc((size_t)nf * q.r);
-      m.r = pl.r = q.r;
-      recon_face(w, q.A, n, q.r, periodic, SIGN_NORMAL[v], st, m.A, pl.A, nf);
-      recon_quad(w, q.B, n, q.r, periodic, SIGN_TANGENT[v], st, m.B);   // shared second core
+      pl.A = w.arena.dalloc((size_t)nf * R);
+      m.r = pl.r = R;
+      recon_face(w, q.A, n, q.r, rule_ax[d], SIGN_NORMAL[v], st, m.A, pl.A, nf);
+      recon_quad(w, q.B, n, q.r, rule_ax[1 - d], SIGN_TANGENT[v], st, m.B);  // shared core
+      if (J) {
+        double *Nx = w.arena.dalloc((size_t)(n + 6) * J), *Tx = w.arena.dalloc((size_t)(n + 6) * J);
+        for (int j = 0; j < J; ++j) {
+          const DevTerm &tm = *gh[j];
+          const int ax = (tm.where == TT_TERM_X_LO || tm.where == TT_TERM_X_HI) ? 0 : 1;
+          const double *nc = ax == d ? tm.e : tm.o, *tc = ax == d ? tm.o : tm.e;
+          copy_scale(w, Nx + (size_t)j * (n + 6), n + 6, nc, n + 6, n + 6, 1,
+                     time_factor(tm, tt));
+          copy_scale(w, Tx + (size_t)j * (n + 6), n + 6, tc, n + 6, n + 6, 1, 1.0);
+        }
+        recon_face(w, Nx, n, J, Ghost::Explicit, 1.0, st, m.A + (size_t)q.r * nf,
+                   pl.A + (size_t)q.r * nf, nf);
+        recon_quad(w, Tx, n, J, Ghost::Explicit, 1.0, st, m.B + (size_t)q.r * n * nq);
+      }
       qm[v] = m;
       qp[v] = pl;
     }
   }
 
   // Algorithms 2 and 3 for one variable and one side, into `out` (n_f x n*nq, cap r_max)
-  void weno_state(Ctx &w, const DTT &q, int v, int side, int site_base, DTT &out) {
+  void weno_state(Ctx &w, const DTT &q, int v, int side, int site_base, int d, DTT &out) {
+    const int nf = nf_ax[d];
     const double eps_w = (1.0 / n) * (1.0 / n);
     const int site = site_base + 16 + v * 4 + side;
     double *Ae = w.arena.dalloc((size_t)(n + 6) * q.r);
-    ghost_extend(w, q.A, n, q.r, periodic, SIGN_NORMAL[v], Ae);
+    ghost_extend(w, q.A, n, q.r, rule_ax[d], SIGN_NORMAL[v], Ae);
     FiberSpec f1;
     f1.fn = side == 0 ? TT_FN_WENO_FACE_M : TT_FN_WENO_FACE_P;
     f1.n_in = 1;
@@ -361,7 +414,7 @@ struct Solver {
     copy_scale(w, y0.A, nf, vt.A, nf, nf, vt.r, 1.0);
     gather_rows(w, y0.B, n * nq, vt.B, n, rep_idx, n * nq, vt.r);
     double *Be = w.arena.dalloc((size_t)(n + 6) * vt.r);
-    ghost_extend(w, vt.B, n, vt.r, periodic, SIGN_TANGENT[v], Be);
+    ghost_extend(w, vt.B, n, vt.r, rule_ax[1 - d], SIGN_TANGENT[v], Be);
     FiberSpec f2;
     f2.fn = TT_FN_WENO_QUAD;
     f2.n_in = 1;
@@ -397,26 +450,26 @@ struct Solver {
     }
   }
 
-  DTT finish(Ctx &w, const DTT &Fh, DTT &o) {
+  DTT finish(Ctx &w, const DTT &Fh, int d, DTT &o) {
     o.r = Fh.r;
-    face_diff(w, Fh.A, nf, n, Fh.r, periodic, 1.0, o.A, n);
+    face_diff(w, Fh.A, nf_ax[d], n, Fh.r, periodic_ax[d], 1.0, o.A, n);
     quad_sum(w, Fh.B, n, nq, Fh.r, st, o.B);
     return o;
   }
 
   // dF[d][v] (n x n, cap r_max): flux differences of both directions, d = 0 x, d = 1 y
   // (the y result is in transposed orientation)
-  void fluxes(const DTT (*QD)[3], int stage, DTT (*dF)[3]) {
+  void fluxes(const DTT (*QD)[3], int stage, double tt, DTT (*dF)[3]) {
     const int sb[2] = {(0 * 3 + stage) << 6, (1 * 3 + stage) << 6};
     DTT qm[2][3], qp[2][3];
     if (p.scheme != 55) {
-      for (int d = 0; d < 2; ++d) states_upwind(c, QD[d], qm[d], qp[d]);
+      for (int d = 0; d < 2; ++d) states_upwind(c, QD[d], d, tt, qm[d], qp[d]);
       c.sync();
     } else {
       for (int d = 0; d < 2; ++d)
         for (int v = 0; v < 3; ++v) {
-          qm[d][v] = alloc(c, nf, n * nq, p.r_max);
-          qp[d][v] = alloc(c, nf, n * nq, p.r_max);
+          qm[d][v] = alloc(c, nf_ax[d], n * nq, p.r_max);
+          qp[d][v] = alloc(c, nf_ax[d], n * nq, p.r_max);
         }
       c.sync();
       std::vector<Pool::Task> tasks;
@@ -424,7 +477,7 @@ struct Solver {
         for (int v = 0; v < 3; ++v)
           for (int side = 0; side < 2; ++side)
             tasks.push_back([this, &QD, &qm, &qp, &sb, d, v, side](Ctx &w) {
-              weno_state(w, QD[d][v], v, side, sb[d], side == 0 ? qm[d][v] : qp[d][v]);
+              weno_state(w, QD[d][v], v, side, sb[d], d, side == 0 ? qm[d][v] : qp[d][v]);
             });
       run_tasks(std::move(tasks));
     }
@@ -439,7 +492,7 @@ struct Solver {
         Fh[2] = add(c, {{-0.5 * cw, qp[d][2]}, {0.5 * cw, qm[d][2]}});
         for (int v = 0; v < 3; ++v) {
           dF[d][v] = alloc(c, n, n, Fh[v].r);
-          finish(c, Fh[v], dF[d][v]);
+          finish(c, Fh[v], d, dF[d][v]);
         }
       }
       return;
@@ -454,15 +507,15 @@ struct Solver {
     for (int d = 0; d < 2; ++d)
       for (int s = 0; s < 2; ++s) {
         F[d][s][0] = s == 0 ? qm[d][1] : qp[d][1];
-        F[d][s][1] = alloc(c, nf, n * nq, p.r_max);
-        F[d][s][2] = alloc(c, nf, n * nq, p.r_max);
-        rh[d][s] = alloc(c, nf, n * nq, p.r_max);
-        P2[d][s] = alloc(c, nf, n * nq, p.r_max);
-        U[d][s] = alloc(c, nf, n * nq, p.r_max);
-        Wv[d][s] = alloc(c, nf, n * nq, p.r_max);
+        F[d][s][1] = alloc(c, nf_ax[d], n * nq, p.r_max);
+        F[d][s][2] = alloc(c, nf_ax[d], n * nq, p.r_max);
+        rh[d][s] = alloc(c, nf_ax[d], n * nq, p.r_max);
+        P2[d][s] = alloc(c, nf_ax[d], n * nq, p.r_max);
+        U[d][s] = alloc(c, nf_ax[d], n * nq, p.r_max);
+        Wv[d][s] = alloc(c, nf_ax[d], n * nq, p.r_max);
       }
     DTT lam[2];
-    for (int d = 0; d < 2; ++d) lam[d] = alloc(c, nf, n * nq, p.r_max);
+    for (int d = 0; d < 2; ++d) lam[d] = alloc(c, nf_ax[d], n * nq, p.r_max);
     c.sync();
     auto side = [&](int d, int s) { return s == 0 ? qm[d] : qp[d]; };
     {
@@ -481,7 +534,7 @@ struct Solver {
           const DTT *in[4] = {&qm[d][0], &qm[d][1], &qp[d][0], &qp[d][1]};
           for (int k = 0; k < 4; ++k) fl.in[k] = {in[k]->A, in[k]->B, in[k]->n1, in[k]->n2, in[k]->r};
           fl.g = p.g;
-          cross(w, fl, nf, n * nq, y0, sb[d], lam[d]);
+          cross(w, fl, nf_ax[d], n * nq, y0, sb[d], lam[d]);
         });
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s)
@@ -530,29 +583,32 @@ struct Solver {
             DTT dq = add(w, {{1.0, qp[d][v]}, {-1.0, qm[d][v]}});
             DTT D = rnd(w, had(w, lam[d], dq));
             DTT Fh = rnd(w, add(w, {{0.5, F[d][0][v]}, {0.5, F[d][1][v]}, {-0.5, D}}));
-            finish(w, Fh, dF[d][v]);
+            finish(w, Fh, d, dF[d][v]);
           });
       run_tasks(std::move(tasks));
     }
   }
 
   // out[v] = round(Q[v] + dt L(Q)[v]); out buffers allocated by the caller (cap r_max)
-  void euler(const DTT *Qv, double dt, int stage, DTT *out) {
+  void euler(const DTT *Qv, double dt, int stage, double tt, DTT *out) {
     Scope sc(c.arena);
     DTT QD[2][3] = {{Qv[0], Qv[1], Qv[2]},
                     {transposed(Qv[0]), transposed(Qv[2]), transposed(Qv[1])}};
     DTT dF[2][3];
-    fluxes(QD, stage, dF);
+    fluxes(QD, stage, tt, dF);
     DTT G[3] = {transposed(dF[1][0]), transposed(dF[1][2]), transposed(dF[1][1])};
     const double dx = 1.0 / n;
     std::vector<Pool::Task> tasks;
     for (int v = 0; v < 3; ++v)
-      tasks.push_back([this, Qv, &dF, &G, dt, dx, out, v](Ctx &w) {
-        std::vector<std::pair<double, DTT>> terms{{1.0, Qv[v]}, {-dt / dx, dF[0][v]},
-                                                  {-dt / dx, G[v]}};
-        if (p.f != 0.0 && v == 1) terms.push_back({dt * p.f, Qv[2]});
-        if (p.f != 0.0 && v == 2) terms.push_back({-dt * p.f, Qv[1]});
-        round_tt(w, add(w, terms), eps_q[v], p.r_max, out[v], nullptr);
+      tasks.push_back([this, Qv, &dF, &G, dt, dx, tt, out, v](Ctx &w) {
+        std::vector<std::pair<double, DTT>> sum{{1.0, Qv[v]}, {-dt / dx, dF[0][v]},
+                                                {-dt / dx, G[v]}};
+        if (p.f != 0.0 && v == 1) sum.push_back({dt * p.f, Qv[2]});
+        if (p.f != 0.0 && v == 2) sum.push_back({-dt * p.f, Qv[1]});
+        for (const DevTerm &tm : terms)
+          if (tm.var == v && tm.where == TT_TERM_FORCING)
+            sum.push_back({dt * time_factor(tm, tt), DTT{n, n, 1, tm.e, tm.o}});
+        round_tt(w, add(w, sum), eps_q[v], p.r_max, out[v], nullptr);
       });
     c.sync();
     run_tasks(std::move(tasks));
@@ -597,10 +653,11 @@ struct Solver {
       F2[v] = alloc(c, n, n, p.r_max);
       Qn[v] = alloc(c, n, n, p.r_max);
     }
-    euler(Q, dt, 0, Q1);
-    euler(Q1, dt, 1, F1);
+    // stage times of SSP-RK3: t, t + dt, t + dt/2
+    euler(Q, dt, 0, t, Q1);
+    euler(Q1, dt, 1, t + dt, F1);
     combine(Q, 0.75, F1, 0.25, Q2);
-    euler(Q2, dt, 2, F2);
+    euler(Q2, dt, 2, t + 0.5 * dt, F2);
     combine(Q, 1.0 / 3.0, F2, 2.0 / 3.0, Qn);
     for (int v = 0; v < 3; ++v) {
       copy_scale(c, Q[v].A, n, Qn[v].A, n, n, Qn[v].r, 1.0);
@@ -609,6 +666,62 @@ struct Solver {
     }
     c.sync();
     ++step_index;
+    t += dt;
+  }
+
+  // replace the separable terms: ghost terms get their exact-axis column (zero inside the
+  // domain) and their other factor extended by the other axis's rule, both n + 6 rows
+  void set_terms(const tt_fv_term *tv, int count) {
+    TT_REQUIRE(count >= 0 && (count == 0 || tv), "tt_fv_set_terms: bad term list");
+    const size_t col = (size_t)n + 6;
+    std::vector<double> host((size_t)count * 2 * col, 0.0);
+    std::vector<DevTerm> nt;
+    for (int k = 0; k < count; ++k) {
+      const tt_fv_term &a = tv[k];
+      TT_REQUIRE(a.var >= 0 && a.var < 3, "tt_fv_set_terms: var must be 0, 1 or 2");
+      TT_REQUIRE(a.where >= TT_TERM_FORCING && a.where <= TT_TERM_Y_HI,
+                 "tt_fv_set_terms: unknown where");
+      TT_REQUIRE(a.X && a.Y, "tt_fv_set_terms: null factor");
+      TT_REQUIRE(std::isfinite(a.amp) && std::isfinite(a.omega) && std::isfinite(a.phase),
+                 "tt_fv_set_terms: non-finite time factor");
+      double *e = host.data() + (size_t)k * 2 * col, *o = e + col;
+      if (a.where == TT_TERM_FORCING) {
+        std::copy(a.X, a.X + n, e);
+        std::copy(a.Y, a.Y + n, o);
+      } else {
+        const int ax = (a.where == TT_TERM_X_LO || a.where == TT_TERM_X_HI) ? 0 : 1;
+        TT_REQUIRE(rule_ax[ax] == Ghost::Zero,
+                   "tt_fv_set_terms: ghost terms need an exact boundary on their axis");
+        const bool lo = a.where == TT_TERM_X_LO || a.where == TT_TERM_Y_LO;
+        const double *g = ax == 0 ? a.X : a.Y, *other = ax == 0 ? a.Y : a.X;
+        for (int i = 0; i < 3; ++i) e[lo ? i : n + 3 + i] = g[i];
+        // the other factor along axis 1 - ax: its rule; walls negate the momentum normal to it
+        const int b = 1 - ax;
+        const double sign = (b == 0 && a.var == 1) || (b == 1 && a.var == 2) ? -1.0 : 1.0;
+        for (int q = -3; q < n + 3; ++q) {
+          double v;
+          if (q >= 0 && q < n) v = other[q];
+          else if (rule_ax[b] == Ghost::Periodic) v = other[((q % n) + n) % n];
+          else v = sign * other[q < 0 ? -1 - q : 2 * n - 1 - q];
+          o[q + 3] = v;
+        }
+      }
+      nt.push_back({a.var, a.where, a.amp, a.omega, a.phase, nullptr, nullptr});
+    }
+    c.sync();
+    if (term_mem) HIP_CHECK(hipFree(term_mem));
+    term_mem = nullptr;
+    terms.clear();
+    if (count) {
+      HIP_CHECK(hipMalloc((void **)&term_mem, host.size() * sizeof(double)));
+      HIP_CHECK(hipMemcpy(term_mem, host.data(), host.size() * sizeof(double),
+                          hipMemcpyHostToDevice));
+      for (int k = 0; k < count; ++k) {
+        nt[k].e = term_mem + (size_t)k * 2 * col;
+        nt[k].o = nt[k].e + col;
+      }
+    }
+    terms = std::move(nt);
   }
 };
 
@@ -621,6 +734,13 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   TT_REQUIRE(p->eps >= 0.0, "tt_fv_init: eps < 0");
   TT_REQUIRE(p->eps_rule == TT_EPS_FIXED || p->eps_rule == TT_EPS_PAPER,
              "tt_fv_init: unknown eps_rule");
+  TT_REQUIRE(p->bc_x >= 0 && p->bc_x <= TT_BC_EXACT && p->bc_y >= 0 && p->bc_y <= TT_BC_EXACT,
+             "tt_fv_init: unknown boundary kind");
+  TT_REQUIRE(!(p->bc_x == TT_BC_EXACT && p->bc_y == TT_BC_EXACT),
+             "tt_fv_init: at most one axis can have exact boundaries");
+  TT_REQUIRE(p->scheme != 55 || (p->bc_x != TT_BC_EXACT && p->bc_y != TT_BC_EXACT),
+             "tt_fv_init: exact boundaries are built for Upwind3/5");
+  TT_REQUIRE(std::isfinite(p->t0), "tt_fv_init: t0 not finite");
   TT_REQUIRE(p->eps_rule != TT_EPS_PAPER || (p->c_eps > 0.0 && std::isfinite(p->c_eps)),
              "tt_fv_init: c_eps must be positive with TT_EPS_PAPER");
   TT_REQUIRE(!p->nonlinear || p->taylor_terms >= 1 || p->recip == 1,
@@ -669,8 +789,16 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->wt = derive_weno_tables();
     s->n = p->n;
     s->nq = s->st.nq;
-    s->periodic = p->periodic != 0;
-    s->nf = s->periodic ? p->n : p->n + 1;
+    for (int a = 0; a < 2; ++a) {
+      const int kind = (a == 0 ? p->bc_x : p->bc_y) ? (a == 0 ? p->bc_x : p->bc_y)
+                                                    : (p->periodic ? TT_BC_PERIODIC : TT_BC_WALL);
+      s->rule_ax[a] = kind == TT_BC_PERIODIC ? Ghost::Periodic
+                      : kind == TT_BC_WALL   ? Ghost::Wall
+                                             : Ghost::Zero;
+      s->periodic_ax[a] = kind == TT_BC_PERIODIC;
+      s->nf_ax[a] = s->periodic_ax[a] ? p->n : p->n + 1;
+    }
+    s->t = p->t0;
     for (int v = 0; v < 3; ++v) {
       s->Q[v] = Solver::alloc(s->c, p->n, p->n, p->r_max);
       s->Q[v].r = q0[v].rank;
@@ -692,6 +820,10 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     throw;
   }
   return s;
+}
+
+void solver_set_terms(Solver *s, const tt_fv_term *terms, int count) {
+  s->set_terms(terms, count);
 }
 
 void solver_step(Solver *s, double dt, int nsteps) {
@@ -823,6 +955,7 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   o->jacobi_capped = jcap;
   o->qr_redos = t.qr_redos;
   o->eps_inner = s->eps_in;
+  o->time = s->t;
   for (int v = 0; v < 3; ++v) o->eps_var[v] = s->eps_q[v];
   o->flops = t.flops;
   o->bytes = t.bytes;

@@ -11,8 +11,9 @@
 //   3-4. the same for the y-faces;
 //   5. per cell L = -((Fhat_r - Fhat_l) + (Ghat_t - Ghat_b)) / dx + Coriolis source, then the
 //      stage: U1 = U + dt L; U2 = 3/4 U0 + 1/4 (U1 + dt L); U' = U0/3 + 2/3 (U2 + dt L).
-// Boundaries: periodic, or reflective walls (ghost cells mirrored, normal momentum negated;
-// corners mirrored in both directions).
+// Boundaries per axis: periodic, reflective walls (ghost cells mirrored, normal momentum
+// negated), or exact (ghost cells from separable terms amp cos(omega t + phase) X Y at the
+// stage time; corners follow the other axis's rule).  Separable forcing terms are added to L.
 //
 // Layout in HBM: U[v][i][j] (variable, x cell, y cell; y contiguous), FP64.  Bound: the
 // reconstruction arithmetic (about 1.5 kflop per cell and stage for Upwind5) against
@@ -29,11 +30,22 @@ namespace {
 constexpr int TI = 8, TJ = 32, NT = 256;   // tile: 8 x-cells by 32 y-cells, one thread per cell
 static_assert(TI * TJ == NT, "one thread per cell in the last phase");
 
+constexpr int BC_PERIODIC = 0, BC_WALL = 1, BC_EXACT = 2;
+constexpr int MAX_TERMS = 256;
+
+struct GridTerm {
+  int var, where;
+  double amp, omega, phase;
+  const double *X, *Y;
+};
+
 struct GridArgs {
-  int n, periodic;
+  int n, bc[2];
   double g, H, f, dx, dt;
   StencilSet st;
   WenoArgs w;
+  const GridTerm *terms;   // device, nterms entries
+  int nterms;
 };
 
 template <int K>
@@ -146,29 +158,70 @@ __device__ __forceinline__ void llf(const GridArgs &a, int d, const double *um, 
   for (int v = 0; v < 3; ++v) F[v] = 0.5 * (fm[v] + fp[v]) - 0.5 * lam * (up[v] - um[v]);
 }
 
-template <int SCH, bool NL>
+// sum of the ghost terms of variable v on one side at ghost cell g (0..2) and cell c of the
+// other axis (x sides: X[g] Y[c]; y sides: X[c] Y[g])
+__device__ __forceinline__ double ghost_sum(const GridArgs &a, const double *tf, int v,
+                                            int where, int g, int c) {
+  double s = 0.0;
+  const bool xs = where == TT_TERM_X_LO || where == TT_TERM_X_HI;
+  for (int k = 0; k < a.nterms; ++k) {
+    const GridTerm &tm = a.terms[k];
+    if (tm.var != v || tm.where != where) continue;
+    s += tf[k] * (xs ? tm.X[g] * tm.Y[c] : tm.X[c] * tm.Y[g]);
+  }
+  return s;
+}
+
 // U0 and out are the same array in the last stage (each thread reads its own cells of U0
 // before writing them; halos come from U), so neither is declared restrict
+template <int SCH, bool NL>
 __global__ __launch_bounds__(NT) void k_grid_stage(GridArgs a, const double *__restrict__ U,
-                                                   const double *U0, double *out, int stage) {
+                                                   const double *U0, double *out, int stage,
+                                                   double tstage) {
   constexpr int K = SCH == 3 ? 1 : 2, NQ = SCH == 3 ? 2 : 3;
   using D = Dims<K>;
   __shared__ double sU[3][D::LI][D::LJ];
   __shared__ double sFm[3][D::FACES], sFp[3][D::FACES];
   __shared__ double sX[3][TI + 1][TJ];    // x-face fluxes
   __shared__ double sY[3][TJ + 1][TI];    // y-face fluxes
+  __shared__ double sTf[MAX_TERMS];       // time factors of the terms at this stage
   const int n = a.n;
-  const bool periodic = a.periodic != 0;
+  const bool per[2] = {a.bc[0] == BC_PERIODIC, a.bc[1] == BC_PERIODIC};
   const int i0 = blockIdx.y * TI, j0 = blockIdx.x * TJ;
   const size_t nn = (size_t)n * n;
   const int tid = threadIdx.x;
+  for (int k = tid; k < a.nterms; k += NT)
+    sTf[k] = a.terms[k].amp * cos(a.terms[k].omega * tstage + a.terms[k].phase);
+  __syncthreads();
 
-  // tile with halo; ghost cells by periodic wrap or mirror (normal momentum negated)
+  // tile with halo; ghost cells by periodic wrap, mirror (normal momentum negated) or, on an
+  // exact axis, the ghost terms (at the other axis's mapped cell)
   for (int e = tid; e < D::LI * D::LJ; e += NT) {
     const int ii = e / D::LJ, jj = e - ii * D::LJ;
+    const int ci = i0 - D::H + ii, cj = j0 - D::H + jj;
     bool fx, fy;
-    const int gi = map_cell(i0 - D::H + ii, n, periodic, fx);
-    const int gj = map_cell(j0 - D::H + jj, n, periodic, fy);
+    if ((ci < 0 || ci >= n) && a.bc[0] == BC_EXACT) {
+      const int gj = map_cell(cj, n, per[1], fy);
+      const int where = ci < 0 ? TT_TERM_X_LO : TT_TERM_X_HI;
+      const int g = min(max(ci < 0 ? ci + 3 : ci - n, 0), 2);
+      for (int v = 0; v < 3; ++v) {
+        const double x = ghost_sum(a, sTf, v, where, g, gj);
+        sU[v][ii][jj] = (v == 2 && fy) ? -x : x;
+      }
+      continue;
+    }
+    if ((cj < 0 || cj >= n) && a.bc[1] == BC_EXACT) {
+      const int gi = map_cell(ci, n, per[0], fx);
+      const int where = cj < 0 ? TT_TERM_Y_LO : TT_TERM_Y_HI;
+      const int g = min(max(cj < 0 ? cj + 3 : cj - n, 0), 2);
+      for (int v = 0; v < 3; ++v) {
+        const double x = ghost_sum(a, sTf, v, where, g, gi);
+        sU[v][ii][jj] = (v == 1 && fx) ? -x : x;
+      }
+      continue;
+    }
+    const int gi = map_cell(ci, n, per[0], fx);
+    const int gj = map_cell(cj, n, per[1], fy);
     const size_t off = (size_t)gi * n + gj;
     sU[0][ii][jj] = U[off];
     sU[1][ii][jj] = fx ? -U[nn + off] : U[nn + off];
@@ -272,6 +325,10 @@ __global__ __launch_bounds__(NT) void k_grid_stage(GridArgs a, const double *__r
     L[1] = L[1] + a.f * u2;
     L[2] = L[2] - a.f * u1;
   }
+  for (int k = 0; k < a.nterms; ++k) {
+    const GridTerm &tm = a.terms[k];
+    if (tm.where == TT_TERM_FORCING) L[tm.var] += sTf[k] * tm.X[gi] * tm.Y[gj];
+  }
   for (int v = 0; v < 3; ++v) {
     const double u = sU[v][D::H + il][D::H + jl];
     const double e = u + a.dt * L[v];
@@ -289,9 +346,9 @@ __global__ __launch_bounds__(NT) void k_grid_stage(GridArgs a, const double *__r
 
 template <int SCH, bool NL>
 void launch_stage(Ctx &c, const GridArgs &a, const double *U, const double *U0, double *out,
-                  int stage) {
+                  int stage, double tstage) {
   const dim3 grid((a.n + TJ - 1) / TJ, (a.n + TI - 1) / TI);
-  TT_LAUNCH(c, (k_grid_stage<SCH, NL>), grid, dim3(NT), 0, a, U, U0, out, stage);
+  TT_LAUNCH(c, (k_grid_stage<SCH, NL>), grid, dim3(NT), 0, a, U, U0, out, stage, tstage);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -302,6 +359,8 @@ struct Grid {
   Ctx c;
   GridArgs a{};
   double *U1 = nullptr, *U2 = nullptr;
+  double t = 0.0;                 // time at the start of the next step
+  void *term_mem = nullptr;       // GridTerm array followed by the factor vectors
 };
 
 Grid *grid_create(const tt_fv_params *p, void *stream) {
@@ -309,6 +368,11 @@ Grid *grid_create(const tt_fv_params *p, void *stream) {
   TT_REQUIRE(p->n >= 6, "tt_grid_init: n must be >= 6");
   TT_REQUIRE(p->scheme == 3 || p->scheme == 5 || p->scheme == 55, "tt_grid_init: bad scheme");
   TT_REQUIRE(p->nonlinear || p->g * p->H0 > 0.0, "tt_grid_init: g H0 must be positive");
+  TT_REQUIRE(p->bc_x >= 0 && p->bc_x <= TT_BC_EXACT && p->bc_y >= 0 && p->bc_y <= TT_BC_EXACT,
+             "tt_grid_init: unknown boundary kind");
+  TT_REQUIRE(!(p->bc_x == TT_BC_EXACT && p->bc_y == TT_BC_EXACT),
+             "tt_grid_init: at most one axis can have exact boundaries");
+  TT_REQUIRE(std::isfinite(p->t0), "tt_grid_init: t0 not finite");
   Grid *s = new Grid();
   try {
     s->p = *p;
@@ -318,7 +382,14 @@ Grid *grid_create(const tt_fv_params *p, void *stream) {
     HIP_CHECK(hipMalloc((void **)&s->U2, bytes));
     GridArgs &a = s->a;
     a.n = p->n;
-    a.periodic = p->periodic ? 1 : 0;
+    for (int ax = 0; ax < 2; ++ax) {
+      const int kind = (ax == 0 ? p->bc_x : p->bc_y) ? (ax == 0 ? p->bc_x : p->bc_y)
+                                                     : (p->periodic ? TT_BC_PERIODIC : TT_BC_WALL);
+      a.bc[ax] = kind == TT_BC_PERIODIC ? BC_PERIODIC : kind == TT_BC_WALL ? BC_WALL : BC_EXACT;
+    }
+    a.terms = nullptr;
+    a.nterms = 0;
+    s->t = p->t0;
     a.g = p->g;
     a.H = p->H0;
     a.f = p->f;
@@ -340,15 +411,66 @@ void grid_destroy(Grid *s) {
   (void)hipStreamSynchronize(s->c.stream);
   (void)hipFree(s->U1);
   (void)hipFree(s->U2);
+  if (s->term_mem) (void)hipFree(s->term_mem);
   delete s;
+}
+
+void grid_set_terms(Grid *s, const tt_fv_term *tv, int count) {
+  TT_REQUIRE(count >= 0 && count <= MAX_TERMS && (count == 0 || tv),
+             "tt_grid_set_terms: bad term list (at most 256 terms)");
+  const int n = s->a.n;
+  // device block: the GridTerm array, then every term's X and Y
+  size_t doubles = 0;
+  for (int k = 0; k < count; ++k) {
+    const tt_fv_term &t = tv[k];
+    TT_REQUIRE(t.var >= 0 && t.var < 3, "tt_grid_set_terms: var must be 0, 1 or 2");
+    TT_REQUIRE(t.where >= TT_TERM_FORCING && t.where <= TT_TERM_Y_HI,
+               "tt_grid_set_terms: unknown where");
+    TT_REQUIRE(t.X && t.Y, "tt_grid_set_terms: null factor");
+    const bool xs = t.where == TT_TERM_X_LO || t.where == TT_TERM_X_HI;
+    const bool ys = t.where == TT_TERM_Y_LO || t.where == TT_TERM_Y_HI;
+    TT_REQUIRE(!xs || s->a.bc[0] == BC_EXACT, "tt_grid_set_terms: x ghost terms need bc_x exact");
+    TT_REQUIRE(!ys || s->a.bc[1] == BC_EXACT, "tt_grid_set_terms: y ghost terms need bc_y exact");
+    doubles += (xs ? 3 : n) + (ys ? 3 : n);
+  }
+  const size_t head = ((size_t)count * sizeof(GridTerm) + 255) & ~(size_t)255;
+  std::vector<unsigned char> host(head + doubles * sizeof(double));
+  HIP_CHECK(hipStreamSynchronize(s->c.stream));
+  if (s->term_mem) HIP_CHECK(hipFree(s->term_mem));
+  s->term_mem = nullptr;
+  s->a.terms = nullptr;
+  s->a.nterms = 0;
+  if (!count) return;
+  HIP_CHECK(hipMalloc(&s->term_mem, host.size()));
+  auto *dev = (unsigned char *)s->term_mem;
+  auto *gt = (GridTerm *)host.data();
+  double *vec = (double *)(host.data() + head);
+  size_t off = 0;
+  for (int k = 0; k < count; ++k) {
+    const tt_fv_term &t = tv[k];
+    const bool xs = t.where == TT_TERM_X_LO || t.where == TT_TERM_X_HI;
+    const bool ys = t.where == TT_TERM_Y_LO || t.where == TT_TERM_Y_HI;
+    const int nx = xs ? 3 : n, ny = ys ? 3 : n;
+    std::copy(t.X, t.X + nx, vec + off);
+    std::copy(t.Y, t.Y + ny, vec + off + nx);
+    gt[k] = {t.var, t.where, t.amp, t.omega, t.phase,
+             (const double *)(dev + head) + off, (const double *)(dev + head) + off + nx};
+    off += nx + ny;
+  }
+  HIP_CHECK(hipMemcpy(s->term_mem, host.data(), host.size(), hipMemcpyHostToDevice));
+  s->a.terms = (const GridTerm *)s->term_mem;
+  s->a.nterms = count;
 }
 
 template <int SCH, bool NL>
 void grid_steps(Grid *s, double *U, int nsteps) {
+  const double dt = s->a.dt;
   for (int k = 0; k < nsteps; ++k) {
-    launch_stage<SCH, NL>(s->c, s->a, U, U, s->U1, 0);
-    launch_stage<SCH, NL>(s->c, s->a, s->U1, U, s->U2, 1);
-    launch_stage<SCH, NL>(s->c, s->a, s->U2, U, U, 2);
+    // stage times of SSP-RK3: t, t + dt, t + dt/2
+    launch_stage<SCH, NL>(s->c, s->a, U, U, s->U1, 0, s->t);
+    launch_stage<SCH, NL>(s->c, s->a, s->U1, U, s->U2, 1, s->t + dt);
+    launch_stage<SCH, NL>(s->c, s->a, s->U2, U, U, 2, s->t + 0.5 * dt);
+    s->t += dt;
   }
 }
 

@@ -13,26 +13,35 @@ namespace {
 
 constexpr int TPB = 256;
 
-__device__ __forceinline__ int ghost_map(int q, int n, bool periodic, double sign, double &s) {
+// row of cell q (in [-3, n + 3)) in a core column under a ghost rule, and the factor the
+// rule applies: wrap; mirror times sign; zero (the value comes from separate boundary
+// columns); or an explicitly extended column of n + 6 rows (cell q at row q + 3)
+__device__ __forceinline__ int ghost_map(int q, int n, Ghost rule, double sign, double &s) {
+  if (rule == Ghost::Explicit) { s = 1.0; return q + 3; }
   if (q >= 0 && q < n) { s = 1.0; return q; }
-  if (periodic) { s = 1.0; int m = q % n; return m < 0 ? m + n : m; }
+  if (rule == Ghost::Periodic) { s = 1.0; int m = q % n; return m < 0 ? m + n : m; }
+  if (rule == Ghost::Zero) { s = 0.0; return 0; }
   s = sign;                                   // mirror about the wall: ghost k <-> cell k
   return q < 0 ? (-1 - q) : (2 * n - 1 - q);
 }
 
-__global__ void k_recon_face(const double *__restrict__ A, int n, bool periodic, double sign,
+__host__ __device__ __forceinline__ int core_ld(int n, Ghost rule) {
+  return rule == Ghost::Explicit ? n + 6 : n;
+}
+
+__global__ void k_recon_face(const double *__restrict__ A, int n, Ghost rule, double sign,
                              StencilSet st, double *__restrict__ Am, double *__restrict__ Ap,
                              int nf) {
   int f = blockIdx.x * TPB + threadIdx.x;
   int c = blockIdx.y;
   if (f >= nf) return;
-  const double *col = A + (size_t)c * n;
+  const double *col = A + (size_t)c * core_ld(n, rule);
   double m = 0.0, p = 0.0;
   const int k = st.k;
   for (int o = -k; o <= k; ++o) {
     double s1, s2;
-    int i1 = ghost_map(f - 1 + o, n, periodic, sign, s1);   // right face of cell f-1
-    int i2 = ghost_map(f - o, n, periodic, sign, s2);       // left face of cell f (mirrored)
+    int i1 = ghost_map(f - 1 + o, n, rule, sign, s1);   // right face of cell f-1
+    int i2 = ghost_map(f - o, n, rule, sign, s2);       // left face of cell f (mirrored)
     double w = st.face[o + k];
     m += w * s1 * col[i1];
     p += w * s2 * col[i2];
@@ -41,17 +50,17 @@ __global__ void k_recon_face(const double *__restrict__ A, int n, bool periodic,
   Ap[(size_t)c * nf + f] = p;
 }
 
-__global__ void k_recon_quad(const double *__restrict__ B, int n, bool periodic, double sign,
+__global__ void k_recon_quad(const double *__restrict__ B, int n, Ghost rule, double sign,
                              StencilSet st, double *__restrict__ Bq) {
   int j = blockIdx.x * TPB + threadIdx.x;
   int c = blockIdx.y;
   if (j >= n) return;
-  const double *col = B + (size_t)c * n;
+  const double *col = B + (size_t)c * core_ld(n, rule);
   const int k = st.k;
   double v[5];
   for (int o = -k; o <= k; ++o) {
     double s;
-    int i = ghost_map(j + o, n, periodic, sign, s);
+    int i = ghost_map(j + o, n, rule, sign, s);
     v[o + k] = s * col[i];
   }
   double *out = Bq + (size_t)c * n * st.nq + (size_t)j * st.nq;
@@ -83,14 +92,14 @@ __global__ void k_face_diff(const double *__restrict__ A, int nf, int n, bool pe
   Ao[(size_t)c * ldo + i] = scale * (col[ip] - col[i]);
 }
 
-__global__ void k_ghost_extend(const double *__restrict__ A, int n, bool periodic, double sign,
+__global__ void k_ghost_extend(const double *__restrict__ A, int n, Ghost rule, double sign,
                                double *__restrict__ E) {
   int q = blockIdx.x * TPB + threadIdx.x;     // 0 .. n+5
   int c = blockIdx.y;
   if (q >= n + 6) return;
   double s;
-  int i = ghost_map(q - 3, n, periodic, sign, s);
-  E[(size_t)c * (n + 6) + q] = s * A[(size_t)c * n + i];
+  int i = ghost_map(q - 3, n, rule, sign, s);
+  E[(size_t)c * (n + 6) + q] = s * A[(size_t)c * core_ld(n, rule) + i];
 }
 
 __global__ void k_khatri_rao(double *__restrict__ out, int n, const double *__restrict__ X,
@@ -188,19 +197,19 @@ inline dim3 grid2(int rows, int cols) { return dim3((rows + TPB - 1) / TPB, cols
 
 }  // namespace
 
-void recon_face(Ctx &c, const double *A, int n, int r, bool periodic, double sign,
+void recon_face(Ctx &c, const double *A, int n, int r, Ghost rule, double sign,
                 const StencilSet &st, double *Am, double *Ap, int nf) {
   if (r <= 0 || nf <= 0) return;
-  hipLaunchKernelGGL(k_recon_face, grid2(nf, r), dim3(TPB), 0, c.stream, A, n, periodic, sign,
+  hipLaunchKernelGGL(k_recon_face, grid2(nf, r), dim3(TPB), 0, c.stream, A, n, rule, sign,
                      st, Am, Ap, nf);
   c.cnt.flops += 4.0 * (2 * st.k + 1) * nf * r;
   c.cnt.bytes += 8.0 * r * (n + 2.0 * nf);
 }
 
-void recon_quad(Ctx &c, const double *B, int n, int r, bool periodic, double sign,
+void recon_quad(Ctx &c, const double *B, int n, int r, Ghost rule, double sign,
                 const StencilSet &st, double *Bq) {
   if (r <= 0) return;
-  hipLaunchKernelGGL(k_recon_quad, grid2(n, r), dim3(TPB), 0, c.stream, B, n, periodic, sign, st,
+  hipLaunchKernelGGL(k_recon_quad, grid2(n, r), dim3(TPB), 0, c.stream, B, n, rule, sign, st,
                      Bq);
   c.cnt.flops += 2.0 * (2 * st.k + 1) * st.nq * n * r;
   c.cnt.bytes += 8.0 * r * n * (1.0 + st.nq);
@@ -221,9 +230,9 @@ void face_diff(Ctx &c, const double *A, int nf, int n, int r, bool periodic, dou
   c.cnt.bytes += 8.0 * r * (nf + n);
 }
 
-void ghost_extend(Ctx &c, const double *A, int n, int r, bool periodic, double sign, double *E) {
+void ghost_extend(Ctx &c, const double *A, int n, int r, Ghost rule, double sign, double *E) {
   if (r <= 0) return;
-  hipLaunchKernelGGL(k_ghost_extend, grid2(n + 6, r), dim3(TPB), 0, c.stream, A, n, periodic,
+  hipLaunchKernelGGL(k_ghost_extend, grid2(n + 6, r), dim3(TPB), 0, c.stream, A, n, rule,
                      sign, E);
 }
 

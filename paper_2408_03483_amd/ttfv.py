@@ -43,7 +43,14 @@ class ParamsC(ctypes.Structure):
                 ("taylor_terms", ctypes.c_int), ("cross_sweeps", ctypes.c_int),
                 ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int),
                 ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double),
-                ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double)]
+                ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double),
+                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("t0", ctypes.c_double)]
+
+
+class TermC(ctypes.Structure):
+    _fields_ = [("var", ctypes.c_int), ("where", ctypes.c_int), ("amp", ctypes.c_double),
+                ("omega", ctypes.c_double), ("phase", ctypes.c_double),
+                ("X", ctypes.POINTER(ctypes.c_double)), ("Y", ctypes.POINTER(ctypes.c_double))]
 
 
 class StatsC(ctypes.Structure):
@@ -58,12 +65,29 @@ class StatsC(ctypes.Structure):
                 ("max_learned_err", ctypes.c_double), ("sketch_fallbacks", ctypes.c_longlong),
                 ("sketch_unconverged", ctypes.c_longlong), ("jacobi_capped", ctypes.c_longlong),
                 ("qr_redos", ctypes.c_longlong), ("eps_inner", ctypes.c_double),
-                ("eps_var", ctypes.c_double * 3)]
+                ("eps_var", ctypes.c_double * 3), ("time", ctypes.c_double)]
 
 
 PRECISIONS = {"f64": 0, "f32": 1}
 QR_METHODS = {"auto": 0, "cholesky": 1, "householder": 2}
 EPS_RULES = {"fixed": 0, "paper": 1}
+BCS = {None: 0, "periodic": 1, "wall": 2, "exact": 3}
+TERM_WHERE = {"forcing": 0, "x_lo": 1, "x_hi": 2, "y_lo": 3, "y_hi": 4}
+
+
+def _terms_c(terms):
+    """ctypes array of tt_fv_term from objects with var, where, amp, omega, phase, X, Y; the
+    returned list keeps the factor arrays alive for the call."""
+    import numpy as np
+    keep, arr = [], (TermC * max(len(terms), 1))()
+    for k, t in enumerate(terms):
+        X = np.ascontiguousarray(t.X, dtype=np.float64)
+        Y = np.ascontiguousarray(t.Y, dtype=np.float64)
+        keep += [X, Y]
+        arr[k] = TermC(int(t.var), TERM_WHERE[t.where], float(t.amp), float(t.omega),
+                       float(t.phase), X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       Y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return arr, keep
 
 EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_precision",
            "tt_round", "tt_round_noalloc",
@@ -75,7 +99,8 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_pm_topk", "tt_fv_set_pivots", "tt_gemm_autotune", "tt_last_error",
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
-           "tt_grid_init", "tt_grid_step", "tt_grid_destroy"]
+           "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
+           "tt_fv_set_terms"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -120,6 +145,8 @@ def load_library(path: str = LIB_PATH):
     L.tt_grid_step.argtypes = [P, P, D, I]
     L.tt_grid_destroy.argtypes = [P]
     L.tt_grid_destroy.restype = None
+    L.tt_grid_set_terms.argtypes = [P, ctypes.POINTER(TermC), I]
+    L.tt_fv_set_terms.argtypes = [P, ctypes.POINTER(TermC), I]
     L.tt_ens_create.argtypes = [ctypes.POINTER(P), I, S]
     L.tt_ens_step.argtypes = [P, ctypes.POINTER(P), I, ctypes.POINTER(D), I, I]
     L.tt_ens_destroy.argtypes = [P]
@@ -368,18 +395,31 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
                arena_bytes: int = 4 << 30, precision: str = "f64",
                qr: str = "auto", cross_drop: float = 0.0, eps_rule: str = "fixed",
-               c_eps: float = 1.0) -> Solver:
+               c_eps: float = 1.0, bc=None, t0: float = 0.0, terms=()) -> Solver:
+    """bc: per-axis boundary kinds ("periodic", "wall", "exact") overriding `periodic`;
+    terms: separable forcing / ghost terms (see tt_fv_set_terms)."""
     L = load_library()
     _torch()
+    bx, by = (None, None) if bc is None else bc
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
                 workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop,
-                EPS_RULES[eps_rule], c_eps)
+                EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
            "tt_fv_init")
-    return Solver(h, p, stream)
+    s = Solver(h, p, stream)
+    if terms:
+        tt_fv_set_terms(s, terms)
+    return s
+
+
+def tt_fv_set_terms(s: Solver, terms) -> None:
+    """Separable terms amp cos(omega t + phase) X Y: forcing of L, or ghost cells of an exact
+    boundary ("x_lo", "x_hi", "y_lo", "y_hi")."""
+    arr, keep = _terms_c(list(terms))
+    _check(_lib.tt_fv_set_terms(s.h, arr, len(terms)), "tt_fv_set_terms")
 
 
 def tt_fv_step(s: Solver, dt: float, nsteps: int = 1) -> int:
@@ -409,7 +449,7 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "max_learned_err": st.max_learned_err, "sketch_fallbacks": st.sketch_fallbacks,
             "sketch_unconverged": st.sketch_unconverged, "jacobi_capped": st.jacobi_capped,
             "qr_redos": st.qr_redos, "eps_inner": st.eps_inner,
-            "eps_var": list(st.eps_var)}
+            "eps_var": list(st.eps_var), "time": st.time}
 
 
 def tt_fv_time_kernel(s: Solver, name: Optional[str], every: int = 32) -> None:
@@ -424,15 +464,24 @@ class Grid:
     """Full-grid comparator (tt_grid_*): the same scheme on n x n cell-average arrays."""
 
     def __init__(self, n: int, scheme: str, nonlinear: bool, periodic: bool, g: float = 9.81,
-                 H0: float = 1.0, f: float = 0.0, stream=None):
+                 H0: float = 1.0, f: float = 0.0, stream=None, bc=None, t0: float = 0.0,
+                 terms=()):
         L = load_library()
         _torch()
+        bx, by = (None, None) if bc is None else bc
         self.params = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0,
-                              g, H0, f, 0.0, 1, 1, 1, 0, 0, 0, 0, 0, 0.0, 0, 1.0)
+                              g, H0, f, 0.0, 1, 1, 1, 0, 0, 0, 0, 0, 0.0, 0, 1.0,
+                              BCS[bx], BCS[by], t0)
         self.h = ctypes.c_void_p()
         self._stream = stream
         _check(L.tt_grid_init(ctypes.byref(self.h), ctypes.byref(self.params),
                               _stream_ptr(stream)), "tt_grid_init")
+        if terms:
+            self.set_terms(terms)
+
+    def set_terms(self, terms) -> None:
+        arr, keep = _terms_c(list(terms))
+        _check(_lib.tt_grid_set_terms(self.h, arr, len(terms)), "tt_grid_set_terms")
 
     def step(self, U, dt: float, nsteps: int = 1) -> None:
         """Advance U (torch float64 CUDA tensor, 3 x n x n, contiguous) in place; asynchronous
@@ -457,8 +506,9 @@ class Grid:
 
 
 def tt_grid_init(n: int, scheme: str, nonlinear: bool, periodic: bool, g: float = 9.81,
-                 H0: float = 1.0, f: float = 0.0, stream=None) -> Grid:
-    return Grid(n, scheme, nonlinear, periodic, g, H0, f, stream)
+                 H0: float = 1.0, f: float = 0.0, stream=None, bc=None, t0: float = 0.0,
+                 terms=()) -> Grid:
+    return Grid(n, scheme, nonlinear, periodic, g, H0, f, stream, bc, t0, terms)
 
 
 def tt_grid_step(grid: Grid, U, dt: float, nsteps: int = 1) -> None:
