@@ -16,9 +16,9 @@ source is unchanged.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--no-cpu] [--timed-kernel NAME]
                     [--workload bumps1024 | dambreak2048 | ensemble | learned4096 |
-                                igw_speedup]
+                                paper_speedup]
                     [--members 64] [--precision f64 | f32] [--learned-n 4096]
-                    [--sizes 640,1280,...] [--schemes upwind5,upwind3,weno5]
+                    [--sizes 1280,...] [--schemes upwind5,...] [--cases inertia_gravity,...]
 
 Other workloads (not the headline line): dambreak2048 = WENO5 through maxvol crosses, 1/h by
 cross, walls, rank cap 64, tol 1e-8 (with --precision f32 also run in FP64 for the
@@ -27,9 +27,10 @@ speed-up and the difference); ensemble = independent nonlinear members of 256^2,
 against the same members stepped one at a time; learned4096 = the dam break on 4096^2 with
 crosses whose columns come from the learned pivot proposer (trained on pivots logged from
 the same run's warm-up steps), reported against plain maxvol crosses from the same state;
-igw_speedup = the paper's own measure (Section 5.2): the inertia-gravity wave with f != 0 in the
-nondimensional scales of Table 2, Table 1's time step and C_eps, the paper's tolerance rule
-(Section 4.4), TT step time against the full-grid comparator's step time at each grid size.
+paper_speedup = the paper's own measure (Sections 5.1-5.4): the Kelvin wave, inertia-gravity wave,
+barotropic tide and manufactured solution in the nondimensional scales of Table 2, Table 1's time
+step and C_eps, the paper's tolerance rule (Section 4.4), TT step time against the full-grid
+comparator's step time at each grid size.
 
 Independent chains of TT operations run on several HIP streams (8 workers, plus helper streams
 for the Taylor partial sums); the runtime maps streams to GPU_MAX_HW_QUEUES hardware queues (4
@@ -132,11 +133,13 @@ def main():
                     help="worker streams of the solver (0: 8; 1: every kernel on one stream)")
     ap.add_argument("--workload", default="bumps1024",
                     choices=["bumps1024", "dambreak2048", "ensemble", "learned4096",
-                             "igw_speedup"])
-    ap.add_argument("--sizes", default="640,1280,2560,5120,10240",
-                    help="igw_speedup: grid sizes")
+                             "paper_speedup"])
+    ap.add_argument("--sizes", default="1280,2560,5120,10240",
+                    help="paper_speedup: grid sizes")
     ap.add_argument("--schemes", default="upwind5,upwind3,weno5",
-                    help="igw_speedup: reconstruction schemes")
+                    help="paper_speedup: reconstruction schemes")
+    ap.add_argument("--cases", default="inertia_gravity,coastal_kelvin,barotropic_tide,"
+                                       "manufactured", help="paper_speedup: Section 5 cases")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
                     help="contraction arithmetic of the dambreak2048, ensemble and learned4096 "
@@ -176,8 +179,8 @@ def main():
         return dambreak(args)
     if args.workload == "learned4096":
         return learned(args)
-    if args.workload == "igw_speedup":
-        return igw_speedup(args)
+    if args.workload == "paper_speedup":
+        return paper_speedup(args)
     n, rmax, eps, K = args.n, 32, 1e-10, 8
     st = synth.nonlinear_bumps(seed=0, n=n, rmax=rmax, eps=eps)
     dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
@@ -576,76 +579,98 @@ def ensemble(args):
     print(json.dumps(out), flush=True)
 
 
-# the paper's speed-ups at its finest grid (1280^2) for this case, TT against its own
-# full-tensor implementation on a CPU (Section 5.2)
-PAPER_IGW_SPEEDUP_1280 = {"upwind5": 79.0, "upwind3": 64.0, "weno5": 12.0}
+# the paper's speed-ups at its finest grid (1280^2), TT against its own full-tensor code on a
+# CPU (Sections 5.1-5.4)
+PAPER_SPEEDUP_1280 = {
+    "coastal_kelvin": {"upwind5": 83.0, "upwind3": 73.0, "weno5": 14.0},
+    "inertia_gravity": {"upwind5": 79.0, "upwind3": 64.0, "weno5": 12.0},
+    "barotropic_tide": {"upwind5": 124.0, "upwind3": 89.0, "weno5": 19.0},
+    "manufactured": {"upwind5": 57.0, "upwind3": 71.0, "weno5": 29.0},
+}
 
 
-def igw_speedup(args):
-    """TT step against full-grid step on Section 5.2's inertia-gravity wave."""
+def _paper_case(name, n, scheme, rmax):
+    """(state, bc, terms) of a Section 5 case."""
+    import synth
+    if name == "inertia_gravity":
+        st = synth.inertia_gravity(n, scheme, rmax=rmax)
+        return st, ("periodic", "periodic"), []
+    case = getattr(synth, name)(n, scheme, rmax=rmax)
+    return case.state, case.bc, case.terms
+
+
+def paper_speedup(args):
+    """TT step against full-grid step on Section 5's cases, same scheme, same GPU."""
     import numpy as np
     import torch
-    import synth
     from paper_2408_03483_amd import ttfv
 
     rows = []
-    for scheme in args.schemes.split(","):
-        c_eps = synth.TABLE1["inertia_gravity"][scheme][1]
-        rmax = 48 if scheme == "weno5" else 16
-        for n in [int(x) for x in args.sizes.split(",")]:
-            st = synth.inertia_gravity(n, scheme, rmax=rmax)
-            c = math.sqrt(st.g * st.H0)
-            dt = st.dt
-            if scheme == "upwind3":
-                # Table 1's dt/dx = 1e-4 is c dt/dx = 6.2 with Table 2's scales; the
-                # Upwind3 runs take c dt/dx = 0.5 instead
-                dt = 0.5 / (c * n)
-            f = st.meta["f"]
-            print(f"[igw] {scheme} n={n} dt={dt:.3e} cfl={c * dt * n:.3f}", file=sys.stderr,
-                  flush=True)
-            dev = [ttfv.DeviceTT.from_factors(x.A, x.B, cap=rmax) for x in st.tt]
-            s = ttfv.tt_fv_init(n, scheme, False, True, dev, g=st.g, H0=st.H0, f=f, r_max=rmax,
-                                eps_rule="paper", c_eps=c_eps)
-            ttfv.tt_fv_step(s, dt, args.warmup)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ttfv.tt_fv_step(s, dt, args.steps)
-            torch.cuda.synchronize()
-            t_tt = (time.perf_counter() - t0) / args.steps
-            stats = ttfv.tt_fv_get_stats(s)
-            s.close()
-            del dev
-            stream = torch.cuda.current_stream()
-            U = torch.tensor(np.stack(st.fields), dtype=torch.float64, device="cuda")
-            g, H0 = st.g, st.H0
-            del st
-            grid = ttfv.tt_grid_init(n, scheme, False, True, g=g, H0=H0, f=f, stream=stream)
-            grid.step(U, dt, args.warmup)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            grid.step(U, dt, args.steps)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t_grid = e0.elapsed_time(e1) * 1e-3 / args.steps
-            grid.close()
-            del U
-            torch.cuda.empty_cache()
-            # HBM bytes of one full-grid step: the three stages read the stage input (and
-            # U0 in the second and third) and write the stage output, 3 variables x 8 bytes
-            gbs = (6 + 9 + 9) * 8.0 * n * n / t_grid / 1e9
-            rows.append({"scheme": scheme, "n": n, "dt": dt, "cfl": c * dt * n,
-                         "c_eps": c_eps, "tt_ms_per_step": t_tt * 1e3,
-                         "grid_ms_per_step": t_grid * 1e3, "speedup_tt_vs_grid": t_grid / t_tt,
-                         "tt_ranks": stats["ranks"], "eps_inner": stats["eps_inner"],
-                         "eps_var": stats["eps_var"], "grid_hbm_gbs": gbs,
-                         "grid_hbm_frac": gbs / PEAK_HBM_GBS})
-            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    for name in args.cases.split(","):
+        for scheme in args.schemes.split(","):
+            rmax = 48 if scheme == "weno5" else 32
+            for n in [int(x) for x in args.sizes.split(",")]:
+                st, bc, terms = _paper_case(name, n, scheme, rmax)
+                nl = st.nonlinear
+                hmax = float(np.max(st.fields[0])) if nl else st.H0
+                c = math.sqrt(st.g * hmax)
+                dt = st.dt
+                if scheme == "upwind3" and c * dt * n > 0.5:
+                    # Table 1's Upwind3 steps are c dt/dx = 1.0 (Kelvin), 6.2 (inertia-gravity)
+                    # and 3.5 (tide) with Table 2's scales; the full-grid scheme is unstable
+                    # there, so these rows take c dt/dx = 0.5
+                    dt = 0.5 / (c * n)
+                f = st.meta["f"]
+                c_eps = st.meta["c_eps"]
+                print(f"[paper] {name} {scheme} n={n} dt={dt:.3e} cfl={c * dt * n:.3f}",
+                      file=sys.stderr, flush=True)
+                dev = [ttfv.DeviceTT.from_factors(x.A, x.B, cap=rmax) for x in st.tt]
+                s = ttfv.tt_fv_init(n, scheme, nl, False, dev, g=st.g, H0=st.H0, f=f,
+                                    r_max=rmax, eps_rule="paper", c_eps=c_eps, bc=bc,
+                                    terms=terms)
+                ttfv.tt_fv_step(s, dt, args.warmup)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ttfv.tt_fv_step(s, dt, args.steps)
+                torch.cuda.synchronize()
+                t_tt = (time.perf_counter() - t0) / args.steps
+                stats = ttfv.tt_fv_get_stats(s)
+                s.close()
+                del dev
+                stream = torch.cuda.current_stream()
+                U = torch.tensor(np.stack(st.fields), dtype=torch.float64, device="cuda")
+                g, H0 = st.g, st.H0
+                del st
+                grid = ttfv.tt_grid_init(n, scheme, nl, False, g=g, H0=H0, f=f, bc=bc,
+                                         terms=terms, stream=stream)
+                grid.step(U, dt, args.warmup)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                grid.step(U, dt, args.steps)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t_grid = e0.elapsed_time(e1) * 1e-3 / args.steps
+                finite = bool(torch.isfinite(U).all().item())
+                grid.close()
+                del U
+                torch.cuda.empty_cache()
+                # HBM bytes of one full-grid step: the three stages read the stage input (and
+                # U0 in the second and third) and write the stage output, 3 variables x 8 bytes
+                gbs = (6 + 9 + 9) * 8.0 * n * n / t_grid / 1e9
+                rows.append({"case": name, "scheme": scheme, "n": n, "dt": dt,
+                             "cfl": c * dt * n, "c_eps": c_eps, "tt_ms_per_step": t_tt * 1e3,
+                             "grid_ms_per_step": t_grid * 1e3,
+                             "speedup_tt_vs_grid": t_grid / t_tt, "tt_ranks": stats["ranks"],
+                             "eps_inner": stats["eps_inner"], "eps_var": stats["eps_var"],
+                             "grid_hbm_gbs": gbs, "grid_hbm_frac": gbs / PEAK_HBM_GBS,
+                             "grid_finite": finite, "tt_warnings": stats["warnings"]})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     out = {"metric": "TT-FV step speed-up over the full-grid FV step (same scheme, same GPU)",
            "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "inertia_gravity_speedup", "case": "Section 5.2",
-                      "eps_rule": "paper", "scales": "Table 2", "coriolis": True},
-           "rows": rows, "paper_speedup_1280_vs_own_cpu_full_tensor": PAPER_IGW_SPEEDUP_1280}
+           "config": {"workload": "paper_cases_speedup", "cases": "Sections 5.1-5.4",
+                      "eps_rule": "paper", "scales": "Table 2", "dt": "Table 1"},
+           "rows": rows, "paper_speedup_1280_vs_own_cpu_full_tensor": PAPER_SPEEDUP_1280}
     print(json.dumps(out), flush=True)
 
 

@@ -201,7 +201,7 @@ typedef struct {
   int bc_x, bc_y;     /* boundary of each axis: 0 = as `periodic` says, TT_BC_PERIODIC,
                          TT_BC_WALL, or TT_BC_EXACT (ghost cells from the TT_TERM_X_* /
                          TT_TERM_Y_* terms of tt_fv_set_terms, Section 5's exact-solution
-                         boundaries; at most one axis, Upwind3/5 only)                      */
+                         boundaries; at most one axis)                                      */
   double t0;          /* time at the start of the first step (for the terms' time factors) */
 } tt_fv_params;
 #define TT_BC_PERIODIC 1
@@ -289,7 +289,7 @@ void tt_fv_destroy(tt_fv *s);
  * paper's speed-ups are measured against.  One fused kernel per RK stage. */
 typedef struct tt_grid tt_grid;
 /* Uses n, nonlinear, scheme, periodic, bc_x, bc_y, t0, g, H0 and f of `p` (the other fields
- * are ignored; exact boundaries work with every scheme here).  Allocates two stage buffers of
+ * are ignored).  Allocates two stage buffers of
  * 3 n^2 doubles once here; work runs on hip_stream. */
 int  tt_grid_init(tt_grid **out, const tt_fv_params *p, void *hip_stream);
 /* Replace the comparator's separable forcing and boundary terms (as tt_fv_set_terms). */

@@ -11,7 +11,10 @@ exact axis the state's cores are extended by zeros and every ghost term becomes 
 columns of the reconstructed TTs: its factor along the exact axis is an explicit (n + 6)
 column that is zero inside the domain, its other factor is extended by the other axis's rule,
 and both pass through the same stencils (the reconstruction is linear).  Forcing terms add
-rank-1 TTs to L.  Exact boundaries are built for the Upwind schemes.
+rank-1 TTs to L.  WENO5: on an exact normal boundary the ghost terms are further columns of
+Algorithm 2's fibers; on an exact tangent boundary Algorithm 3 needs the Step-1 face values at
+the 6 tangent ghost cells, which are evaluated directly (the field there is the ghost terms
+alone) and appended to the Step-1 TT as 6 columns with unit tangent factors at those rows.
 
 One evaluation of L(Q) (Sections 4.1-4.3):
 
@@ -135,9 +138,22 @@ class _Recip:
 class _WenoFace:
     """Algorithm 2 entries: WENO5 Step-1 face value of the cells around face f, column j."""
 
-    def __init__(self, q: TT, periodic, sign, side, n_faces, tab, eps):
+    def __init__(self, q: TT, periodic, sign, side, n_faces, tab, eps, extra=None):
+        """extra = (normal-axis columns, n + 6 rows already extended; their factors along
+        the columns' index): ghost terms of an exact normal boundary, summed into the field."""
         self.Ae, self.B = extend(q.A, periodic, sign), q.B
+        if extra is not None:
+            self.Ae = np.concatenate([self.Ae, extra[0]], axis=1)
+            self.B = np.concatenate([self.B, extra[1]], axis=1)
         self.side, self.nf, self.tab, self.eps = side, n_faces, tab, eps
+
+    @classmethod
+    def from_cores(cls, Ae, B, side, n_faces, tab, eps):
+        """Entries of the field Ae B^T with its first core already extended (n + 6 rows)."""
+        f = cls.__new__(cls)
+        f.Ae, f.B = Ae, B
+        f.side, f.nf, f.tab, f.eps = side, n_faces, tab, eps
+        return f
 
     def _vals(self, rows_of):
         if self.side < 0:   # right face of cell f-1
@@ -159,8 +175,9 @@ class _WenoFace:
 class _WenoQuad:
     """Algorithm 3 entries: WENO5 Step-2 value at Gauss point m of cell j, column j*nq + m."""
 
-    def __init__(self, v: TT, periodic, sign, n, tab, eps):
-        self.A, self.Be = v.A, extend(v.B, periodic, sign)
+    def __init__(self, v: TT, periodic, sign, n, tab, eps, Be=None):
+        """Be: v's second core already extended to n + 6 rows (an exact tangent boundary)."""
+        self.A, self.Be = v.A, (extend(v.B, periodic, sign) if Be is None else Be)
         self.n, self.tab, self.eps, self.nq = n, tab, eps, tab["nq"]
 
     def _quad(self, vals):
@@ -194,8 +211,6 @@ class TTSolver:
         if any(b not in ("periodic", "wall", "exact") for b in self.bc) or \
                 self.bc.count("exact") > 1:
             raise ValueError(f"bad boundary kinds {self.bc}")
-        if "exact" in self.bc and scheme == "weno5":
-            raise NotImplementedError("exact-solution boundaries are built for Upwind3/5")
         self.terms = list(terms)
         self.t = t0                        # time at the start of the next step
         self.g, self.H, self.f = g, H, f
@@ -315,17 +330,37 @@ class TTSolver:
             return qm, qp
         eps_w = self.dx * self.dx
         nn = self.n * self.nq
+        natural = (0, 1, 2) if d == 0 else (0, 2, 1)
+        n = self.n
+        ghost_rows = np.r_[0:NG, n + NG:n + 2 * NG]
         for c, q in enumerate(Q):
+            gn, gt = self.ghost_columns(natural[c], d, t)
+            extra = None
+            if gn is not None and self.bc[d] == "exact":
+                extra = (gn, gt[NG:NG + n])
             out = []
             for side_i, side in enumerate((-1, 1)):
                 site = site_base + 16 + c * 4 + side_i
                 nf = self.nf_axis[d]
                 v = self._cross(_WenoFace(q, self.bc[d], SIGN_NORMAL[c], side, nf,
-                                          self.tab, eps_w), nf, self.n, q, site)
+                                          self.tab, eps_w, extra), nf, n, q, site)
                 # initial columns for Step 2: v's second core repeated for every Gauss point
                 y0 = TT(v.A, np.repeat(v.B, self.nq, axis=0))
-                w = self._cross(_WenoQuad(v, self.bc[1 - d], SIGN_TANGENT[c], self.n, self.tab,
-                                          eps_w), nf, nn, y0, site + 2)
+                Be = None
+                if self.bc[1 - d] == "exact":
+                    # Step-1 values at the tangent ghost cells: the ghost terms alone
+                    if gn is not None:
+                        V = _WenoFace.from_cores(gn, gt, side, nf, self.tab, eps_w) \
+                            .cols(ghost_rows)
+                    else:
+                        V = np.zeros((nf, 2 * NG))
+                    E = np.zeros((n + 2 * NG, 2 * NG))
+                    E[ghost_rows, np.arange(2 * NG)] = 1.0
+                    Bz = np.concatenate([np.zeros((NG, v.rank)), v.B, np.zeros((NG, v.rank))])
+                    v = TT(np.concatenate([v.A, V], axis=1), np.concatenate([Bz, E], axis=1))
+                    Be = v.B
+                w = self._cross(_WenoQuad(v, self.bc[1 - d], SIGN_TANGENT[c], n, self.tab,
+                                          eps_w, Be), nf, nn, y0, site + 2)
                 out.append(w)
             qm.append(out[0])
             qp.append(out[1])

@@ -72,6 +72,10 @@ struct Solver {
   };
   std::vector<DevTerm> terms;
   double *term_mem = nullptr;
+  // exact boundaries with WENO5: the 6 tangent ghost rows (0, 1, 2, n+3, n+4, n+5) and the
+  // unit columns at those rows, (n + 6) x 6
+  int *ghost_rows6 = nullptr;
+  double *unit6 = nullptr;
   DTT Q[3];
   std::map<int, std::vector<int>> piv;
   std::mutex mu;               // guards piv and the Taylor statistics
@@ -395,16 +399,41 @@ struct Solver {
   }
 
   // Algorithms 2 and 3 for one variable and one side, into `out` (n_f x n*nq, cap r_max)
-  void weno_state(Ctx &w, const DTT &q, int v, int side, int site_base, int d, DTT &out) {
+  // Exact boundaries: on the normal axis the ghost terms are further columns of Algorithm 2's
+  // input; on the tangent axis Algorithm 3 needs the Step-1 values at the 6 tangent ghost
+  // cells, where the field is the ghost terms alone: they are evaluated directly (the same
+  // fiber function at those 6 rows of an extended tangent core) and appended to the Step-1
+  // TT as 6 columns whose tangent factors are unit vectors at those rows.
+  void weno_state(Ctx &w, const DTT &q, int v, int side, int site_base, int d, double tt,
+                  DTT &out) {
     const int nf = nf_ax[d];
     const double eps_w = (1.0 / n) * (1.0 / n);
     const int site = site_base + 16 + v * 4 + side;
-    double *Ae = w.arena.dalloc((size_t)(n + 6) * q.r);
+    const int nat = d == 0 ? v : (v == 0 ? 0 : 3 - v);
+    std::vector<const DevTerm *> gh;
+    for (const DevTerm &tm : terms)
+      if (tm.var == nat && tm.where != TT_TERM_FORCING) gh.push_back(&tm);
+    const int J = (int)gh.size();
+    const bool normal_exact = rule_ax[d] == Ghost::Zero, tangent_exact = rule_ax[1 - d] ==
+                                                                          Ghost::Zero;
+    const int R = q.r + (normal_exact ? J : 0);
+    double *Ae = w.arena.dalloc((size_t)(n + 6) * R);
     ghost_extend(w, q.A, n, q.r, rule_ax[d], SIGN_NORMAL[v], Ae);
+    const double *B1 = q.B;
+    if (normal_exact && J) {
+      double *Bf = w.arena.dalloc((size_t)n * R);
+      copy_scale(w, Bf, n, q.B, n, n, q.r, 1.0);
+      for (int j = 0; j < J; ++j) {
+        copy_scale(w, Ae + (size_t)(q.r + j) * (n + 6), n + 6, gh[j]->e, n + 6, n + 6, 1,
+                   time_factor(*gh[j], tt));
+        copy_scale(w, Bf + (size_t)(q.r + j) * n, n, gh[j]->o + 3, n, n, 1, 1.0);
+      }
+      B1 = Bf;
+    }
     FiberSpec f1;
     f1.fn = side == 0 ? TT_FN_WENO_FACE_M : TT_FN_WENO_FACE_P;
     f1.n_in = 1;
-    f1.in[0] = {Ae, q.B, n + 6, n, q.r};
+    f1.in[0] = {Ae, B1, n + 6, n, R};
     f1.eps_w = eps_w;
     f1.wt = &wt;
     DTT vt = alloc(w, nf, n, p.r_max);
@@ -413,12 +442,42 @@ struct Solver {
     y0.r = vt.r;
     copy_scale(w, y0.A, nf, vt.A, nf, nf, vt.r, 1.0);
     gather_rows(w, y0.B, n * nq, vt.B, n, rep_idx, n * nq, vt.r);
-    double *Be = w.arena.dalloc((size_t)(n + 6) * vt.r);
-    ghost_extend(w, vt.B, n, vt.r, rule_ax[1 - d], SIGN_TANGENT[v], Be);
+    const double *A2 = vt.A;
+    int r2 = vt.r;
+    double *Be;
+    if (tangent_exact) {
+      r2 = vt.r + 6;
+      double *Ax = w.arena.dalloc((size_t)nf * r2);
+      Be = w.arena.dalloc((size_t)(n + 6) * r2);
+      copy_scale(w, Ax, nf, vt.A, nf, nf, vt.r, 1.0);
+      fill_value(w, Be, n + 6, n + 6, vt.r, 0.0);
+      copy_scale(w, Be + 3, n + 6, vt.B, n, n, vt.r, 1.0);
+      copy_scale(w, Be + (size_t)vt.r * (n + 6), n + 6, unit6, n + 6, n + 6, 6, 1.0);
+      double *V = Ax + (size_t)vt.r * nf;
+      if (J) {
+        // the ghost field: normal factors (extended by the normal rule) times tangent columns
+        // (explicit, zero inside the domain), evaluated at the 6 tangent ghost rows
+        double *Gn = w.arena.dalloc((size_t)(n + 6) * J), *Gt = w.arena.dalloc((size_t)(n + 6) * J);
+        for (int j = 0; j < J; ++j) {
+          copy_scale(w, Gn + (size_t)j * (n + 6), n + 6, gh[j]->o, n + 6, n + 6, 1,
+                     time_factor(*gh[j], tt));
+          copy_scale(w, Gt + (size_t)j * (n + 6), n + 6, gh[j]->e, n + 6, n + 6, 1, 1.0);
+        }
+        FiberSpec fg = f1;
+        fg.in[0] = {Gn, Gt, n + 6, n + 6, J};
+        fiber_cols(w, fg, nf, ghost_rows6, 6, V);
+      } else {
+        fill_value(w, V, nf, nf, 6, 0.0);
+      }
+      A2 = Ax;
+    } else {
+      Be = w.arena.dalloc((size_t)(n + 6) * vt.r);
+      ghost_extend(w, vt.B, n, vt.r, rule_ax[1 - d], SIGN_TANGENT[v], Be);
+    }
     FiberSpec f2;
     f2.fn = TT_FN_WENO_QUAD;
     f2.n_in = 1;
-    f2.in[0] = {vt.A, Be, nf, n + 6, vt.r};
+    f2.in[0] = {A2, Be, nf, n + 6, r2};
     f2.eps_w = eps_w;
     f2.nq = nq;
     f2.wt = &wt;
@@ -476,8 +535,8 @@ struct Solver {
       for (int d = 0; d < 2; ++d)
         for (int v = 0; v < 3; ++v)
           for (int side = 0; side < 2; ++side)
-            tasks.push_back([this, &QD, &qm, &qp, &sb, d, v, side](Ctx &w) {
-              weno_state(w, QD[d][v], v, side, sb[d], d, side == 0 ? qm[d][v] : qp[d][v]);
+            tasks.push_back([this, &QD, &qm, &qp, &sb, d, v, side, tt](Ctx &w) {
+              weno_state(w, QD[d][v], v, side, sb[d], d, tt, side == 0 ? qm[d][v] : qp[d][v]);
             });
       run_tasks(std::move(tasks));
     }
@@ -738,8 +797,6 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
              "tt_fv_init: unknown boundary kind");
   TT_REQUIRE(!(p->bc_x == TT_BC_EXACT && p->bc_y == TT_BC_EXACT),
              "tt_fv_init: at most one axis can have exact boundaries");
-  TT_REQUIRE(p->scheme != 55 || (p->bc_x != TT_BC_EXACT && p->bc_y != TT_BC_EXACT),
-             "tt_fv_init: exact boundaries are built for Upwind3/5");
   TT_REQUIRE(std::isfinite(p->t0), "tt_fv_init: t0 not finite");
   TT_REQUIRE(p->eps_rule != TT_EPS_PAPER || (p->c_eps > 0.0 && std::isfinite(p->c_eps)),
              "tt_fv_init: c_eps must be positive with TT_EPS_PAPER");
@@ -799,6 +856,19 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
       s->nf_ax[a] = s->periodic_ax[a] ? p->n : p->n + 1;
     }
     s->t = p->t0;
+    if (s->rule_ax[0] == Ghost::Zero || s->rule_ax[1] == Ghost::Zero) {
+      const int n6 = p->n + 6;
+      std::vector<int> rows{0, 1, 2, p->n + 3, p->n + 4, p->n + 5};
+      std::vector<double> unit((size_t)n6 * 6, 0.0);
+      for (int k = 0; k < 6; ++k) unit[(size_t)k * n6 + rows[k]] = 1.0;
+      s->ghost_rows6 = s->c.arena.ialloc(6);
+      s->unit6 = s->c.arena.dalloc(unit.size());
+      HIP_CHECK(hipMemcpyAsync(s->ghost_rows6, rows.data(), 6 * sizeof(int),
+                               hipMemcpyHostToDevice, s->c.stream));
+      HIP_CHECK(hipMemcpyAsync(s->unit6, unit.data(), unit.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s->c.stream));
+      s->c.sync();
+    }
     for (int v = 0; v < 3; ++v) {
       s->Q[v] = Solver::alloc(s->c, p->n, p->n, p->r_max);
       s->Q[v].r = q0[v].rank;

@@ -83,8 +83,9 @@ def test_kelvin_boundary_terms_matter():
 
 
 @pytest.mark.parametrize("name,scheme", [
-    ("coastal_kelvin", "upwind3"), ("coastal_kelvin", "upwind5"),
-    ("barotropic_tide", "upwind5"), ("manufactured", "upwind3"), ("manufactured", "upwind5"),
+    ("coastal_kelvin", "upwind3"), ("coastal_kelvin", "upwind5"), ("coastal_kelvin", "weno5"),
+    ("barotropic_tide", "upwind5"), ("barotropic_tide", "weno5"), ("manufactured", "upwind3"),
+    ("manufactured", "upwind5"), ("manufactured", "weno5"),
 ])
 def test_tt_oracle_equals_full_grid_with_terms(name, scheme):
     """TT oracle (tolerance 0, no effective cap, Taylor to round-off, full-rank crosses)
@@ -98,4 +99,8 @@ def test_tt_oracle_equals_full_grid_with_terms(name, scheme):
     s = TTSolver(n, scheme, st.nonlinear, g=st.g, H=st.H0, f=st.meta["f"], eps=0.0, rmax=48,
                  taylor_terms=60, cross_full=True, bc=case.bc, terms=case.terms)
     Q = s.run([TT(x.A, x.B) for x in st.tt], dt, 3)
-    assert _rel([q.A @ q.B.T for q in Q], U) < 1e-10
+    # the manufactured momentum fluxes carry g h^2 / 2 ~ 1e8 (Table 2's scales); with WENO5 the
+    # face states are full rank on this grid and the roundings of those fluxes resolve their
+    # O(1) dynamic part only to ~1e-8 absolute, so that case is held to 1e-8
+    bar = 1e-8 if (name, scheme) == ("manufactured", "weno5") else 1e-10
+    assert _rel([q.A @ q.B.T for q in Q], U) < bar
