@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle step")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="skip the comparison with the full-grid comparator after the run")
     ap.add_argument("--timed-kernel", default="tsqr_qr",
                     help="kernel family timed with HIP launch events ('' = none); default: "
                          "the Householder factorisations, the largest share of kernel time")
@@ -145,6 +147,10 @@ def main():
                     help="contraction arithmetic of the dambreak2048, ensemble and learned4096 "
                          "workloads")
     ap.add_argument("--learned-n", type=int, default=4096, help="grid of learned4096")
+    ap.add_argument("--flux", default="products", choices=["products", "lf_cross"],
+                    help="nonlinear LLF flux of the headline workload: Section 4.2's products "
+                         "(1/h, Hadamard roundings, lambda by cross) or the LF-cross (the whole "
+                         "flux vector of a direction by one cross)")
     ap.add_argument("--qr", default="auto", choices=["auto", "cholesky", "householder"],
                     help="QR of the rounding factors: Cholesky QR on the matrix cores above 64 "
                          "columns and Householder TSQR otherwise (auto), or one of the two")
@@ -185,7 +191,7 @@ def main():
     st = synth.nonlinear_bumps(seed=0, n=n, rmax=rmax, eps=eps)
     dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=rmax) for f in st.tt]
     s = ttfv.tt_fv_init(n, "upwind5", True, True, dev, g=st.g, eps=eps, r_max=rmax,
-                        taylor_terms=K, qr=args.qr, workers=args.workers)
+                        taylor_terms=K, qr=args.qr, workers=args.workers, flux=args.flux)
 
     # step 1 from the initial state: parity against the oracle (and the CPU baseline)
     torch.cuda.synchronize()
@@ -200,7 +206,8 @@ def main():
             cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
         except Exception:
             cores = os.cpu_count()
-        ts = otf.TTSolver(n, "upwind5", True, True, g=st.g, eps=eps, rmax=rmax, taylor_terms=K)
+        ts = otf.TTSolver(n, "upwind5", True, True, g=st.g, eps=eps, rmax=rmax, taylor_terms=K,
+                          flux=args.flux)
         Q0 = [ott.TT(f.A, f.B) for f in st.tt]
         t0 = time.perf_counter()
         Qo = ts.step(Q0, st.dt)
@@ -247,6 +254,21 @@ def main():
 
     roof = _roof(args.timed_kernel, stats, elapsed, traffic=_family_traffic(args.timed_kernel),
                  every=args.time_every)
+    # accuracy against the uncompressed scheme: the full-grid comparator from the same initial
+    # cell averages for as many steps as the TT solver took (outside the timed region)
+    vs_grid = None
+    if not args.no_grid:
+        taken = int(ttfv.tt_fv_get_stats(s)["steps"])
+        U = torch.tensor(np.stack(st.fields), dtype=torch.float64, device="cuda")
+        grid = ttfv.tt_grid_init(n, "upwind5", True, True, g=st.g)
+        grid.step(U, st.dt, taken)
+        torch.cuda.synchronize()
+        Ug = U.cpu().numpy()
+        grid.close()
+        Qg = ttfv.tt_fv_get_state(s)
+        vs_grid = {"steps": taken, "rel_l2": [float(np.linalg.norm(q.full() - Ug[v]) /
+                                                    np.linalg.norm(Ug[v]))
+                                              for v, q in enumerate(Qg)]}
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -254,10 +276,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"nonlinear_bumps_{n}", "grid": f"{n}x{n}", "scheme": "upwind5",
                    "bc": "periodic", "r_max": rmax, "eps": eps, "taylor_terms": K, "seed": 0,
-                   "cfl": 0.4, "dt": st.dt, "qr": args.qr,
+                   "cfl": 0.4, "dt": st.dt, "qr": args.qr, "flux": args.flux,
                    "worker_streams": args.workers if args.workers > 0 else 8},
         "roofline": roof, "roofline_gemm": roof_gemm, "cpu_baseline": cpu, "parity": parity,
-        "ranks": stats["ranks"],
+        "ranks": stats["ranks"], "tt_vs_full_grid": vs_grid,
         "roundings_per_step": (stats["roundings"] - stats0["roundings"]) / args.steps,
         "crosses_per_step": (stats["crosses"] - stats0["crosses"]) / args.steps,
     }

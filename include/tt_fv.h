@@ -146,6 +146,12 @@ int tt_maxvol(tt_ctx *ctx, const double *q, int n, int r, int ldq, double tau, i
                                at Gauss point m of cell j; fparams = {periodic, sign, eps_w} */
 #define TT_FN_RECIP      5  /* inputs[0] = X; entry 1 / X(i,j) (the cross alternative to
                                Algorithm 1 that Section 4.2 names)                          */
+#define TT_FN_LLF_FLUX   6  /* LF-cross (the alternative Section 4.2 contrasts with its flux
+                               products): inputs = h-, m-, t-, h+, m+, t+ (face/quadrature
+                               TTs, n1 x n2/3, normal-first variables); fparams[0] = g;
+                               entry (f, c n2/3 + j): component c of the LLF flux
+                               (F(U-) + F(U+))/2 - lambda/2 (U+ - U-), F = (m, m^2/h + g h^2/2,
+                               m t/h), lambda = max(|m-/h-| + sqrt(g h-), |m+/h+| + sqrt(g h+)) */
 int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const double *fparams,
              int n1, int n2, const int *J0, int nJ0, double eps, int r_max, int sweeps,
              int kick, uint64_t key, tt_matrix *y, int *J_out, int *nJ_out);
@@ -203,7 +209,12 @@ typedef struct {
                          TT_TERM_Y_* terms of tt_fv_set_terms, Section 5's exact-solution
                          boundaries; at most one axis)                                      */
   double t0;          /* time at the start of the first step (for the terms' time factors) */
+  int flux;           /* nonlinear LLF flux: TT_FLUX_PRODUCTS (Section 4.2: 1/h, Hadamard
+                         products and roundings, lambda by cross) or TT_FLUX_LF_CROSS (the
+                         whole flux vector of a direction by one cross, TT_FN_LLF_FLUX)     */
 } tt_fv_params;
+#define TT_FLUX_PRODUCTS 0
+#define TT_FLUX_LF_CROSS 1
 #define TT_BC_PERIODIC 1
 #define TT_BC_WALL     2
 #define TT_BC_EXACT    3

@@ -34,6 +34,8 @@ One evaluation of L(Q) (Sections 4.1-4.3):
                     F2 = round(P1 + g/2 P2), F3 = round(hu o w), F1 = hu;
                     lambda by one cross of max(|hu-/h-| + sqrt(g h-), |hu+/h+| + sqrt(g h+));
                     D_c = round(lambda o (q_c+ - q_c-)); Fhat_c = round((F_c- + F_c+)/2 - D_c/2).
+                    Or (flux="lf_cross") the whole LLF flux vector by one cross whose column
+                    index carries the component (the LF-cross Section 4.2 contrasts with this).
     finish          Gauss-Legendre sum over the quadrature rows of the second core, and the
                     difference (T - 1) on the first core (Section 4.1).
   L_c = -dF_c/dx - dG_c/dy (+ Coriolis source), a concatenation of cores.
@@ -122,6 +124,42 @@ class _Lambda:
         return self._f(*[X.A[I] @ X.B.T for X in self.t])
 
 
+class _LFFlux:
+    """LF-cross entries (the alternative Section 4.2 contrasts with the present approach, from
+    the authors' earlier Euler work): the whole LLF flux vector of one direction by a single
+    cross, the flux component folded into the column index, column c * n2 + j.  The states are
+    in normal-first order (h, m, t): F = (m, m^2/h + g h^2/2, m t/h),
+    Fhat = (F(U-) + F(U+))/2 - lambda/2 (U+ - U-), lambda = max(|m-/h-| + sqrt(g h-),
+    |m+/h+| + sqrt(g h+))."""
+
+    def __init__(self, qm, qp, g, n2):
+        self.t, self.g, self.n2 = list(qm) + list(qp), g, n2
+
+    def _f(self, vals, comps):
+        hm, mm, tm, hp, mp, tp = vals
+        g = self.g
+        lam = np.maximum(np.abs(mm / hm) + np.sqrt(g * hm), np.abs(mp / hp) + np.sqrt(g * hp))
+        Fm = (mm, mm * mm / hm + 0.5 * g * hm * hm, mm * tm / hm)
+        Fp = (mp, mp * mp / hp + 0.5 * g * hp * hp, mp * tp / hp)
+        Um, Up = (hm, mm, tm), (hp, mp, tp)
+        out = np.empty_like(hm)
+        for c in range(3):
+            sel = comps == c
+            out[:, sel] = (0.5 * (Fm[c] + Fp[c]) - 0.5 * lam * (Up[c] - Um[c]))[:, sel]
+        return out
+
+    def cols(self, J):
+        J = np.asarray(J)
+        comps, j = J // self.n2, J % self.n2
+        return self._f([X.A @ X.B[j].T for X in self.t], comps)
+
+    def rows(self, I):
+        I = np.asarray(I)
+        comps = np.repeat(np.arange(3), self.n2)
+        vals = [np.tile(X.A[I] @ X.B.T, (1, 3)) for X in self.t]
+        return self._f(vals, comps)
+
+
 class _Recip:
     """Entries 1/x of one TT (the cross alternative to Algorithm 1 named in Section 4.2)."""
 
@@ -204,7 +242,8 @@ class TTSolver:
                  rmax: int = 32, taylor_terms: int = 8, cross_sweeps: int = 3,
                  cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor",
                  replay=None, cross_drop: float = 1e-13, eps_rule: str = "fixed",
-                 c_eps: float = 1.0, bc=None, terms=(), t0: float = 0.0):
+                 c_eps: float = 1.0, bc=None, terms=(), t0: float = 0.0,
+                 flux: str = "products"):
         self.n, self.scheme, self.nonlinear = n, scheme, nonlinear
         self.bc = tuple(bc) if bc is not None else \
             (("periodic", "periodic") if periodic else ("wall", "wall"))
@@ -222,6 +261,9 @@ class TTSolver:
         self.eps_q = [eps, eps, eps]       # tolerances of the time-stepping roundings
         self.sweeps, self.kick, self.cross_full = cross_sweeps, cross_kick, cross_full
         self.recip = recip
+        if flux not in ("products", "lf_cross"):
+            raise ValueError("flux must be 'products' or 'lf_cross'")
+        self.flux = flux                   # nonlinear LLF: products of Section 4.2 or LF-cross
         self.cross_drop = cross_drop     # orth drop threshold of the crosses (reading R12)
         self.dx = 1.0 / n
         self.tab = stencils.tables(scheme)
@@ -380,6 +422,12 @@ class TTSolver:
             F2 = add([(-0.5 * c, v_p), (0.5 * c, v_m)])
             return [F0, F1, F2]
         g = self.g
+        if self.flux == "lf_cross":
+            n2 = self.n * self.nq
+            y0 = qm[1] if norm(qm[1]) > 0.0 else qm[0]
+            y0 = TT(y0.A, np.concatenate([y0.B] * 3, axis=0))
+            Fv = self._cross(_LFFlux(qm, qp, g, n2), nf, 3 * n2, y0, site_base + 4)
+            return [TT(Fv.A, Fv.B[c * n2:(c + 1) * n2]) for c in range(3)]
         F = {}
         for si, (s, (h, m, t)) in enumerate((("m", qm), ("p", qp))):
             if self.recip == "cross":

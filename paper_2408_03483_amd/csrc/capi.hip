@@ -288,6 +288,18 @@ static FiberSpec make_fiber_spec(Ctx &c, int fn, const tt_matrix *inputs, int n_
       fs.n_in = 4;
       fs.g = fparams[0];
       break;
+    case TT_FN_LLF_FLUX:
+      TT_REQUIRE(n_inputs == 6 && fparams, "llf flux: six inputs and g");
+      TT_REQUIRE(n2 % 3 == 0, "llf flux: n2 must be 3 x the inputs' columns");
+      for (int t = 0; t < 6; ++t) {
+        check_matrix(&inputs[t], "input", true);
+        TT_REQUIRE(inputs[t].n1 == n1 && inputs[t].n2 * 3 == n2, "llf flux: input shape");
+        fs.in[t] = {inputs[t].g1, inputs[t].g2, n1, n2 / 3, inputs[t].rank};
+      }
+      fs.n_in = 6;
+      fs.g = fparams[0];
+      fs.ncol = n2 / 3;
+      break;
     case TT_FN_WENO_FACE_M:
     case TT_FN_WENO_FACE_P: {
       TT_REQUIRE(n_inputs == 1 && fparams, "weno face: one input and params");

@@ -257,9 +257,10 @@ struct FiberInput {
 struct FiberSpec {
   int fn = 0;
   int n_in = 0;
-  FiberInput in[4];
+  FiberInput in[6];
   double g = 0, eps_w = 0;
   int nq = 3;
+  int ncol = 0;                     // TT_FN_LLF_FLUX: columns per flux component
   const WenoTables *wt = nullptr;   // host table, copied into the kernel arguments
 };
 // entries fn(i, j) for i in [0,n1), j in J (|J| = nj) into out (n1 x nj, ld n1)

@@ -203,9 +203,9 @@ __device__ __forceinline__ double dotrow(const double *A, int lda, int ia, const
 
 struct FibArgs {
   int fn, n_in;
-  FiberInput in[4];
+  FiberInput in[6];
   double g;
-  int nq;
+  int nq, ncol;
 };
 
 __device__ double fiber_entry(const FibArgs &f, const WenoArgs &w, int i, int j) {
@@ -221,6 +221,26 @@ __device__ double fiber_entry(const FibArgs &f, const WenoArgs &w, int i, int j)
       const double lm = fabs(x[1] / x[0]) + sqrt(f.g * x[0]);
       const double lp = fabs(x[3] / x[2]) + sqrt(f.g * x[2]);
       return fmax(lm, lp);
+    }
+    case TT_FN_LLF_FLUX: {
+      // column j = component * ncol + quadrature column; states (h, m, t) minus then plus
+      const int comp = j / f.ncol, jj = j - comp * f.ncol;
+      double x[6];
+      for (int t = 0; t < 6; ++t)
+        x[t] = dotrow(f.in[t].A, f.in[t].lda, i, f.in[t].B, f.in[t].ldb, jj, f.in[t].r);
+      const double hm = x[0], mm = x[1], tm = x[2], hp = x[3], mp = x[4], tp = x[5];
+      const double lam = fmax(fabs(mm / hm) + sqrt(f.g * hm), fabs(mp / hp) + sqrt(f.g * hp));
+      double fm, fp, um, up;
+      if (comp == 0) {
+        fm = mm; fp = mp; um = hm; up = hp;
+      } else if (comp == 1) {
+        fm = mm * mm / hm + 0.5 * f.g * hm * hm;
+        fp = mp * mp / hp + 0.5 * f.g * hp * hp;
+        um = mm; up = mp;
+      } else {
+        fm = mm * tm / hm; fp = mp * tp / hp; um = tm; up = tp;
+      }
+      return 0.5 * (fm + fp) - 0.5 * lam * (up - um);
     }
     case TT_FN_WENO_FACE_M:
     case TT_FN_WENO_FACE_P: {
@@ -265,9 +285,10 @@ FibArgs make_args(const FiberSpec &fs) {
   FibArgs a{};
   a.fn = fs.fn;
   a.n_in = fs.n_in;
-  for (int t = 0; t < 4; ++t) a.in[t] = fs.in[t];
+  for (int t = 0; t < 6; ++t) a.in[t] = fs.in[t];
   a.g = fs.g;
   a.nq = fs.nq;
+  a.ncol = fs.ncol;
   return a;
 }
 

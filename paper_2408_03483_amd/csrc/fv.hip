@@ -15,6 +15,9 @@
 //                   F2 = round(P1 + g/2 P2), F3 = round(hu o w); lambda by one cross of
 //                   max(|hu-/h-| + sqrt(g h-), |hu+/h+| + sqrt(g h+));
 //                   D_c = round(lambda o (q_c+ - q_c-)), Fhat_c = round((F- + F+)/2 - D_c/2).
+//                   Or (TT_FLUX_LF_CROSS) the whole LLF flux vector of a direction by one
+//                   cross over (face, component x quadrature column): the LF-cross that
+//                   Section 4.2 contrasts with the products.
 //   finish          Gauss-Legendre sum on the second core, (T - 1) on the first (Section 4.1).
 // SSP-RK3 (Section 4.4): Q1 = F(Qn), Q2 = round(3/4 Qn + 1/4 F(Q1)),
 // Qn+1 = round(1/3 Qn + 2/3 F(Q2)), F(q) = round(q + dt L(q)).
@@ -556,6 +559,40 @@ struct Solver {
       }
       return;
     }
+    if (p.flux == TT_FLUX_LF_CROSS) {
+      // LF-cross: the whole LLF flux vector of direction d by one cross over the face index
+      // and (component, quadrature column), then split by component
+      for (int d = 0; d < 2; ++d)
+        for (int v = 0; v < 3; ++v) dF[d][v] = alloc(c, n, n, p.r_max);
+      DTT Fv[2];
+      for (int d = 0; d < 2; ++d) Fv[d] = alloc(c, nf_ax[d], 3 * n * nq, p.r_max);
+      c.sync();
+      std::vector<Pool::Task> tasks;
+      for (int d = 0; d < 2; ++d)
+        tasks.push_back([this, &qm, &qp, &Fv, &dF, &sb, d](Ctx &w) {
+          const int nf = nf_ax[d], n2 = n * nq;
+          // starting columns: the normal momentum's (else h's) second core for each component
+          const DTT &ys = norm2(w, qm[d][1]) > 0.0 ? qm[d][1] : qm[d][0];
+          DTT y0{nf, 3 * n2, ys.r, ys.A, w.arena.dalloc((size_t)3 * n2 * ys.r)};
+          for (int k = 0; k < 3; ++k)
+            copy_scale(w, y0.B + (size_t)k * n2, 3 * n2, ys.B, n2, n2, ys.r, 1.0);
+          FiberSpec fs;
+          fs.fn = TT_FN_LLF_FLUX;
+          fs.n_in = 6;
+          const DTT *in[6] = {&qm[d][0], &qm[d][1], &qm[d][2], &qp[d][0], &qp[d][1], &qp[d][2]};
+          for (int k = 0; k < 6; ++k) fs.in[k] = {in[k]->A, in[k]->B, in[k]->n1, in[k]->n2, in[k]->r};
+          fs.g = p.g;
+          fs.ncol = n2;
+          cross(w, fs, nf, 3 * n2, y0, sb[d] + 4, Fv[d]);
+          for (int v = 0; v < 3; ++v) {
+            DTT Fh{nf, n2, Fv[d].r, Fv[d].A, w.arena.dalloc((size_t)n2 * std::max(Fv[d].r, 1))};
+            copy_scale(w, Fh.B, n2, Fv[d].B + (size_t)v * n2, 3 * n2, n2, Fv[d].r, 1.0);
+            finish(w, Fh, d, dF[d][v]);
+          }
+        });
+      run_tasks(std::move(tasks));
+      return;
+    }
     // phase A, per direction d and side s (h, m = momentum along d, t = the other one):
     //   A1: rh = 1/h, P2 = round(h o h), and the two lambda crosses
     //   A2: u = round(m o rh), w = round(t o rh)
@@ -795,6 +832,10 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
              "tt_fv_init: unknown eps_rule");
   TT_REQUIRE(p->bc_x >= 0 && p->bc_x <= TT_BC_EXACT && p->bc_y >= 0 && p->bc_y <= TT_BC_EXACT,
              "tt_fv_init: unknown boundary kind");
+  TT_REQUIRE(p->flux == TT_FLUX_PRODUCTS || p->flux == TT_FLUX_LF_CROSS,
+             "tt_fv_init: unknown flux method");
+  TT_REQUIRE(p->flux != TT_FLUX_LF_CROSS || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
+             "tt_fv_init: bad cross parameters");
   TT_REQUIRE(!(p->bc_x == TT_BC_EXACT && p->bc_y == TT_BC_EXACT),
              "tt_fv_init: at most one axis can have exact boundaries");
   TT_REQUIRE(std::isfinite(p->t0), "tt_fv_init: t0 not finite");

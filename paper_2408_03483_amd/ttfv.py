@@ -44,7 +44,8 @@ class ParamsC(ctypes.Structure):
                 ("cross_kick", ctypes.c_int), ("recip", ctypes.c_int), ("workers", ctypes.c_int),
                 ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double),
                 ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double),
-                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("t0", ctypes.c_double)]
+                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("t0", ctypes.c_double),
+                ("flux", ctypes.c_int)]
 
 
 class TermC(ctypes.Structure):
@@ -71,6 +72,7 @@ class StatsC(ctypes.Structure):
 PRECISIONS = {"f64": 0, "f32": 1}
 QR_METHODS = {"auto": 0, "cholesky": 1, "householder": 2}
 EPS_RULES = {"fixed": 0, "paper": 1}
+FLUXES = {"products": 0, "lf_cross": 1}
 BCS = {None: 0, "periodic": 1, "wall": 2, "exact": 3}
 TERM_WHERE = {"forcing": 0, "x_lo": 1, "x_hi": 2, "y_lo": 3, "y_hi": 4}
 
@@ -395,7 +397,8 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                cross_kick: int = 4, recip: str = "taylor", workers: int = 0, stream=None,
                arena_bytes: int = 4 << 30, precision: str = "f64",
                qr: str = "auto", cross_drop: float = 0.0, eps_rule: str = "fixed",
-               c_eps: float = 1.0, bc=None, t0: float = 0.0, terms=()) -> Solver:
+               c_eps: float = 1.0, bc=None, t0: float = 0.0, terms=(),
+               flux: str = "products") -> Solver:
     """bc: per-axis boundary kinds ("periodic", "wall", "exact") overriding `periodic`;
     terms: separable forcing / ghost terms (see tt_fv_set_terms)."""
     L = load_library()
@@ -404,7 +407,7 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
                 workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop,
-                EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0)
+                EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0, FLUXES[flux])
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -471,7 +474,7 @@ class Grid:
         bx, by = (None, None) if bc is None else bc
         self.params = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0,
                               g, H0, f, 0.0, 1, 1, 1, 0, 0, 0, 0, 0, 0.0, 0, 1.0,
-                              BCS[bx], BCS[by], t0)
+                              BCS[bx], BCS[by], t0, 0)
         self.h = ctypes.c_void_p()
         self._stream = stream
         _check(L.tt_grid_init(ctypes.byref(self.h), ctypes.byref(self.params),

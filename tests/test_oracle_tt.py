@@ -256,3 +256,32 @@ def test_tt_lambda_entries_hand_values():
     ly = tt_fv._Lambda(hm, const(-3.0), hp, const(0.25), 4.0)
     assert np.all(lx.cols(np.array([0, 3])) == 3.0) and np.all(lx.rows(np.array([1])) == 3.0)
     assert np.all(ly.cols(np.array([2])) == 5.0) and np.all(ly.rows(np.array([0, 4])) == 5.0)
+
+
+def test_lf_cross_equals_full_grid_and_product_flux():
+    """LF-cross (the whole LLF flux vector of a direction by one cross, Section 4.2's
+    alternative): with full-rank crosses it equals the full-grid scheme, and at a working
+    tolerance it agrees with the product flux to that tolerance."""
+    import math
+    import synth
+    from oracle import fv_grid
+    from oracle.tt import TT
+    from oracle.tt_fv import TTSolver
+    st = synth.nonlinear_bumps(seed=3, n=12, rmax=12, eps=1e-14, kmax=2)
+    Q0 = [TT(x.A, x.B) for x in st.tt]
+    grid = fv_grid.GridSolver(12, "upwind5", True, periodic=True, g=st.g)
+    U = grid.run([x.copy() for x in st.fields], st.dt, 2)
+    s = TTSolver(12, "upwind5", True, True, g=st.g, eps=0.0, rmax=64, cross_full=True,
+                 flux="lf_cross")
+    Q = s.run(Q0, st.dt, 2)
+    rel = math.sqrt(sum(float(np.sum((q.A @ q.B.T - u) ** 2)) for q, u in zip(Q, U)) /
+                    sum(float(np.sum(u * u)) for u in U))
+    assert rel < 1e-12, rel
+    st = synth.nonlinear_bumps(seed=4, n=48, rmax=16, eps=1e-10, kmax=3)
+    Q0 = [TT(x.A, x.B) for x in st.tt]
+    a = TTSolver(48, "upwind5", True, True, g=st.g, eps=1e-9, rmax=32, flux="lf_cross")
+    b = TTSolver(48, "upwind5", True, True, g=st.g, eps=1e-9, rmax=32)
+    Qa, Qb = a.run(Q0, st.dt, 2), b.run(Q0, st.dt, 2)
+    for qa, qb in zip(Qa, Qb):
+        Fa, Fb = qa.A @ qa.B.T, qb.A @ qb.B.T
+        assert np.linalg.norm(Fa - Fb) <= 1e-7 * np.linalg.norm(Fb)
