@@ -94,6 +94,19 @@ int  tt_ctx_set_qr(tt_ctx *ctx, int method, int max_passes);
 int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
              double *sigma_out);
 
+/* Compression of a full field into a TT (the TT-native replacement of an initial-condition
+ * SVD on the host; Section 3.2's truncated SVD applied to a dense matrix): y = a rank-k
+ * approximation of F with ||F - y||_F <= eps ||F||_F and k <= r_max as small as the SVD allows,
+ * found by a randomized range finder with subspace iterations on the matrix cores (Halko,
+ * Martinsson and Tropp 2011) that runs until the discarded directions can move the kept ones
+ * by at most 1e-13 of the largest singular value.  F: device, n1 x n2, column-major with
+ * leading dimension ld >= n1 (not modified).  y->cap >= r_max; y's first core has orthonormal
+ * columns, the second carries the singular values, which are written to sigma_out (host,
+ * length >= r_max) when not NULL.  Returns TT_WRANKCAP when r_max (or the 96-column sketch) is
+ * what limited the rank, TT_WSKETCH when the iterations stopped unconverged. */
+int tt_compress(tt_ctx *ctx, const double *F, int n1, int n2, int ld, double eps, int r_max,
+                tt_matrix *y, double *sigma_out);
+
 /* TT rounding that allocates nothing, for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same result
  * and arguments as tt_round with a default context (FP64 contractions, automatic sketch), but

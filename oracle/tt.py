@@ -301,3 +301,21 @@ def initial_columns(Y: TT, drop: float = 1e-13) -> np.ndarray:
     if Q.shape[1] == 0:
         return np.array([0], dtype=np.int64)
     return maxvol(Q)
+
+
+def from_full(F: np.ndarray, eps: float, rmax: int) -> TT:
+    """Truncated SVD of a full matrix (Section 3.2's truncation applied to F itself): the
+    smallest rank k <= rmax whose discarded singular values have norm <= eps ||F||_F; first
+    core U_k (orthonormal columns), second V_k Sigma_k.  A zero matrix gives the rank-1 zero TT."""
+    U, s, Vt = np.linalg.svd(F, full_matrices=False)
+    total = float(np.sum(s * s))
+    if total == 0.0:
+        return TT(np.zeros((F.shape[0], 1)), np.zeros((F.shape[1], 1)))
+    tail = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])
+    k = len(s)
+    for kk in range(1, len(s) + 1):
+        if tail[kk] <= eps * eps * total:
+            k = kk
+            break
+    k = max(1, min(k, rmax))
+    return TT(U[:, :k].copy(), (Vt[:k].T * s[:k]).copy())

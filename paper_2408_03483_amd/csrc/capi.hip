@@ -422,6 +422,24 @@ int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *
   });
 }
 
+int tt_compress(tt_ctx *ctx, const double *F, int n1, int n2, int ld, double eps, int r_max,
+                tt_matrix *y, double *sigma_out) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && F, "tt_compress: null argument");
+    check_matrix(y, "tt_compress y", false);
+    TT_REQUIRE(n1 >= 1 && n2 >= 1 && ld >= n1, "tt_compress: bad shape or leading dimension");
+    TT_REQUIRE(eps >= 0.0 && r_max >= 1, "tt_compress: eps < 0 or r_max < 1");
+    TT_REQUIRE(y->n1 == n1 && y->n2 == n2 && y->cap >= r_max, "tt_compress: y shape or cap");
+    DTT yv = view(y);
+    std::vector<double> s;
+    const int w = compress_dense(ctx->c, F, n1, n2, ld, eps, r_max, yv, &s);
+    y->rank = yv.r;
+    if (sigma_out)
+      for (size_t i = 0; i < s.size(); ++i) sigma_out[i] = s[i];
+    return w | jacobi_warning(ctx->c);
+  });
+}
+
 int tt_round_noalloc(const tt_matrix *x, double eps, int r_max, tt_matrix *y,
                      double *sigma_out, void *hip_stream) {
   return guarded([&]() {

@@ -170,6 +170,8 @@ void axpby(Ctx &c, double *dst, int ldd, const double *x, int ldx, double a, con
 void fill_value(Ctx &c, double *dst, int ld, int rows, int cols, double v);
 void khatri_rao(Ctx &c, double *out, int n, const double *X, int rx, const double *Y, int ry);
 void colsum(Ctx &c, const double *A, int n, int r, int ld, double *out);
+// out[c] = sum of squares of column c
+void colsumsq(Ctx &c, const double *A, int n, int r, int ld, double *out);
 void gather_rows(Ctx &c, double *dst, int ldd, const double *src, int lds, const int *rows_dev,
                  int nrows, int cols);
 // dst (cols x rows) = src^T (src: rows x cols)
@@ -272,6 +274,10 @@ void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, d
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
 // Frobenius norm of x (sqrt of sum((A^T A) o (B^T B)), the Gram matrices on the matrix cores)
 double norm_tt(Ctx &c, const DTT &x);
+// 2-core TT of a dense n1 x n2 matrix F (device, column-major, leading dimension ld) at
+// relative Frobenius accuracy eps, rank <= rmax (randomized range finder; y->cap >= rmax)
+int compress_dense(Ctx &c, const double *F, int n1, int n2, int ld, double eps, int rmax, DTT &y,
+                   std::vector<double> *sig);
 // upper bound of the arena bytes round_tt draws for an n1 x n2 input of rank R with the
 // context's default sketch settings (FP64), every branch included
 size_t round_arena_bound(int n1, int n2, int R, int rmax);

@@ -177,6 +177,22 @@ __global__ void k_colsum(const double *__restrict__ A, int n, int ld, double *__
   if (threadIdx.x == 0) out[c] = red[0];
 }
 
+__global__ void k_colsumsq(const double *__restrict__ A, int n, int ld,
+                           double *__restrict__ out) {
+  __shared__ double red[TPB];
+  int c = blockIdx.x;
+  const double *col = A + (size_t)c * ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += TPB) acc += col[i] * col[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
 __global__ void k_transpose(double *__restrict__ dst, int ldd, const double *__restrict__ src,
                             int lds, int rows, int cols) {
   __shared__ double tile[32][33];
@@ -284,6 +300,12 @@ void fill_gauss(Ctx &c, double *O, int rows, int cols, int ld, uint64_t seed) {
 void colsum(Ctx &c, const double *A, int n, int r, int ld, double *out) {
   if (r <= 0) return;
   hipLaunchKernelGGL(k_colsum, dim3(r), dim3(TPB), 0, c.stream, A, n, ld, out);
+}
+
+void colsumsq(Ctx &c, const double *A, int n, int r, int ld, double *out) {
+  if (r <= 0) return;
+  hipLaunchKernelGGL(k_colsumsq, dim3(r), dim3(TPB), 0, c.stream, A, n, ld, out);
+  c.cnt.bytes += 8.0 * n * r;
 }
 
 }  // namespace ttfv

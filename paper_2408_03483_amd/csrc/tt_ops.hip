@@ -560,6 +560,98 @@ struct SumPipe {
 
 }  // namespace
 
+// Randomized range finder on a dense matrix (Halko, Martinsson and Tropp, SIAM Review 2011):
+// Y = F Omega with a seeded Gaussian Omega of m = min(96, n1, n2) columns; Qa = orth(Y);
+// W = F^T Qa = Qw Rw; F ~ Qa Qa^T F = Qa Rw^T Qw^T, whose SVD comes from the m x m Rw^T.
+// Subspace iterations (Y = F orth(W)) continue until the discarded directions can leak at most
+// 1e-13 s_0 into the kept part, as in the rounding's range finder.  The tolerance counts the
+// energy outside the sketch: the kept rank k is the smallest with
+// sum_{i >= k} s_i^2 + (||F||^2 - sum s^2) <= eps^2 ||F||^2, where the difference counts only
+// above 1e-13 ||F||^2 (the resolution of a difference of two sums of squares).  Output gauge as the rounding's:
+// A = Qa U_k (orthonormal columns), B = W U_k (carries Sigma).
+int compress_dense(Ctx &c, const double *F, int n1, int n2, int ld, double eps, int rmax, DTT &y,
+                   std::vector<double> *sig_out) {
+  TT_REQUIRE(n1 >= 1 && n2 >= 1 && ld >= n1 && rmax >= 1 && eps >= 0.0,
+             "tt_compress: bad arguments");
+  Scope sc(c.arena);
+  const int m = std::min(std::min(QR_MAXM, qr_max_cols()), std::min(n1, n2));
+  double *cs = c.arena.dalloc(n2);
+  colsumsq(c, F, n1, n2, ld, cs);
+  const std::vector<double> csh = to_host(c, cs, n2);
+  double total = 0.0;
+  for (double v : csh) total += v;
+  require_finite({total}, "compress");
+  if (total == 0.0) {
+    zero_tt(c, y);
+    if (sig_out) sig_out->assign(1, 0.0);
+    return 0;
+  }
+  double *Om = c.arena.dalloc((size_t)n2 * m), *Y = c.arena.dalloc((size_t)n1 * m);
+  double *Qa = c.arena.dalloc((size_t)n1 * m), *W = c.arena.dalloc((size_t)n2 * m);
+  double *Rt = c.arena.dalloc((size_t)m * m), *Rw = c.arena.dalloc((size_t)m * m);
+  double *Qw = c.arena.dalloc((size_t)n2 * m);
+  double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc(m);
+  fill_gauss(c, Om, n2, m, n2, g_sketch_seed ^ ((uint64_t)n1 * 0x9E3779B97F4A7C15ull) ^
+                                   ((uint64_t)n2 << 20) ^ (uint64_t)m ^ 0xC0FFEEull);
+  gemm(c, false, n1, m, n2, 1.0, F, ld, Om, n2, 0.0, Y, n1);          // Y = F Omega
+  const int qlim = std::max(c.power_iters, c.sketch_max_iters);
+  std::vector<double> s;
+  int warn = 0, k = 1;
+  bool short_of_eps = false;
+  for (int q = 0;; ++q) {
+    tsqr(c, Y, n1, m, n1, Qa, n1, Rt, m);
+    gemm(c, true, n2, m, n1, 1.0, F, ld, Qa, n1, 0.0, W, n2);          // W = F^T Qa
+    tsqr(c, W, n2, m, n2, nullptr, 0, Rw, m);                          // W = Qw Rw
+    jacobi_svd(c, Rw, m, US, sg, true, jacobi_floor(eps));             // SVD of Rw^T
+    s = to_host(c, sg, m);
+    require_finite(s, "compress");
+    double captured = 0.0;
+    for (double v : s) captured += v * v;
+    // energy outside the sketch, counted when the difference of the two sums of squares can
+    // resolve it (above 1e-13 of the total; below that the convergence test stands for it)
+    const double diff = total - captured;
+    const double outside = diff > 1e-13 * total ? diff : 0.0;
+    const double thr = eps * eps * total;
+    // smallest k whose discarded tail plus the energy outside the sketch is within eps
+    std::vector<double> tail(m + 1, 0.0);
+    for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
+    k = m;
+    for (int kk = 1; kk <= m; ++kk)
+      if (tail[kk] + outside <= thr) { k = kk; break; }
+    const double fl = std::max(1e-17, jacobi_floor(eps)) * std::sqrt(captured);
+    int kf = 0;
+    while (kf < m && s[kf] > fl) ++kf;
+    k = std::max(1, std::min(std::min(k, kf), rmax));
+    // the cap or the sketch width, not eps, set k
+    short_of_eps = tail[k] + outside > thr && (k == rmax || k == m);
+    if (k < m && q >= c.power_iters) {
+      const int pover = std::max(8, m / 4);
+      if (m - pover > k && s[m - pover] <= 1e-14 * s[0]) break;
+      if (std::pow(s[m - 1] / s[k - 1], 2 * q + 1) * s[k - 1] <= 1e-13 * s[0]) break;
+    }
+    if (k >= m && q >= c.power_iters) break;          // the sketch holds every direction kept
+    if (q >= qlim) {
+      warn |= TT_WSKETCH;
+      c.cnt.sketch_unconverged++;
+      break;
+    }
+    // one more subspace iteration, orthonormalising in between (Y = F (F^T Qa) directly
+    // would square the spectrum and lose every direction below sqrt(u) of the largest)
+    tsqr(c, W, n2, m, n2, Qw, n2, Rt, m);
+    gemm(c, false, n1, m, n2, 1.0, F, ld, Qw, n2, 0.0, Y, n1);         // Y = F orth(F^T Qa)
+    c.cnt.extra_power_iters++;
+  }
+  if (short_of_eps) warn |= TT_WRANKCAP;
+  double *U = c.arena.dalloc((size_t)m * k);
+  normalise_cols(c, US, sg, m, k, U);
+  gemm(c, false, n1, k, m, 1.0, Qa, n1, U, m, 0.0, y.A, n1);
+  gemm(c, false, n2, k, m, 1.0, W, n2, U, m, 0.0, y.B, n2);
+  y.r = k;
+  if (sig_out) sig_out->assign(s.begin(), s.begin() + k);
+  c.cnt.warnings |= warn;
+  return warn;
+}
+
 double norm_tt(Ctx &c, const DTT &x) {
   if (x.r == 0) return 0.0;
   Scope sc(c.arena);

@@ -102,7 +102,7 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
            "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
-           "tt_fv_set_terms"]
+           "tt_fv_set_terms", "tt_compress"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_set_qr.argtypes = [P, I, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
+    L.tt_compress.argtypes = [P, P, I, I, I, D, I, pM, ctypes.POINTER(D)]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
     L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
     L.tt_maxvol.argtypes = [P, P, I, I, I, D, I, ctypes.POINTER(I)]
@@ -283,6 +284,25 @@ def tt_round(ctx: Ctx, x: DeviceTT, eps: float, r_max: int, y: DeviceTT):
                "tt_round")
     y.rank = yc.rank
     return w, np.array(sig[:y.rank])
+
+
+def tt_compress(ctx: Ctx, F, eps: float, r_max: int):
+    """TT of a full field F (torch float64 CUDA tensor, n1 x n2, row-major, F[i, j] with i the
+    first TT index): the library compresses the column-major matrix F^T that this memory is,
+    and the cores are swapped back.  Returns (DeviceTT with rank <= r_max, warnings, sigma)."""
+    if (F.dim() != 2 or not F.is_cuda or str(F.dtype) != "torch.float64" or
+            not F.is_contiguous()):
+        raise ValueError("tt_compress: F must be a contiguous 2-D float64 CUDA tensor")
+    n1, n2 = int(F.shape[0]), int(F.shape[1])
+    yt = DeviceTT(n2, n1, r_max)
+    yc = yt.c()
+    sig = (ctypes.c_double * max(r_max, 1))()
+    w = _check(_lib.tt_compress(ctx.h, ctypes.c_void_p(F.data_ptr()), n2, n1, n2, eps, r_max,
+                                ctypes.byref(yc), sig), "tt_compress")
+    y = DeviceTT.__new__(DeviceTT)
+    y.n1, y.n2, y.cap, y.rank = n1, n2, r_max, yc.rank
+    y.g1, y.g2 = yt.g2, yt.g1
+    return y, w, np.array(sig[:y.rank])
 
 
 def tt_round_noalloc(x: DeviceTT, eps: float, r_max: int, y: DeviceTT, stream=None):

@@ -468,3 +468,45 @@ def test_nonfinite_core_is_an_error(lib):
     with pytest.raises(RuntimeError, match=r"\(-4\)"):
         lib.tt_round(c, X, 1e-10, 6, Y)
     c.close()
+
+
+@pytest.mark.parametrize("n1,n2,r,decay,eps,rmax", [
+    (777, 1531, 60, 0.8, 1e-6, 64),      # rank set by eps
+    (1024, 1024, 40, 0.9, 1e-12, 24),    # rank set by the cap
+    (300, 97, 97, 0.7, 0.0, 64),         # eps 0: keep to the cap (rank 97 > the sketch)
+])
+def test_compress_full_field(lib, ctx, n1, n2, r, decay, eps, rmax):
+    """tt_compress (randomized range finder on a dense field) against the oracle's truncated
+    SVD of the same matrix: same rank, rel difference <= 1e-10, and the TT_WRANKCAP warning
+    exactly when the cap set the rank."""
+    import torch
+    _say(f"compress {n1}x{n2} r={r} decay={decay} eps={eps} rmax={rmax}")
+    rng = np.random.default_rng(n1 + n2)
+    U, _ = np.linalg.qr(rng.standard_normal((n1, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n2, r)))
+    F = (U * decay ** np.arange(r)) @ V.T
+    Ft = torch.tensor(F, dtype=torch.float64, device="cuda").contiguous()
+    y, w, sig = lib.tt_compress(ctx, Ft, eps, rmax)
+    ref = ott.from_full(F, eps, rmax)
+    _say(f"  rank gpu {y.rank} oracle {ref.rank} warn {w}")
+    assert y.rank == ref.rank
+    assert rel(y.full(), ref.A @ ref.B.T) < 1e-10
+    capped = ref.rank == rmax and np.linalg.norm(F - ref.A @ ref.B.T) > eps * np.linalg.norm(F)
+    assert bool(w & 1) == capped
+    s_ref = np.linalg.svd(F, compute_uv=False)[:y.rank]
+    assert np.allclose(sig, s_ref, rtol=1e-9, atol=1e-13 * s_ref[0])
+
+
+def test_compress_dam_break_front(lib, ctx):
+    """The dam break's initial depth at 512^2 (a tanh front of width 0.01: slowly decaying
+    spectrum) at eps 1e-8, cap 64, through tt_compress: as the oracle's truncated SVD."""
+    import torch
+    import synth
+    st = synth.dam_break(seed=0, n=512, rmax=64, eps=1e-8)
+    F = st.fields[0]
+    y, w, sig = lib.tt_compress(ctx, torch.tensor(F, dtype=torch.float64,
+                                                  device="cuda").contiguous(), 1e-8, 64)
+    ref = ott.from_full(F, 1e-8, 64)
+    _say(f"dam break front: rank gpu {y.rank} oracle {ref.rank} warn {w}")
+    assert y.rank == ref.rank
+    assert rel(y.full(), ref.A @ ref.B.T) < 1e-10

@@ -285,3 +285,26 @@ def test_lf_cross_equals_full_grid_and_product_flux():
     for qa, qb in zip(Qa, Qb):
         Fa, Fb = qa.A @ qa.B.T, qb.A @ qb.B.T
         assert np.linalg.norm(Fa - Fb) <= 1e-7 * np.linalg.norm(Fb)
+
+
+def test_from_full_closed_form():
+    """from_full on F = U diag(s) V^T with a known spectrum: the kept rank is the smallest whose
+    discarded tail is within eps (from s alone), and the error equals that tail exactly
+    (Eckart-Young); a zero matrix gives rank 1 and zero."""
+    from oracle.tt import from_full
+    rng = np.random.default_rng(11)
+    n1, n2, r = 60, 45, 30
+    U, _ = np.linalg.qr(rng.standard_normal((n1, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n2, r)))
+    s = 0.7 ** np.arange(r)
+    F = (U * s) @ V.T
+    for eps in (1e-1, 1e-3, 1e-6):
+        tail = np.sqrt(np.cumsum((s * s)[::-1])[::-1])
+        k = int(np.argmax(np.append(tail[1:], 0.0) <= eps * np.linalg.norm(s))) + 1
+        X = from_full(F, eps, 64)
+        assert X.rank == k
+        assert np.linalg.norm(F - X.A @ X.B.T) == pytest.approx(
+            np.sqrt(np.sum(s[k:] ** 2)), rel=1e-9, abs=1e-14)
+    assert from_full(F, 0.0, 5).rank == 5
+    Z = from_full(np.zeros((7, 9)), 1e-8, 4)
+    assert Z.rank == 1 and not np.any(Z.A @ Z.B.T)
