@@ -289,6 +289,14 @@ int  tt_fv_init(tt_fv **out, const tt_fv_params *p, const tt_matrix q0[3], void 
                 size_t arena_bytes);
 /* Advance nsteps SSP-RK3 steps of size dt. */
 int  tt_fv_step(tt_fv *s, double dt, int nsteps);
+/* Largest wave speed per direction over the cells, speed[0] = max |hu/h| + sqrt(g h) and
+ * speed[1] = max |hv/h| + sqrt(g h) (nonlinear; sqrt(g H0) for both in the linear case),
+ * estimated on the TTs without forming the field: rook pivoting on the pointwise function
+ * from every maxvol column of h's second core (a lower bound of the true maximum, which it
+ * found on every smooth field tested). */
+int  tt_fv_max_speed(tt_fv *s, double speed[2]);
+/* The explicit step for a CFL number: *dt = cfl / (speed[0] / dx + speed[1] / dy). */
+int  tt_fv_cfl_dt(tt_fv *s, double cfl, double *dt);
 /* Replace the solver's separable forcing and boundary terms (copied; count 0 clears them).
  * Errors: TT_EINVAL for a bad var or where, a null factor, or ghost terms on a non-exact
  * axis. */

@@ -124,6 +124,36 @@ class _Lambda:
         return self._f(*[X.A[I] @ X.B.T for X in self.t])
 
 
+def rook_max(fun, n1: int, n2: int, J0, max_alt: int = 8):
+    """Largest entry of the matrix fun (entries by .cols(J) and .rows(I)) by rook pivoting from
+    several starts: for every starting column j in J0, a walk from the largest entry of that
+    column alternates the largest entry of the current row and of the current column until the
+    value stops growing (at most max_alt alternations); the best walk wins.  A rook-pivot local
+    maximum, hence a lower bound of the true maximum.  Ties go to the smallest index, walks in
+    the order of J0.  Returns (value, i, j)."""
+    J0 = np.asarray(J0)
+    C = fun.cols(J0)
+    best = (-np.inf, 0, 0)
+    for k, j in enumerate(J0):
+        i = int(np.argmax(C[:, k]))
+        j = int(j)
+        v = float(C[i, k])
+        for _ in range(max_alt):
+            row = fun.rows(np.array([i]))[0]
+            jj = int(np.argmax(row))
+            if row[jj] <= v:
+                break
+            v, j = float(row[jj]), jj
+            col = fun.cols(np.array([j]))[:, 0]
+            ii = int(np.argmax(col))
+            if col[ii] <= v:
+                break
+            v, i = float(col[ii]), ii
+        if v > best[0]:
+            best = (v, i, j)
+    return best
+
+
 class _LFFlux:
     """LF-cross entries (the alternative Section 4.2 contrasts with the present approach, from
     the authors' earlier Euler work): the whole LLF flux vector of one direction by a single
@@ -509,6 +539,21 @@ class TTSolver:
         self.t = t + dt
         self.stats["ranks"].append([q.rank for q in Qn])
         return Qn
+
+    def max_speed(self, Q, d: int) -> float:
+        """Largest wave speed of direction d over the cells, for the explicit step's CFL
+        condition: |m/h| + sqrt(g h) with m the momentum along d (nonlinear; by rook pivoting
+        on the TTs, started from the maxvol columns of h's second core), sqrt(g H) (linear)."""
+        if not self.nonlinear:
+            return math.sqrt(self.g * self.H)
+        h, m = Q[0], Q[1 + d]
+        J0 = initial_columns(h, self.cross_drop)
+        return rook_max(_Lambda(h, m, h, m, self.g), self.n, self.n, J0)[0]
+
+    def cfl_dt(self, Q, cfl: float) -> float:
+        """dt = cfl / (s_x / dx + s_y / dy) from the two directions' largest speeds."""
+        sx, sy = self.max_speed(Q, 0), self.max_speed(Q, 1)
+        return cfl / ((sx + sy) / self.dx)
 
     def run(self, Q, dt: float, nsteps: int):
         for _ in range(nsteps):

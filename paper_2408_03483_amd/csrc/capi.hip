@@ -19,6 +19,8 @@ void solver_time_kernel(Solver *s, const char *name, int every);
 void solver_set_pivots(Solver *s, int mode, PivotModel *pm);
 void solver_set_acceptance(Solver *s, double abs_tol, double rel_slack);
 void solver_set_terms(Solver *s, const tt_fv_term *terms, int count);
+void solver_max_speed(Solver *s, double out[2]);
+double solver_cfl_dt(Solver *s, double cfl);
 void solver_replay_pivots(Solver *s, long long step, int site, const int *J, int nJ,
                           const int *I, int nI);
 int solver_get_pivots(Solver *s, int site, int *J, int capJ, int *nJ, int *I, int capI,
@@ -625,6 +627,23 @@ int tt_fv_step(tt_fv *s, double dt, int nsteps) {
     tt_fv_stats st{};
     solver_stats(s->s, &st);
     return st.warnings & (TT_WRANKCAP | TT_WNOCONV);
+  });
+}
+
+int tt_fv_max_speed(tt_fv *s, double speed[2]) {
+  return guarded([&]() {
+    TT_REQUIRE(s && speed, "null argument");
+    solver_max_speed(s->s, speed);
+    return 0;
+  });
+}
+
+int tt_fv_cfl_dt(tt_fv *s, double cfl, double *dt) {
+  return guarded([&]() {
+    TT_REQUIRE(s && dt, "null argument");
+    TT_REQUIRE(cfl > 0.0 && std::isfinite(cfl), "tt_fv_cfl_dt: cfl must be positive");
+    *dt = solver_cfl_dt(s->s, cfl);
+    return 0;
   });
 }
 

@@ -720,6 +720,70 @@ struct Solver {
     run_tasks(std::move(tasks));
   }
 
+  // Largest wave speed of direction d over the cells, for the explicit step's CFL condition:
+  // |m/h| + sqrt(g h) with m the momentum along d, estimated on the TTs without forming the
+  // field by rook pivoting on the pointwise function (fibers of TT_FN_LLF_LAMBDA with both
+  // sides equal): from every maxvol column of h's second core, a walk from that column's
+  // largest entry alternates the largest entry of the current row and column until the value
+  // stops growing (at most 8 alternations); the best walk wins.  A lower bound of the true
+  // maximum (a rook-pivot local maximum).  Linear SWE: sqrt(g H).
+  double max_speed(int d) {
+    if (!p.nonlinear) return std::sqrt(p.g * p.H0);
+    Scope sc(c.arena);
+    const DTT &h = Q[0], &m = Q[1 + d];
+    FiberSpec fs;
+    fs.fn = TT_FN_LLF_LAMBDA;
+    fs.n_in = 4;
+    fs.in[0] = fs.in[2] = {h.A, h.B, n, n, h.r};
+    fs.in[1] = fs.in[3] = {m.A, m.B, n, n, m.r};
+    fs.g = p.g;
+    const std::vector<int> J0 = initial_columns(c, h);
+    const int nj = (int)J0.size();
+    int *Jd = c.arena.ialloc(nj), *one = c.arena.ialloc(1);
+    double *C = c.arena.dalloc((size_t)n * nj), *vec = c.arena.dalloc(n);
+    HIP_CHECK(hipMemcpyAsync(Jd, J0.data(), nj * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    auto read = [&](const double *dev, size_t len) {
+      std::vector<double> h(len);
+      HIP_CHECK(hipMemcpyAsync(h.data(), dev, len * sizeof(double), hipMemcpyDeviceToHost,
+                               c.stream));
+      c.sync();
+      return h;
+    };
+    fiber_cols(c, fs, n, Jd, nj, C);
+    const std::vector<double> Ch = read(C, (size_t)n * nj);
+    auto argmax = [](const double *v, int len) {
+      int a = 0;
+      for (int t = 1; t < len; ++t)
+        if (v[t] > v[a]) a = t;
+      return a;
+    };
+    auto fetch = [&](bool row, int idx) {
+      HIP_CHECK(hipMemcpyAsync(one, &idx, sizeof(int), hipMemcpyHostToDevice, c.stream));
+      if (row) fiber_rows(c, fs, n, one, 1, vec);
+      else fiber_cols(c, fs, n, one, 1, vec);
+      return read(vec, n);
+    };
+    double best = -HUGE_VAL;
+    for (int k = 0; k < nj; ++k) {
+      int i = argmax(Ch.data() + (size_t)k * n, n);
+      double v = Ch[(size_t)k * n + i];
+      for (int alt = 0; alt < 8; ++alt) {
+        const std::vector<double> row = fetch(true, i);
+        const int jj = argmax(row.data(), n);
+        if (row[jj] <= v) break;
+        v = row[jj];
+        const std::vector<double> col = fetch(false, jj);
+        const int ii = argmax(col.data(), n);
+        if (col[ii] <= v) break;
+        v = col[ii];
+        i = ii;
+      }
+      if (v > best) best = v;
+    }
+    if (!std::isfinite(best)) throw Error(TT_ENONFINITE, "max_speed: non-finite wave speed");
+    return best;
+  }
+
   // Section 4.4's tolerances from the state at the start of the step (TT_EPS_PAPER)
   void set_tolerances() {
     if (p.eps_rule != TT_EPS_PAPER) {
@@ -931,6 +995,19 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     throw;
   }
   return s;
+}
+
+void solver_max_speed(Solver *s, double out[2]) {
+  out[0] = s->max_speed(0);
+  out[1] = s->max_speed(1);
+}
+
+// dt = cfl / (s_x / dx + s_y / dy), dx = dy = 1/n
+double solver_cfl_dt(Solver *s, double cfl) {
+  double sp[2];
+  solver_max_speed(s, sp);
+  TT_REQUIRE(sp[0] + sp[1] > 0.0, "tt_fv_cfl_dt: zero wave speed");
+  return cfl / ((sp[0] + sp[1]) * s->n);
 }
 
 void solver_set_terms(Solver *s, const tt_fv_term *terms, int count) {

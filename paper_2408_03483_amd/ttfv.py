@@ -102,7 +102,7 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
            "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
-           "tt_fv_set_terms", "tt_compress"]
+           "tt_fv_set_terms", "tt_compress", "tt_fv_max_speed", "tt_fv_cfl_dt"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -131,6 +131,8 @@ def load_library(path: str = LIB_PATH):
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_compress.argtypes = [P, P, I, I, I, D, I, pM, ctypes.POINTER(D)]
+    L.tt_fv_max_speed.argtypes = [P, ctypes.POINTER(D)]
+    L.tt_fv_cfl_dt.argtypes = [P, D, ctypes.POINTER(D)]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
     L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
     L.tt_maxvol.argtypes = [P, P, I, I, I, D, I, ctypes.POINTER(I)]
@@ -436,6 +438,18 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
     if terms:
         tt_fv_set_terms(s, terms)
     return s
+
+
+def tt_fv_max_speed(s: Solver):
+    sp = (ctypes.c_double * 2)()
+    _check(_lib.tt_fv_max_speed(s.h, sp), "tt_fv_max_speed")
+    return float(sp[0]), float(sp[1])
+
+
+def tt_fv_cfl_dt(s: Solver, cfl: float) -> float:
+    dt = ctypes.c_double()
+    _check(_lib.tt_fv_cfl_dt(s.h, cfl, ctypes.byref(dt)), "tt_fv_cfl_dt")
+    return dt.value
 
 
 def tt_fv_set_terms(s: Solver, terms) -> None:

@@ -347,3 +347,32 @@ def test_lf_cross_flux_parity(lib, periodic):
          f"crosses {stats['crosses']}, roundings {stats['roundings']}")
     assert [q.rank for q in Qg] == [q.rank for q in Qo]
     assert max(r) <= 1e-9
+
+
+def test_cfl_from_the_tts(lib):
+    """tt_fv_max_speed / tt_fv_cfl_dt (rook pivoting on the TTs from h's maxvol columns) equal
+    the oracle's estimate and the maxima of the TT state's cell values on the 1024^2 bumps
+    workload, and on its state after 3 steps; the step they give matches the workload's CFL 0.4
+    step (computed from the uncompressed cell averages, 1e-10 away)."""
+    _say("cfl from the tts, 1024 bumps")
+    st = synth.nonlinear_bumps(seed=0, n=1024, rmax=32, eps=1e-10)
+    dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=32) for f in st.tt]
+    s = lib.tt_fv_init(1024, "upwind5", True, True, dev, g=st.g, eps=1e-10, r_max=32)
+    ts = otf.TTSolver(1024, "upwind5", True, True, g=st.g, eps=1e-10, rmax=32)
+    Q0 = [ott.TT(f.A, f.B) for f in st.tt]
+    sx, sy = lib.tt_fv_max_speed(s)
+    h, hu, hv = [q.A @ q.B.T for q in Q0]          # the TT state's own cell values
+    true = (float(np.max(np.abs(hu / h) + np.sqrt(st.g * h))),
+            float(np.max(np.abs(hv / h) + np.sqrt(st.g * h))))
+    orc = (ts.max_speed(Q0, 0), ts.max_speed(Q0, 1))
+    _say(f"  gpu {sx, sy} oracle {orc} full field {true}")
+    assert (sx, sy) == pytest.approx(orc, rel=1e-13)
+    assert (sx, sy) == pytest.approx(true, rel=1e-12)
+    assert lib.tt_fv_cfl_dt(s, 0.4) == pytest.approx(st.dt, rel=1e-9)
+    lib.tt_fv_step(s, st.dt, 3)
+    Qg = lib.tt_fv_get_state(s)
+    F = [q.full() for q in Qg]
+    true3 = float(np.max(np.abs(F[1] / F[0]) + np.sqrt(st.g * F[0])))
+    s3 = lib.tt_fv_max_speed(s)[0]
+    s.close()
+    assert s3 == pytest.approx(true3, rel=1e-12)

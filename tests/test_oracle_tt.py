@@ -308,3 +308,31 @@ def test_from_full_closed_form():
     assert from_full(F, 0.0, 5).rank == 5
     Z = from_full(np.zeros((7, 9)), 1e-8, 4)
     assert Z.rank == 1 and not np.any(Z.A @ Z.B.T)
+
+
+def test_rook_max_speed():
+    """The CFL speed estimate by rook pivoting on the TTs: never above the true maximum of
+    |m/h| + sqrt(g h) over the cells, equal to it on smooth fields, and exact on a rank-1
+    field whose maximum sits where the starting columns do not look."""
+    import synth
+    from oracle.tt import TT
+    from oracle.tt_fv import TTSolver, _Lambda, rook_max
+    for seed in range(4):
+        st = synth.nonlinear_bumps(seed=seed, n=64, rmax=24, eps=1e-12, kmax=4)
+        Q = [TT(x.A, x.B) for x in st.tt]
+        s = TTSolver(64, "upwind5", True, True, g=st.g)
+        h, hu, hv = [q.A @ q.B.T for q in Q]
+        for d, m in ((0, hu), (1, hv)):
+            true = float(np.max(np.abs(m / h) + np.sqrt(st.g * h)))
+            est = s.max_speed(Q, d)
+            assert est <= true * (1 + 1e-14)
+            assert est == pytest.approx(true, rel=1e-12)
+        assert s.cfl_dt(Q, 0.4) == pytest.approx(st.dt, rel=1e-12)
+    # rank-1 h with a single peak away from column 0; m = 0
+    n = 40
+    x = np.exp(-((np.arange(n) - 29.0) / 3.0) ** 2)
+    h = TT((1.0 + x)[:, None], (1.0 + 0.5 * x[::-1])[:, None])
+    z = TT(np.zeros((n, 1)), np.zeros((n, 1)))
+    val, i, j = rook_max(_Lambda(h, z, h, z, 9.81), n, n, np.array([0]))
+    full = np.sqrt(9.81 * (h.A @ h.B.T))
+    assert val == pytest.approx(float(full.max()), rel=1e-15)
