@@ -86,6 +86,9 @@ int  tt_ctx_set_precision(tt_ctx *ctx, int precision);
 #define TT_QR_CHOLESKY    1
 #define TT_QR_HOUSEHOLDER 2
 int  tt_ctx_set_qr(tt_ctx *ctx, int method, int max_passes);
+/* Column enrichment of this context's crosses (tt_cross): TT_ENRICH_KICKS (default) or
+ * TT_ENRICH_RESIDUAL (see tt_fv_params.cross_enrich). */
+int  tt_ctx_set_enrichment(tt_ctx *ctx, int mode);
 
 /* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
  * eps and rank <= r_max.  x may have any rank <= x->cap; y->cap must be >= r_max.
@@ -225,9 +228,15 @@ typedef struct {
   int flux;           /* nonlinear LLF flux: TT_FLUX_PRODUCTS (Section 4.2: 1/h, Hadamard
                          products and roundings, lambda by cross) or TT_FLUX_LF_CROSS (the
                          whole flux vector of a direction by one cross, TT_FN_LLF_FLUX)     */
+  int cross_enrich;   /* columns a cross adds per non-final sweep (cross_kick of them):
+                         TT_ENRICH_KICKS, seeded fresh indices; TT_ENRICH_RESIDUAL, the
+                         4 x cross_kick seeded candidates with the largest residual of the
+                         current skeleton (AMEn-style enrichment, Section 3.3)              */
 } tt_fv_params;
 #define TT_FLUX_PRODUCTS 0
 #define TT_FLUX_LF_CROSS 1
+#define TT_ENRICH_KICKS    0
+#define TT_ENRICH_RESIDUAL 1
 #define TT_BC_PERIODIC 1
 #define TT_BC_WALL     2
 #define TT_BC_EXACT    3

@@ -258,13 +258,35 @@ def skeleton(fun, n1: int, n2: int, J, I, eps: float, rmax: int, Qc=None) -> TT:
     return tt_round(TT(G1, fun.rows(I).T), eps, rmax)
 
 
+def residual_columns(fun, Qc, I, R, J, n2: int, count: int, key: int):
+    """Residual-based column enrichment (in the spirit of AMEn's enrichment, Section 3.3): 4 x
+    count candidate columns outside J drawn by the kick generator, the skeleton interpolant
+    Qc Qc[I]^-1 f(I, j) of each, and the count candidates with the largest residual norms
+    |f(:, j) - interpolant| (ties to the earlier candidate; residuals below 1e-12 of the largest
+    candidate column's norm, round-off, count as ties at zero).  R = f(I, :)."""
+    cand = kick_indices(J, n2, min(4 * count, n2 - len(J)), key)
+    if not cand:
+        return []
+    cand = np.asarray(cand, dtype=np.int64)
+    Fc = fun.cols(cand)
+    X = Qc @ np.linalg.solve(Qc[I], R[:, cand])
+    res = np.linalg.norm(Fc - X, axis=0)
+    # residuals at round-off (below 1e-12 of the largest candidate column) are ties
+    res[res <= 1e-12 * float(np.max(np.linalg.norm(Fc, axis=0)))] = 0.0
+    order = sorted(range(len(cand)), key=lambda t: (-res[t], t))[:count]
+    return [int(cand[t]) for t in order]
+
+
 def cross(fun, n1: int, n2: int, J0, eps: float, rmax: int, sweeps: int = 3,
-          kick: int = 4, key: int = 0, rows_out: list = None, drop: float = 1e-13):
+          kick: int = 4, key: int = 0, rows_out: list = None, drop: float = 1e-13,
+          enrich: str = "random"):
     """Alternating maxvol skeleton cross of the n1 x n2 matrix defined by `fun`.
 
     fun.cols(J) -> n1 x |J| array of entries, fun.rows(I) -> |I| x n2 array.
     Each sweep: C = f(:, J); Qc = orth(C); I = maxvol(Qc); R = f(I, :); and, except in the
-    last sweep, J = maxvol(orth(R^T)) enlarged by `kick` fresh indices while |J| < rmax.
+    last sweep, J = maxvol(orth(R^T)) enlarged by `kick` fresh indices while |J| < rmax: seeded
+    ones (enrich="random"), or the candidates with the largest residual (enrich="residual",
+    residual_columns).
     Result: the skeleton of the last sweep's (J, I).  Returns (TT, J of the last sweep); the
     last sweep's I is appended to `rows_out` when given.  `drop`: relative singular value
     below which orth discards a direction.
@@ -281,14 +303,19 @@ def cross(fun, n1: int, n2: int, J0, eps: float, rmax: int, sweeps: int = 3,
         I = maxvol(Qc)
         if s == sweeps - 1:
             break
-        Qr = orth(fun.rows(I).T, drop)
+        R = fun.rows(I)
+        Qr = orth(R.T, drop)
         if Qr.shape[1] == 0:
             if rows_out is not None:
                 rows_out.append(np.zeros(0, dtype=np.int64))
             return zero_tt(n1, n2), J
         J = maxvol(Qr)
         if len(J) < rmax and kick > 0:
-            extra = kick_indices(J, n2, min(kick, rmax - len(J)), key + 1000003 * (s + 1))
+            cnt, k2 = min(kick, rmax - len(J)), key + 1000003 * (s + 1)
+            if enrich == "residual":
+                extra = residual_columns(fun, Qc, I, R, J, n2, cnt, k2)
+            else:
+                extra = kick_indices(J, n2, cnt, k2)
             J = np.concatenate([J, np.array(extra, dtype=np.int64)])
     if rows_out is not None:
         rows_out.append(I.copy())

@@ -273,7 +273,7 @@ class TTSolver:
                  cross_kick: int = 4, cross_full: bool = False, recip: str = "taylor",
                  replay=None, cross_drop: float = 1e-13, eps_rule: str = "fixed",
                  c_eps: float = 1.0, bc=None, terms=(), t0: float = 0.0,
-                 flux: str = "products"):
+                 flux: str = "products", cross_enrich: str = "random"):
         self.n, self.scheme, self.nonlinear = n, scheme, nonlinear
         self.bc = tuple(bc) if bc is not None else \
             (("periodic", "periodic") if periodic else ("wall", "wall"))
@@ -294,6 +294,7 @@ class TTSolver:
         if flux not in ("products", "lf_cross"):
             raise ValueError("flux must be 'products' or 'lf_cross'")
         self.flux = flux                   # nonlinear LLF: products of Section 4.2 or LF-cross
+        self.enrich = cross_enrich         # cross enrichment: seeded kicks or largest residual
         self.cross_drop = cross_drop     # orth drop threshold of the crosses (reading R12)
         self.dx = 1.0 / n
         self.tab = stencils.tables(scheme)
@@ -357,7 +358,7 @@ class TTSolver:
         key = (site << 32) | (self.step_index & 0xFFFFFFFF)
         rows = []
         X, J = cross(fun, n1, n2, J0, self.eps, self.rmax, self.sweeps, self.kick, key,
-                     rows_out=rows, drop=self.cross_drop)
+                     rows_out=rows, drop=self.cross_drop, enrich=self.enrich)
         self.pivots[site] = J
         self.cross_log[(self.step_index, site)] = (J.copy(), rows[0])
         return X

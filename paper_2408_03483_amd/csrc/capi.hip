@@ -405,6 +405,16 @@ int tt_ctx_set_qr(tt_ctx *ctx, int method, int max_passes) {
   });
 }
 
+int tt_ctx_set_enrichment(tt_ctx *ctx, int mode) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    TT_REQUIRE(mode == TT_ENRICH_KICKS || mode == TT_ENRICH_RESIDUAL,
+               "tt_ctx_set_enrichment: unknown mode");
+    ctx->c.enrich = mode;
+    return 0;
+  });
+}
+
 int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
              double *sigma_out) {
   return guarded([&]() {

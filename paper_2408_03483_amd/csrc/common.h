@@ -114,6 +114,7 @@ struct Ctx {
   bool fp32 = false;        // core contractions (GEMM, face-splitting products, TSQR) in FP32
   int qr = TT_QR_AUTO;      // QR method of tsqr() (TT_QR_*)
   double cross_drop = 0.0;  // relative singular value below which a cross drops a fiber
+  int enrich = 0;           // cross enrichment: 0 seeded kicks, 1 largest residual
                             // direction (0: 1e-13, or 1e-6 with FP32 contractions)
   double drop() const { return cross_drop > 0.0 ? cross_drop : (fp32 ? 1e-6 : 1e-13); }
   int cqr_passes = 6;       // pass limit of the Cholesky QR

@@ -138,11 +138,13 @@ struct Solver {
     const bool f32 = p.precision == TT_PREC_F32;
     const int qr = p.qr;
     const double drop = p.cross_drop;
+    const int enrich = p.cross_enrich;
     for (auto &t : tasks)
-      t = [f32, qr, drop, f = std::move(t)](Ctx &w) {
+      t = [f32, qr, drop, enrich, f = std::move(t)](Ctx &w) {
         w.fp32 = f32;
         w.qr = qr;
         w.cross_drop = drop;
+        w.enrich = enrich;
         f(w);
       };
     exec->run(std::move(tasks));
@@ -898,6 +900,8 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
              "tt_fv_init: unknown boundary kind");
   TT_REQUIRE(p->flux == TT_FLUX_PRODUCTS || p->flux == TT_FLUX_LF_CROSS,
              "tt_fv_init: unknown flux method");
+  TT_REQUIRE(p->cross_enrich == TT_ENRICH_KICKS || p->cross_enrich == TT_ENRICH_RESIDUAL,
+             "tt_fv_init: unknown cross enrichment");
   TT_REQUIRE(p->flux != TT_FLUX_LF_CROSS || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(!(p->bc_x == TT_BC_EXACT && p->bc_y == TT_BC_EXACT),
@@ -930,6 +934,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->c.fp32 = p->precision == TT_PREC_F32;
     s->c.qr = p->qr;
     s->c.cross_drop = p->cross_drop;
+    s->c.enrich = p->cross_enrich;
     const size_t ab = arena_bytes ? arena_bytes : ((size_t)4 << 30);
     s->c.arena.init(ab);
     int dev = 0;

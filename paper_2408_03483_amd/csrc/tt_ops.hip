@@ -835,6 +835,48 @@ int skeleton_round(Ctx &c, const double *Qc, int n1, int n2, int rc, const int *
 
 }  // namespace
 
+// Residual-based column enrichment (in the spirit of AMEn's, Section 3.3): 4 x count candidate
+// columns outside J drawn by the kick generator, the current skeleton's interpolant
+// Qc Qc[I]^-1 f(I, j) of each (RwT = f(I, :)^T), and the count candidates with the largest
+// residual norms |f(:, j) - interpolant| (ties to the earlier candidate; residuals below 1e-12
+// of the largest candidate column's norm, round-off, count as ties at zero).
+std::vector<int> residual_columns(Ctx &c, const FiberSpec &fs, int n1, int n2, const double *Qc,
+                                  int rc, const int *Id, const double *RwT,
+                                  const std::vector<int> &J, int count, uint64_t key) {
+  const std::vector<int> cand =
+      kick_indices(J, n2, std::min(4 * count, n2 - (int)J.size()), key);
+  const int nc = (int)cand.size();
+  if (nc == 0) return {};
+  Scope sc(c.arena);
+  int *Cd = c.arena.ialloc(nc);
+  HIP_CHECK(hipMemcpyAsync(Cd, cand.data(), nc * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  double *Fs = c.arena.dalloc((size_t)n1 * nc);
+  fiber_cols(c, fs, n1, Cd, nc, Fs);
+  double *cn = c.arena.dalloc(nc);
+  colsumsq(c, Fs, n1, nc, n1, cn);                                  // candidate column norms^2
+  const std::vector<double> c2 = to_host(c, cn, nc);
+  double *QI = c.arena.dalloc((size_t)rc * rc), *QIinv = c.arena.dalloc((size_t)rc * rc);
+  gather_rows(c, QI, rc, Qc, n1, Id, rc, rc);                        // Qc[I]
+  small_inverse(c, QI, rc, rc, QIinv);
+  double *Rs = c.arena.dalloc((size_t)nc * rc), *T = c.arena.dalloc((size_t)rc * nc);
+  gather_rows(c, Rs, nc, RwT, n2, Cd, nc, rc);                      // f(I, cand)^T
+  gemm2(c, false, true, rc, nc, rc, 1.0, QIinv, rc, Rs, nc, 0.0, T, rc);
+  gemm(c, false, n1, nc, rc, -1.0, Qc, n1, T, rc, 1.0, Fs, n1);       // residual columns
+  double *rs = c.arena.dalloc(nc);
+  colsumsq(c, Fs, n1, nc, n1, rs);
+  std::vector<double> r2 = to_host(c, rs, nc);
+  // residuals at round-off (below 1e-12 of the largest candidate column) are ties at zero
+  const double big = *std::max_element(c2.begin(), c2.end());
+  for (double &v : r2)
+    if (v <= 1e-24 * big) v = 0.0;
+  std::vector<int> order(nc);
+  for (int t = 0; t < nc; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return r2[a] > r2[b]; });
+  std::vector<int> out;
+  for (int t = 0; t < std::min(count, nc); ++t) out.push_back(cand[order[t]]);
+  return out;
+}
+
 int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, double eps,
              int rmax, int sweeps, int kick, uint64_t key, DTT &y, std::vector<int> *J_out,
              std::vector<int> *I_out) {
@@ -879,8 +921,11 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
     if (rr == 0) return zero_result();
     J = maxvol_host(c, Qr, n2, rr, n2, 1.05, 100);
     if ((int)J.size() < rmax && kick > 0) {
-      std::vector<int> extra = kick_indices(J, n2, std::min(kick, rmax - (int)J.size()),
-                                            key + 1000003ull * (uint64_t)(s + 1));
+      const int cnt = std::min(kick, rmax - (int)J.size());
+      const uint64_t k2 = key + 1000003ull * (uint64_t)(s + 1);
+      const std::vector<int> extra =
+          c.enrich == 1 ? residual_columns(c, fs, n1, n2, Qc, rc, Id, RwT, J, cnt, k2)
+                        : kick_indices(J, n2, cnt, k2);
       J.insert(J.end(), extra.begin(), extra.end());
     }
   }

@@ -45,7 +45,7 @@ class ParamsC(ctypes.Structure):
                 ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double),
                 ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("t0", ctypes.c_double),
-                ("flux", ctypes.c_int)]
+                ("flux", ctypes.c_int), ("cross_enrich", ctypes.c_int)]
 
 
 class TermC(ctypes.Structure):
@@ -73,6 +73,7 @@ PRECISIONS = {"f64": 0, "f32": 1}
 QR_METHODS = {"auto": 0, "cholesky": 1, "householder": 2}
 EPS_RULES = {"fixed": 0, "paper": 1}
 FLUXES = {"products": 0, "lf_cross": 1}
+ENRICH = {"kicks": 0, "residual": 1}
 BCS = {None: 0, "periodic": 1, "wall": 2, "exact": 3}
 TERM_WHERE = {"forcing": 0, "x_lo": 1, "x_hi": 2, "y_lo": 3, "y_hi": 4}
 
@@ -102,7 +103,8 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_fv_replay_pivots", "tt_fv_get_pivots", "tt_cross_skeleton", "tt_pm_adam",
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
            "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
-           "tt_fv_set_terms", "tt_compress", "tt_fv_max_speed", "tt_fv_cfl_dt"]
+           "tt_fv_set_terms", "tt_compress", "tt_fv_max_speed", "tt_fv_cfl_dt",
+           "tt_ctx_set_enrichment"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -128,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_set_precision.argtypes = [P, I]
     L.tt_ctx_set_limits.argtypes = [P, I, I]
     L.tt_ctx_set_qr.argtypes = [P, I, I]
+    L.tt_ctx_set_enrichment.argtypes = [P, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_compress.argtypes = [P, P, I, I, I, D, I, pM, ctypes.POINTER(D)]
@@ -268,6 +271,10 @@ def tt_ctx_set_sketch(ctx: Ctx, width: int, power_iters: int) -> None:
 
 def tt_ctx_set_qr(ctx: Ctx, method: str, max_passes: int = 6) -> None:
     _check(_lib.tt_ctx_set_qr(ctx.h, QR_METHODS[method], max_passes), "tt_ctx_set_qr")
+
+
+def tt_ctx_set_enrichment(ctx: Ctx, mode: str) -> None:
+    _check(_lib.tt_ctx_set_enrichment(ctx.h, ENRICH[mode]), "tt_ctx_set_enrichment")
 
 
 def tt_ctx_set_limits(ctx: Ctx, jacobi_max_sweeps: int, sketch_max_iters: int) -> None:
@@ -420,7 +427,7 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                arena_bytes: int = 4 << 30, precision: str = "f64",
                qr: str = "auto", cross_drop: float = 0.0, eps_rule: str = "fixed",
                c_eps: float = 1.0, bc=None, t0: float = 0.0, terms=(),
-               flux: str = "products") -> Solver:
+               flux: str = "products", cross_enrich: str = "kicks") -> Solver:
     """bc: per-axis boundary kinds ("periodic", "wall", "exact") overriding `periodic`;
     terms: separable forcing / ghost terms (see tt_fv_set_terms)."""
     L = load_library()
@@ -429,7 +436,8 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
     p = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0, g, H0, f, eps,
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
                 workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop,
-                EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0, FLUXES[flux])
+                EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0, FLUXES[flux],
+                ENRICH[cross_enrich])
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -508,7 +516,7 @@ class Grid:
         bx, by = (None, None) if bc is None else bc
         self.params = ParamsC(n, 1 if nonlinear else 0, SCHEMES[scheme], 1 if periodic else 0,
                               g, H0, f, 0.0, 1, 1, 1, 0, 0, 0, 0, 0, 0.0, 0, 1.0,
-                              BCS[bx], BCS[by], t0, 0)
+                              BCS[bx], BCS[by], t0, 0, 0)
         self.h = ctypes.c_void_p()
         self._stream = stream
         _check(L.tt_grid_init(ctypes.byref(self.h), ctypes.byref(self.params),
