@@ -97,6 +97,26 @@ int  tt_ctx_set_enrichment(tt_ctx *ctx, int mode);
 int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
              double *sigma_out);
 
+/* A d-core tensor train (Section 3.1, equation TT_def): core k (0-based) is an
+ * r[k] x n[k] x r[k+1] array on the device with the left rank index fastest, element
+ * G_k(a, i, b) at a + r[k] (i + n[k] b), so both of its unfoldings are column-major;
+ * r[0] = r[d] = 1. */
+typedef struct {
+  int d;
+  const int *n;          /* host, d mode sizes                                          */
+  int *r;                /* host, d + 1 ranks                                           */
+  double *const *cores;  /* host array of d device pointers                             */
+} tt_tensor;
+/* Rounding of a d-core TT (Section 3.2 extended to d cores: right-to-left orthogonalisation,
+ * then left-to-right truncated SVDs at eps / sqrt(d - 1) of the norm each, ranks <= r_max):
+ * ||x - y|| <= eps ||x|| when no cap binds.  x's ranks <= 96.  y: same d and modes; each
+ * y->cores[k] holds r_max * n[k] * r_max doubles; y->r receives the ranks.  The kept singular
+ * values of the d - 1 bonds are written one after another to sigma_out (host, length >=
+ * (d - 1) r_max) when not NULL.  Returns TT_WRANKCAP when a cap truncated more than its share
+ * of eps. */
+int tt_round_nd(tt_ctx *ctx, const tt_tensor *x, double eps, int r_max, tt_tensor *y,
+                double *sigma_out);
+
 /* Compression of a full field into a TT (the TT-native replacement of an initial-condition
  * SVD on the host; Section 3.2's truncated SVD applied to a dense matrix): y = a rank-k
  * approximation of F with ||F - y||_F <= eps ||F||_F and k <= r_max as small as the SVD allows,

@@ -434,6 +434,25 @@ int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *
   });
 }
 
+int tt_round_nd(tt_ctx *ctx, const tt_tensor *x, double eps, int r_max, tt_tensor *y,
+                double *sigma_out) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx && x && y, "tt_round_nd: null argument");
+    TT_REQUIRE(x->d >= 2 && x->d == y->d && x->n && x->r && x->cores && y->n && y->r && y->cores,
+               "tt_round_nd: bad tensors");
+    TT_REQUIRE(eps >= 0.0 && r_max >= 1, "tt_round_nd: eps < 0 or r_max < 1");
+    for (int k = 0; k < x->d; ++k) {
+      TT_REQUIRE(x->n[k] == y->n[k], "tt_round_nd: modes differ");
+      TT_REQUIRE(x->cores[k] && y->cores[k], "tt_round_nd: null core");
+    }
+    std::vector<double> s;
+    const int w = round_nd(ctx->c, x->d, x->n, x->r, x->cores, eps, r_max, y->cores, y->r, &s);
+    if (sigma_out)
+      for (size_t i = 0; i < s.size(); ++i) sigma_out[i] = s[i];
+    return w | jacobi_warning(ctx->c);
+  });
+}
+
 int tt_compress(tt_ctx *ctx, const double *F, int n1, int n2, int ld, double eps, int r_max,
                 tt_matrix *y, double *sigma_out) {
   return guarded([&]() {

@@ -275,6 +275,9 @@ void fiber_rows(Ctx &c, const FiberSpec &fs, int n2, const int *I_dev, int ni, d
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig);
 // Frobenius norm of x (sqrt of sum((A^T A) o (B^T B)), the Gram matrices on the matrix cores)
 double norm_tt(Ctx &c, const DTT &x);
+// tt_nd.hip: rounding of a d-core TT (cores left-rank-fastest; see tt_round_nd)
+int round_nd(Ctx &c, int d, const int *n, const int *r, const double *const *in, double eps,
+             int rmax, double *const *out, int *r_out, std::vector<double> *sig);
 // 2-core TT of a dense n1 x n2 matrix F (device, column-major, leading dimension ld) at
 // relative Frobenius accuracy eps, rank <= rmax (randomized range finder; y->cap >= rmax)
 int compress_dense(Ctx &c, const double *F, int n1, int n2, int ld, double eps, int rmax, DTT &y,

@@ -48,6 +48,12 @@ class ParamsC(ctypes.Structure):
                 ("flux", ctypes.c_int), ("cross_enrich", ctypes.c_int)]
 
 
+class TensorC(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.POINTER(ctypes.c_int)),
+                ("r", ctypes.POINTER(ctypes.c_int)),
+                ("cores", ctypes.POINTER(ctypes.c_void_p))]
+
+
 class TermC(ctypes.Structure):
     _fields_ = [("var", ctypes.c_int), ("where", ctypes.c_int), ("amp", ctypes.c_double),
                 ("omega", ctypes.c_double), ("phase", ctypes.c_double),
@@ -104,7 +110,7 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
            "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
            "tt_fv_set_terms", "tt_compress", "tt_fv_max_speed", "tt_fv_cfl_dt",
-           "tt_ctx_set_enrichment"]
+           "tt_ctx_set_enrichment", "tt_round_nd"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -135,6 +141,8 @@ def load_library(path: str = LIB_PATH):
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_compress.argtypes = [P, P, I, I, I, D, I, pM, ctypes.POINTER(D)]
     L.tt_fv_max_speed.argtypes = [P, ctypes.POINTER(D)]
+    L.tt_round_nd.argtypes = [P, ctypes.POINTER(TensorC), D, I, ctypes.POINTER(TensorC),
+                              ctypes.POINTER(D)]
     L.tt_fv_cfl_dt.argtypes = [P, D, ctypes.POINTER(D)]
     L.tt_hadamard_round.argtypes = [P, pM, pM, D, I, pM]
     L.tt_reciprocal.argtypes = [P, pM, D, I, I, pM, ctypes.POINTER(D), ctypes.POINTER(I)]
@@ -293,6 +301,57 @@ def tt_round(ctx: Ctx, x: DeviceTT, eps: float, r_max: int, y: DeviceTT):
                "tt_round")
     y.rank = yc.rank
     return w, np.array(sig[:y.rank])
+
+
+class DeviceTTnd:
+    """d cores on the device, core k a float64 tensor with room for cap_k = (r_in or r_max)^2
+    n_k entries; the data of core k is its first r[k] n[k] r[k+1] entries, left rank index
+    fastest (G(a, i, b) at a + r[k] (i + n[k] b))."""
+
+    def __init__(self, modes, ranks, room, device="cuda"):
+        torch = _torch()
+        self.n, self.r = list(modes), list(ranks)
+        self.cores = [torch.zeros(max(int(rm), 1), dtype=torch.float64, device=device)
+                      for rm in room]
+
+    @classmethod
+    def from_cores(cls, cores, device="cuda"):
+        torch = _torch()
+        modes = [c.shape[1] for c in cores]
+        ranks = [cores[0].shape[0]] + [c.shape[2] for c in cores]
+        t = cls(modes, ranks, [c.size for c in cores], device)
+        for k, c in enumerate(cores):
+            t.cores[k][:c.size] = torch.from_numpy(
+                np.ascontiguousarray(np.transpose(c, (2, 1, 0))).reshape(-1)).to(device)
+        return t
+
+    def to_cores(self):
+        out = []
+        for k, n in enumerate(self.n):
+            r0, r1 = self.r[k], self.r[k + 1]
+            flat = self.cores[k][:r0 * n * r1].cpu().numpy()
+            out.append(np.transpose(flat.reshape(r1, n, r0), (2, 1, 0)).copy())
+        return out
+
+    def c(self):
+        d = len(self.n)
+        self._n = (ctypes.c_int * d)(*self.n)
+        self._r = (ctypes.c_int * (d + 1))(*self.r)
+        self._p = (ctypes.c_void_p * d)(*[t.data_ptr() for t in self.cores])
+        return TensorC(d, self._n, self._r, self._p)
+
+
+def tt_round_nd(ctx: Ctx, x: DeviceTTnd, eps: float, r_max: int):
+    """Rounding of a d-core TT; returns (output DeviceTTnd, warnings, bond singular values)."""
+    d = len(x.n)
+    y = DeviceTTnd(x.n, [1] * (d + 1), [r_max * n * r_max for n in x.n])
+    xc, yc = x.c(), y.c()
+    sig = (ctypes.c_double * ((d - 1) * r_max))()
+    w = _check(_lib.tt_round_nd(ctx.h, ctypes.byref(xc), eps, r_max, ctypes.byref(yc), sig),
+               "tt_round_nd")
+    y.r = [int(yc.r[k]) for k in range(d + 1)]
+    kept = sum(y.r[1:d])
+    return y, w, np.array(sig[:kept])
 
 
 def tt_compress(ctx: Ctx, F, eps: float, r_max: int):
