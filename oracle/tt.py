@@ -346,3 +346,93 @@ def from_full(F: np.ndarray, eps: float, rmax: int) -> TT:
             break
     k = max(1, min(k, rmax))
     return TT(U[:, :k].copy(), (Vt[:k].T * s[:k]).copy())
+
+
+# ---------------------------------------------------------------------------
+# The library's randomized rounding, written independently for comparison at round-off.
+# It is not in the paper: the library rounds Hadamard products whose rank exceeds its sketch
+# width by a randomized range finder (Halko, Martinsson and Tropp 2011) with a seeded Gaussian
+# test matrix, so the oracle draws the same matrix from the same published generators
+# (SplitMix64's output function of Steele, Lea and Flood 2014 on hashed counters, then
+# Box-Muller) and takes the same steps with numpy's QR and SVD.
+
+SKETCH_SEED = 0x5EED5EED12345
+
+
+def gauss_sketch(rows: int, cols: int, seed: int) -> np.ndarray:
+    """rows x cols Gaussian matrix: entry (i, c) from counter idx = c rows + i;
+    h1 = mix64(seed xor (2 idx + 1) golden), h2 = mix64(h1 + 0x632BE59BD9B4E019) (mix64 is
+    SplitMix64's output function; 64-bit wrap-around arithmetic); u1 = (h1 >> 11 + 1) / (2^53 + 1)
+    in (0, 1], u2 = (h2 >> 11) / 2^53; value sqrt(-2 log u1) cos(2 pi u2) (Box-Muller)."""
+    u64 = np.uint64
+    idx = (np.arange(cols, dtype=np.uint64)[None, :] * u64(rows) +
+           np.arange(rows, dtype=np.uint64)[:, None])
+
+    def mix(z):
+        z = (z ^ (z >> u64(30))) * u64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> u64(27))) * u64(0x94D049BB133111EB)
+        return z ^ (z >> u64(31))
+
+    with np.errstate(over="ignore"):
+        h1 = mix(u64(seed) ^ ((idx * u64(2) + u64(1)) * u64(0x9E3779B97F4A7C15)))
+        h2 = mix(h1 + u64(0x632BE59BD9B4E019))
+    u1 = ((h1 >> u64(11)).astype(np.float64) + 1.0) * (1.0 / 9007199254740993.0)
+    u2 = (h2 >> u64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def tt_round_sketched(X: TT, eps: float, rmax: int, width: int = 0, power_iters: int = 1,
+                      max_iters: int = 8) -> TT:
+    """The library's rounding of a TT whose rank exceeds the sketch width m = width or
+    min(96, max(2 rmax, 16)): Y = X Omega (Omega = gauss_sketch of the shape's seed), power_iters
+    subspace iterations, then repeatedly Qa = orth(Y), W = X^T Qa = Qw Rb, the SVD of Rb^T and
+    the kept rank k (the tolerance rule of tt_round on those singular values s); stop when k
+    reaches m, when s beyond m - max(8, m/4) is below 1e-14 s_0, or when the discarded
+    directions can leak at most (s_m / s_k)^(2q+1) s_k <= 1e-13 s_0 into the kept ones after q
+    iterations, else iterate once more (Y = X orth(W)); after max(power_iters, max_iters)
+    iterations without convergence it returns the exact rounding if the rank is at most 96,
+    else the sketch's answer as it stands.  Result Qa U_k (W U_k)^T.
+    Inputs whose rank fits the width take the exact rounding."""
+    n1, n2, R = X.A.shape[0], X.B.shape[0], X.rank
+    m = width if width > 0 else min(96, max(2 * rmax, 16))
+    mn = min(n1, n2)
+    if R <= m and R <= mn or mn <= m:
+        return tt_round(X, eps, rmax)
+    m = min(m, mn)
+    seed = (SKETCH_SEED ^ ((n1 * 0x9E3779B97F4A7C15) & MASK64) ^ ((n2 << 20) & MASK64) ^
+            ((R << 40) & MASK64) ^ m) & MASK64
+    Om = gauss_sketch(n2, m, seed)
+    A, B = X.A, X.B
+    Y = A @ (B.T @ Om)
+    q = 0
+    for q in range(power_iters):
+        Qa, _ = np.linalg.qr(Y)
+        Qz, _ = np.linalg.qr(B @ (A.T @ Qa))
+        Y = A @ (B.T @ Qz)
+    q = power_iters
+    qlim = max(power_iters, max_iters)
+    while True:
+        Qa, _ = np.linalg.qr(Y)
+        W = B @ (A.T @ Qa)                          # X^T Qa
+        _, Rb = np.linalg.qr(W)
+        U, s, _ = np.linalg.svd(Rb.T)
+        if s[0] == 0.0:
+            return TT(np.zeros((n1, 1)), np.zeros((n2, 1)))
+        k = trunc_rank(s, eps, rmax)
+        if k >= m:
+            break
+        pover = max(8, m // 4)
+        if m - pover > k and s[m - pover] <= 1e-14 * s[0]:
+            break
+        if (s[m - 1] / s[k - 1]) ** (2 * q + 1) * s[k - 1] <= 1e-13 * s[0]:
+            break
+        if q >= qlim:
+            # unconverged: the exact rounding when the rank fits a factorisation (96 columns),
+            # else the sketch's answer as it stands
+            if R <= 96 and R <= mn:
+                return tt_round(X, eps, rmax)
+            break
+        Qz, _ = np.linalg.qr(W)
+        Y = A @ (B.T @ Qz)
+        q += 1
+    return TT(Qa @ U[:, :k], W @ U[:, :k])

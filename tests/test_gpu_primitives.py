@@ -559,3 +559,33 @@ def test_cross_residual_enrichment(lib):
         c.close()
     _say(f"  feature recovered: {wins}")
     assert wins["residual"] >= wins["kicks"]
+
+
+@pytest.mark.parametrize("n1,n2,r,eps,rmax,decay", [
+    (1000, 3000, 300, 1e-6, 32, 0.8),
+    (777, 1531, 1024, 1e-5, 16, 0.8),
+    (2049, 6144, 400, 1e-8, 40, 0.8),
+    (1000, 3000, 300, 1e-6, 16, 0.97),   # slow spectrum: stops unconverged, keeps the sketch
+])
+def test_round_sketched_equals_the_oracle_sketch(lib, ctx, n1, n2, r, eps, rmax, decay):
+    """The randomized path of tt_round against the oracle's independent implementation of the
+    same seeded sketch (same generator, same steps; oracle.tt.tt_round_sketched): agreement to
+    round-off (1e-12 of the norm).  On the slow spectrum the iterations stop before the leak
+    bound, both keep the sketch's answer, and it differs from the exact rounding by far more
+    than from the oracle's sketch."""
+    _say(f"round sketched {n1}x{n2} r={r} eps={eps} rmax={rmax}")
+    rng = np.random.default_rng(r)
+    A, B = decaying_tt(rng, n1, n2, r, decay=decay)
+    x = lib.DeviceTT.from_factors(A, B)
+    y = lib.DeviceTT(n1, n2, rmax)
+    w, _ = lib.tt_round(ctx, x, eps, rmax, y)
+    ref = ott.tt_round_sketched(ott.TT(A, B), eps, rmax)
+    ex = ott.tt_round(ott.TT(A, B), eps, rmax)
+    F = y.full()
+    d_sk = np.linalg.norm(F - ref.A @ ref.B.T) / np.linalg.norm(ref.A @ ref.B.T)
+    d_ex = np.linalg.norm(F - ex.A @ ex.B.T) / np.linalg.norm(ex.A @ ex.B.T)
+    _say(f"  rank gpu {y.rank} sketch oracle {ref.rank}; vs sketch {d_sk:.2e}, vs exact {d_ex:.2e}")
+    assert y.rank == ref.rank
+    assert d_sk < 1e-12
+    if decay > 0.9:
+        assert w & 4 and d_ex > 1e3 * max(d_sk, 1e-16)   # TT_WSKETCH; far from the exact one

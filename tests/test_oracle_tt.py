@@ -379,3 +379,33 @@ def test_residual_enrichment_finds_a_localised_feature():
     cand = kick_indices(list(J0), n2, 12, 77)
     res = np.linalg.norm(F[:, cand] - Qc @ np.linalg.solve(Qc[I], R[:, cand]), axis=0)
     assert got == [cand[t] for t in np.argsort(-res, kind="stable")[:3]]
+
+
+def test_gauss_sketch_generator_and_sketched_rounding():
+    """The seeded sketch: entries come from SplitMix64's output function (pinned by its
+    published first output through tt.splitmix64) and Box-Muller, so their moments are those of
+    a standard normal; and the sketched rounding of a rank-300 TT whose spectrum decays agrees
+    with the exact rounding to the leak bound."""
+    from oracle.tt import TT, gauss_sketch, splitmix64, tt_round, tt_round_sketched
+    # entry (0, 0) with seed s: h1 = mix64(s ^ golden); SplitMix64 from state 0 outputs
+    # mix64(golden) first, so with s = 0 the h1 of entry 0 is that published output
+    golden, mask = 0x9E3779B97F4A7C15, (1 << 64) - 1
+    s0, first = splitmix64(0)                         # published: 0xE220A8397B1DCDAF
+    _, h2 = splitmix64((first + 0x632BE59BD9B4E019 - golden) & mask)
+    u1 = ((first >> 11) + 1.0) / 9007199254740993.0
+    u2 = (h2 >> 11) / 9007199254740992.0
+    G = gauss_sketch(4, 3, 0)
+    assert np.isfinite(G).all()
+    assert G[0, 0] == pytest.approx(math.sqrt(-2.0 * math.log(u1)) * math.cos(2 * math.pi * u2),
+                                    rel=1e-15)
+    big = gauss_sketch(20000, 5, 1234)
+    assert abs(big.mean()) < 0.02 and abs(big.std() - 1.0) < 0.02
+    assert abs(np.mean(big ** 4) - 3.0) < 0.1
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((400, 300)) * (0.9 ** np.arange(300))[None, :]
+    B = rng.standard_normal((500, 300))
+    X = TT(A, B)
+    Ys, Ye = tt_round_sketched(X, 1e-6, 32), tt_round(X, 1e-6, 32)
+    F = A @ B.T
+    assert Ys.rank == Ye.rank
+    assert np.linalg.norm(Ys.A @ Ys.B.T - Ye.A @ Ye.B.T) <= 1e-10 * np.linalg.norm(F)
