@@ -89,6 +89,15 @@ int  tt_ctx_set_qr(tt_ctx *ctx, int method, int max_passes);
 /* Column enrichment of this context's crosses (tt_cross): TT_ENRICH_KICKS (default) or
  * TT_ENRICH_RESIDUAL (see tt_fv_params.cross_enrich). */
 int  tt_ctx_set_enrichment(tt_ctx *ctx, int mode);
+/* Fixed shapes for this context's tt_round and tt_cross (on = 1; 0 restores the default):
+ * the decisions those calls take on the host are taken on the device (see
+ * tt_fv_params.graph).  tt_round: Householder QR, the range finder runs exactly
+ * max(1, power iterations) subspace iterations, the output buffers hold the static rank
+ * min(r_max, m) of which the columns after the device's rank are zero, and y->rank is the
+ * device's rank; sigma_out is not written.  tt_cross: nJ0 <= r_max, the column set lives on
+ * the device (r_max entries), the kicks use the key's high word as site and its low word as
+ * step.  Each call still reads its rank back; the point of the mode is the solver's graph. */
+int  tt_ctx_set_fixed(tt_ctx *ctx, int on);
 
 /* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
  * eps and rank <= r_max.  x may have any rank <= x->cap; y->cap must be >= r_max.
@@ -252,6 +261,23 @@ typedef struct {
                          TT_ENRICH_KICKS, seeded fresh indices; TT_ENRICH_RESIDUAL, the
                          4 x cross_kick seeded candidates with the largest residual of the
                          current skeleton (AMEn-style enrichment, Section 3.3)              */
+  int graph;          /* 1: fixed shapes captured in a HIP graph.  Every decision the step
+                         otherwise takes on the host is taken on the device: a rounding's
+                         kept rank (the same rule; the TT keeps the static rank min(r_max, m)
+                         of its buffer with zero columns after the device's rank), a cross's
+                         kept directions, maxvol rows and seeded kicks (column sets stay on
+                         the device per site), the Taylor reciprocal's stop (all
+                         taylor_terms terms are formed; those after the first with
+                         Err <= eps enter times zero), the range finder's iteration count
+                         (exactly max(1, power iterations); TT_WSKETCH when its stopping test
+                         fails).  The first tt_fv_step step runs eagerly and sets the static
+                         ranks and the cross sites' starting columns; the next step is
+                         captured on the solver's stream (again after a change of dt) and
+                         every later step replays the graph, with no host round trip.  Needs
+                         Upwind3/5, TT_EPS_FIXED, TT_FLUX_PRODUCTS, seeded kicks, no exact
+                         boundaries or terms, n > 2 r_max; `workers` is ignored (one stream).
+                         Results equal the dynamic path's up to round-off where the range
+                         finder's extra iterations are not needed.  0: off.                */
 } tt_fv_params;
 #define TT_FLUX_PRODUCTS 0
 #define TT_FLUX_LF_CROSS 1
@@ -310,6 +336,7 @@ typedef struct {
   double eps_inner;           /* tolerance of the last step's roundings inside L(Q)        */
   double eps_var[3];          /* tolerances of its time-stepping roundings, per variable   */
   double time;                /* time reached (t0 + dt of every step taken)                */
+  long long graph_launches;   /* steps replayed from the captured graph (graph mode)       */
 } tt_fv_stats;
 
 /* Copy the three initial TTs (caller's device buffers) into solver-owned state and build

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libttfv.so")
 SOURCES = ["kernels.hip", "gemm.hip", "tsqr.hip", "cholqr.hip", "jacobi.hip", "cross.hip", "tt_ops.hip",
-           "fv.hip", "grid.hip", "tt_nd.hip", "mlp.hip", "capi.hip", "stencils.cpp"]
+           "fixed.hip", "fv.hip", "grid.hip", "tt_nd.hip", "mlp.hip", "capi.hip", "stencils.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -79,6 +79,7 @@ void *Arena::alloc(size_t bytes) {
 }
 
 void Ctx::sync() {
+  if (capturing) return;   // nothing runs before the graph is launched
   if (no_alloc) {          // creates no event
     HIP_CHECK(hipStreamSynchronize(stream));
     return;
@@ -415,6 +416,16 @@ int tt_ctx_set_enrichment(tt_ctx *ctx, int mode) {
   });
 }
 
+int tt_ctx_set_fixed(tt_ctx *ctx, int on) {
+  return guarded([&]() {
+    TT_REQUIRE(ctx, "null ctx");
+    TT_REQUIRE(on == 0 || on == 1, "tt_ctx_set_fixed: on must be 0 or 1");
+    ctx->c.fixed = on == 1;
+    ctx->c.householder = on == 1;
+    return 0;
+  });
+}
+
 int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *y,
              double *sigma_out) {
   return guarded([&]() {
@@ -425,6 +436,18 @@ int tt_round(tt_ctx *ctx, const tt_matrix *x, double eps, int r_max, tt_matrix *
     TT_REQUIRE(y->cap >= r_max, "tt_round: y->cap < r_max");
     TT_REQUIRE(x->n1 == y->n1 && x->n2 == y->n2, "tt_round: shape mismatch");
     DTT xv = view(x), yv = view(y);
+    if (ctx->c.fixed) {
+      // the rank chosen on the device; the buffers' columns after it up to the static rank
+      // are zero
+      Scope sc(ctx->c.arena);
+      int *kd = ctx->c.arena.ialloc(1);
+      round_fixed(ctx->c, xv, eps, r_max, yv, kd);
+      int k = 0;
+      HIP_CHECK(hipMemcpyAsync(&k, kd, sizeof(int), hipMemcpyDeviceToHost, ctx->c.stream));
+      const int w = fixed_status(ctx->c);
+      y->rank = std::max(k, 1);
+      return w | jacobi_warning(ctx->c);
+    }
     std::vector<double> s;
     const int w = round_tt(ctx->c, xv, eps, r_max, yv, &s);
     y->rank = yv.r;
@@ -576,6 +599,31 @@ int tt_cross(tt_ctx *ctx, int fn, const tt_matrix *inputs, int n_inputs, const d
     FiberSpec fs = make_fiber_spec(c, fn, inputs, n_inputs, fparams, n1, n2);
     DTT yv = view(y);
     std::vector<int> Jo;
+    if (c.fixed) {
+      // device column set of r_max entries; the kicks' key split into (site, step) words
+      TT_REQUIRE(nJ0 <= r_max, "tt_cross: fixed shapes need nJ0 <= r_max");
+      int *Jd = c.arena.ialloc(r_max + 1), *kd = c.arena.ialloc(1);
+      long long *sd = static_cast<long long *>(c.arena.alloc(sizeof(long long)));
+      std::vector<int> h(r_max + 1, 0);
+      std::copy(J.begin(), J.end(), h.begin());
+      h[r_max] = nJ0;
+      const long long step = (long long)(key & 0xFFFFFFFFull);
+      HIP_CHECK(hipMemcpyAsync(Jd, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice,
+                               c.stream));
+      HIP_CHECK(hipMemcpyAsync(sd, &step, sizeof(step), hipMemcpyHostToDevice, c.stream));
+      cross_fixed(c, fs, n1, n2, Jd, Jd + r_max, r_max, eps, r_max, sweeps, kick, key >> 32, sd,
+                  yv, kd);
+      int k = 0;
+      HIP_CHECK(hipMemcpyAsync(h.data(), Jd, h.size() * sizeof(int), hipMemcpyDeviceToHost,
+                               c.stream));
+      HIP_CHECK(hipMemcpyAsync(&k, kd, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+      const int w = fixed_status(c);
+      y->rank = std::max(k, 1);
+      if (J_out)
+        for (int i = 0; i < h[r_max]; ++i) J_out[i] = h[i];
+      if (nJ_out) *nJ_out = h[r_max];
+      return w | jacobi_warning(ctx->c);
+    }
     const int w = cross_tt(c, fs, n1, n2, J, eps, r_max, sweeps, kick, key, yv, &Jo);
     y->rank = yv.r;
     if (J_out)

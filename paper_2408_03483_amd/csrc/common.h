@@ -53,6 +53,7 @@ class Arena {
   // status words at the arena's base (zeroed at init, never sub-allocated): [0] counts the
   // Jacobi SVDs on this arena's stream that stopped at their sweep cap
   int *status() const { return reinterpret_cast<int *>(base_); }
+  // [FX_WARN]: TT_W* bits and [FX_ERRORS]: FX_ERR_* bits raised by fixed-shape kernels
   size_t mark() const { return top_; }
   void release(size_t m) { top_ = m; }
   size_t capacity() const { return cap_; }
@@ -89,6 +90,10 @@ struct Counters {
   int warnings = 0;
 };
 
+// status words of fixed-shape execution (fixed.hip) at the arena's base, after the Jacobi count
+constexpr int FX_WARN = 1, FX_ERRORS = 2;
+constexpr int FX_ERR_NONFINITE = 1, FX_ERR_MEAN = 2, FX_ERR_DOMAIN = 4;
+
 // Optional event timing of one kernel family: one launch in `every` of the kernels whose
 // timing name starts with `name` is launched with a start and a stop event, which HIP sets to
 // that kernel's own start and end on its stream; pairs are resolved at the next sync.
@@ -121,6 +126,11 @@ struct Ctx {
   bool householder = false; // force Householder TSQR (the redo after a failed Cholesky QR)
   int jacobi_max_sweeps = 40;     // sweep cap of the one-sided Jacobi SVD
   int sketch_max_iters = 8;       // subspace iterations after which a range finder stops
+  // fixed shapes (fixed.hip): ranks and the other decisions stay on the device, every TT keeps
+  // its buffer's static rank (zero columns beyond the device's), no host round trip; capturing:
+  // the stream is being captured into a HIP graph (sync() does nothing, host reads are errors)
+  bool fixed = false;
+  bool capturing = false;
   Counters cnt;
   KernelTimer timer;
   int *tile_cnt = nullptr;  // zeroed per-tile arrival counters of split-K GEMMs (this stream)
@@ -242,9 +252,35 @@ void small_inverse(Ctx &c, const double *M, int m, int ldm, double *Minv);
 // normalise the first k columns of US by sig into U
 void normalise_cols(Ctx &c, const double *US, const double *sig, int m, int k, double *U);
 
-// cross.hip
+// cross.hip.  k_dev (fixed shapes): Q's columns from *k_dev on are zero; the rows chosen for
+// them are valid indices but carry no meaning
 void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int maxit,
-                int *rows_dev);
+                int *rows_dev, const int *k_dev = nullptr);
+
+// fixed.hip: device-side decisions of fixed-shape execution.  trunc_mask: kept rank by the
+// rounding rule (rule 0: eps, floor_rel, rmax; q >= 0 also checks a range finder's stop after q
+// subspace iterations) or the orthogonalisation rule (rule 1: s_j > eps s_0), written to
+// *k_out when not null, and U (m x kcap) = US / s for the kept columns, zero after them;
+// *ss_out = sum of the kept s^2 when not null
+void trunc_mask(Ctx &c, const double *sg, const double *US, int m, int kcap, int rule,
+                double eps, double floor_rel, int rmax, int q, double *U, int *k_out,
+                double *ss_out);
+void qi_pad(Ctx &c, double *QI, int m, const int *k_dev);
+void mask_cols(Ctx &c, double *X, int ld, int rows, int m, const int *k_dev);
+// *nJ = *src, then the seeded fresh columns of sweep `sweep` (as kick_indices) while < rmax
+void device_kicks(Ctx &c, int *J, int *nJ, const int *src, int n, int kick, int rmax,
+                  uint64_t site, const long long *step_dev, int sweep);
+// dst = (mul * s[0]) src (mode 0) or (mul / s[0]) src (mode 1), s on the device
+void scale_dev(Ctx &c, double *dst, int ldd, const double *src, int lds, int rows, int cols,
+               const double *s, double mul, int mode);
+void mean_dev(Ctx &c, const double *cs, int r, double N, double *out);
+void taylor_start(Ctx &c, double *hist);
+void taylor_err(Ctx &c, const double *ss, double N, double eps, double *hist, int terms,
+                bool last);
+void inc_step(Ctx &c, long long *step);
+void count_rank(Ctx &c, const double *B, int n, int r, int *out);
+// reads and clears the fixed-shape status words: throws on an error bit, returns TT_W* bits
+int fixed_status(Ctx &c);
 
 struct WenoTables {          // candidate stencils and weights for WENO5 (k = 2)
   double face_C[3][3];       // Step 1 candidate r, cell j-r+l, at +1/2
@@ -302,6 +338,23 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
 // f(:, J), y = round(Qc Qc[I]^-1 f(I, :), eps, rmax)
 int skeleton_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, const std::vector<int> &J,
                 const std::vector<int> &I, double eps, int rmax, DTT &y);
+// fixed shapes: a rounding whose output keeps the static rank min(rmax, m) with zero columns
+// after the rank chosen on the device (into *k_dev when not null; *ss_dev = sum of the kept
+// s^2); the range finder runs exactly max(power_iters, 1) subspace iterations
+int round_fixed(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, int *k_dev = nullptr,
+                double *ss_dev = nullptr);
+// fixed shapes: orth with the kept count on the device (Q: n x m, zero after it)
+void orth_fixed(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q,
+                int *k_dev);
+// fixed shapes: the maxvol cross from the device column set Jd (capacity m, *nJ active, every
+// entry a valid column), updated in place to the set of the last sweep; kicks keyed by site
+// and *step_dev as cross_tt's
+int cross_fixed(Ctx &c, const FiberSpec &fs, int n1, int n2, int *Jd, int *nJ, int m,
+                double eps, int rmax, int sweeps, int kick, uint64_t site,
+                const long long *step_dev, DTT &y, int *k_dev = nullptr);
+// fixed shapes: Algorithm 1 with K terms, the stopping test as a device predicate (terms after
+// the first with Err <= eps are added times zero)
+int reciprocal_fixed(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y);
 uint64_t splitmix64_next(uint64_t &state);
 std::vector<int> kick_indices(const std::vector<int> &have, int n, int count, uint64_t key);
 

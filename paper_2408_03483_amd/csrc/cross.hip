@@ -310,7 +310,7 @@ double fiber_cost(const FiberSpec &fs) {
 }  // namespace
 
 void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int maxit,
-                int *rows_dev) {
+                int *rows_dev, const int *k_dev) {
   TT_REQUIRE(r >= 1 && r <= 96 && n >= r, "maxvol: need n >= r, 1 <= r <= 96");
   Scope sc(c.arena);
   double *R = c.arena.dalloc((size_t)n * r);
@@ -336,6 +336,9 @@ void maxvol_dev(Ctx &c, const double *Q, int n, int r, int ldq, double tau, int 
   double *QIinv = c.arena.dalloc((size_t)r * r);
   double *B = c.arena.dalloc((size_t)n * r);
   gather_rows(c, QI, r, Q, ldq, rows_dev, r, r);
+  // with zero columns from *k_dev on, Q[I] is completed by the identity outside its leading
+  // block: B keeps those columns zero, so the swaps never touch them
+  if (k_dev) qi_pad(c, QI, r, k_dev);
   small_inverse(c, QI, r, r, QIinv);
   gemm(c, false, n, r, r, 1.0, Q, ldq, QIinv, r, 0.0, B, n);
   hipLaunchKernelGGL(k_maxvol_swaps, dim3(1), dim3(NT), 0, c.stream, B, n, r, tau, maxit,

@@ -108,8 +108,34 @@ struct Solver {
   std::map<int, std::pair<std::vector<int>, std::vector<int>>> last_piv;
   long long sweeps_run = 0, learned = 0, fallbacks = 0;
   double max_learned_err = 0.0;
+  // graph mode (tt_fv_params.graph): fixed shapes on the solver's stream, the step captured in a
+  // HIP graph after one eager step and replayed.  Device state: the step counter the crosses'
+  // kicks are keyed by, and per cross site its column set (site_cap entries, then the count).
+  long long *dev_step = nullptr;
+  int *site_J = nullptr;
+  int site_cap = 0;
+  static constexpr int kSites = 6 << 6;
+  std::vector<char> site_have;
+  bool warm = false;              // an eager fixed-shape step has set the static ranks
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double graph_dt = 0.0;
+  size_t graph_mark = 0;
+  Counters graph_cnt;             // host counters of one captured step
+  long long graph_sweeps = 0;
+  long long graph_launches = 0;
+  hipStream_t own_stream = nullptr;   // graph mode: the solver's stream (capturable)
+  hipStream_t user_stream = nullptr;  // the stream given at init
 
   ~Solver() {
+    if (gexec || graph) (void)hipStreamSynchronize(c.stream);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own_stream) {
+      (void)hipStreamSynchronize(own_stream);
+      c.stream = user_stream;   // the context's own clean-up must not see the destroyed stream
+      (void)hipStreamDestroy(own_stream);
+    }
     if (term_mem) {
       (void)hipStreamSynchronize(c.stream);
       (void)hipFree(term_mem);
@@ -147,6 +173,13 @@ struct Solver {
         w.enrich = enrich;
         f(w);
       };
+    if (p.graph) {                // one stream: the tasks in order, temporaries per task
+      for (auto &t : tasks) {
+        Scope sc(c.arena);
+        t(c);
+      }
+      return;
+    }
     exec->run(std::move(tasks));
   }
 
@@ -263,7 +296,39 @@ struct Solver {
   // cross into the preallocated `out` (capacity r_max).  Pivots: the same site's columns of
   // the previous step (or maxvol of the starting TT), refined by the maxvol sweeps; with the
   // learned proposer, its top-K columns and one sweep when the validation check passes.
+  bool site_ready(int site) const {
+    return p.graph && site >= 0 && site < kSites && site_have[site];
+  }
+
+  // graph mode: the cross from the site's device column set (set by maxvol of the starting
+  // TT on the site's first, eager, call)
+  void cross_graph(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y0, int site,
+                   DTT &out) {
+    TT_REQUIRE(site >= 0 && site < kSites, "graph mode: cross site out of range");
+    int *Jd = site_J + (size_t)site * (site_cap + 1), *nJ = Jd + site_cap;
+    if (!site_have[site]) {
+      TT_REQUIRE(!w.capturing, "graph mode: a cross site without pivots during capture");
+      std::vector<int> J0 = initial_columns(w, y0);
+      TT_REQUIRE((int)J0.size() <= site_cap, "graph mode: starting columns exceed r_max");
+      std::vector<int> h(site_cap + 1, 0);
+      std::copy(J0.begin(), J0.end(), h.begin());
+      h[site_cap] = (int)J0.size();
+      HIP_CHECK(hipMemcpyAsync(Jd, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice,
+                               w.stream));
+      w.sync();
+      site_have[site] = 1;
+    }
+    const uint64_t key = (uint64_t)site;
+    cross_fixed(w, fs, n1, n2, Jd, nJ, site_cap, eps_in, p.r_max, p.cross_sweeps, p.cross_kick,
+                key, dev_step, out);
+    sweeps_run += p.cross_sweeps;
+  }
+
   void cross(Ctx &w, const FiberSpec &fs, int n1, int n2, const DTT &y0, int site, DTT &out) {
+    if (p.graph) {
+      cross_graph(w, fs, n1, n2, y0, site, out);
+      return;
+    }
     std::vector<int> J0;
     double ref = -1.0;
     if (piv_mode == TT_PIV_REPLAY) {
@@ -493,6 +558,10 @@ struct Solver {
   // one side: 1/h (Algorithm 1), u, w, P1, P2 -> F2 = round(P1 + g/2 P2), F3 = round(m o w)
   // 1/h of one side: cross of the pointwise reciprocal or Algorithm 1, into rh (cap r_max)
   void reciprocal(Ctx &w, const DTT &h, int recip_site, int chain, DTT &rh) {
+    if (p.graph && p.recip == 0) {
+      reciprocal_fixed(w, h, eps_in, p.taylor_terms, p.r_max, rh);
+      return;
+    }
     if (p.recip == 1) {
       FiberSpec fr;
       fr.fn = TT_FN_RECIP;
@@ -625,7 +694,8 @@ struct Solver {
           });
       for (int d = 0; d < 2; ++d)
         tasks.push_back([this, &qm, &qp, &lam, &sb, d](Ctx &w) {
-          const DTT &y0 = norm2(w, qm[d][1]) > 0.0 ? qm[d][1] : qm[d][0];
+          // (the starting TT matters only for a site's first cross)
+          const DTT &y0 = site_ready(sb[d]) || norm2(w, qm[d][1]) > 0.0 ? qm[d][1] : qm[d][0];
           FiberSpec fl;
           fl.fn = TT_FN_LLF_LAMBDA;
           fl.n_in = 4;
@@ -805,6 +875,83 @@ struct Solver {
   }
 
   void step(double dt) {
+    if (p.graph) {
+      step_graph(dt);
+      return;
+    }
+    step_body(dt);
+    ++step_index;
+    t += dt;
+  }
+
+  // graph mode: one eager fixed-shape step sets the static ranks and every cross site's
+  // pivots; the next step (and the first after a change of dt) is captured, and every step
+  // launches the captured graph.  The kernels' scalar arguments (dt, tolerances) are part of
+  // the graph; the step count the kicks use lives on the device.
+  void step_graph(double dt) {
+    TT_REQUIRE(c.timer.name.empty(), "graph mode: kernel timing is not available");
+    if (!warm) {
+      step_body(dt);
+      ++step_index;
+      t += dt;
+      warm = true;
+      return;
+    }
+    if (!gexec || dt != graph_dt || c.arena.mark() != graph_mark) capture(dt);
+    HIP_CHECK(hipGraphLaunch(gexec, c.stream));
+    ++graph_launches;
+    const Counters &g = graph_cnt;
+    c.cnt.roundings += g.roundings;
+    c.cnt.crosses += g.crosses;
+    c.cnt.flops += g.flops;
+    c.cnt.bytes += g.bytes;
+    sweeps_run += graph_sweeps;
+    ++step_index;
+    t += dt;
+  }
+
+  void capture(double dt) {
+    if (gexec) {
+      HIP_CHECK(hipStreamSynchronize(c.stream));
+      (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    if (graph) {
+      (void)hipGraphDestroy(graph);
+      graph = nullptr;
+    }
+    const Counters before = c.cnt;
+    const long long sw = sweeps_run;
+    const size_t mark = c.arena.mark();
+    hipGraph_t g = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
+    c.capturing = true;
+    try {
+      step_body(dt);
+    } catch (...) {
+      c.capturing = false;
+      if (hipStreamEndCapture(c.stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      c.cnt = before;
+      sweeps_run = sw;
+      throw;
+    }
+    c.capturing = false;
+    HIP_CHECK(hipStreamEndCapture(c.stream, &g));
+    graph = g;
+    HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    graph_cnt = Counters{};
+    graph_cnt.roundings = c.cnt.roundings - before.roundings;
+    graph_cnt.crosses = c.cnt.crosses - before.crosses;
+    graph_cnt.flops = c.cnt.flops - before.flops;
+    graph_cnt.bytes = c.cnt.bytes - before.bytes;
+    graph_sweeps = sweeps_run - sw;
+    c.cnt = before;
+    sweeps_run = sw;
+    graph_dt = dt;
+    graph_mark = mark;
+  }
+
+  void step_body(double dt) {
     Scope sc(c.arena);
     set_tolerances();
     DTT Q1[3], F1[3], Q2[3], F2[3], Qn[3];
@@ -826,9 +973,8 @@ struct Solver {
       copy_scale(c, Q[v].B, n, Qn[v].B, n, n, Qn[v].r, 1.0);
       Q[v].r = Qn[v].r;
     }
+    if (p.graph) inc_step(c, dev_step);
     c.sync();
-    ++step_index;
-    t += dt;
   }
 
   // replace the separable terms: ghost terms get their exact-axis column (zero inside the
@@ -922,6 +1068,19 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
+  TT_REQUIRE(p->graph == 0 || p->graph == 1, "tt_fv_init: graph must be 0 or 1");
+  if (p->graph) {
+    // every decision of these paths has a device-side form; the others read the host
+    TT_REQUIRE(p->scheme == 3 || p->scheme == 5, "graph mode: Upwind3 or Upwind5 only");
+    TT_REQUIRE(p->eps_rule == TT_EPS_FIXED, "graph mode: fixed eps only");
+    TT_REQUIRE(p->flux == TT_FLUX_PRODUCTS, "graph mode: the product flux only");
+    TT_REQUIRE(p->cross_enrich == TT_ENRICH_KICKS, "graph mode: seeded kicks only");
+    TT_REQUIRE(p->bc_x != TT_BC_EXACT && p->bc_y != TT_BC_EXACT,
+               "graph mode: no exact-solution boundaries");
+    TT_REQUIRE(!p->nonlinear || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
+               "tt_fv_init: bad cross parameters");
+    TT_REQUIRE(2 * p->r_max < p->n, "graph mode: n must exceed 2 r_max");
+  }
   for (int v = 0; v < 3; ++v) {
     TT_REQUIRE(q0[v].n1 == p->n && q0[v].n2 == p->n, "tt_fv_init: state shape != n x n");
     TT_REQUIRE(q0[v].rank >= 1 && q0[v].rank <= p->r_max, "tt_fv_init: state rank out of range");
@@ -939,7 +1098,29 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->c.arena.init(ab);
     int dev = 0;
     HIP_CHECK(hipGetDevice(&dev));
-    const int nw = p->workers == 0 ? 8 : p->workers;
+    const int nw = p->graph ? 0 : p->workers == 0 ? 8 : p->workers;
+    if (p->graph) {
+      // the step is captured on a stream of the solver's own (the caller's may be the null
+      // stream); the initial state was copied on the caller's stream, which is synchronised
+      // before the first step
+      HIP_CHECK(hipStreamSynchronize(s->c.stream));
+      s->user_stream = s->c.stream;
+      HIP_CHECK(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
+      s->c.stream = s->own_stream;
+      s->c.fixed = true;
+      s->c.householder = true;   // no host-side check of a Cholesky QR in a graph
+      // the range finder cannot add iterations on demand: two subspace iterations keep the
+      // leak of the discarded directions at the dynamic path's level at a binding rank cap
+      s->c.power_iters = 2;
+      s->site_cap = p->r_max;
+      s->site_have.assign(Solver::kSites, 0);
+      s->site_J = s->c.arena.ialloc((size_t)Solver::kSites * (s->site_cap + 1));
+      s->dev_step = static_cast<long long *>(s->c.arena.alloc(sizeof(long long)));
+      HIP_CHECK(hipMemsetAsync(s->site_J, 0,
+                               (size_t)Solver::kSites * (s->site_cap + 1) * sizeof(int),
+                               s->c.stream));
+      HIP_CHECK(hipMemsetAsync(s->dev_step, 0, sizeof(long long), s->c.stream));
+    }
     if (nw > 0) {
       s->pool = std::make_unique<Pool>(nw, ab, dev);
       s->exec = s->pool.get();
@@ -1021,14 +1202,113 @@ void solver_set_terms(Solver *s, const tt_fv_term *terms, int count) {
 
 void solver_step(Solver *s, double dt, int nsteps) {
   TT_REQUIRE(nsteps >= 0 && std::isfinite(dt), "tt_fv_step: bad dt or nsteps");
-  TT_REQUIRE(s->exec, "tt_fv_step: solver made with workers = -1 steps only inside an ensemble");
+  TT_REQUIRE(s->exec || s->p.graph,
+             "tt_fv_step: solver made with workers = -1 steps only inside an ensemble");
   for (int k = 0; k < nsteps; ++k) s->step(dt);
+  if (s->p.graph) fixed_status(s->c);
 }
 
 // ---- ensemble: members share one pool; host threads take members in cost order --------
 struct Ensemble {
   std::unique_ptr<Pool> pool;
+  std::vector<hipStream_t> gstreams;   // graph mode: streams the members' graphs replay on
+  ~Ensemble() {
+    for (hipStream_t st : gstreams) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  }
 };
+
+// Graph mode: each member's first step runs eagerly and its next step is captured, on
+// `concurrency` host threads (members on their own streams); then one host thread launches
+// every member's graph for the remaining steps, each member on one of `concurrency` streams
+// chosen longest-processing-time first, with no host round trip until the end.
+void ensemble_step_graph(Ensemble *e, Solver *const *members, int count, const double *dts,
+                         int nsteps, int concurrency) {
+  std::vector<int> order(count), rem(count, nsteps);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const double r = members[i]->p.r_max, n = members[i]->n;
+    return n * r * r * r * r;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  // prepare: eager first steps and captures, in parallel over members
+  {
+    std::mutex qm;
+    size_t next = 0;
+    std::exception_ptr err;
+    auto worker = [&]() {
+      for (;;) {
+        int idx;
+        {
+          std::lock_guard<std::mutex> lk(qm);
+          if (next >= order.size() || err) return;
+          idx = order[next++];
+        }
+        try {
+          Solver *m = members[idx];
+          TT_REQUIRE(std::isfinite(dts[idx]), "tt_ens_step: bad dt");
+          if (rem[idx] > 0 && !m->warm) {
+            m->step_graph(dts[idx]);
+            --rem[idx];
+          }
+          if (rem[idx] > 0 &&
+              (!m->gexec || dts[idx] != m->graph_dt || m->c.arena.mark() != m->graph_mark))
+            m->capture(dts[idx]);
+          HIP_CHECK(hipStreamSynchronize(m->c.stream));
+        } catch (...) {
+          std::lock_guard<std::mutex> lk(qm);
+          if (!err) err = std::current_exception();
+          return;
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    for (int t = 0; t < std::min(concurrency, count); ++t)
+      th.emplace_back([&, dev]() {
+        (void)hipSetDevice(dev);
+        worker();
+      });
+    for (auto &t : th) t.join();
+    if (err) std::rethrow_exception(err);
+  }
+  const int ns = std::min(concurrency, count);
+  while ((int)e->gstreams.size() < ns) {
+    hipStream_t st;
+    HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    e->gstreams.push_back(st);
+  }
+  // members to streams: the least loaded stream takes the next most expensive member
+  std::vector<int> sid(count, 0);
+  std::vector<double> load(ns, 0.0);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    sid[i] = k;
+    load[k] += cost(i);
+  }
+  int most = 0;
+  for (int i = 0; i < count; ++i) most = std::max(most, rem[i]);
+  for (int k = 0; k < most; ++k)
+    for (int i : order) {
+      if (k >= rem[i]) continue;
+      Solver *m = members[i];
+      HIP_CHECK(hipGraphLaunch(m->gexec, e->gstreams[sid[i]]));
+      ++m->graph_launches;
+      const Counters &g = m->graph_cnt;
+      m->c.cnt.roundings += g.roundings;
+      m->c.cnt.crosses += g.crosses;
+      m->c.cnt.flops += g.flops;
+      m->c.cnt.bytes += g.bytes;
+      m->sweeps_run += m->graph_sweeps;
+      ++m->step_index;
+      m->t += dts[i];
+    }
+  for (int k = 0; k < ns; ++k) HIP_CHECK(hipStreamSynchronize(e->gstreams[k]));
+  for (int i = 0; i < count; ++i) fixed_status(members[i]->c);
+}
 
 Ensemble *ensemble_create(int workers, size_t arena_bytes) {
   TT_REQUIRE(workers >= 1 && workers <= 32, "tt_ens_create: workers must be in [1, 32]");
@@ -1048,6 +1328,14 @@ void ensemble_step(Ensemble *e, Solver *const *members, int count, const double 
   for (int i = 0; i < count; ++i) {
     TT_REQUIRE(members[i], "tt_ens_step: null member");
     TT_REQUIRE(std::isfinite(dts[i]), "tt_ens_step: bad dt");
+  }
+  int ngraph = 0;
+  for (int i = 0; i < count; ++i) ngraph += members[i]->p.graph ? 1 : 0;
+  TT_REQUIRE(ngraph == 0 || ngraph == count,
+             "tt_ens_step: members must all be in graph mode or none");
+  if (ngraph) {
+    ensemble_step_graph(e, members, count, dts, nsteps, concurrency);
+    return;
   }
   // longest-processing-time first: a Hadamard rounding costs ~ n r^4
   std::vector<int> order(count);
@@ -1112,6 +1400,17 @@ void solver_get_state(Solver *s, tt_matrix q[3]) {
 void solver_stats(Solver *s, tt_fv_stats *o) {
   o->steps = s->step_index;
   for (int v = 0; v < 3; ++v) o->ranks[v] = s->Q[v].r;
+  o->graph_launches = s->graph_launches;
+  if (s->p.graph) {
+    // the static rank of a fixed-shape state holds zero columns after the device's rank
+    Scope sc(s->c.arena);
+    int *rk = s->c.arena.ialloc(3);
+    for (int v = 0; v < 3; ++v) count_rank(s->c, s->Q[v].B, s->n, s->Q[v].r, rk + v);
+    HIP_CHECK(hipMemcpyAsync(o->ranks, rk, 3 * sizeof(int), hipMemcpyDeviceToHost, s->c.stream));
+    HIP_CHECK(hipStreamSynchronize(s->c.stream));
+    for (int v = 0; v < 3; ++v) o->ranks[v] = std::max(o->ranks[v], 1);
+    s->c.cnt.warnings |= fixed_status(s->c);
+  }
   Counters t = s->c.cnt;
   const int npool = s->pool ? s->pool->size() : 0;
   std::vector<const Counters *> cs;

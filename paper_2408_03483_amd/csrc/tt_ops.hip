@@ -29,6 +29,7 @@ namespace {
 // small reads go through the context's pinned staging buffer: a copy into pageable memory
 // is staged by the runtime and costs a longer round trip on this path of every rounding
 std::vector<double> to_host(Ctx &c, const double *dev, size_t n) {
+  TT_REQUIRE(!c.capturing, "graph capture: a step read a device value on the host");
   std::vector<double> h(n);
   double *st = n && n <= Ctx::kPinnedDoubles ? c.pinned_staging() : nullptr;
   if (st) {
@@ -146,6 +147,10 @@ int round_impl(Ctx &c, const DTT &x, double eps, int rmax, DTT &y,
 }  // namespace
 
 int round_tt(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, std::vector<double> *sig_out) {
+  if (c.fixed) {
+    TT_REQUIRE(!sig_out, "fixed shapes: a rounding does not return its singular values");
+    return round_fixed(c, x, eps, rmax, y);
+  }
   const long long r0 = c.cnt.roundings;
   return with_qr_fallback(c, [&]() {
     c.cnt.roundings = r0;     // a redone rounding counts once
@@ -933,6 +938,212 @@ int cross_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, std::vector<int> J, do
   if (J_out) *J_out = J;
   if (I_out) *I_out = I;
   return w;
+}
+
+// ---- fixed shapes: the same algorithms with every decision on the device ---------------
+
+int fixed_status(Ctx &c) {
+  TT_REQUIRE(!c.capturing, "fixed shapes: status read during graph capture");
+  int h[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(h, c.arena.status() + FX_WARN, 2 * sizeof(int),
+                           hipMemcpyDeviceToHost, c.stream));
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  if (h[0] || h[1]) {
+    const int zero[2] = {0, 0};
+    HIP_CHECK(hipMemcpyAsync(c.arena.status() + FX_WARN, zero, 2 * sizeof(int),
+                             hipMemcpyHostToDevice, c.stream));
+    HIP_CHECK(hipStreamSynchronize(c.stream));
+  }
+  if (h[1] & FX_ERR_NONFINITE)
+    throw Error(TT_ENONFINITE, "fixed shapes: non-finite singular value");
+  if (h[1] & FX_ERR_DOMAIN)
+    throw Error(TT_EDOMAIN, "reciprocal: the Taylor terms grow, |1 - x/mean| >= 1");
+  if (h[1] & FX_ERR_MEAN) throw Error(TT_EINVAL, "reciprocal: mean of x is zero or not finite");
+  c.cnt.warnings |= h[0];
+  return h[0];
+}
+
+// The exact path and the range finder of round_tt with the kept rank chosen on the device.
+// The output keeps rank kout = min(rmax, m); its columns beyond the device's k are zero.
+// Without a host check of the sketch's convergence, every input of rank R <= 96 (the
+// factorisation width) takes the exact path, which the dynamic path also reaches when its
+// range finder does not converge; larger ranks take the range finder with a fixed number of
+// subspace iterations.
+int round_fixed(Ctx &c, const DTT &x, double eps, int rmax, DTT &y, int *k_dev,
+                double *ss_dev) {
+  TT_REQUIRE(x.r >= 1 && rmax >= 1, "round: empty input or rmax < 1");
+  TT_REQUIRE(x.n1 == y.n1 && x.n2 == y.n2, "round: shape mismatch");
+  c.cnt.roundings++;
+  Scope sc(c.arena);
+  const int n1 = x.n1, n2 = x.n2, R = x.r;
+  const int qmax = qr_max_cols();
+  int width = c.sketch_width > 0 ? c.sketch_width : std::min(QR_MAXM, std::max(2 * rmax, 16));
+  width = std::min(width, qmax);
+  const int mn = std::min(n1, n2);
+  const double *Qa = nullptr, *Bsrc = nullptr, *Ra_exact = nullptr;
+  double *M = nullptr;
+  bool Mt = false;
+  int m = 0, q_used = -1;
+  if ((R <= width || (c.sketch_width <= 0 && R <= qmax)) && R <= mn) {
+    m = R;
+    double *qa = c.arena.dalloc((size_t)n1 * m), *ra = c.arena.dalloc((size_t)m * m);
+    double *rb = c.arena.dalloc((size_t)m * m);
+    tsqr(c, x.A, n1, m, n1, qa, n1, ra, m);
+    tsqr(c, x.B, n2, m, n2, nullptr, 0, rb, m);
+    M = c.arena.dalloc((size_t)m * m);
+    gemm2(c, false, true, m, m, m, 1.0, ra, m, rb, m, 0.0, M, m);     // Ra Rb^T
+    Qa = qa;
+    Bsrc = x.B;
+    Ra_exact = ra;
+  } else {
+    TT_REQUIRE(mn > width, "fixed shapes: a mode no longer than the sketch width");
+    m = std::min(width, mn);
+    double *Om = c.arena.dalloc((size_t)n2 * m);
+    fill_gauss(c, Om, n2, m, n2,
+               g_sketch_seed ^ ((uint64_t)n1 * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)n2 << 20) ^
+                   ((uint64_t)R << 40) ^ (uint64_t)m);
+    double *T = c.arena.dalloc((size_t)R * m);
+    double *Y = c.arena.dalloc((size_t)n1 * m);
+    double *Z = c.arena.dalloc((size_t)n2 * m);
+    double *qa = c.arena.dalloc((size_t)n1 * m), *qz = c.arena.dalloc((size_t)n2 * m);
+    double *rb = c.arena.dalloc((size_t)m * m), *rtmp = c.arena.dalloc((size_t)m * m);
+    gemm(c, true, R, m, n2, 1.0, x.B, n2, Om, n2, 0.0, T, R);          // B^T Omega
+    gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);          // Y = X Omega
+    const int iters = std::max(c.power_iters, 1);
+    for (int q = 0; q < iters; ++q) {
+      tsqr(c, Y, n1, m, n1, qa, n1, rtmp, m);
+      gemm(c, true, R, m, n1, 1.0, x.A, n1, qa, n1, 0.0, T, R);
+      gemm(c, false, n2, m, R, 1.0, x.B, n2, T, R, 0.0, Z, n2);        // X^T Qy
+      tsqr(c, Z, n2, m, n2, qz, n2, rtmp, m);
+      gemm(c, true, R, m, n2, 1.0, x.B, n2, qz, n2, 0.0, T, R);
+      gemm(c, false, n1, m, R, 1.0, x.A, n1, T, R, 0.0, Y, n1);        // Y = X Qz
+    }
+    tsqr(c, Y, n1, m, n1, qa, n1, rtmp, m);
+    gemm(c, true, R, m, n1, 1.0, x.A, n1, qa, n1, 0.0, T, R);
+    gemm(c, false, n2, m, R, 1.0, x.B, n2, T, R, 0.0, Z, n2);          // W = X^T Qa
+    tsqr(c, Z, n2, m, n2, nullptr, 0, rb, m);                          // R of W only
+    M = rb;
+    Mt = true;
+    Qa = qa;
+    Bsrc = Z;
+    q_used = iters;
+  }
+  double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc((size_t)m);
+  if (Mt) jacobi_svd(c, M, m, US, sg, true, jacobi_floor(eps));
+  else small_svd(c, M, m, US, sg, jacobi_floor(eps));
+  const int kout = std::min(rmax, m);
+  double *U = c.arena.dalloc((size_t)m * kout);
+  trunc_mask(c, sg, US, m, kout, 0, eps, jacobi_floor(eps), rmax, q_used, U, k_dev, ss_dev);
+  gemm(c, false, n1, kout, m, 1.0, Qa, n1, U, m, 0.0, y.A, n1);
+  if (!Ra_exact) {
+    gemm(c, false, n2, kout, m, 1.0, Bsrc, n2, U, m, 0.0, y.B, n2);    // W U_k
+  } else {
+    double *W = c.arena.dalloc((size_t)m * kout);
+    gemm(c, true, m, kout, m, 1.0, Ra_exact, m, U, m, 0.0, W, m);      // Ra^T U_k
+    gemm(c, false, n2, kout, m, 1.0, Bsrc, n2, W, m, 0.0, y.B, n2);
+  }
+  y.r = kout;
+  return 0;
+}
+
+void orth_fixed(Ctx &c, const double *C, int n, int m, int ldc, double drop, double *Q,
+                int *k_dev) {
+  TT_REQUIRE(m >= 1 && m <= n && m <= qr_max_cols(), "orth: need 1 <= m <= min(n, 96)");
+  Scope sc(c.arena);
+  double *q = c.arena.dalloc((size_t)n * m), *r = c.arena.dalloc((size_t)m * m);
+  tsqr(c, C, n, m, ldc, q, n, r, m);
+  double *US = c.arena.dalloc((size_t)m * m), *sg = c.arena.dalloc(m);
+  small_svd(c, r, m, US, sg, 1e-2 * drop);
+  double *U = c.arena.dalloc((size_t)m * m);
+  trunc_mask(c, sg, US, m, m, 1, drop, 0.0, m, -1, U, k_dev, nullptr);
+  gemm(c, false, n, m, m, 1.0, q, n, U, m, 0.0, Q, n);
+}
+
+int cross_fixed(Ctx &c, const FiberSpec &fs, int n1, int n2, int *Jd, int *nJ, int m,
+                double eps, int rmax, int sweeps, int kick, uint64_t site,
+                const long long *step_dev, DTT &y, int *k_dev) {
+  TT_REQUIRE(sweeps >= 1, "cross: sweeps < 1");
+  TT_REQUIRE(m >= 1 && m <= qr_max_cols() && m <= n1 && m <= n2,
+             "fixed shapes: cross width must be in [1, min(n1, n2, 96)]");
+  c.cnt.crosses++;
+  Scope sc(c.arena);
+  int *Id = c.arena.ialloc(m), *kc = c.arena.ialloc(1), *kr = c.arena.ialloc(1);
+  double *C = c.arena.dalloc((size_t)n1 * m), *Qc = c.arena.dalloc((size_t)n1 * m);
+  double *RwT = c.arena.dalloc((size_t)n2 * m), *Qr = c.arena.dalloc((size_t)n2 * m);
+  const double drop = c.drop();
+  for (int s = 0; s < sweeps; ++s) {
+    fiber_cols(c, fs, n1, Jd, m, C);
+    mask_cols(c, C, n1, n1, m, nJ);
+    orth_fixed(c, C, n1, m, n1, drop, Qc, kc);
+    maxvol_dev(c, Qc, n1, m, n1, 1.05, 100, Id, kc);
+    fiber_rows(c, fs, n2, Id, m, RwT);
+    mask_cols(c, RwT, n2, n2, m, kc);
+    if (s == sweeps - 1) break;
+    orth_fixed(c, RwT, n2, m, n2, drop, Qr, kr);
+    maxvol_dev(c, Qr, n2, m, n2, 1.05, 100, Jd, kr);
+    device_kicks(c, Jd, nJ, kr, n2, kick, rmax, site, step_dev, s);
+  }
+  // skeleton: G1 = Qc Qc[I]^-1 (leading kc block; the identity outside it), G2^T = RwT
+  double *QI = c.arena.dalloc((size_t)m * m), *QIi = c.arena.dalloc((size_t)m * m);
+  gather_rows(c, QI, m, Qc, n1, Id, m, m);
+  qi_pad(c, QI, m, kc);
+  small_inverse(c, QI, m, m, QIi);
+  double *G1 = c.arena.dalloc((size_t)n1 * m);
+  gemm(c, false, n1, m, m, 1.0, Qc, n1, QIi, m, 0.0, G1, n1);
+  DTT sk{n1, n2, m, G1, RwT};
+  return round_fixed(c, sk, eps, rmax, y, k_dev);
+}
+
+int reciprocal_fixed(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y) {
+  TT_REQUIRE(K >= 1, "reciprocal: max_terms < 1");
+  Scope sc(c.arena);
+  const int n1 = x.n1, n2 = x.n2;
+  const double N = (double)n1 * (double)n2;
+  double *cs = c.arena.dalloc(2 * (size_t)x.r), *xavg = c.arena.dalloc(1);
+  colsum(c, x.A, n1, x.r, n1, cs);
+  colsum(c, x.B, n2, x.r, n2, cs + x.r);
+  mean_dev(c, cs, x.r, N, xavg);
+  const int cap = std::max(rmax, 1);
+  DTT xt{n1, n2, 0, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+  {
+    Scope s2(c.arena);
+    DTT t{n1, n2, x.r + 1, c.arena.dalloc((size_t)n1 * (x.r + 1)),
+          c.arena.dalloc((size_t)n2 * (x.r + 1))};
+    fill_value(c, t.A, n1, n1, 1, 1.0);
+    fill_value(c, t.B, n2, n2, 1, 1.0);
+    scale_dev(c, t.A + n1, n1, x.A, n1, n1, x.r, xavg, -1.0, 1);      // -x / x_avg
+    copy_scale(c, t.B + n2, n2, x.B, n2, n2, x.r, 1.0);
+    round_fixed(c, t, eps, rmax, xt);
+  }
+  DTT dy{n1, n2, 1, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+  DTT dy2{n1, n2, 0, c.arena.dalloc((size_t)n1 * cap), c.arena.dalloc((size_t)n2 * cap)};
+  fill_value(c, dy.A, n1, n1, 1, 1.0);
+  fill_value(c, dy.B, n2, n2, 1, 1.0);
+  fill_value(c, y.A, n1, n1, 1, 1.0);
+  fill_value(c, y.B, n2, n2, 1, 1.0);
+  y.r = 1;
+  double *hist = c.arena.dalloc(4), *ss = c.arena.dalloc(1);
+  taylor_start(c, hist);
+  for (int terms = 1; terms < K; ++terms) {
+    Scope s3(c.arena);
+    const int R = dy.r * xt.r;
+    DTT p{n1, n2, R, c.arena.dalloc((size_t)n1 * R), c.arena.dalloc((size_t)n2 * R)};
+    khatri_rao(c, p.A, n1, dy.A, dy.r, xt.A, xt.r);
+    khatri_rao(c, p.B, n2, dy.B, dy.r, xt.B, xt.r);
+    round_fixed(c, p, eps, rmax, dy2, nullptr, ss);
+    std::swap(dy, dy2);
+    const int Rs = y.r + dy.r;
+    DTT s{n1, n2, Rs, c.arena.dalloc((size_t)n1 * Rs), c.arena.dalloc((size_t)n2 * Rs)};
+    copy_scale(c, s.A, n1, y.A, n1, n1, y.r, 1.0);
+    // the term enters while the series runs (hist[3] = 1); after the stop it enters times 0
+    scale_dev(c, s.A + (size_t)n1 * y.r, n1, dy.A, n1, n1, dy.r, hist + 3, 1.0, 0);
+    copy_scale(c, s.B, n2, y.B, n2, n2, y.r, 1.0);
+    copy_scale(c, s.B + (size_t)n2 * y.r, n2, dy.B, n2, n2, dy.r, 1.0);
+    round_fixed(c, s, eps, rmax, y);
+    taylor_err(c, ss, N, eps, hist, terms + 1, terms + 1 == K);
+  }
+  scale_dev(c, y.A, n1, y.A, n1, n1, y.r, xavg, 1.0, 1);                // y / x_avg
+  return 0;
 }
 
 int skeleton_tt(Ctx &c, const FiberSpec &fs, int n1, int n2, const std::vector<int> &J,

@@ -45,7 +45,8 @@ class ParamsC(ctypes.Structure):
                 ("precision", ctypes.c_int), ("qr", ctypes.c_int), ("cross_drop", ctypes.c_double),
                 ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("t0", ctypes.c_double),
-                ("flux", ctypes.c_int), ("cross_enrich", ctypes.c_int)]
+                ("flux", ctypes.c_int), ("cross_enrich", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class TensorC(ctypes.Structure):
@@ -72,7 +73,8 @@ class StatsC(ctypes.Structure):
                 ("max_learned_err", ctypes.c_double), ("sketch_fallbacks", ctypes.c_longlong),
                 ("sketch_unconverged", ctypes.c_longlong), ("jacobi_capped", ctypes.c_longlong),
                 ("qr_redos", ctypes.c_longlong), ("eps_inner", ctypes.c_double),
-                ("eps_var", ctypes.c_double * 3), ("time", ctypes.c_double)]
+                ("eps_var", ctypes.c_double * 3), ("time", ctypes.c_double),
+                ("graph_launches", ctypes.c_longlong)]
 
 
 PRECISIONS = {"f64": 0, "f32": 1}
@@ -110,7 +112,7 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
            "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
            "tt_fv_set_terms", "tt_compress", "tt_fv_max_speed", "tt_fv_cfl_dt",
-           "tt_ctx_set_enrichment", "tt_round_nd"]
+           "tt_ctx_set_enrichment", "tt_round_nd", "tt_ctx_set_fixed"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -137,6 +139,7 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_set_limits.argtypes = [P, I, I]
     L.tt_ctx_set_qr.argtypes = [P, I, I]
     L.tt_ctx_set_enrichment.argtypes = [P, I]
+    L.tt_ctx_set_fixed.argtypes = [P, I]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_compress.argtypes = [P, P, I, I, I, D, I, pM, ctypes.POINTER(D)]
@@ -283,6 +286,11 @@ def tt_ctx_set_qr(ctx: Ctx, method: str, max_passes: int = 6) -> None:
 
 def tt_ctx_set_enrichment(ctx: Ctx, mode: str) -> None:
     _check(_lib.tt_ctx_set_enrichment(ctx.h, ENRICH[mode]), "tt_ctx_set_enrichment")
+
+
+def tt_ctx_set_fixed(ctx: Ctx, on: bool) -> None:
+    """Fixed shapes (device-side ranks) for this context's tt_round and tt_cross."""
+    _check(_lib.tt_ctx_set_fixed(ctx.h, 1 if on else 0), "tt_ctx_set_fixed")
 
 
 def tt_ctx_set_limits(ctx: Ctx, jacobi_max_sweeps: int, sketch_max_iters: int) -> None:
@@ -486,9 +494,11 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                arena_bytes: int = 4 << 30, precision: str = "f64",
                qr: str = "auto", cross_drop: float = 0.0, eps_rule: str = "fixed",
                c_eps: float = 1.0, bc=None, t0: float = 0.0, terms=(),
-               flux: str = "products", cross_enrich: str = "kicks") -> Solver:
+               flux: str = "products", cross_enrich: str = "kicks",
+               graph: bool = False) -> Solver:
     """bc: per-axis boundary kinds ("periodic", "wall", "exact") overriding `periodic`;
-    terms: separable forcing / ghost terms (see tt_fv_set_terms)."""
+    terms: separable forcing / ghost terms (see tt_fv_set_terms); graph: fixed shapes and a
+    captured HIP graph per step (tt_fv_params.graph)."""
     L = load_library()
     _torch()
     bx, by = (None, None) if bc is None else bc
@@ -496,7 +506,7 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
                 workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop,
                 EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0, FLUXES[flux],
-                ENRICH[cross_enrich])
+                ENRICH[cross_enrich], 1 if graph else 0)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
@@ -553,7 +563,7 @@ def tt_fv_get_stats(s: Solver) -> dict:
             "max_learned_err": st.max_learned_err, "sketch_fallbacks": st.sketch_fallbacks,
             "sketch_unconverged": st.sketch_unconverged, "jacobi_capped": st.jacobi_capped,
             "qr_redos": st.qr_redos, "eps_inner": st.eps_inner,
-            "eps_var": list(st.eps_var), "time": st.time}
+            "eps_var": list(st.eps_var), "time": st.time, "graph_launches": st.graph_launches}
 
 
 def tt_fv_time_kernel(s: Solver, name: Optional[str], every: int = 32) -> None:
