@@ -34,7 +34,8 @@ comparator's step time at each grid size.
 
 Independent chains of TT operations run on several HIP streams (8 workers, plus helper streams
 for the Taylor partial sums); the runtime maps streams to GPU_MAX_HW_QUEUES hardware queues (4
-by default), which would serialise them, so this script raises it to 16 before HIP starts.
+by default), which would serialise them, so this script raises it to 16 before HIP starts (32
+for the graph-mode ensemble, whose members' graphs each replay on a stream of their own).
 """
 import argparse
 import json
@@ -45,7 +46,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-os.environ["GPU_MAX_HW_QUEUES"] = "16"
+# the graph-mode ensemble replays one single-chain graph per member on its own stream: 32
+# hardware queues (measured 8.1e6 against 6.8e6 cell-updates/s with 16 on 64 streams)
+os.environ["GPU_MAX_HW_QUEUES"] = "32" if "--graph" in sys.argv else "16"
 
 METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA peak"
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector
@@ -156,6 +159,15 @@ def main():
                          "columns and Householder TSQR otherwise (auto), or one of the two")
     ap.add_argument("--gemm-autotune", action="store_true",
                     help="ensemble: tune the GEMM tile shapes on a first pass of every member")
+    ap.add_argument("--graph", action="store_true",
+                    help="ensemble: members in graph mode (fixed shapes, each step a replayed "
+                         "HIP graph, launched from one host thread)")
+    ap.add_argument("--graph-streams", type=int, default=0,
+                    help="ensemble --graph: streams the members' graphs are replayed on "
+                         "(0: one per member)")
+    ap.add_argument("--graph-branches", type=int, default=-1,
+                    help="ensemble --graph: branch streams inside each member's graph "
+                         "(-1: one chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB on the device first (a kernel of known traffic that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -520,16 +532,61 @@ def ensemble(args):
             print(f"[ensemble] generated {m + 1}/{M} members", file=sys.stderr, flush=True)
     cells = float(sum(n * n for n in sizes))
 
-    def make(idx, workers):
+    def make(idx, workers, graph=False):
+        if graph:
+            workers = args.graph_branches
         out = []
         for m in idx:
             st, r = states[m], ranks[m]
             dev = [ttfv.DeviceTT.from_factors(f.A, f.B, cap=r) for f in st.tt]
             out.append(ttfv.tt_fv_init(st.n, "upwind5", True, True, dev, g=st.g, eps=1e-10,
                                        r_max=r, taylor_terms=8, workers=workers,
-                                       arena_bytes=1 << 28, precision=args.precision,
-                                       qr=args.qr))
+                                       arena_bytes=(1 << 29) if graph else (1 << 28),
+                                       precision=args.precision, qr=args.qr, graph=graph))
         return out
+
+    graph = None
+    if args.graph:
+        # graph mode: every member's step captured in a HIP graph (after one eager step), the
+        # graphs replayed on `conc` streams from one host thread; the first tt_ens_step call
+        # (eager step + capture + one replay) is warm-up
+        gens = ttfv.tt_ens_create(workers=1, arena_bytes_per_worker=1 << 24)
+        gconc = args.graph_streams if args.graph_streams > 0 else M
+        gm = make(range(M), -1, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ttfv.tt_ens_step(gens, gm, [st.dt for st in states], 2, gconc)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
+        print(f"[ensemble] graph warm-up (eager step, capture, one replay) {t_prep:.1f} s",
+              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ttfv.tt_ens_step(gens, gm, [st.dt for st in states], args.steps, gconc)
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t0) / args.steps
+        gstats = [ttfv.tt_fv_get_stats(s) for s in gm]
+        for s in gm:
+            s.close()
+        # members equal to themselves stepped alone (graph mode, three steps), bit for bit
+        alone_g = make(range(min(4, M)), -1, graph=True)
+        for m, s in enumerate(alone_g):
+            ttfv.tt_fv_step(s, states[m].dt, 3)
+        refg = [[q.full() for q in ttfv.tt_fv_get_state(s)] for s in alone_g]
+        for s in alone_g:
+            s.close()
+        g4 = make(range(min(4, M)), -1, graph=True)
+        ttfv.tt_ens_step(gens, g4, [states[m].dt for m in range(len(g4))], 3, gconc)
+        same_g = all(np.array_equal(q.full(), r) for s, rr in zip(g4, refg)
+                     for q, r in zip(ttfv.tt_fv_get_state(s), rr))
+        for s in g4:
+            s.close()
+        gens.close()
+        graph = {"value": cells / t_graph, "ms_per_step": t_graph * 1e3, "streams": gconc,
+                 "branches": args.graph_branches,
+                 "warmup_s": t_prep, "members_equal_alone": bool(same_g),
+                 "graph_launches": int(sum(g["graph_launches"] for g in gstats)),
+                 "warnings_or": int(np.bitwise_or.reduce([g["warnings"] for g in gstats]))}
+        print(f"[ensemble] graph {graph}", file=sys.stderr, flush=True)
 
     tune = None
     if args.gemm_autotune:
@@ -598,6 +655,18 @@ def ensemble(args):
            "sequential": {"value": cells / t_seq, "s_per_step": t_seq},
            "speedup_vs_sequential": t_seq / t_ens, "members_equal_alone": bool(same),
            "gemm_autotune": tune}
+    if graph:
+        # the graph ensemble is the line's value; the shared-pool ensemble stays beside it
+        out["pool_ensemble"] = {"value": out["value"], "ms_per_step": out["ms_per_step"],
+                                "autotuned": {"workers": workers, "concurrency": conc},
+                                "members_equal_alone": bool(same)}
+        out["value"] = graph["value"]
+        out["ms_per_step"] = graph["ms_per_step"]
+        out["speedup_vs_sequential"] = t_seq / (graph["ms_per_step"] / 1e3)
+        out["speedup_vs_pool_ensemble"] = t_ens / (graph["ms_per_step"] / 1e3)
+        out["members_equal_alone"] = graph["members_equal_alone"]
+        out["graph"] = graph
+        out["config"]["graph"] = {"streams": graph["streams"]}
     print(json.dumps(out), flush=True)
 
 

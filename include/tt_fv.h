@@ -275,9 +275,14 @@ typedef struct {
                          captured on the solver's stream (again after a change of dt) and
                          every later step replays the graph, with no host round trip.  Needs
                          Upwind3/5, TT_EPS_FIXED, TT_FLUX_PRODUCTS, seeded kicks, no exact
-                         boundaries or terms, n > 2 r_max; `workers` is ignored (one stream).
+                         boundaries or terms, n > 2 r_max.  `workers` sets the branch
+                         streams the independent tasks of a phase fork onto inside the
+                         graph (0: 4; -1, a member for tt_ens_step: 1, one chain).
                          Results equal the dynamic path's up to round-off where the range
                          finder's extra iterations are not needed.  0: off.                */
+  int graph_iters;    /* graph mode: subspace iterations of every randomized rounding;
+                         0 = 2 with FP64 contractions, 1 with FP32 (whose own rounding
+                         error is above what the second iteration removes)                 */
 } tt_fv_params;
 #define TT_FLUX_PRODUCTS 0
 #define TT_FLUX_LF_CROSS 1

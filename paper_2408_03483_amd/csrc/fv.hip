@@ -126,11 +126,25 @@ struct Solver {
   long long graph_launches = 0;
   hipStream_t own_stream = nullptr;   // graph mode: the solver's stream (capturable)
   hipStream_t user_stream = nullptr;  // the stream given at init
+  // graph mode: branch contexts (own stream and arena each) the independent tasks of a phase
+  // fork onto from the solver's stream and join back, by events, so that a captured step
+  // keeps the phases' concurrency as parallel branches of its graph
+  std::vector<std::unique_ptr<Ctx>> branch;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
 
   ~Solver() {
     if (gexec || graph) (void)hipStreamSynchronize(c.stream);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (auto &b : branch) {
+      hipStream_t st = b->stream;
+      (void)hipStreamSynchronize(st);
+      b.reset();
+      (void)hipStreamDestroy(st);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
     if (own_stream) {
       (void)hipStreamSynchronize(own_stream);
       c.stream = user_stream;   // the context's own clean-up must not see the destroyed stream
@@ -173,10 +187,27 @@ struct Solver {
         w.enrich = enrich;
         f(w);
       };
-    if (p.graph) {                // one stream: the tasks in order, temporaries per task
-      for (auto &t : tasks) {
-        Scope sc(c.arena);
-        t(c);
+    if (p.graph) {
+      const int K = std::min((int)branch.size(), (int)tasks.size());
+      if (K <= 1) {               // one stream: the tasks in order, temporaries per task
+        for (auto &t : tasks) {
+          Scope sc(c.arena);
+          t(c);
+        }
+        return;
+      }
+      // fork: the branches wait for the solver's stream; task i runs on branch i mod K, in
+      // that branch's arena; join: the solver's stream waits for every branch used
+      HIP_CHECK(hipEventRecord(fork_ev, c.stream));
+      for (int b = 0; b < K; ++b) HIP_CHECK(hipStreamWaitEvent(branch[b]->stream, fork_ev, 0));
+      for (size_t i = 0; i < tasks.size(); ++i) {
+        Ctx &w = *branch[i % K];
+        Scope sc(w.arena);
+        tasks[i](w);
+      }
+      for (int b = 0; b < K; ++b) {
+        HIP_CHECK(hipEventRecord(join_ev[b], branch[b]->stream));
+        HIP_CHECK(hipStreamWaitEvent(c.stream, join_ev[b], 0));
       }
       return;
     }
@@ -910,6 +941,31 @@ struct Solver {
     t += dt;
   }
 
+  // the host counters of the solver's context and its branches, summed
+  Counters all_counters() const {
+    Counters t = c.cnt;
+    for (auto &b : branch) {
+      const Counters &w = b->cnt;
+      t.roundings += w.roundings;
+      t.crosses += w.crosses;
+      t.flops += w.flops;
+      t.bytes += w.bytes;
+      t.warnings |= w.warnings;
+    }
+    return t;
+  }
+
+  void set_capturing(bool on) {
+    c.capturing = on;
+    for (auto &b : branch) b->capturing = on;
+  }
+
+  int fixed_status_all() {
+    int w = fixed_status(c);
+    for (auto &b : branch) w |= fixed_status(*b);
+    return w;
+  }
+
   void capture(double dt) {
     if (gexec) {
       HIP_CHECK(hipStreamSynchronize(c.stream));
@@ -920,32 +976,39 @@ struct Solver {
       (void)hipGraphDestroy(graph);
       graph = nullptr;
     }
-    const Counters before = c.cnt;
+    std::vector<Counters> saved{c.cnt};
+    for (auto &b : branch) saved.push_back(b->cnt);
+    const Counters before = all_counters();
+    auto restore = [&]() {
+      c.cnt = saved[0];
+      for (size_t b = 0; b < branch.size(); ++b) branch[b]->cnt = saved[b + 1];
+    };
     const long long sw = sweeps_run;
     const size_t mark = c.arena.mark();
     hipGraph_t g = nullptr;
     HIP_CHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeRelaxed));
-    c.capturing = true;
+    set_capturing(true);
     try {
       step_body(dt);
     } catch (...) {
-      c.capturing = false;
+      set_capturing(false);
       if (hipStreamEndCapture(c.stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
-      c.cnt = before;
+      restore();
       sweeps_run = sw;
       throw;
     }
-    c.capturing = false;
+    set_capturing(false);
     HIP_CHECK(hipStreamEndCapture(c.stream, &g));
     graph = g;
     HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    const Counters after = all_counters();
     graph_cnt = Counters{};
-    graph_cnt.roundings = c.cnt.roundings - before.roundings;
-    graph_cnt.crosses = c.cnt.crosses - before.crosses;
-    graph_cnt.flops = c.cnt.flops - before.flops;
-    graph_cnt.bytes = c.cnt.bytes - before.bytes;
+    graph_cnt.roundings = after.roundings - before.roundings;
+    graph_cnt.crosses = after.crosses - before.crosses;
+    graph_cnt.flops = after.flops - before.flops;
+    graph_cnt.bytes = after.bytes - before.bytes;
     graph_sweeps = sweeps_run - sw;
-    c.cnt = before;
+    restore();
     sweeps_run = sw;
     graph_dt = dt;
     graph_mark = mark;
@@ -1069,6 +1132,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
   TT_REQUIRE(p->scheme != 55 || (p->cross_sweeps >= 1 && p->cross_kick >= 0),
              "tt_fv_init: bad cross parameters");
   TT_REQUIRE(p->graph == 0 || p->graph == 1, "tt_fv_init: graph must be 0 or 1");
+  TT_REQUIRE(p->graph_iters >= 0 && p->graph_iters <= 8, "tt_fv_init: graph_iters in [0, 8]");
   if (p->graph) {
     // every decision of these paths has a device-side form; the others read the host
     TT_REQUIRE(p->scheme == 3 || p->scheme == 5, "graph mode: Upwind3 or Upwind5 only");
@@ -1111,7 +1175,30 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
       s->c.householder = true;   // no host-side check of a Cholesky QR in a graph
       // the range finder cannot add iterations on demand: two subspace iterations keep the
       // leak of the discarded directions at the dynamic path's level at a binding rank cap
-      s->c.power_iters = 2;
+      const int gi = p->graph_iters > 0 ? p->graph_iters : (s->c.fp32 ? 1 : 2);
+      s->c.power_iters = gi;
+      // branches: 4 by default; a member made for an ensemble (workers = -1) keeps one chain,
+      // since graphs with branches replayed side by side do not overlap each other, while
+      // single-chain graphs on their own streams do (measured)
+      const int nb = p->workers > 0 ? p->workers : p->workers == 0 ? 4 : 1;
+      // split-K arrival counters now: their first use must not put a memset into a graph
+      (void)s->c.tile_counters();
+      if (nb > 1) {
+        HIP_CHECK(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
+        for (int b = 0; b < nb; ++b) {
+          auto w = std::make_unique<Ctx>();
+          HIP_CHECK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+          w->arena.init(std::max(ab / 2, (size_t)64 << 20));
+          w->fixed = true;
+          w->householder = true;
+          w->power_iters = gi;
+          (void)w->tile_counters();
+          s->branch.push_back(std::move(w));
+          hipEvent_t e;
+          HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+          s->join_ev.push_back(e);
+        }
+      }
       s->site_cap = p->r_max;
       s->site_have.assign(Solver::kSites, 0);
       s->site_J = s->c.arena.ialloc((size_t)Solver::kSites * (s->site_cap + 1));
@@ -1205,7 +1292,7 @@ void solver_step(Solver *s, double dt, int nsteps) {
   TT_REQUIRE(s->exec || s->p.graph,
              "tt_fv_step: solver made with workers = -1 steps only inside an ensemble");
   for (int k = 0; k < nsteps; ++k) s->step(dt);
-  if (s->p.graph) fixed_status(s->c);
+  if (s->p.graph) s->fixed_status_all();
 }
 
 // ---- ensemble: members share one pool; host threads take members in cost order --------
@@ -1221,9 +1308,9 @@ struct Ensemble {
 };
 
 // Graph mode: each member's first step runs eagerly and its next step is captured, on
-// `concurrency` host threads (members on their own streams); then one host thread launches
-// every member's graph for the remaining steps, each member on one of `concurrency` streams
-// chosen longest-processing-time first, with no host round trip until the end.
+// `concurrency` host threads (members on their own streams); then every member's graph is
+// launched for the remaining steps on one of `concurrency` streams (chosen longest-processing-
+// time first), one host thread per stream, with no host round trip until the end.
 void ensemble_step_graph(Ensemble *e, Solver *const *members, int count, const double *dts,
                          int nsteps, int concurrency) {
   std::vector<int> order(count), rem(count, nsteps);
@@ -1289,25 +1376,44 @@ void ensemble_step_graph(Ensemble *e, Solver *const *members, int count, const d
     sid[i] = k;
     load[k] += cost(i);
   }
-  int most = 0;
-  for (int i = 0; i < count; ++i) most = std::max(most, rem[i]);
-  for (int k = 0; k < most; ++k)
-    for (int i : order) {
-      if (k >= rem[i]) continue;
-      Solver *m = members[i];
-      HIP_CHECK(hipGraphLaunch(m->gexec, e->gstreams[sid[i]]));
-      ++m->graph_launches;
-      const Counters &g = m->graph_cnt;
-      m->c.cnt.roundings += g.roundings;
-      m->c.cnt.crosses += g.crosses;
-      m->c.cnt.flops += g.flops;
-      m->c.cnt.bytes += g.bytes;
-      m->sweeps_run += m->graph_sweeps;
-      ++m->step_index;
-      m->t += dts[i];
-    }
-  for (int k = 0; k < ns; ++k) HIP_CHECK(hipStreamSynchronize(e->gstreams[k]));
-  for (int i = 0; i < count; ++i) fixed_status(members[i]->c);
+  // one host thread per stream launches its members' graphs, step by step
+  {
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> errs(ns);
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    for (int k = 0; k < ns; ++k)
+      th.emplace_back([&, k, dev]() {
+        (void)hipSetDevice(dev);
+        try {
+          int most = 0;
+          for (int i : order)
+            if (sid[i] == k) most = std::max(most, rem[i]);
+          for (int step = 0; step < most; ++step)
+            for (int i : order) {
+              if (sid[i] != k || step >= rem[i]) continue;
+              Solver *m = members[i];
+              HIP_CHECK(hipGraphLaunch(m->gexec, e->gstreams[k]));
+              ++m->graph_launches;
+              const Counters &g = m->graph_cnt;
+              m->c.cnt.roundings += g.roundings;
+              m->c.cnt.crosses += g.crosses;
+              m->c.cnt.flops += g.flops;
+              m->c.cnt.bytes += g.bytes;
+              m->sweeps_run += m->graph_sweeps;
+              ++m->step_index;
+              m->t += dts[i];
+            }
+          HIP_CHECK(hipStreamSynchronize(e->gstreams[k]));
+        } catch (...) {
+          errs[k] = std::current_exception();
+        }
+      });
+    for (auto &t : th) t.join();
+    for (auto &x : errs)
+      if (x) std::rethrow_exception(x);
+  }
+  for (int i = 0; i < count; ++i) members[i]->fixed_status_all();
 }
 
 Ensemble *ensemble_create(int workers, size_t arena_bytes) {
@@ -1409,7 +1515,7 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
     HIP_CHECK(hipMemcpyAsync(o->ranks, rk, 3 * sizeof(int), hipMemcpyDeviceToHost, s->c.stream));
     HIP_CHECK(hipStreamSynchronize(s->c.stream));
     for (int v = 0; v < 3; ++v) o->ranks[v] = std::max(o->ranks[v], 1);
-    s->c.cnt.warnings |= fixed_status(s->c);
+    s->c.cnt.warnings |= s->fixed_status_all();
   }
   Counters t = s->c.cnt;
   const int npool = s->pool ? s->pool->size() : 0;
@@ -1417,7 +1523,9 @@ void solver_stats(Solver *s, tt_fv_stats *o) {
   for (int i = 0; i < npool; ++i) cs.push_back(&s->pool->ctx(i).cnt);
   for (auto &a : s->aux)
     if (a) cs.push_back(&a->cnt);
+  for (auto &b : s->branch) cs.push_back(&b->cnt);
   long long jcap = s->c.jacobi_capped();
+  for (auto &b : s->branch) jcap += b->jacobi_capped();
   for (int i = 0; i < npool; ++i) jcap += s->pool->ctx(i).jacobi_capped();
   for (auto &a : s->aux)
     if (a) jcap += a->jacobi_capped();

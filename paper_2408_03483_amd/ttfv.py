@@ -46,7 +46,7 @@ class ParamsC(ctypes.Structure):
                 ("eps_rule", ctypes.c_int), ("c_eps", ctypes.c_double),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("t0", ctypes.c_double),
                 ("flux", ctypes.c_int), ("cross_enrich", ctypes.c_int),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("graph_iters", ctypes.c_int)]
 
 
 class TensorC(ctypes.Structure):
@@ -495,7 +495,7 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                qr: str = "auto", cross_drop: float = 0.0, eps_rule: str = "fixed",
                c_eps: float = 1.0, bc=None, t0: float = 0.0, terms=(),
                flux: str = "products", cross_enrich: str = "kicks",
-               graph: bool = False) -> Solver:
+               graph: bool = False, graph_iters: int = 0) -> Solver:
     """bc: per-axis boundary kinds ("periodic", "wall", "exact") overriding `periodic`;
     terms: separable forcing / ghost terms (see tt_fv_set_terms); graph: fixed shapes and a
     captured HIP graph per step (tt_fv_params.graph)."""
@@ -506,7 +506,7 @@ def tt_fv_init(n: int, scheme: str, nonlinear: bool, periodic: bool, q0: Sequenc
                 r_max, taylor_terms, cross_sweeps, cross_kick, 1 if recip == "cross" else 0,
                 workers, PRECISIONS[precision], QR_METHODS[qr], cross_drop,
                 EPS_RULES[eps_rule], c_eps, BCS[bx], BCS[by], t0, FLUXES[flux],
-                ENRICH[cross_enrich], 1 if graph else 0)
+                ENRICH[cross_enrich], 1 if graph else 0, graph_iters)
     arr = (TTMatrixC * 3)(*[t.c() for t in q0])
     h = ctypes.c_void_p()
     _check(L.tt_fv_init(ctypes.byref(h), ctypes.byref(p), arr, _stream_ptr(stream), arena_bytes),
