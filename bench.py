@@ -576,14 +576,17 @@ def ensemble(args):
             s.close()
         g4 = make(range(min(4, M)), -1, graph=True)
         ttfv.tt_ens_step(gens, g4, [states[m].dt for m in range(len(g4))], 3, gconc)
-        same_g = all(np.array_equal(q.full(), r) for s, rr in zip(g4, refg)
-                     for q, r in zip(ttfv.tt_fv_get_state(s), rr))
+        got_g = [[q.full() for q in ttfv.tt_fv_get_state(s)] for s in g4]
+        same_g = all(np.array_equal(a, b) for x, y in zip(got_g, refg) for a, b in zip(x, y))
+        diff_g = max(float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+                     for x, y in zip(got_g, refg) for a, b in zip(x, y))
         for s in g4:
             s.close()
         gens.close()
         graph = {"value": cells / t_graph, "ms_per_step": t_graph * 1e3, "streams": gconc,
                  "branches": args.graph_branches,
                  "warmup_s": t_prep, "members_equal_alone": bool(same_g),
+                 "max_rel_diff_alone": diff_g,
                  "graph_launches": int(sum(g["graph_launches"] for g in gstats)),
                  "warnings_or": int(np.bitwise_or.reduce([g["warnings"] for g in gstats]))}
         print(f"[ensemble] graph {graph}", file=sys.stderr, flush=True)

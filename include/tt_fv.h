@@ -264,22 +264,24 @@ typedef struct {
   int graph;          /* 1: fixed shapes captured in a HIP graph.  Every decision the step
                          otherwise takes on the host is taken on the device: a rounding's
                          kept rank (the same rule; the TT keeps the static rank min(r_max, m)
-                         of its buffer with zero columns after the device's rank), a cross's
-                         kept directions, maxvol rows and seeded kicks (column sets stay on
-                         the device per site), the Taylor reciprocal's stop (all
+                         of its buffer, zero columns after the device's rank), a cross's kept
+                         directions, maxvol rows and seeded kicks (column sets stay on the
+                         device per cross site), the Taylor reciprocal's stop (all
                          taylor_terms terms are formed; those after the first with
-                         Err <= eps enter times zero), the range finder's iteration count
-                         (exactly max(1, power iterations); TT_WSKETCH when its stopping test
-                         fails).  The first tt_fv_step step runs eagerly and sets the static
-                         ranks and the cross sites' starting columns; the next step is
-                         captured on the solver's stream (again after a change of dt) and
-                         every later step replays the graph, with no host round trip.  Needs
-                         Upwind3/5, TT_EPS_FIXED, TT_FLUX_PRODUCTS, seeded kicks, no exact
-                         boundaries or terms, n > 2 r_max.  `workers` sets the branch
-                         streams the independent tasks of a phase fork onto inside the
-                         graph (0: 4; -1, a member for tt_ens_step: 1, one chain).
-                         Results equal the dynamic path's up to round-off where the range
-                         finder's extra iterations are not needed.  0: off.                */
+                         Err <= eps enter times zero).  Inputs of rank <= 96 are rounded
+                         exactly, larger ones by the range finder with graph_iters subspace
+                         iterations (TT_WSKETCH when its stopping test fails).  The first
+                         tt_fv_step step runs eagerly and sets the static ranks and the cross
+                         sites' starting columns (with the GEMM tile autotuner on, a second
+                         eager step tunes the static shapes); the next step is captured on
+                         the solver's own stream (again after a change of dt) and every later
+                         step replays the graph, with no host round trip.  Needs Upwind3/5,
+                         TT_EPS_FIXED, TT_FLUX_PRODUCTS, seeded kicks, no exact boundaries or
+                         terms, n > 2 r_max.  `workers` sets the branch streams the
+                         independent tasks of a phase fork onto inside the graph (0: 4; -1, a
+                         member for tt_ens_step: 1, one chain).  Results equal the dynamic
+                         path's up to what the fixed iteration count leaves of the range
+                         finder's leak.  0: off.                                            */
   int graph_iters;    /* graph mode: subspace iterations of every randomized rounding;
                          0 = 2 with FP64 contractions, 1 with FP32 (whose own rounding
                          error is above what the second iteration removes)                 */

@@ -217,6 +217,7 @@ void gemm2(Ctx &c, bool transA, bool transB, int M, int N, int K, double alpha, 
 size_t gemm_arena_bytes(int M, int N, int K);
 // tile-shape autotuner of the GEMMs (process-wide; off by default)
 void gemm_autotune(bool on);
+bool gemm_autotune_on();
 int gemm_tuned_classes();
 
 // tsqr.hip: Q (n x m, ldq) and R (m x m, ldr) of Y (n x m, n >= m, m <= 96); Q == nullptr

@@ -116,7 +116,9 @@ struct Solver {
   int site_cap = 0;
   static constexpr int kSites = 6 << 6;
   std::vector<char> site_have;
-  bool warm = false;              // an eager fixed-shape step has set the static ranks
+  bool warm = false;              // eager fixed-shape steps have set the static ranks (and,
+                                  // with the GEMM autotuner on, tuned the static shapes)
+  int eager_steps = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double graph_dt = 0.0;
@@ -126,6 +128,16 @@ struct Solver {
   long long graph_launches = 0;
   hipStream_t own_stream = nullptr;   // graph mode: the solver's stream (capturable)
   hipStream_t user_stream = nullptr;  // the stream given at init
+  hipEvent_t user_ev = nullptr;
+
+  // graph mode: the solver's own (non-blocking) stream does not wait for the caller's, which
+  // may be the null stream; calls that read or write caller memory first order it after the
+  // caller's stream
+  void after_user() {
+    if (!own_stream) return;
+    HIP_CHECK(hipEventRecord(user_ev, user_stream));
+    HIP_CHECK(hipStreamWaitEvent(own_stream, user_ev, 0));
+  }
   // graph mode: branch contexts (own stream and arena each) the independent tasks of a phase
   // fork onto from the solver's stream and join back, by events, so that a captured step
   // keeps the phases' concurrency as parallel branches of its graph
@@ -144,6 +156,7 @@ struct Solver {
       (void)hipStreamDestroy(st);
     }
     if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (user_ev) (void)hipEventDestroy(user_ev);
     for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
     if (own_stream) {
       (void)hipStreamSynchronize(own_stream);
@@ -925,7 +938,9 @@ struct Solver {
       step_body(dt);
       ++step_index;
       t += dt;
-      warm = true;
+      // one eager step sets the static ranks; a second one at those shapes lets the GEMM
+      // tile autotuner (when on) time every shape class the captured step will meet
+      warm = ++eager_steps >= (gemm_autotune_on() ? 2 : 1);
       return;
     }
     if (!gexec || dt != graph_dt || c.arena.mark() != graph_mark) capture(dt);
@@ -1170,6 +1185,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
       HIP_CHECK(hipStreamSynchronize(s->c.stream));
       s->user_stream = s->c.stream;
       HIP_CHECK(hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking));
+      HIP_CHECK(hipEventCreateWithFlags(&s->user_ev, hipEventDisableTiming));
       s->c.stream = s->own_stream;
       s->c.fixed = true;
       s->c.householder = true;   // no host-side check of a Cholesky QR in a graph
@@ -1291,6 +1307,7 @@ void solver_step(Solver *s, double dt, int nsteps) {
   TT_REQUIRE(nsteps >= 0 && std::isfinite(dt), "tt_fv_step: bad dt or nsteps");
   TT_REQUIRE(s->exec || s->p.graph,
              "tt_fv_step: solver made with workers = -1 steps only inside an ensemble");
+  s->after_user();
   for (int k = 0; k < nsteps; ++k) s->step(dt);
   if (s->p.graph) s->fixed_status_all();
 }
@@ -1336,7 +1353,7 @@ void ensemble_step_graph(Ensemble *e, Solver *const *members, int count, const d
         try {
           Solver *m = members[idx];
           TT_REQUIRE(std::isfinite(dts[idx]), "tt_ens_step: bad dt");
-          if (rem[idx] > 0 && !m->warm) {
+          while (rem[idx] > 0 && !m->warm) {
             m->step_graph(dts[idx]);
             --rem[idx];
           }
@@ -1491,6 +1508,7 @@ void ensemble_step(Ensemble *e, Solver *const *members, int count, const double 
 }
 
 void solver_get_state(Solver *s, tt_matrix q[3]) {
+  s->after_user();   // the caller's buffers may still be written on its stream
   for (int v = 0; v < 3; ++v) {
     TT_REQUIRE(q[v].n1 == s->n && q[v].n2 == s->n && q[v].cap >= s->Q[v].r,
                "tt_fv_get_state: output too small");

@@ -284,6 +284,8 @@ TileChoice tuned_tiles(Ctx &c, bool transA, bool transB, int M, int N, int K, do
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
   }
+  // under graph capture nothing can be timed: a class not tuned yet takes the fixed rule
+  if (c.capturing) return default_tiles(N);
   std::vector<TileChoice> cand;
   for (int bn2 : {64, 128}) {
     if (bn2 == 128 && N <= 64) continue;
@@ -334,6 +336,7 @@ size_t gemm_arena_bytes(int M, int N, int K) {
 }
 
 void gemm_autotune(bool on) { g_tune = on; }
+bool gemm_autotune_on() { return g_tune; }
 
 int gemm_tuned_classes() {
   std::lock_guard<std::mutex> lk(g_tune_mu);

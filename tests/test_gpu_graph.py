@@ -225,3 +225,18 @@ def test_graph_ensemble_equals_members_alone(lib):
             assert np.array_equal(a, b)
         s.close()
     ens.close()
+
+
+def test_graph_state_reads_follow_the_callers_stream(lib):
+    """The solver's graph stream is its own; reading the state into buffers just made (and
+    zero-filled) on the caller's stream must see the state every time."""
+    _say("graph state reads")
+    st = synth.nonlinear_bumps(seed=5, n=128, rmax=16, eps=1e-10)
+    s = _solver(lib, st, 16, True)
+    lib.tt_fv_step(s, st.dt, 3)
+    first = [q.full() for q in lib.tt_fv_get_state(s)]
+    for _ in range(20):
+        got = [q.full() for q in lib.tt_fv_get_state(s)]
+        for a, b in zip(got, first):
+            assert np.array_equal(a, b)
+    s.close()
