@@ -34,8 +34,8 @@ comparator's step time at each grid size.
 
 Independent chains of TT operations run on several HIP streams (8 workers, plus helper streams
 for the Taylor partial sums); the runtime maps streams to GPU_MAX_HW_QUEUES hardware queues (4
-by default), which would serialise them, so this script raises it to 16 before HIP starts (32
-for the graph-mode ensemble, whose members' graphs each replay on a stream of their own).
+by default), which would serialise them, so this script raises it to 16 before HIP starts
+(--hw-queues sets another count for the whole run).
 """
 import argparse
 import json
@@ -46,9 +46,15 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# the graph-mode ensemble replays one single-chain graph per member on its own stream: 32
-# hardware queues (measured 8.1e6 against 6.8e6 cell-updates/s with 16 on 64 streams)
-os.environ["GPU_MAX_HW_QUEUES"] = "32" if "--graph" in sys.argv else "16"
+# hardware queues for every leg of a run (--hw-queues N, read before HIP starts): 16 by default;
+# 32 suits the graph-mode ensemble alone but slows the dynamic legs it is compared with
+_hwq = "16"
+for _i, _a in enumerate(sys.argv):
+    if _a == "--hw-queues" and _i + 1 < len(sys.argv):
+        _hwq = sys.argv[_i + 1]
+    elif _a.startswith("--hw-queues="):
+        _hwq = _a.split("=", 1)[1]
+os.environ["GPU_MAX_HW_QUEUES"] = _hwq
 
 METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA peak"
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector
@@ -162,6 +168,11 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="ensemble: members in graph mode (fixed shapes, each step a replayed "
                          "HIP graph, launched from one host thread)")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="ensemble --graph: only the graph leg (no one-at-a-time or pool "
+                         "ensemble legs; for kernel profiles)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for the whole run (read before HIP starts)")
     ap.add_argument("--graph-streams", type=int, default=0,
                     help="ensemble --graph: streams the members' graphs are replayed on "
                          "(0: one per member)")
@@ -546,6 +557,9 @@ def ensemble(args):
         return out
 
     graph = None
+    if args.gemm_autotune:
+        # graph members tune their static shapes in a second eager step (see tt_fv_params)
+        ttfv.tt_gemm_autotune(True)
     if args.graph:
         # graph mode: every member's step captured in a HIP graph (after one eager step), the
         # graphs replayed on `conc` streams from one host thread; the first tt_ens_step call
@@ -555,7 +569,9 @@ def ensemble(args):
         gm = make(range(M), -1, graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ttfv.tt_ens_step(gens, gm, [st.dt for st in states], 2, gconc)
+        # warm-up: the eager step(s) (two with the tile autotuner), the capture, one replay
+        nwarm = 3 if args.gemm_autotune else 2
+        ttfv.tt_ens_step(gens, gm, [st.dt for st in states], nwarm, gconc)
         torch.cuda.synchronize()
         t_prep = time.perf_counter() - t0
         print(f"[ensemble] graph warm-up (eager step, capture, one replay) {t_prep:.1f} s",
@@ -603,6 +619,19 @@ def ensemble(args):
         torch.cuda.synchronize()
         tune = {"classes": ttfv.tt_gemm_autotune(True), "s": time.perf_counter() - t0}
         print(f"[ensemble] GEMM tiles tuned: {tune}", file=sys.stderr, flush=True)
+    if graph and args.graph_only:
+        out = {"metric": METRIC, "value": graph["value"], "unit": "cell-updates/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": 3 if args.gemm_autotune else 2,
+               "ms_per_step": graph["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": args.precision,
+               "data": "synthetic",
+               "config": {"workload": f"ensemble_{M}", "members": M, "sizes": sizes,
+                          "r_max": ranks, "eps": 1e-10, "scheme": "upwind5",
+                          "graph": {"streams": graph["streams"]},
+                          "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
+               "members_equal_alone": graph["members_equal_alone"], "graph": graph}
+        print(json.dumps(out), flush=True)
+        return
     # members one at a time (each with its own worker streams)
     alone = make(range(M), 0)
     torch.cuda.synchronize()
@@ -670,6 +699,7 @@ def ensemble(args):
         out["members_equal_alone"] = graph["members_equal_alone"]
         out["graph"] = graph
         out["config"]["graph"] = {"streams": graph["streams"]}
+    out["config"]["hw_queues"] = int(os.environ["GPU_MAX_HW_QUEUES"])
     print(json.dumps(out), flush=True)
 
 
