@@ -240,3 +240,33 @@ def test_graph_state_reads_follow_the_callers_stream(lib):
         for a, b in zip(got, first):
             assert np.array_equal(a, b)
     s.close()
+
+
+def test_graph_ensemble_member_512_cap40_fp32_vs_oracle(lib):
+    """An ensemble member at the batched configuration's real shape (512^2, rank cap 40, FP32
+    contractions, Upwind5, Taylor 8 terms, tol 1e-10) stepped in a graph ensemble beside a
+    small member: an eager step and a replayed graph, within the FP32 bar of 1e-4 of the FP64
+    oracle per field."""
+    _say("graph ensemble member 512 cap 40 fp32 vs oracle")
+    big = synth.nonlinear_bumps(seed=1000, n=512, rmax=40, eps=1e-10)
+    small = synth.nonlinear_bumps(seed=1001, n=256, rmax=12, eps=1e-10)
+    mem = []
+    for st, r in ((big, 40), (small, 12)):
+        dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=r) for f in st.tt]
+        mem.append(lib.tt_fv_init(st.n, "upwind5", True, True, dev, g=st.g, H0=st.H0, eps=1e-10,
+                                  r_max=r, workers=-1, arena_bytes=1 << 29, precision="f32",
+                                  graph=True))
+    ens = lib.tt_ens_create(workers=1, arena_bytes_per_worker=1 << 24)
+    lib.tt_ens_step(ens, mem, [big.dt, small.dt], nsteps=2, concurrency=2)
+    Qg = [q.full() for q in lib.tt_fv_get_state(mem[0])]
+    stats = lib.tt_fv_get_stats(mem[0])
+    for s in mem:
+        s.close()
+    ens.close()
+    ts = otf.TTSolver(big.n, "upwind5", True, True, g=big.g, H=big.H0, eps=1e-10, rmax=40,
+                      taylor_terms=8)
+    Qo = [q.full() for q in ts.run([ott.TT(f.A, f.B) for f in big.tt], big.dt, 2)]
+    r = [rel(a, b) for a, b in zip(Qg, Qo)]
+    _say(f"  rel {r} ranks {stats['ranks']} launches {stats['graph_launches']}")
+    assert stats["graph_launches"] == 1 and stats["steps"] == 2
+    assert max(r) <= 1e-4
