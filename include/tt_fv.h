@@ -15,7 +15,12 @@
  *     after the stream has been synchronised: ranks chosen on the device are read back
  *     to set tt_matrix.rank.  Outputs may not alias inputs.
  *   - Temporary device memory comes from the context's arena, allocated once by
- *     tt_ctx_create / tt_fv_init; no entry point below allocates device memory.
+ *     tt_ctx_create / tt_fv_init (tt_ens_create for an ensemble's workers), which also
+ *     make the split-K arrival counters, the pinned staging buffer of small read-backs and
+ *     the events a context uses; rounding, cross, reciprocal and step calls allocate no
+ *     device or pinned memory and create no event.  The exceptions are opt-in: kernel
+ *     timing (tt_fv_time_kernel) and the GEMM tile autotuner (tt_gemm_autotune) create
+ *     events as they measure.
  *   - Return value: 0 on success, a negative TT_E* code on error (outputs untouched
  *     or partially written), or a positive bitmask of TT_W* warnings.
  *     tt_last_error() gives a message for the last failure in the calling thread.

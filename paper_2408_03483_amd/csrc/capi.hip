@@ -131,6 +131,19 @@ int *Ctx::tile_counters() {
   return tile_cnt;
 }
 
+void Ctx::prepare(int term_events) {
+  if (no_alloc) return;
+  (void)tile_counters();
+  (void)pinned_staging();
+  if (!sync_ev) HIP_CHECK(hipEventCreateWithFlags(&sync_ev, hipEventDisableTiming));
+  while ((int)term_ev.size() < term_events) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    term_ev.push_back(e);
+  }
+  HIP_CHECK(hipStreamSynchronize(stream));
+}
+
 double *Ctx::pinned_staging() {
   if (no_alloc) return nullptr;
   if (!pinned) HIP_CHECK(hipHostMalloc((void **)&pinned, kPinnedDoubles * sizeof(double)));
@@ -140,6 +153,7 @@ double *Ctx::pinned_staging() {
 Ctx::~Ctx() {
   if (tile_cnt || pinned) (void)hipStreamSynchronize(stream);
   if (sync_ev) (void)hipEventDestroy(sync_ev);
+  for (hipEvent_t e : term_ev) (void)hipEventDestroy(e);
   if (tile_cnt && !no_alloc) (void)hipFree(tile_cnt);
   if (pinned) (void)hipHostFree(pinned);
   for (auto &e : timer.spare) {
@@ -350,6 +364,7 @@ int tt_ctx_create(tt_ctx **out, size_t arena_bytes, void *hip_stream) {
     try {
       c->c.stream = (hipStream_t)hip_stream;
       c->c.arena.init(arena_bytes);
+      c->c.prepare();
     } catch (...) {
       delete c;
       throw;

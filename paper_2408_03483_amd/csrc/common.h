@@ -144,6 +144,13 @@ struct Ctx {
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   static constexpr size_t kPinnedDoubles = 4096;
   double *pinned_staging(); // allocates it on first use (nullptr in a no_alloc context)
+  // events of the Taylor partial sums handed to a helper context, one per term
+  std::vector<hipEvent_t> term_ev;
+  static constexpr int kTermEvents = 64;
+  // allocates now what the context would otherwise allocate on first use (split-K counters,
+  // pinned staging, the sync event, the term events), so that rounding, cross and step
+  // calls allocate nothing
+  void prepare(int term_events = kTermEvents);
   void sync();
   int jacobi_capped();      // syncs; Jacobi SVDs of this context stopped at the sweep cap
   int jacobi_seen = 0;      // the count at the last check (jacobi_warning)

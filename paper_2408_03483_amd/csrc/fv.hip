@@ -1198,7 +1198,6 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
       // single-chain graphs on their own streams do (measured)
       const int nb = p->workers > 0 ? p->workers : p->workers == 0 ? 4 : 1;
       // split-K arrival counters now: their first use must not put a memset into a graph
-      (void)s->c.tile_counters();
       if (nb > 1) {
         HIP_CHECK(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming));
         for (int b = 0; b < nb; ++b) {
@@ -1208,7 +1207,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
           w->fixed = true;
           w->householder = true;
           w->power_iters = gi;
-          (void)w->tile_counters();
+          w->prepare();
           s->branch.push_back(std::move(w));
           hipEvent_t e;
           HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1234,6 +1233,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
           a = std::make_unique<Ctx>();
           HIP_CHECK(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));
           a->arena.init((size_t)512 << 20);
+          a->prepare(std::max((int)Ctx::kTermEvents, p->taylor_terms));
         }
     }
     s->st = derive_stencils(p->scheme == 3 ? 3 : 5);
@@ -1277,6 +1277,7 @@ Solver *solver_create(const tt_fv_params *p, const tt_matrix q0[3], void *stream
     s->rep_idx = s->c.arena.ialloc(rep.size());
     HIP_CHECK(hipMemcpyAsync(s->rep_idx, rep.data(), rep.size() * sizeof(int),
                              hipMemcpyHostToDevice, s->c.stream));
+    s->c.prepare();   // nothing of the context is allocated later, in a step
     s->c.sync();
     s->set_tolerances();
   } catch (...) {

@@ -432,6 +432,7 @@ PivotModel::PivotModel(size_t max_rows, uint64_t seed) : cap(max_rows) {
   }
   HIP_CHECK(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   c.arena.init((size_t)1 << 30);
+  c.prepare();
   // He-normal weights from a SplitMix64 stream (Box-Muller), zero biases
   std::vector<float> h(PM_NPARAM, 0.f);
   uint64_t st = seed;

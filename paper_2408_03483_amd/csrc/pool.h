@@ -27,6 +27,7 @@ class Pool {
       HIP_CHECK(hipSetDevice(device));
       HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
       c->arena.init(arena_bytes);
+      c->prepare();
       ctx_.push_back(std::move(c));
     }
     for (int i = 0; i < nworkers; ++i)

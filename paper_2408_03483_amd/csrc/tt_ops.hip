@@ -508,9 +508,12 @@ struct SumPipe {
     });
   }
 
+  // the helper context's term events, one per term of this call (made at its creation)
+  size_t next_ev = 0;
+
   void push(const DTT &dy, hipStream_t producer) {
-    hipEvent_t e;
-    HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    TT_REQUIRE(next_ev < a.term_ev.size(), "reciprocal: more terms than the helper's events");
+    hipEvent_t e = a.term_ev[next_ev++];
     HIP_CHECK(hipEventRecord(e, producer));
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -557,7 +560,6 @@ struct SumPipe {
       } catch (...) {
         if (!err) err = std::current_exception();
       }
-      (void)hipEventDestroy(item.second);
     }
     (void)hipStreamSynchronize(a.stream);
   }
