@@ -49,6 +49,8 @@ extern "C" {
                              limit before its leak bound (rank <= 96 is redone exactly)      */
 #define TT_WJACOBI   8    /* a Jacobi SVD stopped at its sweep cap while still rotating      */
 
+/* A 2-core TT.  Cores are always stored in FP64: the FP32 form (TT_PREC_F32) changes the
+ * arithmetic of the contractions, not the storage, so the type carries no dtype. */
 typedef struct {
   int n1, n2;      /* mode sizes (rows of g1, rows of g2)                                  */
   int rank;        /* current rank: number of valid columns                                */
