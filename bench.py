@@ -18,13 +18,18 @@ source is unchanged.
                     [--workload bumps1024 | dambreak2048 | ensemble | learned4096 |
                                 paper_speedup]
                     [--members 64] [--precision f64 | f32] [--learned-n 4096]
+                    [--graph [--graph-only] [--graph-streams S] [--graph-branches B]]
+                    [--gemm-autotune] [--hw-queues 16]
                     [--sizes 1280,...] [--schemes upwind5,...] [--cases inertia_gravity,...]
 
 Other workloads (not the headline line): dambreak2048 = WENO5 through maxvol crosses, 1/h by
 cross, walls, rank cap 64, tol 1e-8 (with --precision f32 also run in FP64 for the
 speed-up and the difference); ensemble = independent nonlinear members of 256^2, 512^2 or
 1024^2 cells with rank caps 8..48 advanced together on shared worker streams, reported
-against the same members stepped one at a time; learned4096 = the dam break on 4096^2 with
+against the same members stepped one at a time (with --graph: every member in graph mode, its
+step a replayed HIP graph with every decision on the device, all members' graphs replayed side
+by side; the line's value is then that leg, the shared-pool ensemble and the one-at-a-time run
+beside it); learned4096 = the dam break on 4096^2 with
 crosses whose columns come from the learned pivot proposer (trained on pivots logged from
 the same run's warm-up steps), reported against plain maxvol crosses from the same state;
 paper_speedup = the paper's own measure (Sections 5.1-5.4): the Kelvin wave, inertia-gravity wave,
