@@ -65,6 +65,7 @@ METRIC = "cell-updates/s per RK step at fixed rel-L2 vs FP64 oracle; % HBM/MFMA 
 PEAK_FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector
 PEAK_FP64_MFMA_TFLOPS = 78.6        # MI355X FP64 matrix (dense)
 PEAK_FP32_MFMA_TFLOPS = 157.3       # MI355X FP32 matrix (dense)
+PEAK_FP32_VECTOR_TFLOPS = 157.3     # MI355X FP32 vector
 PEAK_HBM_GBS = 8000.0
 # counter traffic summaries per timed family, each tied to the source of its kernels
 TRAFFIC = {
@@ -115,7 +116,8 @@ def _roof(kernel, stats, elapsed, fp32=False, traffic=None, every=128):
     if kernel in ("gemm", "cholqr", "cholqr_slab"):
         bound, peak = "mfma", PEAK_FP32_MFMA_TFLOPS if fp32 else PEAK_FP64_MFMA_TFLOPS
     else:
-        bound, peak = "alu", PEAK_FP64_VECTOR_TFLOPS
+        # the Householder panels run in FP32 registers in the FP32 form
+        bound, peak = "alu", PEAK_FP32_VECTOR_TFLOPS if fp32 else PEAK_FP64_VECTOR_TFLOPS
     gbs = by / (avg_ms * 1e-3) / 1e9
     return {"kernel": kernel, "bound": bound, "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
@@ -483,6 +485,18 @@ def learned(args):
         el = time.perf_counter() - t0
         s1 = ttfv.tt_fv_get_stats(s)
         Q = ttfv.tt_fv_get_state(s)
+        roof = None
+        if mode == "learned" and model is m and rel < 0 and args.timed_kernel:
+            # the dominant family, timed over one more step after the timed region
+            ttfv.tt_fv_time_kernel(s, args.timed_kernel, args.time_every)
+            ttfv.tt_fv_step(s, st.dt, 1)
+            torch.cuda.synchronize()
+            # (the committed counter traffic is the 1024^2 headline's shapes: not these)
+            roof = _roof(args.timed_kernel, ttfv.tt_fv_get_stats(s), 0.0,
+                         fp32=args.precision == "f32", traffic=None, every=args.time_every)
+            if roof:
+                roof["measured_on"] = "1 step after the timed region"
+            ttfv.tt_fv_time_kernel(s, None)
         s.close()
         d = {k: s1[k] - s0[k] for k in ("crosses", "cross_sweeps_run", "learned_crosses",
                                          "learned_fallbacks")}
@@ -492,6 +506,8 @@ def learned(args):
                "accepted": d["learned_crosses"], "fallbacks": d["learned_fallbacks"],
                "acceptance_rate": d["learned_crosses"] / max(tried, 1),
                "max_accepted_validation_err": s1["max_learned_err"]}
+        if roof:
+            out["roofline"] = roof
         print(f"learned: {mode} rel {rel}: {out}", file=sys.stderr, flush=True)
         return el, out, Q
 
@@ -522,7 +538,7 @@ def learned(args):
                       "pivot_model": "16-256-256-1 bf16, trained on plain maxvol pivots of the "
                                      "2048^2 dam break and the 1024^2 bumps workload",
                       "acceptance": "validation error <= 1e-6, else the plain cross"},
-           "roofline": None, "cpu_baseline": None,
+           "roofline": res["learned_abs_1e-6"][1].get("roofline"), "cpu_baseline": None,
            "plain_value": n * n * args.steps / e_plain, "plain": o_plain,
            "train": {"rows": rows, "pivots": pos, "epochs": 30, "loss": loss,
                      "seconds": t_train}}
@@ -581,11 +597,25 @@ def ensemble(args):
         t_prep = time.perf_counter() - t0
         print(f"[ensemble] graph warm-up (eager step, capture, one replay) {t_prep:.1f} s",
               file=sys.stderr, flush=True)
+        g0 = [ttfv.tt_fv_get_stats(s) for s in gm]
         t0 = time.perf_counter()
         ttfv.tt_ens_step(gens, gm, [st.dt for st in states], args.steps, gconc)
         torch.cuda.synchronize()
         t_graph = (time.perf_counter() - t0) / args.steps
         gstats = [ttfv.tt_fv_get_stats(s) for s in gm]
+        # step-level roofline: the library's algorithmic flops and bytes of every member's step
+        # (counted at the graphs' static ranks) over the step time; the kernels inside a graph
+        # cannot carry timing events
+        fl = sum(b["flops"] - a["flops"] for a, b in zip(g0, gstats)) / args.steps
+        by = sum(b["bytes"] - a["bytes"] for a, b in zip(g0, gstats)) / args.steps
+        pk = PEAK_FP32_MFMA_TFLOPS if args.precision == "f32" else PEAK_FP64_MFMA_TFLOPS
+        groof = {"kernel": "whole step, all members", "bound": "mfma",
+                 "achieved": fl / t_graph / 1e12, "peak": pk, "unit": "TFLOP/s",
+                 "frac": fl / t_graph / 1e12 / pk, "traffic": None,
+                 "hbm_achieved_gbs": by / t_graph / 1e9,
+                 "hbm_frac": by / t_graph / 1e9 / PEAK_HBM_GBS,
+                 "alg_flops_per_step": fl, "alg_bytes_per_step": by,
+                 "timed_sample": "the whole timed region (host clock)"}
         for s in gm:
             s.close()
         # members equal to themselves stepped alone (graph mode, three steps), bit for bit
@@ -609,7 +639,8 @@ def ensemble(args):
                  "warmup_s": t_prep, "members_equal_alone": bool(same_g),
                  "max_rel_diff_alone": diff_g,
                  "graph_launches": int(sum(g["graph_launches"] for g in gstats)),
-                 "warnings_or": int(np.bitwise_or.reduce([g["warnings"] for g in gstats]))}
+                 "warnings_or": int(np.bitwise_or.reduce([g["warnings"] for g in gstats])),
+                 "roofline": groof}
         print(f"[ensemble] graph {graph}", file=sys.stderr, flush=True)
 
     tune = None
@@ -634,7 +665,8 @@ def ensemble(args):
                           "r_max": ranks, "eps": 1e-10, "scheme": "upwind5",
                           "graph": {"streams": graph["streams"]},
                           "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
-               "members_equal_alone": graph["members_equal_alone"], "graph": graph}
+               "members_equal_alone": graph["members_equal_alone"], "graph": graph,
+               "roofline": graph["roofline"]}
         print(json.dumps(out), flush=True)
         return
     # members one at a time (each with its own worker streams)
@@ -699,6 +731,7 @@ def ensemble(args):
                                 "members_equal_alone": bool(same)}
         out["value"] = graph["value"]
         out["ms_per_step"] = graph["ms_per_step"]
+        out["roofline"] = graph["roofline"]
         out["speedup_vs_sequential"] = t_seq / (graph["ms_per_step"] / 1e3)
         out["speedup_vs_pool_ensemble"] = t_ens / (graph["ms_per_step"] / 1e3)
         out["members_equal_alone"] = graph["members_equal_alone"]
