@@ -270,3 +270,40 @@ def test_graph_ensemble_member_512_cap40_fp32_vs_oracle(lib):
     _say(f"  rel {r} ranks {stats['ranks']} launches {stats['graph_launches']}")
     assert stats["graph_launches"] == 1 and stats["steps"] == 2
     assert max(r) <= 1e-4
+
+
+@pytest.mark.parametrize("recip", ["taylor", "cross"])
+def test_graph_lake_at_rest(lib, recip):
+    """Degenerate state in graph mode: h = 1, hu = hv = 0 (zero TTs: every device decision
+    keeps rank 0 for the momenta) between walls stays at rest to round-off over an eager step,
+    the capture and two replays."""
+    _say(f"graph lake at rest 40^2 {recip}")
+    n = 40
+    ones = np.ones((n, 1))
+    zero = np.zeros((n, 1))
+    dev = [lib.DeviceTT.from_factors(ones, ones, cap=8), lib.DeviceTT.from_factors(zero, zero, cap=8),
+           lib.DeviceTT.from_factors(zero, zero, cap=8)]
+    s = lib.tt_fv_init(n, "upwind5", True, False, dev, g=9.81, eps=1e-10, r_max=8, recip=recip,
+                       arena_bytes=1 << 28, graph=True)
+    lib.tt_fv_step(s, 1e-3, 4)
+    Qg = lib.tt_fv_get_state(s)
+    stats = lib.tt_fv_get_stats(s)
+    s.close()
+    assert stats["graph_launches"] == 3
+    assert np.max(np.abs(Qg[0].full() - 1.0)) <= 1e-13
+    assert np.max(np.abs(Qg[1].full())) <= 1e-13 and np.max(np.abs(Qg[2].full())) <= 1e-13
+
+
+def test_graph_mass_conservation(lib):
+    """Periodic bumps in graph mode: the total mass sum(h) dx^2 is conserved by the
+    flux-difference form to round-off over an eager step, the capture and eight replays."""
+    _say("graph mass conservation 128^2")
+    st = synth.nonlinear_bumps(seed=9, n=128, rmax=16, eps=1e-10)
+    m0 = float(np.sum(st.tt[0].A @ st.tt[0].B.T))
+    s = _solver(lib, st, 16, True)
+    lib.tt_fv_step(s, st.dt, 10)
+    Q = lib.tt_fv_get_state(s)
+    s.close()
+    m1 = float(np.sum(Q[0].full()))
+    _say(f"  mass {m0!r} -> {m1!r}, rel {abs(m1 - m0) / m0:.2e}")
+    assert abs(m1 - m0) <= 1e-9 * m0
