@@ -1058,6 +1058,9 @@ struct Solver {
   // replace the separable terms: ghost terms get their exact-axis column (zero inside the
   // domain) and their other factor extended by the other axis's rule, both n + 6 rows
   void set_terms(const tt_fv_term *tv, int count) {
+    TT_REQUIRE(!p.graph || count == 0,
+               "tt_fv_set_terms: graph mode has no time-dependent terms (their factors would "
+               "be fixed in the captured step)");
     TT_REQUIRE(count >= 0 && (count == 0 || tv), "tt_fv_set_terms: bad term list");
     const size_t col = (size_t)n + 6;
     std::vector<double> host((size_t)count * 2 * col, 0.0);
@@ -1611,6 +1614,8 @@ void solver_time_kernel(Solver *s, const char *name, int every) {
 }
 
 void solver_set_pivots(Solver *s, int mode, PivotModel *pm) {
+  TT_REQUIRE(!s->p.graph || mode == TT_PIV_MAXVOL,
+             "tt_fv_set_pivots: graph mode runs plain maxvol crosses only");
   std::lock_guard<std::mutex> lk(s->mu);
   s->piv_mode = mode;
   s->pm = pm;

@@ -185,6 +185,15 @@ def test_graph_mode_refuses_host_decided_paths(lib):
         _solver(lib, st, 8, True, scheme="weno5")
     with pytest.raises(RuntimeError, match="graph mode"):
         _solver(lib, st, 24, True)                  # n = 48 is not above 2 r_max
+    s = _solver(lib, st, 8, True)
+    forcing = synth.Term(var=0, where="forcing", amp=1.0, omega=1.0, phase=0.0,
+                         X=np.ones(48), Y=np.ones(48))
+    with pytest.raises(RuntimeError, match="graph mode"):
+        lib.tt_fv_set_terms(s, [forcing])           # time factors would be fixed in the graph
+    with pytest.raises(RuntimeError, match="graph mode"):
+        lib.tt_fv_set_pivots(s, "kicks")            # graph crosses are plain maxvol
+    lib.tt_fv_set_pivots(s, "maxvol")
+    s.close()
 
 
 def _graph_members(lib):
