@@ -284,7 +284,9 @@ typedef struct {
                          the solver's own stream (again after a change of dt) and every later
                          step replays the graph, with no host round trip.  Needs Upwind3/5,
                          TT_EPS_FIXED, TT_FLUX_PRODUCTS, seeded kicks, no exact boundaries or
-                         terms, n > 2 r_max.  `workers` sets the branch streams the
+                         terms (tt_fv_set_terms refuses them), plain maxvol pivots
+                         (tt_fv_set_pivots refuses the other modes), n > 2 r_max.
+                         `workers` sets the branch streams the
                          independent tasks of a phase fork onto inside the graph (0: 4; -1, a
                          member for tt_ens_step: 1, one chain).  Results equal the dynamic
                          path's up to what the fixed iteration count leaves of the range
