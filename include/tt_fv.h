@@ -331,8 +331,9 @@ typedef struct {
   int ranks[3];               /* current state ranks                                      */
   long long roundings;        /* roundings performed                                      */
   long long crosses;          /* crosses performed                                        */
-  int last_taylor_terms;      /* terms used by the last reciprocal                        */
-  double last_taylor_err;     /* its final Err                                            */
+  int last_taylor_terms;      /* terms used by the last reciprocal (graph mode: the terms
+                                 formed, taylor_terms)                                     */
+  double last_taylor_err;     /* its final Err (graph mode: not read back, 0)              */
   int warnings;               /* OR of TT_W* bits since init                              */
   double flops;               /* algorithmic flop count since init                        */
   double bytes;               /* algorithmic HBM bytes since init                         */

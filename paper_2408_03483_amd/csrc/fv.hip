@@ -604,6 +604,7 @@ struct Solver {
   void reciprocal(Ctx &w, const DTT &h, int recip_site, int chain, DTT &rh) {
     if (p.graph && p.recip == 0) {
       reciprocal_fixed(w, h, eps_in, p.taylor_terms, p.r_max, rh);
+      last_terms = p.taylor_terms;   // every term is formed; Err stays on the device
       return;
     }
     if (p.recip == 1) {

@@ -1126,6 +1126,7 @@ int reciprocal_fixed(Ctx &c, const DTT &x, double eps, int K, int rmax, DTT &y) 
   y.r = 1;
   double *hist = c.arena.dalloc(4), *ss = c.arena.dalloc(1);
   taylor_start(c, hist);
+  if (K == 1) c.cnt.warnings |= TT_WNOCONV;   // the constant term alone: Err = 1 > eps
   for (int terms = 1; terms < K; ++terms) {
     Scope s3(c.arena);
     const int R = dy.r * xt.r;
