@@ -106,6 +106,18 @@ def _family_traffic(kernel):
                     os.path.join(ROOT, "paper_2408_03483_amd", "csrc", src))
 
 
+def _step_roof(flops, byts, seconds, fp32):
+    """Step-level roofline: the library's algorithmic flops and bytes of one step over its time
+    (for graph replays, whose kernels carry no timing events)."""
+    pk = PEAK_FP32_MFMA_TFLOPS if fp32 else PEAK_FP64_MFMA_TFLOPS
+    tf = flops / seconds / 1e12
+    gbs = byts / seconds / 1e9
+    return {"kernel": "whole step, all members", "bound": "mfma", "achieved": tf, "peak": pk,
+            "unit": "TFLOP/s", "frac": tf / pk, "traffic": None, "hbm_achieved_gbs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS, "alg_flops_per_step": flops,
+            "alg_bytes_per_step": byts, "timed_sample": "the whole timed region (host clock)"}
+
+
 def _roof(kernel, stats, elapsed, fp32=False, traffic=None, every=128):
     if not stats["timed_launches"] or stats["timed_ms"] <= 0:
         return None
@@ -608,14 +620,7 @@ def ensemble(args):
         # cannot carry timing events
         fl = sum(b["flops"] - a["flops"] for a, b in zip(g0, gstats)) / args.steps
         by = sum(b["bytes"] - a["bytes"] for a, b in zip(g0, gstats)) / args.steps
-        pk = PEAK_FP32_MFMA_TFLOPS if args.precision == "f32" else PEAK_FP64_MFMA_TFLOPS
-        groof = {"kernel": "whole step, all members", "bound": "mfma",
-                 "achieved": fl / t_graph / 1e12, "peak": pk, "unit": "TFLOP/s",
-                 "frac": fl / t_graph / 1e12 / pk, "traffic": None,
-                 "hbm_achieved_gbs": by / t_graph / 1e9,
-                 "hbm_frac": by / t_graph / 1e9 / PEAK_HBM_GBS,
-                 "alg_flops_per_step": fl, "alg_bytes_per_step": by,
-                 "timed_sample": "the whole timed region (host clock)"}
+        groof = _step_roof(fl, by, t_graph, args.precision == "f32")
         for s in gm:
             s.close()
         # members equal to themselves stepped alone (graph mode, three steps), bit for bit

@@ -38,6 +38,21 @@ def test_roofline_arithmetic():
     f32 = bench._roof("gemm", _stats(100, 10.0, 1e9, 5e8), 1.0, fp32=True, traffic=123.0)
     assert f32["peak"] == bench.PEAK_FP32_MFMA_TFLOPS and f32["traffic"] == 123.0
     assert bench._roof("gemm", _stats(0, 0.0, 0.0, 0.0), 1.0) is None
+    # the Householder family: vector ALU, FP32 peak in the FP32 form
+    qr = bench._roof("tsqr_qr", _stats(10, 1.0, 1e8, 1e7), 1.0, fp32=True)
+    assert qr["bound"] == "alu" and qr["peak"] == bench.PEAK_FP32_VECTOR_TFLOPS
+    assert bench._roof("tsqr_qr", _stats(10, 1.0, 1e8, 1e7), 1.0)["peak"] == \
+        bench.PEAK_FP64_VECTOR_TFLOPS
+
+
+def test_step_roofline_arithmetic():
+    # 3e12 flops and 2e11 bytes per step in 2 s: 1.5 TFLOP/s and 100 GB/s
+    r = bench._step_roof(3e12, 2e11, 2.0, fp32=True)
+    assert r["achieved"] == pytest.approx(1.5) and r["peak"] == bench.PEAK_FP32_MFMA_TFLOPS
+    assert r["frac"] == pytest.approx(1.5 / bench.PEAK_FP32_MFMA_TFLOPS)
+    assert r["hbm_achieved_gbs"] == pytest.approx(100.0)
+    assert r["hbm_frac"] == pytest.approx(100.0 / bench.PEAK_HBM_GBS)
+    assert bench._step_roof(3e12, 2e11, 2.0, fp32=False)["peak"] == bench.PEAK_FP64_MFMA_TFLOPS
 
 
 def test_traffic_follows_the_gemm_source(tmp_path, monkeypatch):
