@@ -34,8 +34,11 @@
 // Separable forcing terms add rank-1 TTs to L.  Terms are evaluated at the SSP-RK3 stage
 // times t, t + dt, t + dt/2.
 //
-// Every TT of the step lives in the solver's arena; ranks are known on the host after each
-// rounding (one stream synchronisation per rounding), so every launch has its exact shape.
+// Every TT of the step lives in the solver's arena.  By default ranks are known on the host after
+// each rounding (one stream synchronisation per rounding), so every launch has its exact shape.
+// In graph mode (tt_fv_params.graph) every decision is taken on the device (fixed.hip), every TT
+// keeps the static rank of its buffer with zero columns after the device's rank, and the step is
+// captured in a HIP graph after one eager step and replayed.
 #include "common.h"
 #include "pool.h"
 
