@@ -4,9 +4,10 @@
 // the static rank of its buffer and the columns beyond the rank chosen on the device are
 // zero, so each TT has the value of the dynamic path's and a step is the same sequence of
 // launches with the same shapes on every call: it can be captured in a HIP graph once and
-// replayed.  The rules are those of the host code (trunc_rank, kept_directions,
-// kick_indices, the reciprocal's Err test), evaluated in the same order.
+// replayed.  The rank, kept-direction and kick rules are the host code's own (rules.h); the
+// reciprocal's Err test follows the host loop's order.
 #include "common.h"
+#include "rules.h"
 
 #include <cmath>
 
@@ -36,25 +37,11 @@ __global__ __launch_bounds__(TB) void k_trunc_mask(const double *__restrict__ sg
     if (bad) {
       atomicOr(&status[FX_ERRORS], FX_ERR_NONFINITE);
     } else if (rule == 1) {
-      if (sg[0] > 0.0)
-        while (k < m && sg[k] > eps * sg[0]) ++k;
+      k = rule_kept_directions(sg, m, eps);
     } else if (sg[0] != 0.0) {
-      tail[m] = 0.0;
-      for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + sg[i] * sg[i];
-      const double thr = eps * eps * tail[0];
-      k = m;
-      for (int kk = 1; kk <= m; ++kk)
-        if (tail[kk] <= thr) {
-          k = kk;
-          break;
-        }
-      const double fl = fmax(1e-17, floor_rel) * sqrt(tail[0]);
-      int kf = 0;
-      while (kf < m && sg[kf] > fl) ++kf;
-      k = min(k, max(kf, 1));
-      const bool cap = k > rmax;
-      k = max(1, min(k, rmax));
-      if (cap && tail[k] > thr) atomicOr(&status[FX_WARN], TT_WRANKCAP);
+      bool capped = false;
+      k = rule_trunc_rank(sg, m, eps, rmax, floor_rel, tail, &capped);
+      if (capped) atomicOr(&status[FX_WARN], TT_WRANKCAP);
       if (q >= 0 && k < m) {
         const int pover = max(8, m / 4);
         bool conv = m - pover > k && sg[m - pover] <= 1e-14 * sg[0];
@@ -100,41 +87,20 @@ __global__ void k_mask_cols(double *__restrict__ X, int ld, int rows, const int 
   X[(size_t)c * ld + i] = 0.0;
 }
 
-__device__ uint64_t splitmix_next(uint64_t &state) {
-  state += 0x9E3779B97F4A7C15ull;
-  uint64_t z = state;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// nJ = *src, then the seeded fresh columns of a non-final sweep (kick_indices with the key
-// (site << 32 | step) + 1000003 (sweep + 1)) appended while nJ < rmax
+// nJ = *src, then the seeded fresh columns of a non-final sweep (rules.h, with the key
+// (site << 32 | step) + 1000003 (sweep + 1) of the host's crosses) appended while nJ < rmax
 __global__ void k_kicks(int *__restrict__ J, int *__restrict__ nJ, const int *__restrict__ src,
                         int n, int kick, int rmax, unsigned long long site,
                         const long long *__restrict__ step, int sweep) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int have = *src;
-  int cnt_all = have;
+  int added = 0;
   if (have < rmax && kick > 0) {
-    const int cnt = min(kick, rmax - have);
-    uint64_t state = ((site << 32) | ((uint64_t)*step & 0xFFFFFFFFull)) +
-                     1000003ull * (uint64_t)(sweep + 1);
-    int out = 0, tries = 0;
-    while (out < cnt && have + out < n && tries < 64 * (cnt + 1)) {
-      const int idx = (int)(splitmix_next(state) % (uint64_t)n);
-      ++tries;
-      bool seen = false;
-      for (int t = 0; t < have + out; ++t)
-        if (J[t] == idx) {
-          seen = true;
-          break;
-        }
-      if (!seen) J[have + out++] = idx;
-    }
-    cnt_all = have + out;
+    const uint64_t key = ((site << 32) | ((uint64_t)*step & 0xFFFFFFFFull)) +
+                         1000003ull * (uint64_t)(sweep + 1);
+    added = rule_kicks(J, have, n, min(kick, rmax - have), key);
   }
-  *nJ = cnt_all;
+  *nJ = have + added;
 }
 
 // dst = alpha src with alpha = mul * s[0] (mode 0) or mul / s[0] (mode 1)

@@ -12,6 +12,7 @@
 //   The rank k is the smallest with sqrt(sum_{i>=k} s_i^2) <= eps ||s|| capped at rmax.
 //   Output gauge: A' = Qa U_k (orthonormal columns), B' = Qb M^T U_k (carries Sigma).
 #include "common.h"
+#include "rules.h"
 
 #include <algorithm>
 #include <cmath>
@@ -44,29 +45,12 @@ std::vector<double> to_host(Ctx &c, const double *dev, size_t n) {
   return h;
 }
 
-// Kept rank of a truncation: the fewest leading singular values whose discarded tail is within
-// eps of the total, at most rmax, and never a direction at or below the SVD's norm floor
-// max(1e-17, floor_rel) ||s||: the Jacobi SVD does not rotate such columns, so they are not
-// orthogonal to the others and keeping one would turn the projection Q U_k U_k^T into a
-// non-projection.  A tolerance below that floor (below round-off) therefore keeps every
-// direction above it.  capped: the rank cap, not eps or the floor, set k.
+// Kept rank of a truncation (rules.h: the rule the fixed-shape kernels take too)
 int trunc_rank(const std::vector<double> &s, double eps, int rmax, double floor_rel,
                bool *capped) {
   const int m = (int)s.size();
   std::vector<double> tail(m + 1, 0.0);
-  for (int i = m - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
-  const double thr = eps * eps * tail[0];
-  int k = m;
-  for (int kk = 1; kk <= m; ++kk)
-    if (tail[kk] <= thr) { k = kk; break; }
-  const double fl = std::max(1e-17, floor_rel) * std::sqrt(tail[0]);
-  int kf = 0;
-  while (kf < m && s[kf] > fl) ++kf;
-  k = std::min(k, std::max(kf, 1));
-  const bool cap = k > rmax;
-  k = std::max(1, std::min(k, rmax));
-  if (capped) *capped = cap && (tail[k] > thr);
-  return k;
+  return rule_trunc_rank(s.data(), m, eps, rmax, floor_rel, tail.data(), capped);
 }
 
 // SVD of an m x m core (not transposed).  From m = 48 on, a pivoted QR first grades the
@@ -108,10 +92,7 @@ int kept_directions(const std::vector<double> &s, double drop, int want) {
                "orth: the columns have fewer nonzero directions than requested");
     return want;
   }
-  int k = 0;
-  if (s[0] > 0.0)
-    while (k < m && s[k] > drop * s[0]) ++k;
-  return k;
+  return rule_kept_directions(s.data(), m, drop);
 }
 
 }  // namespace
@@ -800,29 +781,18 @@ std::vector<int> maxvol_host(Ctx &c, const double *Q, int n, int r, int ldq, dou
   return h;
 }
 
-uint64_t splitmix64_next(uint64_t &state) {
-  state += 0x9E3779B97F4A7C15ull;
-  uint64_t z = state;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
+uint64_t splitmix64_next(uint64_t &state) { return rule_splitmix64(state); }
 
+// seeded fresh columns outside `have_v` (rules.h: the rule the fixed-shape kernels take too)
 std::vector<int> kick_indices(const std::vector<int> &have_v, int n, int count, uint64_t key) {
-  std::unordered_set<int> have(have_v.begin(), have_v.end());
-  std::vector<int> out;
-  uint64_t state = key;
-  int tries = 0;
-  while ((int)out.size() < count && (int)have.size() < n && tries < 64 * (count + 1)) {
-    const uint64_t z = splitmix64_next(state);
-    const int idx = (int)(z % (uint64_t)n);
-    ++tries;
-    if (!have.count(idx)) {
-      have.insert(idx);
-      out.push_back(idx);
-    }
-  }
-  return out;
+  std::vector<int> J;
+  J.reserve(have_v.size() + std::max(count, 0));
+  for (int j : have_v)
+    if (std::find(J.begin(), J.end(), j) == J.end()) J.push_back(j);
+  const int have = (int)J.size();
+  J.resize(have + std::max(count, 0));
+  const int added = count > 0 ? rule_kicks(J.data(), have, n, count, key) : 0;
+  return std::vector<int>(J.begin() + have, J.begin() + have + added);
 }
 
 namespace {
