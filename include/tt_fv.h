@@ -106,6 +106,21 @@ int  tt_ctx_set_enrichment(tt_ctx *ctx, int mode);
  * step.  Each call still reads its rank back; the point of the mode is the solver's graph. */
 int  tt_ctx_set_fixed(tt_ctx *ctx, int on);
 
+/* Host-only (no GPU, no context): the decision rules the library takes on the host in its
+ * dynamic path and in its fixed-shape kernels (one definition for both), exposed for checking.
+ * tt_rule_trunc_rank: the kept rank of a rounding (Section 3.2) from its singular values s
+ * (host, m values, descending): the fewest leading values whose discarded tail is within eps
+ * of the total, never one at or below max(1e-17, floor_rel) ||s||, at most r_max (>= 1);
+ * *capped (optional) = 1 when r_max, not eps or the floor, decided.  Returns the rank, or
+ * TT_EINVAL for m < 1, m > 128, r_max < 1 or a null s.
+ * tt_rule_kicks: the seeded fresh columns of a cross sweep (Section 3.3): up to `count` indices
+ * in [0, n) outside have[0 .. nhave) (distinct), drawn as SplitMix64 outputs mod n from `key`
+ * with at most 64 (count + 1) draws; written to out (host, room for count); returns how many,
+ * or TT_EINVAL for bad arguments (nhave > 4096, count > 4096). */
+int  tt_rule_trunc_rank(const double *s, int m, double eps, int r_max, double floor_rel,
+                        int *capped);
+int  tt_rule_kicks(const int *have, int nhave, int n, int count, uint64_t key, int *out);
+
 /* TT rounding (Section 3.2): y = best approximation of x with relative Frobenius accuracy
  * eps and rank <= r_max.  x may have any rank <= x->cap; y->cap must be >= r_max.
  * Returns TT_WRANKCAP when the cap truncated more than eps.  The kept singular values

@@ -1,6 +1,7 @@
 // C ABI entry points (include/tt_fv.h): argument checks, context/arena management and the
 // translation of internal exceptions into return codes.
 #include "common.h"
+#include "rules.h"
 
 #include <cmath>
 #include <cstring>
@@ -438,6 +439,31 @@ int tt_ctx_set_fixed(tt_ctx *ctx, int on) {
     ctx->c.fixed = on == 1;
     ctx->c.householder = on == 1;
     return 0;
+  });
+}
+
+int tt_rule_trunc_rank(const double *s, int m, double eps, int r_max, double floor_rel,
+                       int *capped) {
+  return guarded([&]() {
+    TT_REQUIRE(s && m >= 1 && m <= 128 && r_max >= 1, "tt_rule_trunc_rank: bad arguments");
+    double tail[129];
+    bool cap = false;
+    const int k = rule_trunc_rank(s, m, eps, r_max, floor_rel, tail, &cap);
+    if (capped) *capped = cap ? 1 : 0;
+    return k;
+  });
+}
+
+int tt_rule_kicks(const int *have, int nhave, int n, int count, uint64_t key, int *out) {
+  return guarded([&]() {
+    TT_REQUIRE((have || nhave == 0) && (out || count == 0) && nhave >= 0 && nhave <= 4096 &&
+                   count >= 0 && count <= 4096 && n >= 1,
+               "tt_rule_kicks: bad arguments");
+    std::vector<int> J(have, have + nhave);
+    J.resize((size_t)nhave + count);
+    const int added = count ? rule_kicks(J.data(), nhave, n, count, key) : 0;
+    for (int i = 0; i < added; ++i) out[i] = J[(size_t)nhave + i];
+    return added;
   });
 }
 

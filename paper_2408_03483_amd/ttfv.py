@@ -112,7 +112,8 @@ EXPORTS = ["tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_sketch", "tt_ctx_set_p
            "tt_ctx_set_limits", "tt_ctx_set_qr", "tt_fv_set_pivot_acceptance",
            "tt_grid_init", "tt_grid_step", "tt_grid_destroy", "tt_grid_set_terms",
            "tt_fv_set_terms", "tt_compress", "tt_fv_max_speed", "tt_fv_cfl_dt",
-           "tt_ctx_set_enrichment", "tt_round_nd", "tt_ctx_set_fixed"]
+           "tt_ctx_set_enrichment", "tt_round_nd", "tt_ctx_set_fixed", "tt_rule_trunc_rank",
+           "tt_rule_kicks"]
 
 PM_NPARAM = 70401
 PIVOTS = {"maxvol": 0, "log": 1, "learned": 2, "replay": 3, "kicks": 4}
@@ -140,6 +141,10 @@ def load_library(path: str = LIB_PATH):
     L.tt_ctx_set_qr.argtypes = [P, I, I]
     L.tt_ctx_set_enrichment.argtypes = [P, I]
     L.tt_ctx_set_fixed.argtypes = [P, I]
+    L.tt_rule_trunc_rank.argtypes = [ctypes.POINTER(ctypes.c_double), I, ctypes.c_double, I,
+                                     ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+    L.tt_rule_kicks.argtypes = [ctypes.POINTER(ctypes.c_int), I, I, I, ctypes.c_uint64,
+                                ctypes.POINTER(ctypes.c_int)]
     L.tt_round.argtypes = [P, pM, D, I, pM, ctypes.POINTER(D)]
     L.tt_round_noalloc.argtypes = [pM, D, I, pM, ctypes.POINTER(D), P]
     L.tt_compress.argtypes = [P, P, I, I, I, D, I, pM, ctypes.POINTER(D)]
@@ -286,6 +291,28 @@ def tt_ctx_set_qr(ctx: Ctx, method: str, max_passes: int = 6) -> None:
 
 def tt_ctx_set_enrichment(ctx: Ctx, mode: str) -> None:
     _check(_lib.tt_ctx_set_enrichment(ctx.h, ENRICH[mode]), "tt_ctx_set_enrichment")
+
+
+def tt_rule_trunc_rank(s, eps: float, r_max: int, floor_rel: float = 0.0):
+    """The library's kept-rank rule on host singular values (no GPU): (rank, capped)."""
+    L = load_library()
+    import numpy as np
+    a = np.ascontiguousarray(s, dtype=np.float64)
+    cap = ctypes.c_int()
+    k = _check(L.tt_rule_trunc_rank(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size,
+                                    eps, r_max, floor_rel, ctypes.byref(cap)),
+               "tt_rule_trunc_rank")
+    return k, bool(cap.value)
+
+
+def tt_rule_kicks(have, n: int, count: int, key: int):
+    """The library's seeded fresh cross columns (no GPU)."""
+    L = load_library()
+    h = (ctypes.c_int * max(len(have), 1))(*[int(v) for v in have])
+    out = (ctypes.c_int * max(count, 1))()
+    m = _check(L.tt_rule_kicks(h, len(have), n, count, ctypes.c_uint64(key & 0xFFFFFFFFFFFFFFFF),
+                               out), "tt_rule_kicks")
+    return [out[i] for i in range(m)]
 
 
 def tt_ctx_set_fixed(ctx: Ctx, on: bool) -> None:
