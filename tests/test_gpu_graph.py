@@ -351,3 +351,27 @@ def test_graph_ensemble_full_size_members_conserve_mass(lib):
         assert d <= 1e-6
         s.close()
     ens.close()
+
+
+@pytest.mark.parametrize("q,decay", [(1, 0.8), (2, 0.8), (1, 0.97), (2, 0.97)])
+def test_fixed_range_finder_equals_the_oracle_sketch(lib, q, decay):
+    """The fixed-shape range finder (exactly q subspace iterations, no host check) against the
+    oracle's implementation of the same seeded sketch with the same fixed count (power and
+    maximum iterations q; above rank 96 an unconverged sketch is kept on both sides): equal to
+    round-off, on a fast and a slow spectrum."""
+    _say(f"fixed range finder q={q} decay={decay}")
+    n1, n2, r, eps, rmax = 1000, 3000, 300, 1e-8, 24
+    rng = np.random.default_rng(int(100 * decay) + q)
+    A, B = decaying(rng, n1, n2, r, decay)
+    x = lib.DeviceTT.from_factors(A, B)
+    c = lib.tt_ctx_create()
+    lib.tt_ctx_set_fixed(c, True)
+    lib.tt_ctx_set_sketch(c, 0, q)
+    y = lib.DeviceTT(n1, n2, rmax)
+    lib.tt_round(c, x, eps, rmax, y)
+    c.close()
+    ref = ott.tt_round_sketched(ott.TT(A, B), eps, rmax, power_iters=q, max_iters=q)
+    d = rel(y.full(), ref.A @ ref.B.T)
+    _say(f"  ranks {y.rank} {ref.rank}; rel {d:.2e}")
+    assert y.rank == ref.rank
+    assert d < 1e-12
