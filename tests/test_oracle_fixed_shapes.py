@@ -79,3 +79,49 @@ def test_predicated_taylor_equals_the_early_exit_loop(amp, K):
     assert _rel(got.full(), ref.full()) < 1e-13, terms
     if amp < 0.1:
         assert terms < K                      # the case where the predicate matters
+
+
+def _masked_maxvol(Qpad: np.ndarray, k: int, tau: float = 1.05, maxit: int = 100):
+    """maxvol as the fixed-shape kernels run it on a basis whose columns from k on are zero:
+    the greedy start over all m columns (steps after the k-th find residuals of zero and pick
+    rows without meaning), Q[I] completed by the identity outside its leading k x k block, then
+    the swap loop on B = Q Q[I]^-1."""
+    n, m = Qpad.shape
+    R = Qpad.copy()
+    rows = []
+    for _ in range(m):
+        nrm = np.einsum("ij,ij->i", R, R)
+        i = int(np.argmax(nrm))
+        rows.append(i)
+        if nrm[i] > 0.0:
+            v = R[i] / math.sqrt(nrm[i])
+            R = R - np.outer(R @ v, v)
+    I = np.array(rows, dtype=np.int64)
+    QI = Qpad[I].copy()
+    QI[k:, :] = 0.0
+    QI[:, k:] = 0.0
+    QI[np.arange(k, m), np.arange(k, m)] = 1.0
+    B = Qpad @ np.linalg.inv(QI)
+    for _ in range(maxit):
+        flat = int(np.argmax(np.abs(B)))
+        i, j = divmod(flat, m)
+        if abs(B[i, j]) <= tau:
+            break
+        bj = B[:, j].copy()
+        bi = B[i, :].copy()
+        bi[j] -= 1.0
+        B -= np.outer(bj, bi) / bj[i]
+        I[j] = i
+    return I
+
+
+@pytest.mark.parametrize("n,k,m", [(200, 7, 16), (500, 24, 32), (129, 1, 40)])
+def test_masked_maxvol_picks_the_live_columns_rows(n, k, m):
+    """Its first k rows are those of maxvol on the k live columns, and the swaps never touch the
+    zero columns."""
+    rng = np.random.default_rng(n + k)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    Qpad = np.hstack([Q, np.zeros((n, m - k))])
+    I_live = ott.maxvol(Q)
+    I_pad = _masked_maxvol(Qpad, k)
+    assert I_pad[:k].tolist() == I_live.tolist()
