@@ -160,6 +160,26 @@ def test_graph_step_equals_dynamic_and_oracle(lib, periodic):
     sg.close()
 
 
+def test_graph_branches_equal_one_chain(lib):
+    """The independent tasks of a phase forked onto 4 branch streams inside the captured step
+    (the default of a standalone solver) give the single-chain graph's state bit for bit (same
+    kernels, same order within each task), on 96^2 capped bumps with walls over an eager step,
+    the capture and four replays."""
+    _say("graph branches vs one chain 96")
+    st = synth.nonlinear_bumps(seed=1, n=96, rmax=16, eps=1e-10)
+    out = []
+    for workers in (1, 4):
+        dev = [lib.DeviceTT.from_factors(f.A, f.B, cap=16) for f in st.tt]
+        s = lib.tt_fv_init(st.n, "upwind5", True, False, dev, g=st.g, H0=st.H0, eps=1e-10,
+                           r_max=16, workers=workers, arena_bytes=1 << 30, graph=True)
+        lib.tt_fv_step(s, st.dt, 6)
+        out.append([q.full() for q in lib.tt_fv_get_state(s)])
+        assert lib.tt_fv_get_stats(s)["graph_launches"] == 5
+        s.close()
+    for a, b in zip(out[1], out[0]):
+        assert np.array_equal(a, b)
+
+
 def test_graph_step_fp32_contractions_vs_oracle(lib):
     """Config-4-like member at 256^2 (rank cap 24, FP32 contractions): three steps, two of them
     replays, within 1e-4 of the FP64 oracle per field."""
