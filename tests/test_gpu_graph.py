@@ -181,7 +181,7 @@ def test_graph_branches_equal_one_chain(lib):
 
 
 def test_graph_step_fp32_contractions_vs_oracle(lib):
-    """Config-4-like member at 256^2 (rank cap 24, FP32 contractions): three steps, two of them
+    """A batched-ensemble member at 256^2 (rank cap 24, FP32 contractions): three steps, two of them
     replays, within 1e-4 of the FP64 oracle per field."""
     _say("graph step 256 fp32")
     st = synth.nonlinear_bumps(seed=1007, n=256, rmax=24, eps=1e-10)
@@ -272,7 +272,7 @@ def test_graph_state_reads_follow_the_callers_stream(lib):
 
 
 def test_graph_ensemble_member_512_cap40_fp32_vs_oracle(lib):
-    """An ensemble member at the batched configuration's real shape (512^2, rank cap 40, FP32
+    """An ensemble member at the batched ensemble workload's member shape (512^2, rank cap 40, FP32
     contractions, Upwind5, Taylor 8 terms, tol 1e-10) stepped in a graph ensemble beside a
     small member: an eager step and a replayed graph, within the FP32 bar of 1e-4 of the FP64
     oracle per field."""
@@ -339,7 +339,7 @@ def test_graph_mass_conservation(lib):
 
 
 def test_graph_ensemble_full_size_members_conserve_mass(lib):
-    """Members at the batched configuration's full shapes (1024^2 cap 48, 512^2 cap 33, 256^2
+    """Members at the batched ensemble workload's full shapes (1024^2 cap 48, 512^2 cap 33, 256^2
     cap 8; FP32 contractions) stepped as a graph ensemble (eager step, capture, two replays):
     the mass sum(h) dx^2 of every member is kept by the flux-difference form to the roundings'
     level (tol 1e-10 in FP32 arithmetic: 1e-6 relative), h stays positive and finite, and the
