@@ -21,6 +21,8 @@
  *     device or pinned memory and create no event.  The exceptions are opt-in: kernel
  *     timing (tt_fv_time_kernel) and the GEMM tile autotuner (tt_gemm_autotune) create
  *     events as they measure.
+ *   - A context, solver or ensemble is used by one host thread at a time (the library runs
+ *     its own threads inside a call); different objects may be used from different threads.
  *   - Return value: 0 on success, a negative TT_E* code on error (outputs untouched
  *     or partially written), or a positive bitmask of TT_W* warnings.
  *     tt_last_error() gives a message for the last failure in the calling thread.
